@@ -1,0 +1,155 @@
+"""CPU oracle for the A-Bruijn graph build -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it,
+and it shares no code with the GPU path: its C core (``dbg_oracle.c``) packs,
+hashes and counts on its own.
+
+Contents:
+  * ``build_graph``   -- the graph as sorted records (the C core, the plain
+                         definition of the build; see ``dbg_oracle.c``);
+  * ``vertex_counts`` -- one vertex's four counters by scanning every window;
+  * ``brute``         -- a second, string-based brute force for tiny inputs;
+  * ``invariants``    -- properties any correct graph satisfies;
+  * ``euler``         -- Eulerian path over the graph's edge multiplicities.
+
+Output form (the canonical comparison form): ``keys`` is ``uint64[V]``
+ascending, ``counts`` is ``uint32[V, 4]`` with column c the counter of letter
+code c (A=0, C=1, T=2, G=3).  A key is the (k-1)-mer as 2-bit codes, first
+base most significant.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dbg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+
+OK, E_INVAL, E_K, E_BASE, E_NOMEM = 0, -1, -2, -3, -4
+
+# Letter code of the paper: counter index (c >> 1) & 3.
+LETTERS = "ACTG"
+
+_lib = None
+
+
+def compile_oracle(force: bool = False) -> str:
+    """Compile the C core with gcc into ``oracle/_liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared",
+                               "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            compile_oracle()
+        L = ctypes.CDLL(_LIB_PATH)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.POINTER(u64p), ctypes.POINTER(u32p),
+                                   ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_build.restype = ctypes.c_int
+        L.oracle_validate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_uint32]
+        L.oracle_validate.restype = ctypes.c_int
+        L.oracle_vertex_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint64, u32p]
+        L.oracle_vertex_counts.restype = ctypes.c_int
+        L.oracle_partition_many.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                            ctypes.c_void_p]
+        L.oracle_partition_many.restype = None
+        L.oracle_free.argtypes = [ctypes.c_void_p]
+        L.oracle_free.restype = None
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__("oracle error %d" % code)
+        self.code = code
+
+
+def _as_inputs(reads, offsets):
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return reads, offsets
+
+
+def validate(reads, offsets, k: int) -> int:
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    return int(lib().oracle_validate(reads.ctypes.data if reads.size else None,
+                                     offsets.ctypes.data if offsets.size else None,
+                                     n, int(k)))
+
+
+def build_graph(reads, offsets, k: int, part_count: int = 1, part_index: int = 0):
+    """Graph of the reads as ``(keys uint64[V] ascending, counts uint32[V, 4])``."""
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    pk = ctypes.POINTER(ctypes.c_uint64)()
+    pc = ctypes.POINTER(ctypes.c_uint32)()
+    nv = ctypes.c_uint64(0)
+    rc = lib().oracle_build(reads.ctypes.data if reads.size else None,
+                            offsets.ctypes.data if offsets.size else None,
+                            n, int(k), int(part_count), int(part_index),
+                            ctypes.byref(pk), ctypes.byref(pc), ctypes.byref(nv))
+    if rc != OK:
+        raise OracleError(rc)
+    V = int(nv.value)
+    try:
+        keys = np.ctypeslib.as_array(pk, shape=(V,)).copy() if V else np.zeros(0, np.uint64)
+        counts = (np.ctypeslib.as_array(pc, shape=(V * 4,)).copy().reshape(V, 4)
+                  if V else np.zeros((0, 4), np.uint32))
+    finally:
+        lib().oracle_free(ctypes.cast(pk, ctypes.c_void_p))
+        lib().oracle_free(ctypes.cast(pc, ctypes.c_void_p))
+    return keys, counts
+
+
+def vertex_counts(reads, offsets, k: int, key: int):
+    """(present, counts[4]) of one vertex by scanning every window."""
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    out = (ctypes.c_uint32 * 4)()
+    seen = lib().oracle_vertex_counts(reads.ctypes.data if reads.size else None,
+                                      offsets.ctypes.data if offsets.size else None,
+                                      n, int(k), int(key), out)
+    return bool(seen), np.array(list(out), dtype=np.uint32)
+
+
+def partition_of(keys, part_count: int) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    parts = np.empty(keys.shape[0], dtype=np.uint32)
+    if keys.size:
+        lib().oracle_partition_many(keys.ctypes.data, keys.shape[0], int(part_count),
+                                    parts.ctypes.data)
+    return parts
+
+
+def decode_key(key: int, k: int) -> str:
+    """(k-1)-mer string of a key (first base in the most significant bits)."""
+    n = k - 1
+    return "".join(LETTERS[(int(key) >> (2 * (n - 1 - i))) & 3] for i in range(n))
+
+
+def graph_to_dict(keys, counts, k: int) -> dict:
+    """{vertex string: {letter: count}} with zero counters omitted."""
+    out = {}
+    for key, c in zip(keys.tolist(), counts.tolist()):
+        out[decode_key(key, k)] = {LETTERS[i]: int(c[i]) for i in range(4) if c[i]}
+    return out
