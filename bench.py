@@ -1,0 +1,197 @@
+"""Benchmark of the A-Bruijn graph build on one MI355X.
+
+One step is one pass of the whole plain-build path over the bacterial-scale
+workload (5 Mbp genome with 50 copies of a 1 kbp repeat, 150 bp reads at 30x =
+1,000,000 reads, 1 % substitutions, k = 31, table load factor 0.5), with the
+ASCII reads and offsets already resident in HBM:
+
+    table reset -> pack -> window scan -> build (find-or-claim + count)
+    -> status readback -> extraction of all vertices into device buffers
+
+and the metric is k-mer inserts per second, inserts = sum over reads of
+max(0, L - k + 1) = 120,000,000 per step.
+
+Besides the driver's JSON fields the line carries:
+  * roofline       -- the build kernel (the dominant one) against HBM peak,
+                      with the algorithmic bytes per launch;
+  * atomic_roofline-- the same kernel against the measured rate of random
+                      64-bit compare-and-swap (and of the other random
+                      access kinds) at the table's footprint and op count;
+  * cpu_baseline   -- the CPU oracle on a bounded sample of the same reads.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int,
+                      vertices_new: int) -> int:
+    """Bytes the build kernel must move per launch, by its algorithm:
+    one 8-byte key read per window looked up, one 4-byte counter read and
+    written per k-mer, one 8-byte key written per vertex claimed, the packed
+    reads (2 bits per base) and, per read, its offset and window prefix."""
+    return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
+
+
+def cpu_baseline(rs, sample_reads: int) -> dict:
+    import oracle
+
+    n = min(sample_reads, rs.n_reads)
+    end = int(rs.offsets[n])
+    reads = rs.reads[:end]
+    offs = rs.offsets[:n + 1]
+    t0 = time.perf_counter()
+    keys, counts = oracle.build_graph(reads, offs, rs.k)
+    dt = time.perf_counter() - t0
+    ins = int(counts.sum())
+    return {"value": ins / dt / 1e9, "unit": "G k-mer inserts/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d reads (%d k-mer inserts, %d vertices), single-threaded C "
+                      "oracle, %.1f s" % (n, rs.n_reads, ins, keys.shape[0], dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--load-factor", type=float, default=0.5)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--wpt", type=int, default=0)
+    ap.add_argument("--merge", action="store_true")
+    ap.add_argument("--entry32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--cpu-sample-reads", type=int, default=250_000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import readsim
+    import paper_2401_02756_amd as dbg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    dbg.lib()
+
+    t0 = time.perf_counter()
+    rs = readsim.make_config(args.config)
+    log("generated config %d: %d reads, %d bases in %.1f s" % (args.config, rs.n_reads,
+                                                              rs.total_bases, time.perf_counter() - t0))
+    d_reads = torch.from_numpy(rs.reads).to(dev)
+    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
+    inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
+    windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
+
+    flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
+    g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
+                  device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
+    st0 = g.stats()
+    cap_out = int(st0["capacity"])
+    d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
+    d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
+
+    def step():
+        g.reset()
+        g.build_device(d_reads, d_off, rs.k)
+        g.sync()
+        return g.extract_device(d_keys, d_counts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    build_ms = []
+    total_ms = []
+    V = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        V = step()
+        s = g.stats()
+        build_ms.append(s["last_build_ms"])
+        total_ms.append(s["last_total_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = g.stats()
+    assert st["inserts"] == inserts, (st["inserts"], inserts)
+    ms_step = dt * 1000.0 / args.steps
+    value = inserts / (dt / args.steps) / 1e9
+    kern_ms = float(np.mean(build_ms))
+    log("step %.3f ms, build kernel %.3f ms (pass %.3f ms), V=%d, cap=%d" %
+        (ms_step, kern_ms, float(np.mean(total_ms)), V, cap_out))
+
+    bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
+    achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_build (persistent find-or-claim + count)",
+            "kernel_ms": round(kern_ms, 4), "algorithmic_bytes": bytes_alg}
+
+    line = {
+        "metric": "k-mer inserts/sec (G/s)",
+        "value": round(value, 4),
+        "unit": "G k-mer inserts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "plain build, bacterial scale: " + rs.meta["name"],
+                   "reads": rs.n_reads, "read_len": int(rs.meta["read_len"]), "k": rs.k,
+                   "inserts_per_step": inserts, "vertices": V, "capacity": cap_out,
+                   "load_factor": args.load_factor, "entry_bytes": st["entry_bytes"],
+                   "block": st["block_size"], "windows_per_thread": st["windows_per_thread"],
+                   "grid": st["grid_size"], "merge": bool(args.merge)},
+        "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
+        "roofline": roof,
+    }
+
+    if not args.no_roofline:
+        foot = int(st["table_bytes"])
+        ar = {"footprint_bytes": foot, "ops": inserts}
+        for name, kind in (("cas64", dbg.ROOF_CAS64), ("add32", dbg.ROOF_ADD32),
+                           ("load64", dbg.ROOF_LOAD64), ("load_add", dbg.ROOF_LOAD_ADD)):
+            best = min(dbg.atomic_roofline(kind, foot, inserts, b, 5) for b in (256, 1024))
+            ar[name + "_gops"] = round(inserts / (best * 1e-3) / 1e9, 4)
+        ar["frac_of_cas64"] = round(line["build_kernel_ginserts_s"] / ar["cas64_gops"], 4)
+        ar["step_frac_of_cas64"] = round(value / ar["cas64_gops"], 4)
+        line["atomic_roofline"] = ar
+        log("atomic roofline %s" % json.dumps(ar))
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_reads)
+        log("cpu baseline %s" % json.dumps(line["cpu_baseline"]))
+
+    g.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

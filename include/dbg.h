@@ -1,0 +1,214 @@
+/*
+ * dbg.h -- C ABI of the MI355X A-Bruijn graph builder (libdbg.so).
+ *
+ * The graph is the one defined in the paper's Background section: every
+ * length-k substring s0..s(k-1) of every read is an edge from the (k-1)-mer
+ * vertex s0..s(k-2) to the (k-1)-mer vertex s1..s(k-1); a vertex has at most
+ * four out-edges, one per letter, and each edge carries the number of times
+ * its k-mer occurs in the reads.  The build follows the paper's makeGraph
+ * (Methods, "Lock-free graph creation algorithm", Algorithms 2-4): for each
+ * k-mer the source vertex is found or added and its counter for the last
+ * letter is raised by one; the target vertex is only made to exist.  Here
+ * vertices live in an open-addressing table in HBM, a slot is claimed with a
+ * 64-bit compare-and-swap (the paper's CAS, Algorithm 1) and counters are
+ * raised with 32-bit atomic adds; no lock is taken.
+ *
+ * Conventions used by every call:
+ *   - Reads: read i is reads[offsets[i] .. offsets[i+1]) (bytes), so offsets
+ *     has n_reads + 1 non-decreasing entries.  Bytes must be in ACGTacgt.  A
+ *     read shorter than k has no k-mer and adds nothing.
+ *   - Letter code (Methods, "Graph data structure"): (c >> 1) & 3, so A=0,
+ *     C=1, T=2, G=3.
+ *   - Vertex key: the (k-1)-mer as 2-bit letter codes, first base most
+ *     significant, right-aligned in a uint64.  2 <= k <= 32.
+ *   - Counts: four uint32 per vertex in letter-code order (A, C, T, G).
+ *     Sink vertices (no out-edge) are vertices with four zero counters.
+ *   - Return values: DBG_OK (0) or a negative DBG_E_* code.
+ *   - Threads: one handle must not be used from two threads at once;
+ *     different handles are independent.
+ *   - Streams: a NULL stream means the handle's own stream.  A stream is a
+ *     hipStream_t passed as void*.
+ */
+#ifndef DBG_H
+#define DBG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define DBG_OK 0
+#define DBG_E_INVAL (-1)  /* NULL pointer, bad offsets, bad configuration */
+#define DBG_E_K (-2)      /* k outside [2, 32], or differs from the handle's k */
+#define DBG_E_BASE (-3)   /* a read byte outside ACGTacgt */
+#define DBG_E_NOMEM (-4)  /* device allocation refused */
+#define DBG_E_FULL (-5)   /* table capacity exhausted; the handle is poisoned */
+#define DBG_E_SPACE (-6)  /* output buffer smaller than the vertex count */
+#define DBG_E_DEVICE (-7) /* HIP runtime error */
+#define DBG_E_RANGE (-8)  /* cumulative k-mers on the handle would exceed 2^32-1 */
+#define DBG_E_STATE (-9)  /* handle poisoned by an earlier DBG_E_FULL */
+
+/* ---- configuration flags ------------------------------------------- */
+#define DBG_F_MERGE 0x1u   /* merge equal vertices within a wavefront first */
+#define DBG_F_TIMING 0x2u  /* time each build kernel with HIP events */
+#define DBG_F_ENTRY32 0x4u /* 32-byte table entries (default 24 bytes) */
+
+typedef struct dbg_graph dbg_graph;
+
+/*
+ * Table sizing follows the paper's constructor, where the user gives the hash
+ * table size (Methods, "Code organization").  capacity, when non-zero, is the
+ * exact number of slots; otherwise capacity = ceil(expected_vertices /
+ * load_factor).  With both zero the table is sized at the first build as
+ * ceil(windows / load_factor): the number of windows bounds the number of
+ * distinct vertices, so that build cannot run out of slots.
+ */
+typedef struct {
+    uint64_t expected_vertices;  /* estimate of distinct (k-1)-mers; 0 = from input */
+    uint64_t capacity;           /* exact slot count; 0 = derive as above */
+    double load_factor;          /* in (0, 1); 0 = 0.5 */
+    int32_t device;              /* HIP device ordinal; -1 = current device */
+    uint32_t flags;              /* DBG_F_* */
+    uint32_t block_size;         /* build kernel threads per block; 0 = 256 */
+    uint32_t windows_per_thread; /* windows per thread per tile; 0 = 4 */
+    void *stream;                /* hipStream_t for all work; NULL = own stream */
+} dbg_config;
+
+typedef struct {
+    uint64_t capacity;        /* table slots */
+    uint64_t table_bytes;     /* device bytes held by the table */
+    uint64_t vertices;        /* occupied slots (distinct (k-1)-mers) */
+    uint64_t inserts;         /* k-mers counted so far: sum of max(0, L-k+1) */
+    uint64_t windows;         /* windows seen so far: vertices looked up */
+    uint64_t builds;          /* completed build calls */
+    uint32_t k;               /* 0 until the first build */
+    int32_t status;           /* DBG_OK, or the code that poisoned the handle */
+    double last_build_ms;     /* build kernel time of the last build (DBG_F_TIMING) */
+    double last_total_ms;     /* whole device pass of the last build (DBG_F_TIMING) */
+    uint32_t block_size;      /* launch shape in use */
+    uint32_t windows_per_thread;
+    uint32_t grid_size;
+    uint32_t entry_bytes;     /* 24 or 32 */
+} dbg_stats;
+
+/* Fill *cfg with the defaults (all zero, device -1). */
+void dbg_config_init(dbg_config *cfg);
+
+/* Create a graph handle.  The table is allocated here when its size is known
+ * (capacity or expected_vertices given), else at the first build.  On success
+ * *out owns all device memory of the graph until dbg_destroy.
+ * Errors: DBG_E_INVAL (NULL, load_factor outside (0,1)), DBG_E_NOMEM,
+ * DBG_E_DEVICE. */
+int dbg_create(const dbg_config *cfg, dbg_graph **out);
+
+/* Add the k-mers of host-resident reads (makeGraph over all reads).  The
+ * input is copied; the caller may free it on return.  Synchronous: returns
+ * after the device work and the status readback.  Builds on one handle
+ * accumulate (counts add), and all must use the same k.
+ * Errors: DBG_E_INVAL (NULL pointers, decreasing offsets), DBG_E_K,
+ * DBG_E_BASE, DBG_E_RANGE -- in all of these nothing was modified;
+ * DBG_E_FULL (counts are partial, handle poisoned), DBG_E_NOMEM,
+ * DBG_E_DEVICE. */
+int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t n_reads,
+              uint32_t k);
+
+/* Same, from device-resident input: d_reads holds reads_len bytes and
+ * d_offsets n_reads + 1 entries, both device pointers that stay valid until
+ * the work on `stream` has finished.  Offsets are taken relative to the first
+ * one: read i is d_reads[d_offsets[i] - d_offsets[0] .. d_offsets[i+1] -
+ * d_offsets[0]), and d_offsets[n_reads] - d_offsets[0] must equal reads_len
+ * (so a slice of a larger concatenation can be passed as is).
+ * Stream-ordered: the call enqueues the work and returns; device-side errors
+ * (DBG_E_BASE, DBG_E_INVAL, DBG_E_RANGE, DBG_E_FULL) are reported by the next
+ * dbg_sync.  As with dbg_build, a rejected input modifies nothing. */
+int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
+                     const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, void *stream);
+
+/* Wait for the handle's outstanding work and return its status: DBG_OK or
+ * the first error the device reported since the previous dbg_sync. */
+int dbg_sync(dbg_graph *g);
+
+/* Copy the graph out as records in unspecified order: keys[i] and
+ * counts[4*i .. 4*i+3] for i < *n_vertices.  With keys == NULL only
+ * *n_vertices is set.  Synchronous.  Errors: DBG_E_SPACE when cap is smaller
+ * than the vertex count (*n_vertices is still set, nothing is written),
+ * DBG_E_INVAL, DBG_E_DEVICE.  Allowed on a poisoned handle (partial counts). */
+int dbg_extract(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap,
+                uint64_t *n_vertices);
+
+/* Same into device buffers d_keys (cap entries) and d_counts (4 * cap),
+ * stream-ordered up to the vertex count, which the call reads back
+ * (synchronising on the stream). */
+int dbg_extract_device(dbg_graph *g, uint64_t *d_keys, uint32_t *d_counts, uint64_t cap,
+                       uint64_t *n_vertices, void *stream);
+
+/* Empty the table (all vertices and counts), keeping its memory; clears a
+ * poisoned state and the handle's k.  Stream-ordered. */
+int dbg_reset(dbg_graph *g);
+
+/* Counters and launch shape of the handle (synchronises first). */
+int dbg_get_stats(dbg_graph *g, dbg_stats *out);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void dbg_destroy(dbg_graph *g);
+
+/* Static description of a DBG_* code. */
+const char *dbg_strerror(int code);
+
+/* ---- batched build ---------------------------------------------------
+ * Many independent read sets built in one persistent launch over per-graph
+ * table segments.  Graph i takes the reads of inputs[i]; its k must match the
+ * graph's k if set.  Each graph's result is exactly that of dbg_build on the
+ * same reads.  Host-resident inputs are concatenated and copied once.
+ * Synchronous; statuses[i] receives graph i's status (DBG_OK, DBG_E_BASE,
+ * DBG_E_INVAL, DBG_E_K, DBG_E_RANGE, DBG_E_FULL).  The call's own return is
+ * DBG_OK when every graph succeeded, else the first failing graph's code.
+ * All graphs must be on the same device. */
+typedef struct {
+    const char *reads;
+    const uint64_t *offsets;
+    uint64_t n_reads;
+    uint32_t k;
+} dbg_input;
+
+int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t m,
+                    int32_t *statuses, void *stream);
+
+/* Same from one device-resident concatenation: graph i takes reads
+ * [read_begin[i], read_begin[i+1]) of d_reads/d_offsets (read j is
+ * d_reads[d_offsets[j] - d_offsets[0] .. d_offsets[j+1] - d_offsets[0]),
+ * d_offsets has read_begin[m] + 1 entries, d_offsets[read_begin[m]] -
+ * d_offsets[0] == reads_len).  read_begin (m + 1 entries, read_begin[0] == 0)
+ * and ks (m entries) are host arrays.  A graph that fails a host check keeps
+ * its reads in the launch but they are skipped.  Synchronous. */
+int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
+                           const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
+                           const uint64_t *d_offsets, int32_t *statuses, void *stream);
+
+/* ---- measurement -----------------------------------------------------
+ * Random-access roofline of the device: n_ops operations at indices drawn by
+ * a 64-bit mixer over a footprint of footprint_bytes (no index array is
+ * read).  kind: 0 = 64-bit load, 1 = 32-bit atomic add (no return),
+ * 2 = 64-bit atomic compare-and-swap (returning), 3 = 64-bit load then a
+ * 32-bit atomic add into the same 24-byte entry.  Returns the median kernel
+ * time over `repeats` timed launches (after one warm-up) in *ms.  Allocates
+ * and frees its own footprint. */
+int dbg_atomic_roofline(int32_t device, uint32_t kind, uint64_t footprint_bytes, uint64_t n_ops,
+                        uint32_t block_size, uint32_t repeats, double *ms);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBG_H */

@@ -1,0 +1,290 @@
+"""Python binding of libdbg, the MI355X A-Bruijn graph builder.
+
+Argument marshalling only: every step of the build runs in the HIP kernels of
+``libdbg.so`` (``csrc/``), called through its C ABI (``include/dbg.h``).
+There is no CPU fallback: if the library is not built, every entry point
+raises.  PyTorch is used only to hand device buffers and streams to the
+library (``build_device``/``extract_device``/``build_batch_device``).
+
+Conventions (the same as the C ABI): read i is
+``reads[offsets[i]:offsets[i+1]]``; keys are (k-1)-mers as 2-bit letter codes
+(A=0, C=1, T=2, G=3), first base most significant; ``counts[:, c]`` is the
+counter of letter code c.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
+
+OK = 0
+E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE = range(-1, -10, -1)
+F_MERGE, F_TIMING, F_ENTRY32 = 0x1, 0x2, 0x4
+
+# every symbol include/dbg.h declares
+EXPORTS = (
+    "dbg_config_init", "dbg_create", "dbg_build", "dbg_build_device", "dbg_sync",
+    "dbg_extract", "dbg_extract_device", "dbg_reset", "dbg_get_stats", "dbg_destroy",
+    "dbg_strerror", "dbg_build_batch", "dbg_build_batch_device", "dbg_atomic_roofline",
+)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("expected_vertices", ctypes.c_uint64),
+        ("capacity", ctypes.c_uint64),
+        ("load_factor", ctypes.c_double),
+        ("device", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("block_size", ctypes.c_uint32),
+        ("windows_per_thread", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("capacity", ctypes.c_uint64),
+        ("table_bytes", ctypes.c_uint64),
+        ("vertices", ctypes.c_uint64),
+        ("inserts", ctypes.c_uint64),
+        ("windows", ctypes.c_uint64),
+        ("builds", ctypes.c_uint64),
+        ("k", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+        ("last_build_ms", ctypes.c_double),
+        ("last_total_ms", ctypes.c_double),
+        ("block_size", ctypes.c_uint32),
+        ("windows_per_thread", ctypes.c_uint32),
+        ("grid_size", ctypes.c_uint32),
+        ("entry_bytes", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Input(ctypes.Structure):
+    _fields_ = [
+        ("reads", ctypes.c_void_p),
+        ("offsets", ctypes.c_void_p),
+        ("n_reads", ctypes.c_uint64),
+        ("k", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libdbg.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdbg.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+        sig = {
+            "dbg_config_init": (None, [ctypes.POINTER(Config)]),
+            "dbg_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(vp)]),
+            "dbg_build": (ctypes.c_int, [vp, vp, vp, u64, u32]),
+            "dbg_build_device": (ctypes.c_int, [vp, vp, u64, vp, u64, u32, vp]),
+            "dbg_sync": (ctypes.c_int, [vp]),
+            "dbg_extract": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
+            "dbg_extract_device": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
+            "dbg_reset": (ctypes.c_int, [vp]),
+            "dbg_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
+            "dbg_destroy": (None, [vp]),
+            "dbg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "dbg_build_batch": (ctypes.c_int, [vp, vp, u32, vp, vp]),
+            "dbg_build_batch_device": (ctypes.c_int, [vp, u32, vp, vp, vp, u64, vp, vp, vp]),
+            "dbg_atomic_roofline": (ctypes.c_int, [i32, u32, u64, u64, u32, u32,
+                                                   ctypes.POINTER(ctypes.c_double)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DbgError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = lib().dbg_strerror(code).decode()
+        super().__init__("%s%s (%d)" % (where + ": " if where else "", msg, code))
+        self.code = code
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise DbgError(rc, where)
+
+
+def _host_inputs(reads, offsets):
+    if isinstance(reads, (bytes, bytearray)):
+        reads = np.frombuffer(bytes(reads), dtype=np.uint8)
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return reads, offsets
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (or an int)."""
+    return int(t) if isinstance(t, int) else int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Graph:
+    """One graph handle (``dbg_create`` .. ``dbg_destroy``)."""
+
+    def __init__(self, expected_vertices: int = 0, capacity: int = 0, load_factor: float = 0.0,
+                 device: int = -1, flags: int = 0, block_size: int = 0,
+                 windows_per_thread: int = 0, stream=None):
+        cfg = Config()
+        lib().dbg_config_init(ctypes.byref(cfg))
+        cfg.expected_vertices = int(expected_vertices)
+        cfg.capacity = int(capacity)
+        cfg.load_factor = float(load_factor)
+        cfg.device = int(device)
+        cfg.flags = int(flags)
+        cfg.block_size = int(block_size)
+        cfg.windows_per_thread = int(windows_per_thread)
+        cfg.stream = _stream(stream)
+        h = ctypes.c_void_p()
+        _check(lib().dbg_create(ctypes.byref(cfg), ctypes.byref(h)), "dbg_create")
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().dbg_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def build(self, reads, offsets, k: int) -> None:
+        reads, offsets = _host_inputs(reads, offsets)
+        n = max(0, offsets.shape[0] - 1)
+        rc = lib().dbg_build(self.handle, reads.ctypes.data if reads.size else None,
+                             offsets.ctypes.data if offsets.size else None, n, int(k))
+        _check(rc, "dbg_build")
+
+    def build_device(self, d_reads, d_offsets, k: int, n_reads: int | None = None,
+                     reads_len: int | None = None, stream=None) -> None:
+        """Enqueue a build from device tensors (uint8 reads, int64/uint64 offsets)."""
+        n = int(d_offsets.numel() - 1) if n_reads is None else int(n_reads)
+        ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+        rc = lib().dbg_build_device(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
+                                    _stream(stream))
+        _check(rc, "dbg_build_device")
+
+    def sync(self) -> None:
+        _check(lib().dbg_sync(self.handle), "dbg_sync")
+
+    def vertex_count(self) -> int:
+        n = ctypes.c_uint64(0)
+        _check(lib().dbg_extract(self.handle, None, None, 0, ctypes.byref(n)), "dbg_extract")
+        return int(n.value)
+
+    def extract(self):
+        """(keys uint64[V], counts uint32[V, 4]) in unspecified order."""
+        V = self.vertex_count()
+        keys = np.empty(V, dtype=np.uint64)
+        counts = np.empty((V, 4), dtype=np.uint32)
+        n = ctypes.c_uint64(0)
+        if V:
+            rc = lib().dbg_extract(self.handle, keys.ctypes.data, counts.ctypes.data, V,
+                                   ctypes.byref(n))
+            _check(rc, "dbg_extract")
+        return keys, counts
+
+    def extract_sorted(self):
+        keys, counts = self.extract()
+        order = np.argsort(keys, kind="stable")
+        return keys[order], counts[order]
+
+    def extract_device(self, d_keys, d_counts, stream=None) -> int:
+        n = ctypes.c_uint64(0)
+        rc = lib().dbg_extract_device(self.handle, _ptr(d_keys), _ptr(d_counts),
+                                      int(d_keys.numel()), ctypes.byref(n), _stream(stream))
+        _check(rc, "dbg_extract_device")
+        return int(n.value)
+
+    def reset(self) -> None:
+        _check(lib().dbg_reset(self.handle), "dbg_reset")
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().dbg_get_stats(self.handle, ctypes.byref(s)), "dbg_get_stats")
+        return s.as_dict()
+
+
+def build_batch(graphs: list[Graph], inputs: list[tuple], stream=None) -> list[int]:
+    """``dbg_build_batch``: inputs[i] = (reads, offsets, k) for graphs[i].
+    Returns the per-graph status codes."""
+    m = len(graphs)
+    keep = []
+    arr = (Input * max(m, 1))()
+    for i, (reads, offsets, k) in enumerate(inputs):
+        reads, offsets = _host_inputs(reads, offsets)
+        keep.append((reads, offsets))
+        arr[i].reads = reads.ctypes.data if reads.size else None
+        arr[i].offsets = offsets.ctypes.data if offsets.size else None
+        arr[i].n_reads = max(0, offsets.shape[0] - 1)
+        arr[i].k = int(k)
+    hs = (ctypes.c_void_p * max(m, 1))(*[g.handle for g in graphs])
+    st = (ctypes.c_int32 * max(m, 1))()
+    lib().dbg_build_batch(hs, arr, m, st, _stream(stream))
+    return [int(st[i]) for i in range(m)]
+
+
+def build_batch_device(graphs: list[Graph], read_begin, ks, d_reads, d_offsets,
+                       reads_len: int | None = None, stream=None) -> list[int]:
+    """``dbg_build_batch_device`` over one device-resident concatenation."""
+    m = len(graphs)
+    rb = np.ascontiguousarray(read_begin, dtype=np.uint64)
+    kk = np.ascontiguousarray(ks, dtype=np.uint32)
+    assert rb.shape[0] == m + 1 and kk.shape[0] == m
+    hs = (ctypes.c_void_p * max(m, 1))(*[g.handle for g in graphs])
+    st = (ctypes.c_int32 * max(m, 1))()
+    ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+    lib().dbg_build_batch_device(hs, m, rb.ctypes.data, kk.ctypes.data, _ptr(d_reads), ln,
+                                 _ptr(d_offsets), st, _stream(stream))
+    return [int(st[i]) for i in range(m)]
+
+
+ROOF_LOAD64, ROOF_ADD32, ROOF_CAS64, ROOF_LOAD_ADD = 0, 1, 2, 3
+
+
+def atomic_roofline(kind: int, footprint_bytes: int, n_ops: int, block_size: int = 256,
+                    repeats: int = 5, device: int = -1) -> float:
+    """Median kernel ms of n_ops random operations of `kind` over the footprint."""
+    ms = ctypes.c_double(0)
+    rc = lib().dbg_atomic_roofline(int(device), int(kind), int(footprint_bytes), int(n_ops),
+                                   int(block_size), int(repeats), ctypes.byref(ms))
+    _check(rc, "dbg_atomic_roofline")
+    return float(ms.value)

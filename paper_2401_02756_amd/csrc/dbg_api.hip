@@ -1,0 +1,826 @@
+// Host runtime and C ABI of libdbg: table sizing and allocation, input
+// staging, the stream-ordered build pass, status readback, extraction, the
+// batched build and the random-access roofline.
+//
+// The paper's constructor takes k, the thread count, the hash table size and
+// the genome size (Methods, "Code organization"); here a handle takes the
+// table size (capacity, or expected vertices and a load factor) and the launch
+// shape; k is fixed by the first build.
+#include "dbg.h"
+#include "dbg_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+using dbgk::CallState;
+using dbgk::Instance;
+using dbgk::InstStatus;
+
+namespace {
+
+constexpr uint64_t kCounterLimit = 0xffffffffull;
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t reserve(size_t want) {
+        if (want <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+        }
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Grow-only pinned host buffer.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t reserve(size_t want) {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Makes `device` current for the scope of a call and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int device) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (device >= 0 && device != prev) ok = hipSetDevice(device) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int err_code_of(uint32_t bits) {
+    if (bits & dbgk::kErrInval) return DBG_E_INVAL;
+    if (bits & dbgk::kErrBase) return DBG_E_BASE;
+    if (bits & dbgk::kErrRange) return DBG_E_RANGE;
+    if (bits & dbgk::kErrFull) return DBG_E_FULL;
+    return DBG_OK;
+}
+
+bool validation_error(uint32_t bits) {
+    return bits & (dbgk::kErrInval | dbgk::kErrBase | dbgk::kErrRange);
+}
+
+int hip_code(hipError_t e) {
+    if (e == hipSuccess) return DBG_OK;
+    return e == hipErrorOutOfMemory ? DBG_E_NOMEM : DBG_E_DEVICE;
+}
+
+// Windows and k-mers of host-resident offsets; false if offsets decrease.
+bool host_counts(const uint64_t *off, uint64_t n, uint32_t k, uint64_t *windows, uint64_t *kmers) {
+    uint64_t w = 0, e = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (off[i + 1] < off[i]) return false;
+        const uint64_t L = off[i + 1] - off[i];
+        if (L >= k) {
+            w += L - k + 2;
+            e += L - k + 1;
+        }
+    }
+    *windows = w;
+    *kmers = e;
+    return true;
+}
+
+uint64_t capacity_for(uint64_t vertices, double lf) {
+    const double c = std::ceil((double)vertices / lf);
+    return std::max<uint64_t>(64, (uint64_t)c);
+}
+
+// Buffers and launch sequence of one build pass over m instances.
+struct Pass {
+    DevBuf packed, ws, partials, tiles, dinst, dstatus;
+    HostBuf hinst, hstatus;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+    uint32_t m = 0;
+    hipStream_t stream = nullptr;
+    bool pending = false;
+    bool timing = false;
+
+    hipError_t init() {
+        hipError_t e = hipEventCreate(&ev_a);
+        if (e == hipSuccess) e = hipEventCreate(&ev_b);
+        if (e == hipSuccess) e = hipEventCreate(&ev_c);
+        return e;
+    }
+    void release() {
+        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dinst, &dstatus};
+        for (DevBuf *b : d) b->release();
+        hinst.release();
+        hstatus.release();
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+        if (ev_c) (void)hipEventDestroy(ev_c);
+        ev_a = ev_b = ev_c = nullptr;
+    }
+    hipError_t reserve_instances(uint32_t mm) {
+        hipError_t e = hinst.reserve(sizeof(Instance) * mm);
+        if (e == hipSuccess) e = dinst.reserve(sizeof(Instance) * mm);
+        if (e == hipSuccess) e = hstatus.reserve(sizeof(InstStatus) * mm + sizeof(CallState));
+        if (e == hipSuccess) e = dstatus.reserve(sizeof(InstStatus) * mm + sizeof(CallState));
+        return e;
+    }
+    Instance *host_instances() const { return hinst.as<Instance>(); }
+    const InstStatus *host_status() const { return hstatus.as<InstStatus>(); }
+
+    // Enqueue the pass; hinst[0..mm) must be filled (tables, read ranges,
+    // prior k-mers, k, entry words).  Reads are device-resident and gap-free:
+    // read i is d_reads[off[i] - off[0] .. off[i+1] - off[0]).
+    hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
+                       uint64_t n, dbgk::BuildShape shape, bool check_ends, bool time_it,
+                       hipStream_t s) {
+        const uint64_t T = (uint64_t)shape.block * shape.wpt;
+        const uint64_t tile_cap = dbgk::max_tiles(len, T);
+        hipError_t e;
+        if ((e = packed.reserve(dbgk::packed_words(len) * 8)) != hipSuccess ||
+            (e = ws.reserve((n + 1) * 8)) != hipSuccess ||
+            (e = partials.reserve(dbgk::scan_blocks(n) * 8 + 8)) != hipSuccess ||
+            (e = tiles.reserve(tile_cap * 8)) != hipSuccess)
+            return e;
+        InstStatus *dst = dstatus.as<InstStatus>();
+        CallState *cs = reinterpret_cast<CallState *>(dst + mm);
+        Instance *di = dinst.as<Instance>();
+        if (time_it) (void)hipEventRecord(ev_a, s);
+        e = hipMemcpyAsync(di, hinst.p, sizeof(Instance) * mm, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = dbgk::launch_prepare(di, mm, dst, cs, d_off, n, s);
+        if (e == hipSuccess) e = dbgk::launch_pack(d_reads, len, packed.as<uint64_t>(), di, mm, dst, s);
+        if (e == hipSuccess)
+            e = dbgk::launch_scan(d_off, n, len, check_ends, di, mm, dst, ws.as<uint64_t>(),
+                                  partials.as<uint64_t>(), tiles.as<uint64_t>(), tile_cap,
+                                  (uint32_t)T, cs, s);
+        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
+        if (e == hipSuccess)
+            e = dbgk::launch_build(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(),
+                                   tiles.as<uint64_t>(), n, dst, cs, shape, s);
+        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_c, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * mm + sizeof(CallState),
+                               hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        m = mm;
+        stream = s;
+        pending = true;
+        timing = time_it;
+        return hipSuccess;
+    }
+
+    // Wait for the enqueued pass; times in ms when it was timed.
+    hipError_t wait(double *build_ms, double *total_ms) {
+        if (!pending) return hipSuccess;
+        pending = false;
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e == hipSuccess && timing) {
+            float a = 0, b = 0;
+            if (hipEventElapsedTime(&a, ev_b, ev_c) == hipSuccess && build_ms) *build_ms = a;
+            if (hipEventElapsedTime(&b, ev_a, ev_c) == hipSuccess && total_ms) *total_ms = b;
+        }
+        return e;
+    }
+};
+
+}  // namespace
+
+struct dbg_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t flags = 0;
+    double lf = 0.5;
+    uint64_t expected = 0, cap_req = 0;
+    dbgk::BuildShape shape{256, 4, 0, 0};
+
+    uint64_t cap = 0;
+    uint32_t ew = 3;
+    DevBuf table;
+
+    uint32_t k = 0;
+    int32_t poisoned = DBG_OK;
+    int32_t unreported = DBG_OK;
+
+    Pass pass;
+    uint32_t pending_k = 0;
+    DevBuf reads, offsets;   // staging of host input
+    DevBuf xkeys, xcnt, xn;  // extraction staging
+
+    uint64_t vertices = 0, inserts = 0, windows = 0, builds = 0;
+    double last_build_ms = 0, last_total_ms = 0;
+
+    hipStream_t pick(void *s) const { return s ? static_cast<hipStream_t>(s) : stream; }
+    uint64_t table_words() const { return cap * ew; }
+};
+
+namespace {
+
+hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
+    g->cap = cap;
+    hipError_t e = g->table.reserve(g->table_words() * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        g->cap = 0;
+        return e;
+    }
+    e = dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e;
+}
+
+int ensure_table(dbg_graph *g, uint64_t windows_bound) {
+    if (g->cap) return DBG_OK;
+    uint64_t cap = g->cap_req;
+    if (!cap) cap = capacity_for(g->expected ? g->expected : std::max<uint64_t>(windows_bound, 1), g->lf);
+    return hip_code(allocate_table(g, cap));
+}
+
+void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint64_t read_end, uint32_t k) {
+    in.table = g->table.as<uint64_t>();
+    in.cap = g->cap;
+    in.read_begin = read_begin;
+    in.read_end = read_end;
+    in.byte_begin = 0;
+    in.byte_end = 0;
+    in.prior_inserts = g->inserts;
+    in.k = k;
+    in.entry_words = g->ew;
+    in.skip = 0;
+    in.pad = 0;
+}
+
+// Fold one instance's status of a finished pass into its graph.
+int fold_status(dbg_graph *g, const InstStatus &st, uint32_t k) {
+    if (validation_error(st.err)) return err_code_of(st.err);  // nothing was modified
+    g->k = k;
+    g->vertices += st.claimed;
+    g->inserts += st.inserts;
+    g->windows += st.windows;
+    g->builds += 1;
+    if (st.err & dbgk::kErrFull) {
+        g->poisoned = DBG_E_FULL;
+        return DBG_E_FULL;
+    }
+    return DBG_OK;
+}
+
+// Waits for the handle's own enqueued build and folds its status.
+int harvest(dbg_graph *g) {
+    if (!g->pass.pending) return DBG_OK;
+    if (g->pass.wait(&g->last_build_ms, &g->last_total_ms) != hipSuccess) return DBG_E_DEVICE;
+    return fold_status(g, g->pass.host_status()[0], g->pending_k);
+}
+
+int check_common(dbg_graph *g, uint32_t k) {
+    if (!g) return DBG_E_INVAL;
+    if (g->poisoned) return DBG_E_STATE;
+    if (k < 2 || k > 32) return DBG_E_K;
+    if (g->k && g->k != k) return DBG_E_K;
+    return DBG_OK;
+}
+
+int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
+                   uint64_t n, uint32_t k, hipStream_t s) {
+    hipError_t e = g->pass.reserve_instances(1);
+    if (e != hipSuccess) return hip_code(e);
+    fill_instance(g->pass.host_instances()[0], g, 0, n, k);
+    e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, true, (g->flags & DBG_F_TIMING) != 0, s);
+    if (e != hipSuccess) return hip_code(e);
+    g->pending_k = k;
+    return DBG_OK;
+}
+
+// ---------------------------------------------------------------- batch context
+
+// Per-device scratch of batched builds (one batched call at a time per
+// device; calls are serialised by the mutex).
+struct BatchCtx {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    Pass pass;
+    DevBuf reads, offsets;
+    std::vector<uint64_t> hoff;
+    bool ready = false;
+};
+
+std::mutex g_ctx_mu;
+std::map<int, std::unique_ptr<BatchCtx>> g_ctx;
+
+BatchCtx *batch_ctx(int device) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    auto &p = g_ctx[device];
+    if (!p) p.reset(new BatchCtx());
+    return p.get();
+}
+
+}  // namespace
+
+// Shared by the host- and device-input batched calls: graphs[i] takes reads
+// [read_begin[i], read_begin[i+1]) of the device-resident concatenation.  A
+// graph that fails a host-side check stays in the launch as a skipped
+// instance, so its reads are attributed to it and never touched.
+static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
+                              const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
+                              const uint64_t *d_offsets, int32_t *statuses, hipStream_t stream,
+                              BatchCtx *ctx, bool check_ends) {
+    const int device = graphs[0]->device;
+    std::vector<uint8_t> run(m, 0);
+    uint32_t n_run = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        dbg_graph *g = graphs[i];
+        int rc = check_common(g, ks[i]);
+        if (rc == DBG_OK && g->device != device) rc = DBG_E_INVAL;
+        if (rc == DBG_OK && read_begin[i + 1] < read_begin[i]) rc = DBG_E_INVAL;
+        for (uint32_t j = 0; rc == DBG_OK && j < i; ++j)
+            if (graphs[j] == g) rc = DBG_E_INVAL;  // one graph per instance
+        if (rc == DBG_OK && g->pass.pending) rc = harvest(g);
+        if (rc == DBG_OK && read_begin[i + 1] > read_begin[i]) {
+            // a graph never sized takes the whole input's byte count as bound
+            rc = ensure_table(g, std::max<uint64_t>(reads_len, 1));
+            if (rc == DBG_OK) {
+                run[i] = 1;
+                ++n_run;
+            }
+        }
+        statuses[i] = rc;
+    }
+    if (!n_run) return;
+
+    Pass &pass = ctx->pass;
+    hipError_t e = pass.reserve_instances(m);
+    if (e != hipSuccess) {
+        for (uint32_t i = 0; i < m; ++i)
+            if (run[i]) statuses[i] = hip_code(e);
+        return;
+    }
+    Instance *hi = pass.host_instances();
+    const dbg_graph *g0 = nullptr;
+    for (uint32_t i = 0; i < m; ++i) {
+        fill_instance(hi[i], graphs[i], read_begin[i], read_begin[i + 1], run[i] ? ks[i] : 32u);
+        hi[i].skip = run[i] ? 0u : 1u;
+        if (run[i] && !g0) g0 = graphs[i];
+    }
+    const bool timing = (g0->flags & DBG_F_TIMING) != 0;
+    const uint64_t n = read_begin[m];
+    e = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, check_ends, timing, stream);
+    double bms = 0, tms = 0;
+    if (e == hipSuccess) e = pass.wait(&bms, &tms);
+    const InstStatus *st = pass.host_status();
+    for (uint32_t i = 0; i < m; ++i) {
+        if (!run[i]) continue;
+        if (e != hipSuccess) {
+            statuses[i] = DBG_E_DEVICE;
+            continue;
+        }
+        statuses[i] = fold_status(graphs[i], st[i], ks[i]);
+        if (timing) {
+            graphs[i]->last_build_ms = bms;
+            graphs[i]->last_total_ms = tms;
+        }
+    }
+}
+
+static int first_error(const int32_t *statuses, uint32_t m) {
+    for (uint32_t i = 0; i < m; ++i)
+        if (statuses[i] != DBG_OK) return statuses[i];
+    return DBG_OK;
+}
+
+extern "C" {
+
+void dbg_config_init(dbg_config *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->device = -1;
+}
+
+int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
+    if (!out) return DBG_E_INVAL;
+    *out = nullptr;
+    dbg_config cfg;
+    dbg_config_init(&cfg);
+    if (cfg_in) cfg = *cfg_in;
+    const double lf = cfg.load_factor == 0 ? 0.5 : cfg.load_factor;
+    if (!(lf > 0 && lf < 1)) return DBG_E_INVAL;
+    const uint32_t block = cfg.block_size ? cfg.block_size : 256;
+    if (block % 64 || block > 1024) return DBG_E_INVAL;
+    const uint32_t wpt = cfg.windows_per_thread ? cfg.windows_per_thread : 4;
+    if (wpt > 64) return DBG_E_INVAL;
+
+    int device = cfg.device;
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
+    DeviceGuard guard(device);
+    if (!guard.ok) return DBG_E_DEVICE;
+
+    dbg_graph *g = new dbg_graph();
+    g->device = device;
+    g->flags = cfg.flags;
+    g->lf = lf;
+    g->expected = cfg.expected_vertices;
+    g->cap_req = cfg.capacity;
+    g->ew = (cfg.flags & DBG_F_ENTRY32) ? 4 : 3;
+    g->shape.block = block;
+    g->shape.wpt = wpt;
+    g->shape.merge = (cfg.flags & DBG_F_MERGE) ? 1 : 0;
+    g->shape.grid = dbgk::build_grid(device, block);
+
+    int rc = DBG_OK;
+    if (cfg.stream) {
+        g->stream = static_cast<hipStream_t>(cfg.stream);
+    } else if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) == hipSuccess) {
+        g->own_stream = true;
+    } else {
+        rc = DBG_E_DEVICE;
+    }
+    if (rc == DBG_OK && g->pass.init() != hipSuccess) rc = DBG_E_DEVICE;
+    if (rc == DBG_OK && (g->cap_req || g->expected)) rc = ensure_table(g, 0);
+    if (rc != DBG_OK) {
+        dbg_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return DBG_OK;
+}
+
+int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
+                     const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, void *stream) {
+    int rc = check_common(g, k);
+    if (rc != DBG_OK) return rc;
+    if (n_reads == 0) return DBG_OK;
+    if (!d_offsets || (!d_reads && reads_len)) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        rc = harvest(g);
+        if (rc != DBG_OK) return rc;
+    }
+    rc = ensure_table(g, reads_len);
+    if (rc != DBG_OK) return rc;
+    return enqueue_single(g, d_reads, reads_len, d_offsets, n_reads, k, g->pick(stream));
+}
+
+int dbg_sync(dbg_graph *g) {
+    if (!g) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    int rc = harvest(g);
+    if (rc == DBG_OK && g->unreported != DBG_OK) rc = g->unreported;
+    g->unreported = DBG_OK;
+    return rc;
+}
+
+int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t n_reads, uint32_t k) {
+    int rc = check_common(g, k);
+    if (rc != DBG_OK) return rc;
+    if (n_reads == 0) return DBG_OK;
+    if (!offsets) return DBG_E_INVAL;
+    uint64_t windows = 0, kmers = 0;
+    if (!host_counts(offsets, n_reads, k, &windows, &kmers)) return DBG_E_INVAL;
+    const uint64_t base = offsets[0];
+    const uint64_t len = offsets[n_reads] - base;
+    if (len && !reads) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        rc = harvest(g);
+        if (rc != DBG_OK) return rc;
+    }
+    if (g->inserts + kmers > kCounterLimit) return DBG_E_RANGE;
+    rc = ensure_table(g, windows);
+    if (rc != DBG_OK) return rc;
+
+    hipError_t e;
+    if ((e = g->reads.reserve(std::max<uint64_t>(len, 1))) != hipSuccess ||
+        (e = g->offsets.reserve((n_reads + 1) * 8)) != hipSuccess)
+        return hip_code(e);
+    hipStream_t s = g->stream;
+    if (len && hipMemcpyAsync(g->reads.p, reads + base, len, hipMemcpyHostToDevice, s) != hipSuccess)
+        return DBG_E_DEVICE;
+    if (hipMemcpyAsync(g->offsets.p, offsets, (n_reads + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return DBG_E_DEVICE;
+    rc = enqueue_single(g, g->reads.as<uint8_t>(), len, g->offsets.as<uint64_t>(), n_reads, k, s);
+    if (rc != DBG_OK) return rc;
+    return harvest(g);
+}
+
+static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap,
+                        uint64_t *n_vertices, bool device_out, hipStream_t s) {
+    if (!g || !n_vertices) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    const uint64_t V = g->vertices;
+    *n_vertices = V;
+    if (!keys) return DBG_OK;
+    if (cap < V) return DBG_E_SPACE;
+    if (!counts) return DBG_E_INVAL;
+    if (V == 0) return DBG_OK;
+
+    uint64_t *okeys = keys;
+    uint32_t *ocnt = counts;
+    hipError_t e;
+    if (!device_out) {
+        if ((e = g->xkeys.reserve(V * 8)) != hipSuccess || (e = g->xcnt.reserve(V * 16)) != hipSuccess)
+            return hip_code(e);
+        okeys = g->xkeys.as<uint64_t>();
+        ocnt = g->xcnt.as<uint32_t>();
+    }
+    if (g->xn.reserve(8) != hipSuccess) return DBG_E_DEVICE;
+    uint64_t found = 0;
+    e = dbgk::launch_fill_zero(g->xn.as<uint64_t>(), 1, s);
+    if (e == hipSuccess)
+        e = dbgk::launch_extract(g->table.as<uint64_t>(), g->ew, g->cap, okeys, ocnt, V,
+                                 g->xn.as<uint64_t>(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&found, g->xn.p, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !device_out) {
+        e = hipMemcpyAsync(keys, okeys, V * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(counts, ocnt, V * 16, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return DBG_E_DEVICE;
+    return found == V ? DBG_OK : DBG_E_DEVICE;
+}
+
+int dbg_extract(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap, uint64_t *n_vertices) {
+    return extract_impl(g, keys, counts, cap, n_vertices, false, g ? g->stream : nullptr);
+}
+
+int dbg_extract_device(dbg_graph *g, uint64_t *d_keys, uint32_t *d_counts, uint64_t cap,
+                       uint64_t *n_vertices, void *stream) {
+    return extract_impl(g, d_keys, d_counts, cap, n_vertices, true, g ? g->pick(stream) : nullptr);
+}
+
+int dbg_reset(dbg_graph *g) {
+    if (!g) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (g->pass.pending) (void)harvest(g);
+    g->k = 0;
+    g->poisoned = DBG_OK;
+    g->unreported = DBG_OK;
+    g->vertices = g->inserts = g->windows = g->builds = 0;
+    if (!g->cap) return DBG_OK;
+    return dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) == hipSuccess
+               ? DBG_OK
+               : DBG_E_DEVICE;
+}
+
+int dbg_get_stats(dbg_graph *g, dbg_stats *out) {
+    if (!g || !out) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    std::memset(out, 0, sizeof *out);
+    out->capacity = g->cap;
+    out->table_bytes = g->table_words() * 8;
+    out->vertices = g->vertices;
+    out->inserts = g->inserts;
+    out->windows = g->windows;
+    out->builds = g->builds;
+    out->k = g->k;
+    out->status = g->poisoned;
+    out->last_build_ms = g->last_build_ms;
+    out->last_total_ms = g->last_total_ms;
+    out->block_size = g->shape.block;
+    out->windows_per_thread = g->shape.wpt;
+    out->grid_size = g->shape.grid;
+    out->entry_bytes = g->ew * 8;
+    return DBG_OK;
+}
+
+void dbg_destroy(dbg_graph *g) {
+    if (!g) return;
+    DeviceGuard guard(g->device);
+    if (g->pass.pending) (void)g->pass.wait(nullptr, nullptr);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    DevBuf *bufs[] = {&g->table, &g->reads, &g->offsets, &g->xkeys, &g->xcnt, &g->xn};
+    for (DevBuf *b : bufs) b->release();
+    g->pass.release();
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+const char *dbg_strerror(int code) {
+    switch (code) {
+    case DBG_OK: return "ok";
+    case DBG_E_INVAL: return "invalid argument (NULL pointer, bad offsets or configuration)";
+    case DBG_E_K: return "k outside [2, 32] or different from the graph's k";
+    case DBG_E_BASE: return "read byte outside ACGTacgt";
+    case DBG_E_NOMEM: return "device memory allocation refused";
+    case DBG_E_FULL: return "table capacity exhausted; graph poisoned";
+    case DBG_E_SPACE: return "output buffer smaller than the vertex count";
+    case DBG_E_DEVICE: return "HIP runtime error";
+    case DBG_E_RANGE: return "cumulative k-mers would exceed 2^32-1";
+    case DBG_E_STATE: return "graph poisoned by an earlier capacity overflow";
+    default: return "unknown error";
+    }
+}
+
+int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t m,
+                    int32_t *statuses, void *stream) {
+    if (m == 0) return DBG_OK;
+    if (!graphs || !inputs || !statuses) return DBG_E_INVAL;
+    for (uint32_t i = 0; i < m; ++i)
+        if (!graphs[i]) return DBG_E_INVAL;
+    const int device = graphs[0]->device;
+    DeviceGuard guard(device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    BatchCtx *ctx = batch_ctx(device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->ready) {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+            ctx->pass.init() != hipSuccess)
+            return DBG_E_DEVICE;
+        ctx->ready = true;
+    }
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+
+    // Host-side validation and the concatenated layout.  Instances that fail
+    // here keep zero reads in the launch, so nothing of theirs is touched.
+    std::vector<uint64_t> read_begin(m + 1, 0);
+    std::vector<uint32_t> ks(m);
+    std::vector<int32_t> pre(m, DBG_OK);
+    uint64_t total_bytes = 0, total_reads = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const dbg_input &in = inputs[i];
+        ks[i] = in.k;
+        read_begin[i] = total_reads;
+        int rc = check_common(graphs[i], in.k);
+        uint64_t w = 0, km = 0;
+        if (rc == DBG_OK && in.n_reads && !in.offsets) rc = DBG_E_INVAL;
+        if (rc == DBG_OK && in.n_reads && !host_counts(in.offsets, in.n_reads, in.k, &w, &km))
+            rc = DBG_E_INVAL;
+        if (rc == DBG_OK && in.n_reads && in.offsets[in.n_reads] > in.offsets[0] && !in.reads)
+            rc = DBG_E_INVAL;
+        if (rc == DBG_OK && graphs[i]->inserts + km > kCounterLimit) rc = DBG_E_RANGE;
+        pre[i] = rc;
+        if (rc == DBG_OK && in.n_reads) {
+            total_reads += in.n_reads;
+            total_bytes += in.offsets[in.n_reads] - in.offsets[0];
+        }
+    }
+    read_begin[m] = total_reads;
+    std::vector<uint64_t> &hoff = ctx->hoff;
+    hoff.assign(total_reads + 1, 0);
+    hipError_t e;
+    if ((e = ctx->reads.reserve(std::max<uint64_t>(total_bytes, 1))) != hipSuccess ||
+        (e = ctx->offsets.reserve((total_reads + 1) * 8)) != hipSuccess) {
+        for (uint32_t i = 0; i < m; ++i) statuses[i] = hip_code(e);
+        return hip_code(e);
+    }
+    uint64_t byte_at = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const dbg_input &in = inputs[i];
+        if (pre[i] != DBG_OK || !in.n_reads) continue;
+        const uint64_t b0 = in.offsets[0], len = in.offsets[in.n_reads] - b0;
+        for (uint64_t r = 0; r < in.n_reads; ++r) hoff[read_begin[i] + r] = byte_at + (in.offsets[r] - b0);
+        if (len && hipMemcpyAsync(ctx->reads.as<uint8_t>() + byte_at, in.reads + b0, len,
+                                  hipMemcpyHostToDevice, s) != hipSuccess)
+            return DBG_E_DEVICE;
+        byte_at += len;
+    }
+    hoff[total_reads] = byte_at;
+    if (hipMemcpyAsync(ctx->offsets.p, hoff.data(), (total_reads + 1) * 8, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DBG_E_DEVICE;
+
+    // graphs that failed host validation take part with no reads
+    std::vector<dbg_graph *> gs(graphs, graphs + m);
+    std::vector<uint32_t> kk(ks);
+    std::vector<uint64_t> rb(read_begin);
+    std::vector<dbg_graph *> run_g;
+    std::vector<uint32_t> run_k;
+    std::vector<uint64_t> run_rb;
+    std::vector<uint32_t> where;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (pre[i] != DBG_OK) continue;
+        run_g.push_back(gs[i]);
+        run_k.push_back(kk[i]);
+        run_rb.push_back(rb[i]);
+        where.push_back(i);
+    }
+    for (uint32_t i = 0; i < m; ++i) statuses[i] = pre[i];
+    if (run_g.empty()) return first_error(statuses, m);
+    run_rb.push_back(total_reads);
+    std::vector<int32_t> st(run_g.size(), DBG_OK);
+    if (total_reads == 0) return first_error(statuses, m);
+    batch_device_impl(run_g.data(), (uint32_t)run_g.size(), run_rb.data(), run_k.data(),
+                      ctx->reads.as<uint8_t>(), byte_at, ctx->offsets.as<uint64_t>(), st.data(), s,
+                      ctx, true);
+    for (size_t j = 0; j < where.size(); ++j) statuses[where[j]] = st[j];
+    return first_error(statuses, m);
+}
+
+int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
+                           const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
+                           const uint64_t *d_offsets, int32_t *statuses, void *stream) {
+    if (m == 0) return DBG_OK;
+    if (!graphs || !read_begin || !ks || !statuses || !d_offsets || (!d_reads && reads_len))
+        return DBG_E_INVAL;
+    for (uint32_t i = 0; i < m; ++i)
+        if (!graphs[i]) return DBG_E_INVAL;
+    if (read_begin[0] != 0) return DBG_E_INVAL;
+    const int device = graphs[0]->device;
+    DeviceGuard guard(device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    BatchCtx *ctx = batch_ctx(device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->ready) {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+            ctx->pass.init() != hipSuccess)
+            return DBG_E_DEVICE;
+        ctx->ready = true;
+    }
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    if (read_begin[m] == 0) {
+        for (uint32_t i = 0; i < m; ++i) statuses[i] = check_common(graphs[i], ks[i]);
+        return first_error(statuses, m);
+    }
+    batch_device_impl(graphs, m, read_begin, ks, d_reads, reads_len, d_offsets, statuses, s, ctx, true);
+    return first_error(statuses, m);
+}
+
+int dbg_atomic_roofline(int32_t device, uint32_t kind, uint64_t footprint_bytes, uint64_t n_ops,
+                        uint32_t block_size, uint32_t repeats, double *ms) {
+    if (!ms || kind > 3 || footprint_bytes < 64 || block_size == 0 || block_size % 64 ||
+        block_size > 1024)
+        return DBG_E_INVAL;
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
+    DeviceGuard guard(device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    const uint64_t words = footprint_bytes / 8;
+    uint64_t *mem = nullptr, *sink = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    std::vector<double> t;
+    hipError_t e = hipMalloc(&mem, words * 8);
+    if (e == hipSuccess) e = hipMalloc(&sink, 8);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    for (uint32_t r = 0; e == hipSuccess && r <= repeats; ++r) {
+        e = dbgk::launch_fill_zero(mem, words, s);
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = dbgk::launch_roofline(mem, words, n_ops, kind, 0x9E3779B97F4A7C15ull * (r + 1),
+                                                       block_size, sink, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float x = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&x, a, b);
+        if (e == hipSuccess && r > 0) t.push_back(x);  // launch 0 warms up
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s) (void)hipStreamDestroy(s);
+    if (mem) (void)hipFree(mem);
+    if (sink) (void)hipFree(sink);
+    if (e != hipSuccess) return hip_code(e);
+    if (t.empty()) {
+        *ms = 0;
+        return DBG_OK;
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return DBG_OK;
+}
+
+}  // extern "C"

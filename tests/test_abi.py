@@ -1,0 +1,105 @@
+"""The C-ABI library loads, exports what the header declares, and rejects bad
+arguments on the host before touching a device.  Runs without a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2401_02756_amd as dbg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dbg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbg_[a-z_]+)\s*\(", text)))
+
+
+def declared_codes():
+    text = open(os.path.join(ROOT, "include", "dbg.h")).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"#define DBG_(E_[A-Z]+|OK) \(?(-?\d+)\)?", text)}
+
+
+def test_library_exports_every_declared_symbol():
+    L = dbg.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(dbg.EXPORTS) == names
+
+
+def test_binding_codes_match_header():
+    codes = declared_codes()
+    assert codes["OK"] == dbg.OK
+    assert codes["E_INVAL"] == dbg.E_INVAL and codes["E_K"] == dbg.E_K
+    assert codes["E_BASE"] == dbg.E_BASE and codes["E_NOMEM"] == dbg.E_NOMEM
+    assert codes["E_FULL"] == dbg.E_FULL and codes["E_SPACE"] == dbg.E_SPACE
+    assert codes["E_DEVICE"] == dbg.E_DEVICE and codes["E_RANGE"] == dbg.E_RANGE
+    assert codes["E_STATE"] == dbg.E_STATE
+
+
+def test_struct_layouts_match_header():
+    # dbg_config: 2 x u64, double, i32, 3 x u32, pointer -> 48 bytes on LP64
+    assert ctypes.sizeof(dbg.Config) == 48
+    assert ctypes.sizeof(dbg.Stats) == 6 * 8 + 8 + 16 + 16
+    assert ctypes.sizeof(dbg.Input) == 32
+
+
+def test_strerror_and_config_init():
+    L = dbg.lib()
+    for code in range(0, -10, -1):
+        assert L.dbg_strerror(code)
+    assert L.dbg_strerror(-99) == b"unknown error"
+    cfg = dbg.Config()
+    cfg.flags = 7
+    L.dbg_config_init(ctypes.byref(cfg))
+    assert cfg.flags == 0 and cfg.device == -1 and cfg.load_factor == 0.0
+
+
+def test_host_side_argument_errors_need_no_device():
+    L = dbg.lib()
+    h = ctypes.c_void_p()
+    assert L.dbg_create(None, None) == dbg.E_INVAL
+    cfg = dbg.Config()
+    L.dbg_config_init(ctypes.byref(cfg))
+    for lf in (-0.5, 1.0, 2.0):
+        cfg.load_factor = lf
+        assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    cfg.load_factor = 0.5
+    cfg.block_size = 100  # not a multiple of 64
+    assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    assert L.dbg_build(None, None, None, 1, 21) == dbg.E_INVAL
+    assert L.dbg_build_device(None, None, 0, None, 1, 21, None) == dbg.E_INVAL
+    assert L.dbg_sync(None) == dbg.E_INVAL
+    assert L.dbg_reset(None) == dbg.E_INVAL
+    assert L.dbg_get_stats(None, None) == dbg.E_INVAL
+    n = ctypes.c_uint64()
+    assert L.dbg_extract(None, None, None, 0, ctypes.byref(n)) == dbg.E_INVAL
+    L.dbg_destroy(None)
+    assert L.dbg_build_batch(None, None, 0, None, None) == dbg.OK
+    assert L.dbg_build_batch(None, None, 2, None, None) == dbg.E_INVAL
+    assert L.dbg_build_batch_device(None, 0, None, None, None, 0, None, None, None) == dbg.OK
+    ms = ctypes.c_double()
+    assert L.dbg_atomic_roofline(-1, 9, 1 << 20, 10, 256, 1, ctypes.byref(ms)) == dbg.E_INVAL
+    assert L.dbg_atomic_roofline(-1, 0, 1 << 20, 10, 100, 1, ctypes.byref(ms)) == dbg.E_INVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(dbg, "_lib", None)
+    monkeypatch.setattr(dbg, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        dbg.lib()
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2401_02756_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                for pat in (r"^\s*import oracle", r"^\s*from oracle", r"liboracle", r"dbg_oracle"):
+                    assert not re.search(pat, text, flags=re.M), (f, pat)
