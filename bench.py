@@ -75,6 +75,7 @@ def main() -> int:
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wpt", type=int, default=0)
+    ap.add_argument("--mode", choices=["direct", "binned"], default="direct")
     ap.add_argument("--merge", action="store_true")
     ap.add_argument("--entry32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,6 +108,8 @@ def main() -> int:
     windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
 
     flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
+    if args.mode == "binned":
+        flags |= dbg.F_BINNED
     g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
                   device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
     st0 = g.stats()
@@ -167,7 +170,7 @@ def main() -> int:
                    "inserts_per_step": inserts, "vertices": V, "capacity": cap_out,
                    "load_factor": args.load_factor, "entry_bytes": st["entry_bytes"],
                    "block": st["block_size"], "windows_per_thread": st["windows_per_thread"],
-                   "grid": st["grid_size"], "merge": bool(args.merge)},
+                   "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode},
         "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
         "roofline": roof,
     }

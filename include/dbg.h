@@ -59,6 +59,10 @@ extern "C" {
 #define DBG_F_MERGE 0x1u   /* merge equal vertices within a wavefront first */
 #define DBG_F_TIMING 0x2u  /* time each build kernel with HIP events */
 #define DBG_F_ENTRY32 0x4u /* 32-byte table entries (default 24 bytes) */
+#define DBG_F_BINNED 0x8u  /* binned build: records partitioned by table segment,
+                              claimed and counted in LDS (k <= 31; a graph whose
+                              first build has k = 32 falls back to the direct
+                              build) */
 
 typedef struct dbg_graph dbg_graph;
 

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
 
 OK = 0
 E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE = range(-1, -10, -1)
-F_MERGE, F_TIMING, F_ENTRY32 = 0x1, 0x2, 0x4
+F_MERGE, F_TIMING, F_ENTRY32, F_BINNED = 0x1, 0x2, 0x4, 0x8
 
 # every symbol include/dbg.h declares
 EXPORTS = (

@@ -130,6 +130,8 @@ uint64_t capacity_for(uint64_t vertices, double lf) {
 // Buffers and launch sequence of one build pass over m instances.
 struct Pass {
     DevBuf packed, ws, partials, tiles, dinst, dstatus;
+    // binned-mode scratch
+    DevBuf bplan, bbuckets, btotals, hist1, scan1, hist2, scan2, bpartials, rec1, rec2, pstart;
     HostBuf hinst, hstatus;
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
     uint32_t m = 0;
@@ -144,7 +146,8 @@ struct Pass {
         return e;
     }
     void release() {
-        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dinst, &dstatus};
+        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dinst, &dstatus, &bplan, &bbuckets,
+                       &btotals, &hist1, &scan1, &hist2, &scan2, &bpartials, &rec1, &rec2, &pstart};
         for (DevBuf *b : d) b->release();
         hinst.release();
         hstatus.release();
@@ -163,35 +166,93 @@ struct Pass {
     Instance *host_instances() const { return hinst.as<Instance>(); }
     const InstStatus *host_status() const { return hstatus.as<InstStatus>(); }
 
+    // Reserve the binned-mode scratch for mm instances over len bytes.
+    hipError_t reserve_binned(uint32_t mm, uint64_t len, dbgk::BinBuffers &bb) {
+        const Instance *hi = host_instances();
+        uint64_t G1 = 0, P = 0, d1max = 1, fanmax = 1;
+        bb.entry_words = 3;
+        for (uint32_t i = 0; i < mm; ++i) {
+            G1 += hi[i].d1;
+            P += hi[i].parts;
+            d1max = std::max<uint64_t>(d1max, hi[i].d1);
+            fanmax = std::max<uint64_t>(fanmax, hi[i].fan);
+            if (hi[i].parts) bb.entry_words = hi[i].entry_words;
+        }
+        bb.d1_max = (uint32_t)d1max;
+        bb.fan_max = (uint32_t)fanmax;
+        bb.tiles1_cap = len / dbgk::kBinTile + mm + 1;
+        bb.hist1_cap = d1max * bb.tiles1_cap;
+        bb.tiles2_cap = len / dbgk::kRefTile + G1 + 1;
+        bb.hist2_cap = fanmax * bb.tiles2_cap;
+        const uint64_t chunk = 1024;
+        bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
+        bb.buckets_total = G1;
+        bb.parts_total = P;
+        const uint64_t recs = std::max<uint64_t>(len, 1);
+        hipError_t e;
+        if ((e = bplan.reserve(sizeof(dbgk::BinPlan) * mm)) != hipSuccess ||
+            (e = bbuckets.reserve(sizeof(dbgk::Bucket) * std::max<uint64_t>(G1, 1))) != hipSuccess ||
+            (e = btotals.reserve(sizeof(dbgk::BinTotals))) != hipSuccess ||
+            (e = hist1.reserve(4 * bb.hist1_cap)) != hipSuccess ||
+            (e = scan1.reserve(8 * (bb.hist1_cap + 1))) != hipSuccess ||
+            (e = hist2.reserve(4 * bb.hist2_cap)) != hipSuccess ||
+            (e = scan2.reserve(8 * (bb.hist2_cap + 1))) != hipSuccess ||
+            (e = bpartials.reserve(8 * bb.partials_cap)) != hipSuccess ||
+            (e = rec1.reserve(8 * recs)) != hipSuccess || (e = rec2.reserve(8 * recs)) != hipSuccess ||
+            (e = pstart.reserve(8 * (P + 1))) != hipSuccess)
+            return e;
+        bb.plan = bplan.as<dbgk::BinPlan>();
+        bb.buckets = bbuckets.as<dbgk::Bucket>();
+        bb.totals = btotals.as<dbgk::BinTotals>();
+        bb.hist1 = hist1.as<uint32_t>();
+        bb.scan1 = scan1.as<uint64_t>();
+        bb.hist2 = hist2.as<uint32_t>();
+        bb.scan2 = scan2.as<uint64_t>();
+        bb.partials = bpartials.as<uint64_t>();
+        bb.rec1 = rec1.as<uint64_t>();
+        bb.rec2 = rec2.as<uint64_t>();
+        bb.pstart = pstart.as<uint64_t>();
+        return hipSuccess;
+    }
+
     // Enqueue the pass; hinst[0..mm) must be filled (tables, read ranges,
-    // prior k-mers, k, entry words).  Reads are device-resident and gap-free:
-    // read i is d_reads[off[i] - off[0] .. off[i+1] - off[0]).
+    // prior k-mers, k, entry words, and the segment geometry when binned).
+    // Reads are device-resident and gap-free: read i is
+    // d_reads[off[i] - off[0] .. off[i+1] - off[0]).
     hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
-                       uint64_t n, dbgk::BuildShape shape, bool check_ends, bool time_it,
-                       hipStream_t s) {
+                       uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
+                       bool time_it, hipStream_t s) {
         const uint64_t T = (uint64_t)shape.block * shape.wpt;
-        const uint64_t tile_cap = dbgk::max_tiles(len, T);
+        const uint64_t tile_cap = binned ? 0 : dbgk::max_tiles(len, T);
+        dbgk::BinBuffers bb{};
         hipError_t e;
         if ((e = packed.reserve(dbgk::packed_words(len) * 8)) != hipSuccess ||
             (e = ws.reserve((n + 1) * 8)) != hipSuccess ||
             (e = partials.reserve(dbgk::scan_blocks(n) * 8 + 8)) != hipSuccess ||
-            (e = tiles.reserve(tile_cap * 8)) != hipSuccess)
+            (!binned && (e = tiles.reserve(tile_cap * 8)) != hipSuccess) ||
+            (binned && (e = reserve_binned(mm, len, bb)) != hipSuccess))
             return e;
         InstStatus *dst = dstatus.as<InstStatus>();
         CallState *cs = reinterpret_cast<CallState *>(dst + mm);
         Instance *di = dinst.as<Instance>();
+        const uint64_t max_windows = binned ? len : (tile_cap - 1) * T;
         if (time_it) (void)hipEventRecord(ev_a, s);
         e = hipMemcpyAsync(di, hinst.p, sizeof(Instance) * mm, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = dbgk::launch_prepare(di, mm, dst, cs, d_off, n, s);
         if (e == hipSuccess) e = dbgk::launch_pack(d_reads, len, packed.as<uint64_t>(), di, mm, dst, s);
         if (e == hipSuccess)
             e = dbgk::launch_scan(d_off, n, len, check_ends, di, mm, dst, ws.as<uint64_t>(),
-                                  partials.as<uint64_t>(), tiles.as<uint64_t>(), tile_cap,
-                                  (uint32_t)T, cs, s);
+                                  partials.as<uint64_t>(), binned ? nullptr : tiles.as<uint64_t>(),
+                                  tile_cap, (uint32_t)T, max_windows, cs, s);
         if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
-        if (e == hipSuccess)
-            e = dbgk::launch_build(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(),
-                                   tiles.as<uint64_t>(), n, dst, cs, shape, s);
+        if (e == hipSuccess) {
+            if (binned)
+                e = dbgk::launch_binned(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(), n, dst,
+                                        bb, shape.merge, device, s);
+            else
+                e = dbgk::launch_build(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(),
+                                       tiles.as<uint64_t>(), n, dst, cs, shape, s);
+        }
         if (time_it && e == hipSuccess) (void)hipEventRecord(ev_c, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * mm + sizeof(CallState),
@@ -232,6 +293,10 @@ struct dbg_graph {
     uint64_t cap = 0;
     uint32_t ew = 3;
     DevBuf table;
+    bool binned = false;     // table cut into segments, built by the binned kernels
+    bool fresh = true;       // binned: logically empty (contents need not be zero)
+    uint32_t parts = 0, d1 = 0, fan = 0;
+    DevBuf seg_count, seg_off, seg_partials, seg_len;  // binned: per-segment occupancy
 
     uint32_t k = 0;
     int32_t poisoned = DBG_OK;
@@ -251,7 +316,32 @@ struct dbg_graph {
 
 namespace {
 
+// Segment geometry of a binned table of `parts` segments: d1 level-1 buckets
+// of `fan` segments each (about the square root, so both partition passes
+// write runs of similar length).
+bool binned_geometry(uint64_t parts, uint32_t *d1, uint32_t *fan) {
+    uint64_t target = (uint64_t)std::ceil(std::sqrt((double)parts));
+    target = std::max<uint64_t>(1, std::min<uint64_t>(target, dbgk::kMaxD1));
+    uint64_t f = (parts + target - 1) / target;
+    if (f > dbgk::kMaxFan) return false;
+    *fan = (uint32_t)f;
+    *d1 = (uint32_t)((parts + f - 1) / f);
+    return true;
+}
+
 hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
+    if (g->binned) {
+        const uint64_t parts = (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots;
+        if (parts > 0xffffffffull || !binned_geometry(parts, &g->d1, &g->fan)) return hipErrorInvalidValue;
+        g->parts = (uint32_t)parts;
+        cap = parts * dbgk::kSegSlots;
+        hipError_t e;
+        if ((e = g->seg_count.reserve(4 * parts)) != hipSuccess ||
+            (e = g->seg_off.reserve(8 * (parts + 1))) != hipSuccess ||
+            (e = g->seg_partials.reserve(8 * ((parts + 1023) / 1024 + 2))) != hipSuccess ||
+            (e = g->seg_len.reserve(8)) != hipSuccess)
+            return e;
+    }
     g->cap = cap;
     hipError_t e = g->table.reserve(g->table_words() * sizeof(uint64_t));
     if (e != hipSuccess) {
@@ -267,7 +357,21 @@ int ensure_table(dbg_graph *g, uint64_t windows_bound) {
     if (g->cap) return DBG_OK;
     uint64_t cap = g->cap_req;
     if (!cap) cap = capacity_for(g->expected ? g->expected : std::max<uint64_t>(windows_bound, 1), g->lf);
-    return hip_code(allocate_table(g, cap));
+    const hipError_t e = allocate_table(g, cap);
+    if (e == hipErrorInvalidValue) return DBG_E_INVAL;
+    g->fresh = true;
+    return hip_code(e);
+}
+
+// A binned graph whose first build has k = 32 (keys too wide for the 8-byte
+// records) becomes a direct one; its table must then hold zeros.
+int settle_mode(dbg_graph *g, uint32_t k) {
+    if (!g->binned || k <= 31) return DBG_OK;
+    if (g->k || g->vertices) return DBG_E_K;
+    g->binned = false;
+    if (g->cap && dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) != hipSuccess)
+        return DBG_E_DEVICE;
+    return DBG_OK;
 }
 
 void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint64_t read_end, uint32_t k) {
@@ -281,6 +385,15 @@ void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint64_t rea
     in.k = k;
     in.entry_words = g->ew;
     in.skip = 0;
+    in.part_base = 0;
+    in.parts = g->binned ? g->parts : 0;
+    in.d1 = g->binned ? g->d1 : 0;
+    in.fan = g->binned ? g->fan : 0;
+    in.fresh = (g->binned && g->fresh) ? 1u : 0u;
+    in.seg_count = g->binned ? g->seg_count.as<uint32_t>() : nullptr;
+    // Lemire, Kaser, Kurz, "Faster remainder by direct computation" (2019):
+    // for 32-bit n, n / d is the high 64 bits of ceil(2^64 / d) * n
+    in.fan_magic = (g->binned && g->fan > 1) ? (~0ull / g->fan + 1) : 0;
     in.pad = 0;
 }
 
@@ -288,6 +401,7 @@ void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint64_t rea
 int fold_status(dbg_graph *g, const InstStatus &st, uint32_t k) {
     if (validation_error(st.err)) return err_code_of(st.err);  // nothing was modified
     g->k = k;
+    g->fresh = false;
     g->vertices += st.claimed;
     g->inserts += st.inserts;
     g->windows += st.windows;
@@ -319,7 +433,8 @@ int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, const uin
     hipError_t e = g->pass.reserve_instances(1);
     if (e != hipSuccess) return hip_code(e);
     fill_instance(g->pass.host_instances()[0], g, 0, n, k);
-    e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, true, (g->flags & DBG_F_TIMING) != 0, s);
+    e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, g->binned, g->device, true,
+                        (g->flags & DBG_F_TIMING) != 0, s);
     if (e != hipSuccess) return hip_code(e);
     g->pending_k = k;
     return DBG_OK;
@@ -361,6 +476,7 @@ static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64
     const int device = graphs[0]->device;
     std::vector<uint8_t> run(m, 0);
     uint32_t n_run = 0;
+    int mode = -1;  // direct (0) or binned with 3/4-word entries: the first graph that runs decides
     for (uint32_t i = 0; i < m; ++i) {
         dbg_graph *g = graphs[i];
         int rc = check_common(g, ks[i]);
@@ -372,6 +488,10 @@ static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64
         if (rc == DBG_OK && read_begin[i + 1] > read_begin[i]) {
             // a graph never sized takes the whole input's byte count as bound
             rc = ensure_table(g, std::max<uint64_t>(reads_len, 1));
+            if (rc == DBG_OK) rc = settle_mode(g, ks[i]);
+            const int gm = g->binned ? (int)g->ew : 0;  // binned launches share one entry width
+            if (rc == DBG_OK && mode < 0) mode = gm;
+            if (rc == DBG_OK && gm != mode) rc = DBG_E_INVAL;  // one mode per launch
             if (rc == DBG_OK) {
                 run[i] = 1;
                 ++n_run;
@@ -390,14 +510,24 @@ static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64
     }
     Instance *hi = pass.host_instances();
     const dbg_graph *g0 = nullptr;
+    uint64_t part_base = 0;
     for (uint32_t i = 0; i < m; ++i) {
-        fill_instance(hi[i], graphs[i], read_begin[i], read_begin[i + 1], run[i] ? ks[i] : 32u);
+        fill_instance(hi[i], graphs[i], read_begin[i], read_begin[i + 1], run[i] ? ks[i] : 31u);
         hi[i].skip = run[i] ? 0u : 1u;
+        if (mode == 0 || !run[i]) {
+            // segments only for the graphs a binned launch builds
+            hi[i].parts = hi[i].d1 = hi[i].fan = 0;
+            hi[i].fresh = 0;
+            hi[i].fan_magic = 0;
+        }
+        hi[i].part_base = part_base;
+        part_base += hi[i].parts;
         if (run[i] && !g0) g0 = graphs[i];
     }
     const bool timing = (g0->flags & DBG_F_TIMING) != 0;
     const uint64_t n = read_begin[m];
-    e = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, check_ends, timing, stream);
+    e = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, mode != 0, device, check_ends,
+                     timing, stream);
     double bms = 0, tms = 0;
     if (e == hipSuccess) e = pass.wait(&bms, &tms);
     const InstStatus *st = pass.host_status();
@@ -454,6 +584,7 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     g->expected = cfg.expected_vertices;
     g->cap_req = cfg.capacity;
     g->ew = (cfg.flags & DBG_F_ENTRY32) ? 4 : 3;
+    g->binned = (cfg.flags & DBG_F_BINNED) != 0;
     g->shape.block = block;
     g->shape.wpt = wpt;
     g->shape.merge = (cfg.flags & DBG_F_MERGE) ? 1 : 0;
@@ -490,6 +621,7 @@ int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
         if (rc != DBG_OK) return rc;
     }
     rc = ensure_table(g, reads_len);
+    if (rc == DBG_OK) rc = settle_mode(g, k);
     if (rc != DBG_OK) return rc;
     return enqueue_single(g, d_reads, reads_len, d_offsets, n_reads, k, g->pick(stream));
 }
@@ -521,6 +653,7 @@ int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t
     }
     if (g->inserts + kmers > kCounterLimit) return DBG_E_RANGE;
     rc = ensure_table(g, windows);
+    if (rc == DBG_OK) rc = settle_mode(g, k);
     if (rc != DBG_OK) return rc;
 
     hipError_t e;
@@ -565,7 +698,12 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
     if (g->xn.reserve(8) != hipSuccess) return DBG_E_DEVICE;
     uint64_t found = 0;
     e = dbgk::launch_fill_zero(g->xn.as<uint64_t>(), 1, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && g->binned)
+        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, g->parts,
+                                        g->seg_count.as<uint32_t>(), g->seg_off.as<uint64_t>(),
+                                        g->seg_partials.as<uint64_t>(), g->seg_len.as<uint64_t>(), okeys,
+                                        ocnt, V, g->xn.as<uint64_t>(), g->device, s);
+    else if (e == hipSuccess)
         e = dbgk::launch_extract(g->table.as<uint64_t>(), g->ew, g->cap, okeys, ocnt, V,
                                  g->xn.as<uint64_t>(), s);
     if (e == hipSuccess) e = hipMemcpyAsync(&found, g->xn.p, 8, hipMemcpyDeviceToHost, s);
@@ -595,7 +733,10 @@ int dbg_reset(dbg_graph *g) {
     g->poisoned = DBG_OK;
     g->unreported = DBG_OK;
     g->vertices = g->inserts = g->windows = g->builds = 0;
-    if (!g->cap) return DBG_OK;
+    g->fresh = true;
+    // A binned build rewrites every slot of a fresh table, so its reset only
+    // marks the table empty; the direct build needs the zeros.
+    if (!g->cap || g->binned) return DBG_OK;
     return dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) == hipSuccess
                ? DBG_OK
                : DBG_E_DEVICE;
@@ -631,7 +772,8 @@ void dbg_destroy(dbg_graph *g) {
     DeviceGuard guard(g->device);
     if (g->pass.pending) (void)g->pass.wait(nullptr, nullptr);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
-    DevBuf *bufs[] = {&g->table, &g->reads, &g->offsets, &g->xkeys, &g->xcnt, &g->xn};
+    DevBuf *bufs[] = {&g->table,    &g->reads,  &g->offsets,      &g->xkeys,  &g->xcnt,
+                      &g->xn,       &g->seg_count, &g->seg_off, &g->seg_partials, &g->seg_len};
     for (DevBuf *b : bufs) b->release();
     g->pass.release();
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);

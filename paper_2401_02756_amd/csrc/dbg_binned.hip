@@ -1,0 +1,864 @@
+// Binned build for gfx950: the same graph as the direct build, with the
+// per-k-mer claims and counts moved from device-scope atomics (which MI355X
+// executes past the per-XCD L2, at most ~27 G/s) into LDS.
+//
+// Each instance's table is cut into segments of kSegSlots slots; a key's
+// segment is chosen by the top bits of its hash and its home slot inside the
+// segment by the low 32 bits.  The windows of all reads become 8-byte
+// records (key << 3 | sink << 2 | letter; k <= 31) that are partitioned by
+// segment in two passes:
+//
+//   pass 1  windows -> records grouped by level-1 bucket (d1 buckets per
+//           instance, each covering `fan` consecutive segments)
+//   pass 2  records of each bucket -> records grouped by segment
+//
+// Every pass is count -> flat exclusive scan -> scatter.  The count kernel
+// writes one histogram per tile, laid out bucket-major and tile-minor, so one
+// exclusive scan over the whole histogram array gives each (tile, bucket) its
+// output offset directly; the scatter kernel sorts its tile by bucket in LDS
+// and writes each bucket's run contiguously.
+//
+// Finally one workgroup owns each segment: it stages the segment in LDS,
+// finds or claims each record's vertex with a 64-bit LDS compare-and-swap
+// (the paper's CAS, Algorithm 1, on the segment's slots), raises its counter
+// with a 32-bit LDS atomic add (Algorithm 3's increment), and writes the
+// segment back.  No global atomic is issued per k-mer; a segment is only ever
+// touched by its owner, so plain loads and stores move it.
+#include "dbg_device.h"
+
+#include <algorithm>
+
+namespace dbgk {
+namespace {
+
+constexpr uint32_t kSkipMask = kErrBase | kErrInval | kErrRange | kErrSkip;
+static_assert((kSegSlots & (kSegSlots - 1)) == 0, "segment size must be a power of two");
+static_assert(kBinTile <= 4096 && kRefTile <= 4096, "ranks are packed into 12 bits");
+static_assert(kMaxD1 % kBinBlock == 0 && kMaxFan % kRefBlock == 0, "bucket scans");
+
+__device__ __forceinline__ uint64_t lds_load64(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_add32(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Segment of a key within its instance (top bits of the hash).
+__device__ __forceinline__ uint32_t segment_of(uint64_t h, uint32_t parts) {
+    return (uint32_t)home_slot(h, parts);
+}
+
+// Level-1 bucket of a segment: seg / fan, by multiply-high with the
+// instance's precomputed ceil(2^64 / fan) (exact for 32-bit seg).
+__device__ __forceinline__ uint32_t bucket_of(uint32_t seg, uint32_t fan, uint64_t magic) {
+    return fan == 1 ? seg : (uint32_t)__umul64hi(magic, (uint64_t)seg);
+}
+
+// Home slot inside a segment (low 32 bits of the hash).
+__device__ __forceinline__ uint32_t seg_home(uint64_t h) {
+    return (uint32_t)(((h & 0xffffffffull) * kSegSlots) >> 32);
+}
+
+// Last index i in [0, n) with base(i) <= x, for a non-decreasing base.
+template <typename F>
+__device__ __forceinline__ uint64_t last_le(uint64_t n, uint64_t x, F base) {
+    uint64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (base(mid) <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// XCD-aware order of a persistent loop over n tiles.  Workgroups are
+// dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8), and
+// each XCD has its own L2.  Tile t's output runs sit next to tile t+1's, so
+// giving every XCD one contiguous range of tiles lets its L2 merge the
+// partial cache lines that neighbouring tiles write.  Only speed depends on
+// the dispatch order; every tile is visited exactly once for any grid.
+struct XcdTiles {
+    uint64_t next, end, step;
+    __device__ XcdTiles(uint64_t n) {
+        const uint32_t G = gridDim.x, b = blockIdx.x;
+        const uint32_t groups = G >= 8 ? 8 : 1;
+        const uint32_t g = b % groups;
+        const uint32_t per_group = (G + groups - 1 - g) / groups;  // workgroups in group g
+        const uint64_t span = (n + groups - 1) / groups;
+        const uint64_t lo = min((uint64_t)g * span, n);
+        next = lo + b / groups;
+        end = min(lo + span, n);
+        step = per_group;
+    }
+    __device__ bool valid() const { return next < end; }
+    __device__ void advance() { next += step; }
+};
+
+// ---------------------------------------------------------------- window decode
+
+// Reads of one pass-1 tile staged in LDS (all windows of the tile belong to
+// one instance).
+struct ReadStage {
+    uint64_t ws[kMapReads + 1];
+    uint64_t delta[kMapReads];
+    uint64_t r0;
+    uint32_t R;
+};
+
+// Stage the reads from the one holding window w0 on.  Requires
+// ws[rb] <= w0 < ws[re].  Contains barriers: call from the whole block.
+__device__ void stage_reads(ReadStage &S, const uint64_t *ws, const uint64_t *off, uint64_t off0,
+                            uint64_t rb, uint64_t re, uint64_t w0) {
+    if (threadIdx.x == 0) {
+        uint64_t lo = rb, hi = re;  // ws[lo] <= w0 < ws[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (ws[mid] <= w0) lo = mid; else hi = mid;
+        }
+        S.r0 = lo;
+        S.R = (uint32_t)min<uint64_t>(kMapReads, re - lo);
+    }
+    __syncthreads();
+    const uint64_t r0 = S.r0;
+    const uint32_t R = S.R;
+    for (uint32_t i = threadIdx.x; i <= R; i += blockDim.x) {
+        const uint64_t r = r0 + i;
+        const uint64_t wr = ws[r];
+        S.ws[i] = wr;
+        if (i < R) S.delta[i] = off[r] - off0 - wr;
+    }
+    __syncthreads();
+}
+
+// Local index of the staged read holding window w, found by binary search;
+// kMapReads + 1 if w lies past the staged reads.
+__device__ __forceinline__ uint32_t staged_read(const ReadStage &S, uint64_t w) {
+    const uint32_t R = S.R;
+    if (w >= S.ws[R]) return kMapReads + 1;
+    uint32_t lo = 0, hi = R;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (S.ws[mid] <= w) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Record (key << 3 | sink << 2 | letter) of window w (ws[S.r0] <= w <
+// ws[re]).  `hint` is a staged read at or before w's read (the read of the
+// wavefront's first window): consecutive windows of a wavefront lie in one or
+// two reads, so walking forward from it replaces a search per lane.
+__device__ __forceinline__ uint64_t decode_record(const ReadStage &S, const uint64_t *ws,
+                                                  const uint64_t *off, uint64_t off0, uint64_t re,
+                                                  const uint64_t *packed, uint32_t km1, uint64_t w,
+                                                  uint32_t hint) {
+    uint64_t wr1, delta;
+    const uint32_t R = S.R;
+    uint32_t lo = hint;
+    if (lo <= kMapReads)
+        while (lo < R && S.ws[lo + 1] <= w) ++lo;
+    if (lo < R) {
+        wr1 = S.ws[lo + 1];
+        delta = S.delta[lo];
+    } else {
+        uint64_t glo = S.r0 + R, ghi = re;  // ws[glo] <= w < ws[ghi]
+        while (ghi - glo > 1) {
+            const uint64_t mid = (glo + ghi) >> 1;
+            if (ws[mid] <= w) glo = mid; else ghi = mid;
+        }
+        wr1 = ws[glo + 1];
+        delta = off[glo] - off0 - ws[glo];
+    }
+    const uint64_t b = bases_at(packed, w + delta);
+    const uint64_t key = b >> (64 - 2 * km1);
+    const uint32_t letter = (uint32_t)(b >> (62 - 2 * km1)) & 3u;
+    const uint32_t sink = (w + 1 == wr1) ? 4u : 0u;
+    return (key << 3) | sink | letter;
+}
+
+// Window range end and base delta (position = window + delta) of the read
+// holding window w (ws[S.r0] <= w < ws[re]).
+struct ReadPos {
+    uint64_t wr1;    // one past the read's last window
+    uint64_t delta;  // off[r] - off[0] - ws[r]
+};
+
+__device__ __forceinline__ ReadPos locate_read(const ReadStage &S, const uint64_t *ws,
+                                               const uint64_t *off, uint64_t off0, uint64_t re,
+                                               uint64_t w) {
+    const uint32_t lo = staged_read(S, w);
+    if (lo <= kMapReads && lo < S.R) return ReadPos{S.ws[lo + 1], S.delta[lo]};
+    uint64_t glo = S.r0 + S.R, ghi = re;  // ws[glo] <= w < ws[ghi]
+    while (ghi - glo > 1) {
+        const uint64_t mid = (glo + ghi) >> 1;
+        if (ws[mid] <= w) glo = mid; else ghi = mid;
+    }
+    return ReadPos{ws[glo + 1], off[glo] - off0 - ws[glo]};
+}
+
+// 64 bases starting `o` bits into the 192-bit big-endian word triple.
+__device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, uint32_t o) {
+    if (o >= 64) {
+        a = b;
+        b = c;
+        o -= 64;
+    }
+    return o ? (a << o) | (b >> (64 - o)) : a;
+}
+
+// Exclusive prefix of s_cnt[0..n) in place (whole block); returns nothing,
+// leaves the starts in s_cnt.  For each bucket j, gbase(j, start) is stored in
+// s_gbase[j].
+template <typename G>
+__device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, G gbase) {
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t j0 = threadIdx.x * per;
+    uint64_t sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (j0 + q < n) sum += s_cnt[j0 + q];
+    uint64_t total;
+    uint64_t pre = block_exclusive_scan(sum, &total);
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t j = j0 + q;
+        if (j < n) {
+            const uint32_t c = s_cnt[j];
+            s_cnt[j] = (uint32_t)pre;
+            s_gbase[j] = gbase(j) - pre;
+            pre += c;
+        }
+    }
+}
+
+__host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// ---------------------------------------------------------------- plan
+
+// Per instance: its window range, pass-1 tiles, histogram and bucket bases.
+// An instance that failed validation (or whose k-mer total would overflow a
+// counter) gets no tiles, so it produces no records.
+__global__ void k_bin_plan(const Instance *inst, uint32_t m, const uint64_t *ws, InstStatus *st,
+                           BinPlan *plan, BinTotals *tot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t tiles = 0, hist = 0, buckets = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const Instance &in = inst[i];
+        uint32_t e = st[i].err;
+        if (!(e & kErrRange) && in.prior_inserts + st[i].inserts > 0xffffffffull) {
+            atomic_or_u32(&st[i].err, kErrRange);
+            e |= kErrRange;
+        }
+        BinPlan pl;
+        pl.w_begin = ws[in.read_begin];
+        pl.w_end = ws[in.read_end];
+        const bool run = !(e & kSkipMask) && pl.w_end > pl.w_begin;
+        pl.tiles = run ? (pl.w_end - pl.w_begin + kBinTile - 1) / kBinTile : 0;
+        pl.tile_base = tiles;
+        pl.hist_base = hist;
+        pl.bucket_base = buckets;
+        tiles += pl.tiles;
+        hist += (uint64_t)in.d1 * pl.tiles;
+        buckets += in.d1;
+        plan[i] = pl;
+    }
+    tot->tiles1 = tiles;
+    tot->hist1_len = hist;
+    tot->buckets = buckets;
+    tot->tiles2 = 0;
+    tot->hist2_len = 0;
+    tot->records = 0;
+}
+
+// ---------------------------------------------------------------- pass 1
+
+// Dynamic LDS of the pass-1 kernels: s_cnt[d1_max] (+ s_gbase[d1_max],
+// s_rec[kBinTile], s_bin[kBinTile] when scattering).
+__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter) {
+    uint32_t b = align16(4 * d1_max);
+    if (scatter) b += align16(8 * d1_max) + 8 * kBinTile + 2 * kBinTile;
+    return b;
+}
+
+// Pass 1.  A thread takes kBinPerThread consecutive windows of the tile: it
+// finds their read once, loads three packed words, and slides through them,
+// so a window costs a few shifts instead of a search and two loads.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBinBlock) void k_bin(const Instance *__restrict__ inst, uint32_t m,
+                                                  const uint64_t *__restrict__ packed,
+                                                  const uint64_t *__restrict__ off,
+                                                  const uint64_t *__restrict__ ws,
+                                                  const BinPlan *__restrict__ plan,
+                                                  const BinTotals *__restrict__ tot,
+                                                  uint32_t *__restrict__ hist1,
+                                                  const uint64_t *__restrict__ scan1,
+                                                  uint64_t *__restrict__ rec1, uint32_t d1_max) {
+    __shared__ ReadStage S;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
+    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * d1_max));
+    uint64_t *s_rec = s_gbase + d1_max;
+    uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tiles = tot->tiles1;
+    const uint64_t off0 = off[0];
+    for (XcdTiles it(tiles); it.valid(); it.advance()) {
+        const uint64_t t = it.next;
+        const uint32_t i = (uint32_t)last_le(m, t, [&](uint64_t j) { return plan[j].tile_base; });
+        const Instance &in = inst[i];
+        const BinPlan pl = plan[i];
+        const uint64_t tl = t - pl.tile_base;
+        const uint64_t w0 = pl.w_begin + tl * kBinTile;
+        const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, pl.w_end) - w0);
+        const uint32_t d1 = in.d1, fan = in.fan, parts = in.parts;
+        const uint64_t magic = in.fan_magic;
+        const uint32_t kshift = 64 - 2 * (in.k - 1), lshift = 62 - 2 * (in.k - 1);
+        for (uint32_t j = tid; j < d1; j += blockDim.x) s_cnt[j] = 0;
+        stage_reads(S, ws, off, off0, in.read_begin, in.read_end, w0);
+
+        uint64_t rec[kBinPerThread];
+        uint32_t tag[kBinPerThread];  // bucket << 12 | rank within the bucket
+        const uint32_t j0 = tid * kBinPerThread;
+#pragma unroll
+        for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = 0xffffffffu;
+        if (j0 < n_in) {
+            uint64_t w = w0 + j0;
+            ReadPos rp = locate_read(S, ws, off, off0, in.read_end, w);
+            uint64_t p = w + rp.delta;
+            uint64_t wbase = p >> 5;
+            uint64_t a = packed[wbase], b = packed[wbase + 1], c = packed[wbase + 2];
+#pragma unroll
+            for (uint32_t q = 0; q < kBinPerThread; ++q) {
+                if (j0 + q >= n_in) break;
+                if (w >= rp.wr1) {  // the next window starts another read
+                    rp = locate_read(S, ws, off, off0, in.read_end, w);
+                    p = w + rp.delta;
+                    wbase = p >> 5;
+                    a = packed[wbase];
+                    b = packed[wbase + 1];
+                    c = packed[wbase + 2];
+                }
+                const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
+                const uint64_t key = v >> kshift;
+                rec[q] = (key << 3) | (w + 1 == rp.wr1 ? 4u : 0u) | ((uint32_t)(v >> lshift) & 3u);
+                const uint32_t bk = bucket_of(segment_of(mix64(key), parts), fan, magic);
+                if (SCATTER) {
+                    tag[q] = (bk << 12) | lds_add32(&s_cnt[bk], 1u);
+                } else {
+                    __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                ++w;
+                ++p;
+            }
+        }
+        __syncthreads();
+        if (!SCATTER) {
+            for (uint32_t j = tid; j < d1; j += blockDim.x)
+                hist1[pl.hist_base + (uint64_t)j * pl.tiles + tl] = s_cnt[j];
+            __syncthreads();
+            continue;
+        }
+        bucket_starts(s_cnt, s_gbase, d1,
+                      [&](uint32_t j) { return scan1[pl.hist_base + (uint64_t)j * pl.tiles + tl]; });
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q = 0; q < kBinPerThread; ++q) {
+            if (tag[q] == 0xffffffffu) continue;
+            const uint32_t bk = tag[q] >> 12;
+            const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
+            s_rec[pos] = rec[q];
+            s_bin[pos] = (uint16_t)bk;
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < n_in; j += blockDim.x) rec1[s_gbase[s_bin[j]] + j] = s_rec[j];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- flat scan
+
+// Exclusive scan of `*len` uint32 values into uint64 (out[len] = total).
+constexpr uint32_t kFlatBlock = 256;
+constexpr uint32_t kFlatPer = 4;
+constexpr uint32_t kFlatChunk = kFlatBlock * kFlatPer;
+
+__global__ __launch_bounds__(kFlatBlock) void k_flat_local(const uint32_t *__restrict__ in,
+                                                          const uint64_t *len_ptr,
+                                                          uint64_t *__restrict__ out,
+                                                          uint64_t *__restrict__ partials) {
+    const uint64_t n = *len_ptr;
+    const uint64_t base = (uint64_t)blockIdx.x * kFlatChunk;
+    if (base >= n) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0;
+        return;
+    }
+    const uint64_t i0 = base + (uint64_t)threadIdx.x * kFlatPer;
+    uint32_t v[kFlatPer];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kFlatPer; ++j) {
+        v[j] = i0 + j < n ? in[i0 + j] : 0u;
+        sum += v[j];
+    }
+    uint64_t total;
+    uint64_t pre = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (uint32_t j = 0; j < kFlatPer; ++j) {
+        if (i0 + j < n) out[i0 + j] = pre;
+        pre += v[j];
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_flat_partials(uint64_t *partials, uint64_t nb,
+                                                       const uint64_t *len_ptr, uint64_t *out) {
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < nb; base += blockDim.x) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t v = i < nb ? partials[i] : 0;
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan(v, &total);
+        if (i < nb) partials[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[*len_ptr] = carry;
+}
+
+__global__ __launch_bounds__(kFlatBlock) void k_flat_add(const uint64_t *len_ptr, uint64_t *out,
+                                                        const uint64_t *partials) {
+    const uint64_t n = *len_ptr;
+    const uint64_t base = (uint64_t)blockIdx.x * kFlatChunk;
+    if (base >= n) return;
+    const uint64_t add = partials[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < kFlatChunk; j += blockDim.x)
+        if (base + j < n) out[base + j] += add;
+}
+
+// ---------------------------------------------------------------- pass 2
+
+// Per level-1 bucket: its record range, pass-2 tiles and histogram base.
+__global__ __launch_bounds__(1024) void k_refine_plan(const Instance *__restrict__ inst, uint32_t m,
+                                                     const BinPlan *__restrict__ plan,
+                                                     const uint64_t *__restrict__ scan1,
+                                                     BinTotals *tot, Bucket *__restrict__ buckets) {
+    const uint64_t G = tot->buckets;
+    uint64_t carry_t = 0, carry_h = 0;
+    for (uint64_t base = 0; base < G; base += blockDim.x) {
+        const uint64_t g = base + threadIdx.x;
+        Bucket B{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint64_t nt = 0, nh = 0;
+        if (g < G) {
+            const uint32_t i = (uint32_t)last_le(m, g, [&](uint64_t j) { return plan[j].bucket_base; });
+            const Instance &in = inst[i];
+            const BinPlan pl = plan[i];
+            const uint32_t b = (uint32_t)(g - pl.bucket_base);
+            B.start = scan1[pl.hist_base + (uint64_t)b * pl.tiles];
+            B.size = scan1[pl.hist_base + (uint64_t)(b + 1) * pl.tiles] - B.start;
+            B.inst = i;
+            B.b = b;
+            B.fan = min(in.fan, in.parts - b * in.fan);
+            nt = (B.size + kRefTile - 1) / kRefTile;
+            nh = nt * B.fan;
+        }
+        uint64_t tt, th;
+        const uint64_t pt = block_exclusive_scan(nt, &tt);
+        const uint64_t ph = block_exclusive_scan(nh, &th);
+        if (g < G) {
+            B.tiles = nt;
+            B.tile_base = carry_t + pt;
+            B.hist_base = carry_h + ph;
+            buckets[g] = B;
+        }
+        carry_t += tt;
+        carry_h += th;
+    }
+    if (threadIdx.x == 0) {
+        tot->tiles2 = carry_t;
+        tot->hist2_len = carry_h;
+        tot->records = scan1[tot->hist1_len];
+    }
+}
+
+// Dynamic LDS of the pass-2 kernels: s_cnt[fan_max] (+ s_gbase[fan_max],
+// s_rec[kRefTile], s_child[kRefTile] when scattering).
+__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter) {
+    uint32_t b = align16(4 * fan_max);
+    if (scatter) b += align16(8 * fan_max) + 8 * kRefTile + 2 * kRefTile;
+    return b;
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict__ inst,
+                                                     const Bucket *__restrict__ buckets,
+                                                     const BinTotals *__restrict__ tot,
+                                                     const uint64_t *__restrict__ rec1,
+                                                     uint32_t *__restrict__ hist2,
+                                                     const uint64_t *__restrict__ scan2,
+                                                     uint64_t *__restrict__ rec2, uint32_t fan_max) {
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
+    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * fan_max));
+    uint64_t *s_rec = s_gbase + fan_max;
+    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tiles = tot->tiles2;
+    const uint64_t G = tot->buckets;
+    for (XcdTiles xt(tiles); xt.valid(); xt.advance()) {
+        const uint64_t t = xt.next;
+        const uint64_t g = last_le(G, t, [&](uint64_t j) { return buckets[j].tile_base; });
+        const Bucket B = buckets[g];
+        const Instance &in = inst[B.inst];
+        const uint64_t tl = t - B.tile_base;
+        const uint64_t r0 = B.start + tl * kRefTile;
+        const uint64_t r1 = min(r0 + kRefTile, B.start + B.size);
+        const uint32_t first = B.b * in.fan;
+        for (uint32_t j = tid; j < B.fan; j += blockDim.x) s_cnt[j] = 0;
+        __syncthreads();
+        uint64_t rec[kRefPerThread];
+        uint32_t tag[kRefPerThread];
+#pragma unroll
+        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            const uint64_t r = r0 + (uint64_t)it * blockDim.x + tid;
+            rec[it] = r < r1 ? rec1[r] : 0;
+        }
+#pragma unroll
+        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            const uint64_t r = r0 + (uint64_t)it * blockDim.x + tid;
+            tag[it] = 0xffffffffu;
+            if (r < r1) {
+                const uint32_t c = segment_of(mix64(rec[it] >> 3), in.parts) - first;
+                if (SCATTER) {
+                    tag[it] = (c << 12) | lds_add32(&s_cnt[c], 1u);
+                } else {
+                    __hip_atomic_fetch_add(&s_cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+        __syncthreads();
+        if (!SCATTER) {
+            for (uint32_t j = tid; j < B.fan; j += blockDim.x)
+                hist2[B.hist_base + (uint64_t)j * B.tiles + tl] = s_cnt[j];
+            __syncthreads();
+            continue;
+        }
+        bucket_starts(s_cnt, s_gbase, B.fan,
+                      [&](uint32_t j) { return scan2[B.hist_base + (uint64_t)j * B.tiles + tl]; });
+        __syncthreads();
+#pragma unroll
+        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            if (tag[it] == 0xffffffffu) continue;
+            const uint32_t c = tag[it] >> 12;
+            const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
+            s_rec[pos] = rec[it];
+            s_child[pos] = (uint16_t)c;
+        }
+        __syncthreads();
+        const uint32_t n_in = (uint32_t)(r1 - r0);
+        for (uint32_t j = tid; j < n_in; j += blockDim.x) rec2[s_gbase[s_child[j]] + j] = s_rec[j];
+        __syncthreads();
+    }
+}
+
+// First record of every segment (and the total after the last).
+__global__ void k_part_starts(const Instance *__restrict__ inst, uint32_t m,
+                              const BinPlan *__restrict__ plan, const Bucket *__restrict__ buckets,
+                              const uint64_t *__restrict__ scan2, const BinTotals *__restrict__ tot,
+                              uint64_t *__restrict__ pstart, uint64_t parts_total) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t gp = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < parts_total; gp += stride) {
+        const uint32_t i = (uint32_t)last_le(m, gp, [&](uint64_t j) { return inst[j].part_base; });
+        const Instance &in = inst[i];
+        const uint32_t p = (uint32_t)(gp - in.part_base);
+        const uint32_t b = p / in.fan, c = p - b * in.fan;
+        const Bucket &B = buckets[plan[i].bucket_base + b];
+        pstart[gp] = scan2[B.hist_base + (uint64_t)c * B.tiles];
+        if (gp + 1 == parts_total) pstart[parts_total] = scan2[tot->hist2_len];
+    }
+}
+
+// ---------------------------------------------------------------- reduce
+
+// Sum of v over the block; thread 0 adds it to *dst.  Whole block.
+__device__ void flush_block_sum(uint64_t v, uint64_t *dst, uint64_t *s_sum) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (threadIdx.x == 0) *s_sum = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && v)
+        __hip_atomic_fetch_add(s_sum, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_sum) atomic_add_u64(dst, *s_sum);
+    __syncthreads();
+}
+
+constexpr uint32_t kReducePrefetch = 8;  // records a thread loads before using them
+constexpr uint64_t kNoRecord = ~0ull;     // no record value: keys stay below 2^61
+
+// Find-or-claim one record's vertex in the LDS segment and count its letter.
+// Returns false when the segment has no free slot for it.
+__device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uint32_t *s_cnt,
+                                              uint64_t &claims) {
+    const uint64_t key = rec >> 3;
+    const uint64_t tagv = key | kOccupied;
+    uint32_t s = seg_home(mix64(key));
+    for (uint32_t q = 0; q < kSegSlots; ++q) {
+        const uint64_t cur = lds_load64(&s_key[s]);
+        bool hit = cur == tagv;
+        if (!hit && cur == 0) {
+            uint64_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                ++claims;
+                hit = true;
+            } else {
+                hit = expected == tagv;
+            }
+        }
+        if (hit) {
+            if (!(rec & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec & 3)], 1u);
+            return true;
+        }
+        s = (s + 1) & (kSegSlots - 1);
+    }
+    return false;
+}
+
+// One workgroup per segment: stage it in LDS, find-or-claim and count every
+// record of the segment with LDS atomics, write the segment back, and record
+// how many of its slots are occupied.  Each workgroup takes a contiguous run
+// of segments, so it meets few instances and flushes its claim count once per
+// instance.
+template <uint32_t EW>
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(const Instance *__restrict__ inst, uint32_t m,
+                                                        const uint64_t *__restrict__ pstart,
+                                                        const uint64_t *__restrict__ rec2,
+                                                        InstStatus *st, uint64_t parts_total) {
+    __shared__ uint64_t s_key[kSegSlots];
+    __shared__ __align__(16) uint32_t s_cnt[kSegSlots * 4];
+    __shared__ uint32_t s_skip;
+    __shared__ uint64_t s_sum;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t per_block = (parts_total + gridDim.x - 1) / gridDim.x;
+    const uint64_t gp0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t gp1 = min(gp0 + per_block, parts_total);
+    uint32_t cur_inst = 0xffffffffu;
+    uint64_t my_claims = 0;  // claims of cur_inst by this thread, not yet flushed
+    for (uint64_t gp = gp0; gp < gp1; ++gp) {
+        const uint32_t i = (uint32_t)last_le(m, gp, [&](uint64_t j) { return inst[j].part_base; });
+        if (i != cur_inst) {  // uniform: gp is the same for the whole block
+            if (cur_inst != 0xffffffffu) flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
+            my_claims = 0;
+            cur_inst = i;
+        }
+        const Instance &in = inst[i];
+        if (tid == 0)
+            s_skip = __hip_atomic_load(&st[i].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kSkipMask;
+        __syncthreads();
+        if (s_skip) {  // rejected input: the table is left untouched
+            __syncthreads();
+            continue;
+        }
+        const uint64_t seg_idx = gp - in.part_base;
+        uint64_t *seg = in.table + seg_idx * (uint64_t)kSegSlots * EW;
+        if (in.fresh) {
+            for (uint32_t s = tid; s < kSegSlots; s += blockDim.x) {
+                s_key[s] = 0;
+                reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+            }
+        } else {
+            for (uint32_t w = tid; w < kSegSlots * EW; w += blockDim.x) {
+                const uint32_t s = w / EW, f = w - s * EW;
+                const uint64_t v = seg[w];
+                if (f == 0) {
+                    s_key[s] = v;
+                } else if (f <= 2) {
+                    s_cnt[4 * s + 2 * (f - 1)] = (uint32_t)v;
+                    s_cnt[4 * s + 2 * (f - 1) + 1] = (uint32_t)(v >> 32);
+                }
+            }
+        }
+        __syncthreads();
+        const uint64_t a = pstart[gp], z = pstart[gp + 1];
+        bool full = false;
+        for (uint64_t base = a; base < z; base += (uint64_t)blockDim.x * kReducePrefetch) {
+            uint64_t rv[kReducePrefetch];
+#pragma unroll
+            for (uint32_t c = 0; c < kReducePrefetch; ++c) {
+                const uint64_t r = base + (uint64_t)c * blockDim.x + tid;
+                rv[c] = r < z ? rec2[r] : kNoRecord;
+            }
+#pragma unroll
+            for (uint32_t c = 0; c < kReducePrefetch; ++c)
+                if (rv[c] != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims)) full = true;
+        }
+        if (full) atomic_or_u32(&st[i].err, kErrFull);
+        __syncthreads();
+        uint32_t occupied = 0;
+        for (uint32_t w = tid; w < kSegSlots * EW; w += blockDim.x) {
+            const uint32_t s = w / EW, f = w - s * EW;
+            uint64_t v = 0;
+            if (f == 0) {
+                v = s_key[s];
+                occupied += v != 0;
+            } else if (f <= 2) {
+                v = (uint64_t)s_cnt[4 * s + 2 * (f - 1)] |
+                    ((uint64_t)s_cnt[4 * s + 2 * (f - 1) + 1] << 32);
+            }
+            seg[w] = v;
+        }
+        uint64_t total;
+        block_exclusive_scan(occupied, &total);
+        if (tid == 0 && in.seg_count) in.seg_count[seg_idx] = (uint32_t)total;
+    }
+    if (cur_inst != 0xffffffffu) flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
+}
+
+// ---------------------------------------------------------------- extract
+
+constexpr uint32_t kExtractSegBlock = 256;
+
+// Vertices of segment gp go to [seg_off[gp], seg_off[gp + 1]).  The segment
+// is read with coalesced loads into LDS first.
+template <uint32_t EW>
+__global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t *__restrict__ table,
+                                                                 uint32_t parts,
+                                                                 const uint64_t *__restrict__ seg_off,
+                                                                 uint64_t *__restrict__ okeys,
+                                                                 uint32_t *__restrict__ ocnt,
+                                                                 uint64_t ocap, uint64_t *out_n) {
+    __shared__ __align__(16) uint64_t s_seg[kSegSlots * EW];
+    constexpr uint32_t per = kSegSlots / kExtractSegBlock;  // slots per thread, strided
+    for (uint32_t gp = blockIdx.x; gp < parts; gp += gridDim.x) {
+        const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(table + (uint64_t)gp * kSegSlots * EW);
+        ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(s_seg);
+        for (uint32_t w = threadIdx.x; w < kSegSlots * EW / 2; w += blockDim.x) dst[w] = src[w];
+        __syncthreads();
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < per; ++q) mine += s_seg[(q * kExtractSegBlock + threadIdx.x) * EW] != 0;
+        uint64_t total;
+        uint64_t idx = seg_off[gp] + block_exclusive_scan(mine, &total);
+#pragma unroll
+        for (uint32_t q = 0; q < per; ++q) {
+            const uint64_t *e = s_seg + (q * kExtractSegBlock + threadIdx.x) * EW;
+            if (!e[0]) continue;
+            if (idx < ocap) {
+                okeys[idx] = e[0] & ~kOccupied;
+                const uint64_t c01 = e[1], c23 = e[2];
+                *reinterpret_cast<uint4 *>(ocnt + 4 * idx) =
+                    make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
+            }
+            ++idx;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out_n = seg_off[parts];
+}
+
+__global__ void k_set_len(uint64_t *len, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *len = v;
+}
+
+template <typename K>
+uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint32_t dyn_lds) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)block, dyn_lds) != hipSuccess ||
+        per <= 0)
+        per = 1;
+    uint64_t g = std::min<uint64_t>((uint64_t)cus * per, cap);
+    if (g >= 8) g &= ~7ull;  // whole rounds over the 8 XCDs
+    return (uint32_t)std::max<uint64_t>(1, g);
+}
+
+}  // namespace
+
+hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packed,
+                         const uint64_t *offsets, const uint64_t *ws, uint64_t n_reads,
+                         InstStatus *st, const BinBuffers &bb, uint32_t merge, int device,
+                         hipStream_t s) {
+    (void)merge;
+    (void)n_reads;
+    hipError_t e;
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, inst, m, ws, st, bb.plan, bb.totals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // pass 1
+    const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false), lb1 = bin_lds_bytes(bb.d1_max, true);
+    const uint32_t g1c = occupancy_grid(k_bin<false>, device, kBinBlock, bb.tiles1_cap, lb0);
+    const uint32_t g1s = occupancy_grid(k_bin<true>, device, kBinBlock, bb.tiles1_cap, lb1);
+    hipLaunchKernelGGL((k_bin<false>), dim3(g1c), dim3(kBinBlock), lb0, s, inst, m, packed, offsets, ws,
+                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.d1_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t nb1 = (bb.hist1_cap + kFlatChunk - 1) / kFlatChunk;
+    const uint64_t *len1 = &bb.totals->hist1_len;
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)std::max<uint64_t>(nb1, 1)), dim3(kFlatBlock), 0, s,
+                       bb.hist1, len1, bb.scan1, bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, std::max<uint64_t>(nb1, 1),
+                       len1, bb.scan1);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb1, 1)), dim3(kFlatBlock), 0, s,
+                       len1, bb.scan1, bb.partials);
+    hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, inst, m, packed, offsets, ws,
+                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.d1_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // pass 2
+    hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, inst, m, bb.plan, bb.scan1, bb.totals,
+                       bb.buckets);
+    const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false), lr1 = ref_lds_bytes(bb.fan_max, true);
+    const uint32_t g2c = occupancy_grid(k_refine<false>, device, kRefBlock, bb.tiles2_cap, lr0);
+    const uint32_t g2s = occupancy_grid(k_refine<true>, device, kRefBlock, bb.tiles2_cap, lr1);
+    hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, inst, bb.buckets, bb.totals,
+                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t nb2 = (bb.hist2_cap + kFlatChunk - 1) / kFlatChunk;
+    const uint64_t *len2 = &bb.totals->hist2_len;
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)std::max<uint64_t>(nb2, 1)), dim3(kFlatBlock), 0, s,
+                       bb.hist2, len2, bb.scan2, bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, std::max<uint64_t>(nb2, 1),
+                       len2, bb.scan2);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb2, 1)), dim3(kFlatBlock), 0, s,
+                       len2, bb.scan2, bb.partials);
+    hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, inst, bb.buckets, bb.totals,
+                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // segment starts and the reduction
+    const uint64_t P = bb.parts_total;
+    const uint32_t gs = (uint32_t)std::min<uint64_t>((P + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, inst, m, bb.plan, bb.buckets, bb.scan2,
+                       bb.totals, bb.pstart, P);
+    // every instance of a binned launch has the same entry width
+    if (bb.entry_words == 4) {
+        const uint32_t gr = occupancy_grid(k_reduce<4>, device, kReduceBlock, P, 0);
+        hipLaunchKernelGGL((k_reduce<4>), dim3(gr), dim3(kReduceBlock), 0, s, inst, m, bb.pstart, bb.rec2,
+                           st, P);
+    } else {
+        const uint32_t gr = occupancy_grid(k_reduce<3>, device, kReduceBlock, P, 0);
+        hipLaunchKernelGGL((k_reduce<3>), dim3(gr), dim3(kReduceBlock), 0, s, inst, m, bb.pstart, bb.rec2,
+                           st, P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t parts,
+                                 const uint32_t *seg_count, uint64_t *seg_off, uint64_t *partials,
+                                 uint64_t *len, uint64_t *out_keys, uint32_t *out_counts,
+                                 uint64_t out_cap, uint64_t *out_n, int device, hipStream_t s) {
+    const uint64_t nb = std::max<uint64_t>((parts + kFlatChunk - 1) / kFlatChunk, 1);
+    hipLaunchKernelGGL(k_set_len, dim3(1), dim3(64), 0, s, len, (uint64_t)parts);
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb), dim3(kFlatBlock), 0, s, seg_count, len, seg_off,
+                       partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, partials, nb, len, seg_off);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb), dim3(kFlatBlock), 0, s, len, seg_off, partials);
+    if (entry_words == 4) {
+        const uint32_t g = occupancy_grid(k_extract_seg<4>, device, kExtractSegBlock, parts, 0);
+        hipLaunchKernelGGL((k_extract_seg<4>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
+                           out_keys, out_counts, out_cap, out_n);
+    } else {
+        const uint32_t g = occupancy_grid(k_extract_seg<3>, device, kExtractSegBlock, parts, 0);
+        hipLaunchKernelGGL((k_extract_seg<3>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
+                           out_keys, out_counts, out_cap, out_n);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dbgk

@@ -1,0 +1,102 @@
+// Device helpers shared by the kernels of libdbg (internal header).
+#pragma once
+
+#include "dbg_kernels.h"
+
+namespace dbgk {
+
+
+constexpr uint64_t kAllOnes = ~0ull;
+
+// SplitMix64 output function (Steele, Lea, Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014): a bijective 64-bit mixer.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return z;
+}
+
+// Home slot in [0, cap): high 64 bits of h * cap (Lemire's multiply-shift
+// range reduction, "Fast random integer generation in an interval", 2019).
+__device__ __forceinline__ uint64_t home_slot(uint64_t h, uint64_t cap) {
+    return __umul64hi(h, cap);
+}
+
+__device__ __forceinline__ bool valid_letter(uint32_t c) {
+    const uint32_t lc = c | 0x20u;
+    return lc == 'a' || lc == 'c' || lc == 'g' || lc == 't';
+}
+
+__device__ __forceinline__ uint32_t atomic_or_u32(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_add_u64(uint64_t *p, uint64_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Instance owning a global read index: the last i with read_begin <= r.
+__device__ __forceinline__ uint32_t instance_of_read(const Instance *inst, uint32_t m, uint64_t r) {
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (inst[mid].read_begin <= r) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t instance_of_byte(const Instance *inst, uint32_t m, uint64_t b) {
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (inst[mid].byte_begin <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The 32 bases starting at base position p, first base in bits 63..62.
+__device__ __forceinline__ uint64_t bases_at(const uint64_t *__restrict__ packed, uint64_t p) {
+    const uint64_t wi = p >> 5;
+    const uint32_t sh = (uint32_t)(p & 31) * 2;
+    const uint64_t hi = packed[wi];
+    if (sh == 0) return hi;
+    const uint64_t lo = packed[wi + 1];
+    return (hi << sh) | (lo >> (64 - sh));
+}
+
+__device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t v) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim <= 1024).
+// Returns the exclusive prefix; *total receives the block sum.
+__device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t *total) {
+    __shared__ uint64_t s_wave[16];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t nwaves = (blockDim.x + 63) >> 6;
+    const uint64_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        uint64_t x = lane < nwaves ? s_wave[lane] : 0;
+        x = wave_inclusive_scan(x);
+        if (lane < nwaves) s_wave[lane] = x;
+    }
+    __syncthreads();
+    const uint64_t before = wave ? s_wave[wave - 1] : 0;
+    *total = s_wave[nwaves - 1];
+    __syncthreads();
+    return before + inc - v;
+}
+
+
+}  // namespace dbgk

@@ -44,9 +44,16 @@ struct Instance {
     uint64_t byte_begin;    // first byte of its reads, relative to the first read
     uint64_t byte_end;      // (both filled on the device from the offsets)
     uint64_t prior_inserts; // k-mers already counted into the table
+    uint64_t part_base;     // binned: global index of its first table segment
+    uint32_t *seg_count;    // binned: occupied slots per segment (written by the build)
+    uint64_t fan_magic;     // binned: ceil(2^64 / fan) for fan > 1 (division by multiply-high)
     uint32_t k;
     uint32_t entry_words;
     uint32_t skip;          // nonzero: the host left this instance out
+    uint32_t parts;         // binned: table segments (cap / kSegSlots)
+    uint32_t d1;            // binned: level-1 buckets
+    uint32_t fan;           // binned: segments per level-1 bucket (the last may have fewer)
+    uint32_t fresh;         // binned: the table is logically empty; segments are not read
     uint32_t pad;
 };
 
@@ -71,6 +78,62 @@ struct BuildShape {
     uint32_t merge;     // wavefront merge of equal vertices
 };
 
+// Binned build: the table of an instance is cut into segments of kSegSlots
+// slots.  The records of all windows ((k-1)-mer << 3 | sink << 2 | letter)
+// are partitioned by segment in two levels (d1 buckets, each split into at
+// most `fan` segments), and one workgroup then owns each segment: it stages
+// the segment in LDS, claims and counts there, and writes it back.
+constexpr uint32_t kSegSlots = 2048;
+constexpr uint32_t kMaxD1 = 1024;     // level-1 buckets per instance, at most
+constexpr uint32_t kMaxFan = 2048;    // segments per level-1 bucket, at most
+constexpr uint32_t kBinBlock = 512;
+constexpr uint32_t kBinPerThread = 8;
+constexpr uint32_t kBinTile = kBinBlock * kBinPerThread;  // windows per pass-1 tile
+constexpr uint32_t kRefBlock = 512;
+constexpr uint32_t kRefPerThread = 8;
+constexpr uint32_t kRefTile = kRefBlock * kRefPerThread;  // records per pass-2 tile
+constexpr uint32_t kReduceBlock = 512;
+
+struct BinPlan {        // per instance
+    uint64_t w_begin, w_end;  // its windows
+    uint64_t tiles;           // pass-1 tiles
+    uint64_t tile_base;       // first pass-1 tile
+    uint64_t hist_base;       // first pass-1 histogram entry
+    uint64_t bucket_base;     // first level-1 bucket
+};
+
+struct Bucket {         // per level-1 bucket
+    uint64_t start, size;     // record range in the level-1 output
+    uint64_t tiles;           // pass-2 tiles
+    uint64_t tile_base;       // first pass-2 tile
+    uint64_t hist_base;       // first pass-2 histogram entry
+    uint32_t inst;            // owning instance
+    uint32_t b;               // bucket index within the instance
+    uint32_t fan;             // segments in this bucket
+    uint32_t pad;
+};
+
+struct BinTotals {
+    uint64_t tiles1, hist1_len, buckets, tiles2, hist2_len, records;
+};
+
+struct BinBuffers {     // device scratch of one binned pass
+    BinPlan *plan;            // m
+    Bucket *buckets;          // sum of d1
+    BinTotals *totals;
+    uint32_t *hist1;          // hist1_cap
+    uint64_t *scan1;          // hist1_cap + 1
+    uint32_t *hist2;          // hist2_cap
+    uint64_t *scan2;          // hist2_cap + 1
+    uint64_t *partials;       // for the flat scans
+    uint64_t *rec1, *rec2;    // records, windows_cap each
+    uint64_t *pstart;         // parts_total + 1
+    uint64_t hist1_cap, hist2_cap, partials_cap;
+    uint64_t tiles1_cap, tiles2_cap, buckets_total, parts_total;
+    uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)
+    uint32_t entry_words;      // of every instance in the launch
+};
+
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanPerThread = 4;
 constexpr uint32_t kScanReads = kScanBlock * kScanPerThread;  // reads per scan block
@@ -86,10 +149,12 @@ hipError_t launch_prepare(Instance *inst, uint32_t m, InstStatus *st, CallState 
 hipError_t launch_fill_zero(uint64_t *words, uint64_t n_words, hipStream_t s);
 hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bytes, uint64_t *packed,
                        const Instance *inst, uint32_t m, InstStatus *st, hipStream_t s);
+// tile_read may be null (no tile map); max_windows bounds the total window
+// count (valid offsets give at most one window per byte).
 hipError_t launch_scan(const uint64_t *offsets, uint64_t n_reads, uint64_t reads_len,
                        bool check_ends, const Instance *inst, uint32_t m, InstStatus *st,
                        uint64_t *ws, uint64_t *partials, uint64_t *tile_read, uint64_t tile_cap,
-                       uint32_t tile, CallState *cs, hipStream_t s);
+                       uint32_t tile, uint64_t max_windows, CallState *cs, hipStream_t s);
 hipError_t launch_build(const Instance *inst, uint32_t m, const uint64_t *packed,
                         const uint64_t *offsets, const uint64_t *ws, const uint64_t *tile_read,
                         uint64_t n_reads, InstStatus *st, CallState *cs, BuildShape shape,
@@ -101,6 +166,21 @@ hipError_t launch_count(const uint64_t *table, uint32_t entry_words, uint64_t ca
                         uint64_t *out_n, hipStream_t s);
 hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32_t kind,
                            uint64_t seed, uint32_t block, uint64_t *sink, hipStream_t s);
+
+hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packed,
+                         const uint64_t *offsets, const uint64_t *ws, uint64_t n_reads,
+                         InstStatus *st, const BinBuffers &bb, uint32_t merge, int device,
+                         hipStream_t s);
+
+// Extraction of a binned table: seg_count (parts entries) is scanned into
+// seg_off (parts + 1 entries, using `partials` of ceil(parts / 1024) + 1
+// entries and a device word `len` that the call fills with parts), then each
+// segment writes its vertices at its offset (segment order; unspecified
+// order within a segment).  *out_n receives the total on the device.
+hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t parts,
+                                 const uint32_t *seg_count, uint64_t *seg_off, uint64_t *partials,
+                                 uint64_t *len, uint64_t *out_keys, uint32_t *out_counts,
+                                 uint64_t out_cap, uint64_t *out_n, int device, hipStream_t s);
 
 // Occupancy-derived persistent grid for the build kernel.
 uint32_t build_grid(int device, uint32_t block);

@@ -19,64 +19,12 @@
 //   * the out-edge pointers are not stored: the target of (v, c) is
 //     (v << 2 | c) masked to 2(k-1) bits;
 //   * counters are uint32, not uint8 (255 is exceeded by repeat-rich inputs).
-#include "dbg_kernels.h"
+#include "dbg_device.h"
 
 #include <algorithm>
 
 namespace dbgk {
 namespace {
-
-constexpr uint64_t kAllOnes = ~0ull;
-
-// SplitMix64 output function (Steele, Lea, Flood, "Fast splittable
-// pseudorandom number generators", OOPSLA 2014): a bijective 64-bit mixer.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    z ^= z >> 30;
-    z *= 0xbf58476d1ce4e5b9ull;
-    z ^= z >> 27;
-    z *= 0x94d049bb133111ebull;
-    z ^= z >> 31;
-    return z;
-}
-
-// Home slot in [0, cap): high 64 bits of h * cap (Lemire's multiply-shift
-// range reduction, "Fast random integer generation in an interval", 2019).
-__device__ __forceinline__ uint64_t home_slot(uint64_t h, uint64_t cap) {
-    return __umul64hi(h, cap);
-}
-
-__device__ __forceinline__ bool valid_letter(uint32_t c) {
-    const uint32_t lc = c | 0x20u;
-    return lc == 'a' || lc == 'c' || lc == 'g' || lc == 't';
-}
-
-__device__ __forceinline__ uint32_t atomic_or_u32(uint32_t *p, uint32_t v) {
-    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void atomic_add_u64(uint64_t *p, uint64_t v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Instance owning a global read index: the last i with read_begin <= r.
-__device__ __forceinline__ uint32_t instance_of_read(const Instance *inst, uint32_t m, uint64_t r) {
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (inst[mid].read_begin <= r) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ uint32_t instance_of_byte(const Instance *inst, uint32_t m, uint64_t b) {
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (inst[mid].byte_begin <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------- prepare
 
 __global__ void k_prepare(Instance *inst, uint32_t m, InstStatus *st, CallState *cs,
@@ -155,37 +103,6 @@ __global__ __launch_bounds__(256) void k_pack(const uint8_t *__restrict__ ascii,
 }
 
 // ---------------------------------------------------------------- scan
-
-__device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t v) {
-    const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t o = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += o;
-    }
-    return v;
-}
-
-// Block-wide exclusive scan of one value per thread (blockDim <= 1024).
-// Returns the exclusive prefix; *total receives the block sum.
-__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *total) {
-    __shared__ uint64_t s_wave[16];
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t nwaves = (blockDim.x + 63) >> 6;
-    const uint64_t inc = wave_inclusive_scan(v);
-    if (lane == 63) s_wave[wave] = inc;
-    __syncthreads();
-    if (wave == 0) {
-        uint64_t x = lane < nwaves ? s_wave[lane] : 0;
-        x = wave_inclusive_scan(x);
-        if (lane < nwaves) s_wave[lane] = x;
-    }
-    __syncthreads();
-    const uint64_t before = wave ? s_wave[wave - 1] : 0;
-    *total = s_wave[nwaves - 1];
-    __syncthreads();
-    return before + inc - v;
-}
 
 // Windows and k-mers of one read.  A read with bad offsets has none (the
 // instance is flagged and the build skips it).
@@ -320,8 +237,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(
         ws[r] = s;
         if (r + 1 == n) ws[n] = s + rc.windows;
         // tiles whose first window falls inside this read start here
-        for (uint64_t tt = (s + tile - 1) / tile; tt * tile < s + rc.windows && tt < tile_cap; ++tt)
-            tile_read[tt] = r;
+        if (tile_read)
+            for (uint64_t tt = (s + tile - 1) / tile; tt * tile < s + rc.windows && tt < tile_cap; ++tt)
+                tile_read[tt] = r;
     }
 }
 
@@ -372,16 +290,6 @@ __device__ __forceinline__ void add_count(uint64_t *table, uint32_t ew, uint64_t
                                           uint32_t inc) {
     uint32_t *cnt = reinterpret_cast<uint32_t *>(table + s * ew + 1);
     __hip_atomic_fetch_add(cnt + letter, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The 32 bases starting at base position p, first base in bits 63..62.
-__device__ __forceinline__ uint64_t bases_at(const uint64_t *__restrict__ packed, uint64_t p) {
-    const uint64_t wi = p >> 5;
-    const uint32_t sh = (uint32_t)(p & 31) * 2;
-    const uint64_t hi = packed[wi];
-    if (sh == 0) return hi;
-    const uint64_t lo = packed[wi + 1];
-    return (hi << sh) | (lo >> (64 - sh));
 }
 
 constexpr uint32_t kMergeSlots = 128;
@@ -756,15 +664,15 @@ hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bytes, uint64_t *packed,
 hipError_t launch_scan(const uint64_t *offsets, uint64_t n_reads, uint64_t reads_len, bool check_ends,
                        const Instance *inst, uint32_t m, InstStatus *st, uint64_t *ws,
                        uint64_t *partials, uint64_t *tile_read, uint64_t tile_cap, uint32_t tile,
-                       CallState *cs, hipStream_t s) {
+                       uint64_t max_windows, CallState *cs, hipStream_t s) {
     if (n_reads == 0) return hipSuccess;
     const uint64_t nb = scan_blocks(n_reads);
     hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, offsets, n_reads,
                        reads_len, check_ends ? 1 : 0, inst, m, st, ws, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb, cs,
-                       (tile_cap - 1) * (uint64_t)tile, st, m);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb, cs, max_windows,
+                       st, m);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, offsets, n_reads,

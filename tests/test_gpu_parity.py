@@ -72,8 +72,13 @@ def test_worked_example(worked_example):
 
 # ---------------------------------------------------------------- configuration 1
 
+MODES = [0, dbg.F_BINNED]
+MODE_IDS = ["direct", "binned"]
+
 SHAPES = [
     dict(),
+    dict(flags=dbg.F_BINNED),
+    dict(flags=dbg.F_BINNED | dbg.F_ENTRY32),
     dict(block_size=64, windows_per_thread=1),
     dict(block_size=1024, windows_per_thread=2),
     dict(block_size=256, windows_per_thread=16),
@@ -97,10 +102,11 @@ def test_config1_launch_shapes(config1, shape):
     assert_same(gpu_build(rs, **shape), want, "config1 %r" % shape)
 
 
-def test_config1_device_build(config1):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_config1_device_build(config1, mode):
     rs, want = config1
-    say("config1 device build")
-    assert_same(gpu_build_device(rs), want, "config1 device")
+    say("config1 device build mode %d" % mode)
+    assert_same(gpu_build_device(rs, flags=mode), want, "config1 device")
 
 
 @pytest.mark.parametrize("lf", [0.3, 0.7, 0.95])
@@ -109,6 +115,8 @@ def test_config1_load_factors(config1, lf):
     say("config1 load factor %.2f" % lf)
     V = want[0].shape[0]
     assert_same(gpu_build(rs, capacity=int(V / lf) + 1), want, "lf %.2f" % lf)
+    if lf <= 0.7:  # a binned table fails when one 2048-slot segment overflows
+        assert_same(gpu_build(rs, capacity=int(V / lf) + 1, flags=dbg.F_BINNED), want, "binned lf %.2f" % lf)
 
 
 def test_config1_stats_and_timing(config1):
@@ -129,6 +137,33 @@ def test_repeated_runs_identical(config1):
     V = want[0].shape[0]
     for _ in range(3):
         assert_same(gpu_build(rs, capacity=V + V // 16), want, "repeat")
+        assert_same(gpu_build(rs, capacity=int(V / 0.7), flags=dbg.F_BINNED), want, "repeat binned")
+
+
+def test_binned_reset_does_not_leak_old_contents(config1):
+    rs, want = config1
+    say("binned: lazy reset between two different builds")
+    other = readsim.make_config(2, scale=0.002)
+    other.k = rs.k
+    with dbg.Graph(flags=dbg.F_BINNED, expected_vertices=60000) as g:
+        g.build(other.reads, other.offsets, rs.k)
+        g.reset()
+        assert g.vertex_count() == 0
+        g.build(rs.reads, rs.offsets, rs.k)
+        got = g.extract_sorted()
+    assert_same(got, want, "after reset")
+
+
+def test_binned_k32_falls_back_to_direct():
+    say("binned graph with k=32")
+    rng = np.random.default_rng(32)
+    reads = ["".join(rng.choice(list("ACGT"), size=120)) for _ in range(500)]
+    rs = readsim.reads_from_strings(reads, 32)
+    want = oracle_of(rs)
+    with dbg.Graph(flags=dbg.F_BINNED) as g:
+        g.build(rs.reads, rs.offsets, 32)
+        got = g.extract_sorted()
+    assert_same(got, want, "k=32 binned graph")
 
 
 # ---------------------------------------------------------------- edge cases
@@ -161,6 +196,7 @@ def test_ragged_reads_all_k(k):
     assert_same(gpu_build(rs), want, "ragged k=%d" % k)
     assert_same(gpu_build(rs, flags=dbg.F_MERGE, block_size=128, windows_per_thread=3), want,
                 "ragged merged k=%d" % k)
+    assert_same(gpu_build(rs, flags=dbg.F_BINNED), want, "ragged binned k=%d" % k)
 
 
 def test_offsets_not_starting_at_zero():
@@ -174,6 +210,10 @@ def test_offsets_not_starting_at_zero():
         g.build(reads, offsets, rs.k)
         got = g.extract_sorted()
     assert_same(got, want, "host offsets with a base")
+    with dbg.Graph(flags=dbg.F_BINNED) as g:
+        g.build(reads, offsets, rs.k)
+        got = g.extract_sorted()
+    assert_same(got, want, "binned host offsets with a base")
     # device slice of a larger concatenation
     d_reads = torch.from_numpy(reads[pad:]).cuda()
     d_off = torch.from_numpy(offsets.astype(np.int64)).cuda()
@@ -193,16 +233,18 @@ def test_hot_key_poly_a_and_tandem_repeats():
     assert_same(gpu_build(rs, flags=dbg.F_MERGE), want, "hot keys merged")
     assert_same(gpu_build(rs, flags=dbg.F_MERGE, block_size=64, windows_per_thread=1), want,
                 "hot keys merged wave64")
+    assert_same(gpu_build(rs, flags=dbg.F_BINNED), want, "hot keys binned")
     assert int(want[1].max()) == 5000 * 120
 
 
-def test_incremental_builds_accumulate(config1):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_incremental_builds_accumulate(config1, mode):
     rs, want = config1
-    say("incremental: two halves")
+    say("incremental: two halves, mode %d" % mode)
     h = rs.n_reads // 2
     a = readsim.reads_from_strings([rs.read(i) for i in range(h)], rs.k)
     b = readsim.reads_from_strings([rs.read(i) for i in range(h, rs.n_reads)], rs.k)
-    with dbg.Graph(expected_vertices=20000) as g:
+    with dbg.Graph(expected_vertices=20000, flags=mode) as g:
         g.build(a.reads, a.offsets, rs.k)
         g.build(b.reads, b.offsets, rs.k)
         got = g.extract_sorted()
@@ -210,10 +252,11 @@ def test_incremental_builds_accumulate(config1):
     assert_same(got, want, "two halves")
 
 
-def test_full_table_is_reported_and_poisons():
-    say("undersized table -> FULL")
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_full_table_is_reported_and_poisons(mode):
+    say("undersized table -> FULL, mode %d" % mode)
     rs = readsim.make_config(1)
-    with dbg.Graph(capacity=1000) as g:
+    with dbg.Graph(capacity=1000, flags=mode) as g:
         with pytest.raises(dbg.DbgError) as e:
             g.build(rs.reads, rs.offsets, rs.k)
         assert e.value.code == dbg.E_FULL
@@ -222,17 +265,18 @@ def test_full_table_is_reported_and_poisons():
             g.build(rs.reads, rs.offsets, rs.k)
         assert e.value.code == dbg.E_STATE
         keys, counts = g.extract()  # partial graph is still readable
-        assert keys.shape[0] <= 1000
+        assert keys.shape[0] <= g.stats()["capacity"]
         g.reset()
         g.build(readsim.reads_from_strings(["ACGTACGT"], 5).reads,
                 readsim.reads_from_strings(["ACGTACGT"], 5).offsets, 5)
         assert g.vertex_count() == 4
 
 
-def test_rejected_inputs_modify_nothing(config1):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_rejected_inputs_modify_nothing(config1, mode):
     rs, want = config1
-    say("bad base / bad k / bad offsets leave the graph unchanged")
-    with dbg.Graph(expected_vertices=20000) as g:
+    say("bad base / bad k / bad offsets leave the graph unchanged, mode %d" % mode)
+    with dbg.Graph(expected_vertices=20000, flags=mode) as g:
         g.build(rs.reads, rs.offsets, rs.k)
         bad = readsim.reads_from_strings(["ACGTACGTACGTACGTACGTACGTACGTNACGT"] * 10, rs.k)
         with pytest.raises(dbg.DbgError) as e:
@@ -266,11 +310,12 @@ def test_rejected_inputs_modify_nothing(config1):
     assert_same(got, want, "after rejected inputs")
 
 
-def test_extract_space_and_device_extract(config1):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_extract_space_and_device_extract(config1, mode):
     rs, want = config1
-    say("extract: too small buffer, device buffers")
+    say("extract: too small buffer, device buffers, mode %d" % mode)
     import ctypes
-    with dbg.Graph() as g:
+    with dbg.Graph(flags=mode) as g:
         g.build(rs.reads, rs.offsets, rs.k)
         V = g.vertex_count()
         keys = np.empty(V - 1, np.uint64)
@@ -297,12 +342,15 @@ def test_config2_scaled():
     want = oracle_of(rs)
     assert_same(gpu_build(rs, expected_vertices=rs.meta["expected_vertices"]), want, "config2 5%")
     assert_same(gpu_build(rs, flags=dbg.F_MERGE), want, "config2 5% merged")
+    assert_same(gpu_build(rs, flags=dbg.F_BINNED, expected_vertices=rs.meta["expected_vertices"]), want,
+                "config2 5% binned")
 
 
 # ---------------------------------------------------------------- batched
 
-def test_batch_matches_per_instance_oracle():
-    say("batched build of 12 small instances + failures")
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_batch_matches_per_instance_oracle(mode):
+    say("batched build of 12 small instances + failures, mode %d" % mode)
     sets = []
     for j in range(40):
         p = readsim.instance_params(4, j)
@@ -312,7 +360,7 @@ def test_batch_matches_per_instance_oracle():
             break
     assert len(sets) >= 6
     bad = readsim.reads_from_strings(["ACGTNNACGT" * 5], 21)
-    graphs = [dbg.Graph() for _ in range(len(sets) + 1)]
+    graphs = [dbg.Graph(flags=mode) for _ in range(len(sets) + 1)]
     inputs = [(rs.reads, rs.offsets, rs.k) for rs in sets] + [(bad.reads, bad.offsets, 21)]
     try:
         st = dbg.build_batch(graphs, inputs)
@@ -333,8 +381,9 @@ def test_batch_matches_per_instance_oracle():
             g.close()
 
 
-def test_batch_device_matches_plain_device():
-    say("batched device build vs plain device builds on slices")
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_batch_device_matches_plain_device(mode):
+    say("batched device build vs plain device builds on slices, mode %d" % mode)
     sets = [readsim.make_instance(4, j) for j in range(6)]
     sets = [s for s in sets if s.total_bases < 40_000_000]
     reads = np.concatenate([s.reads for s in sets])
@@ -346,14 +395,14 @@ def test_batch_device_matches_plain_device():
     ks = [s.k for s in sets]
     d_reads = torch.from_numpy(reads).cuda()
     d_off = torch.from_numpy(offs).cuda()
-    graphs = [dbg.Graph() for _ in sets]
+    graphs = [dbg.Graph(flags=mode) for _ in sets]
     try:
         st = dbg.build_batch_device(graphs, rb, ks, d_reads, d_off)
         assert st == [0] * len(sets)
         for i, (s, g) in enumerate(zip(sets, graphs)):
             got = g.extract_sorted()
             b0, b1 = int(offs[rb[i]]), int(offs[rb[i + 1]])
-            with dbg.Graph() as p:
+            with dbg.Graph(flags=mode) as p:
                 p.build_device(d_reads[b0:b1], d_off[int(rb[i]):int(rb[i + 1]) + 1], s.k)
                 p.sync()
                 plain = p.extract_sorted()
