@@ -132,6 +132,7 @@ struct Pass {
     DevBuf packed, ws, partials, tiles, dinst, dstatus;
     // binned-mode scratch
     DevBuf bplan, bbuckets, btotals, hist1, scan1, hist2, scan2, bpartials, rec1, rec2, pstart;
+    DevBuf tread1, tbucket2;
     HostBuf hinst, hstatus;
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
     uint32_t m = 0;
@@ -147,7 +148,8 @@ struct Pass {
     }
     void release() {
         DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dinst, &dstatus, &bplan, &bbuckets,
-                       &btotals, &hist1, &scan1, &hist2, &scan2, &bpartials, &rec1, &rec2, &pstart};
+                       &btotals, &hist1, &scan1, &hist2, &scan2, &bpartials, &rec1, &rec2, &pstart,
+                       &tread1, &tbucket2};
         for (DevBuf *b : d) b->release();
         hinst.release();
         hstatus.release();
@@ -199,8 +201,12 @@ struct Pass {
             (e = scan2.reserve(8 * (bb.hist2_cap + 1))) != hipSuccess ||
             (e = bpartials.reserve(8 * bb.partials_cap)) != hipSuccess ||
             (e = rec1.reserve(8 * recs)) != hipSuccess || (e = rec2.reserve(8 * recs)) != hipSuccess ||
-            (e = pstart.reserve(8 * (P + 1))) != hipSuccess)
+            (e = pstart.reserve(8 * (P + 1))) != hipSuccess ||
+            (e = tread1.reserve(8 * bb.tiles1_cap)) != hipSuccess ||
+            (e = tbucket2.reserve(4 * bb.tiles2_cap)) != hipSuccess)
             return e;
+        bb.tile_read1 = tread1.as<uint64_t>();
+        bb.tile_bucket2 = tbucket2.as<uint32_t>();
         bb.plan = bplan.as<dbgk::BinPlan>();
         bb.buckets = bbuckets.as<dbgk::Bucket>();
         bb.totals = btotals.as<dbgk::BinTotals>();

@@ -105,21 +105,15 @@ struct ReadStage {
     uint32_t R;
 };
 
-// Stage the reads from the one holding window w0 on.  Requires
-// ws[rb] <= w0 < ws[re].  Contains barriers: call from the whole block.
+// Stage the reads from r0 (the read holding the tile's first window) on,
+// up to re.  Contains barriers: call from the whole block.
 __device__ void stage_reads(ReadStage &S, const uint64_t *ws, const uint64_t *off, uint64_t off0,
-                            uint64_t rb, uint64_t re, uint64_t w0) {
+                            uint64_t r0, uint64_t re) {
     if (threadIdx.x == 0) {
-        uint64_t lo = rb, hi = re;  // ws[lo] <= w0 < ws[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (ws[mid] <= w0) lo = mid; else hi = mid;
-        }
-        S.r0 = lo;
-        S.R = (uint32_t)min<uint64_t>(kMapReads, re - lo);
+        S.r0 = r0;
+        S.R = (uint32_t)min<uint64_t>(kMapReads, re - r0);
     }
     __syncthreads();
-    const uint64_t r0 = S.r0;
     const uint32_t R = S.R;
     for (uint32_t i = threadIdx.x; i <= R; i += blockDim.x) {
         const uint64_t r = r0 + i;
@@ -267,6 +261,24 @@ __global__ void k_bin_plan(const Instance *inst, uint32_t m, const uint64_t *ws,
     tot->records = 0;
 }
 
+// First read of every pass-1 tile: read r writes the tiles whose first
+// window falls among its windows.
+__global__ void k_tile_reads(const Instance *__restrict__ inst, uint32_t m, const uint64_t *__restrict__ ws,
+                             uint64_t n, const BinPlan *__restrict__ plan, uint64_t *__restrict__ tile_read1,
+                             uint64_t tiles_cap) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const uint64_t a = ws[r], z = ws[r + 1];
+        if (z == a) continue;
+        const uint32_t i = m == 1 ? 0u : instance_of_read(inst, m, r);
+        const BinPlan pl = plan[i];
+        if (!pl.tiles) continue;  // instance not built in this launch
+        uint64_t tl = (a - pl.w_begin + kBinTile - 1) / kBinTile;
+        for (; pl.w_begin + tl * kBinTile < z; ++tl)
+            if (pl.tile_base + tl < tiles_cap) tile_read1[pl.tile_base + tl] = r;
+    }
+}
+
 // ---------------------------------------------------------------- pass 1
 
 // Dynamic LDS of the pass-1 kernels: s_cnt[d1_max] (+ s_gbase[d1_max],
@@ -289,7 +301,9 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const Instance *__restrict__ 
                                                   const BinTotals *__restrict__ tot,
                                                   uint32_t *__restrict__ hist1,
                                                   const uint64_t *__restrict__ scan1,
-                                                  uint64_t *__restrict__ rec1, uint32_t d1_max) {
+                                                  uint64_t *__restrict__ rec1,
+                                                  const uint64_t *__restrict__ tile_read1,
+                                                  uint32_t d1_max) {
     __shared__ ReadStage S;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
@@ -311,7 +325,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const Instance *__restrict__ 
         const uint64_t magic = in.fan_magic;
         const uint32_t kshift = 64 - 2 * (in.k - 1), lshift = 62 - 2 * (in.k - 1);
         for (uint32_t j = tid; j < d1; j += blockDim.x) s_cnt[j] = 0;
-        stage_reads(S, ws, off, off0, in.read_begin, in.read_end, w0);
+        stage_reads(S, ws, off, off0, tile_read1[t], in.read_end);
 
         uint64_t rec[kBinPerThread];
         uint32_t tag[kBinPerThread];  // bucket << 12 | rank within the bucket
@@ -491,7 +505,9 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict
                                                      const uint64_t *__restrict__ rec1,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
-                                                     uint64_t *__restrict__ rec2, uint32_t fan_max) {
+                                                     uint64_t *__restrict__ rec2,
+                                                     const uint32_t *__restrict__ tile_bucket2,
+                                                     uint32_t fan_max) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * fan_max));
@@ -499,11 +515,9 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict
     uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);
     const uint32_t tid = threadIdx.x;
     const uint64_t tiles = tot->tiles2;
-    const uint64_t G = tot->buckets;
     for (XcdTiles xt(tiles); xt.valid(); xt.advance()) {
         const uint64_t t = xt.next;
-        const uint64_t g = last_le(G, t, [&](uint64_t j) { return buckets[j].tile_base; });
-        const Bucket B = buckets[g];
+        const Bucket B = buckets[tile_bucket2[t]];
         const Instance &in = inst[B.inst];
         const uint64_t tl = t - B.tile_base;
         const uint64_t r0 = B.start + tl * kRefTile;
@@ -553,6 +567,18 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict
         const uint32_t n_in = (uint32_t)(r1 - r0);
         for (uint32_t j = tid; j < n_in; j += blockDim.x) rec2[s_gbase[s_child[j]] + j] = s_rec[j];
         __syncthreads();
+    }
+}
+
+// Level-1 bucket of every pass-2 tile.
+__global__ void k_tile_buckets(const Bucket *__restrict__ buckets, const BinTotals *__restrict__ tot,
+                               uint32_t *__restrict__ tile_bucket2, uint64_t tiles_cap) {
+    const uint64_t G = tot->buckets;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += stride) {
+        const Bucket B = buckets[g];
+        for (uint64_t t = B.tile_base; t < B.tile_base + B.tiles && t < tiles_cap; ++t)
+            tile_bucket2[t] = (uint32_t)g;
     }
 }
 
@@ -619,26 +645,36 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
     return false;
 }
 
-// One workgroup per segment: stage it in LDS, find-or-claim and count every
-// record of the segment with LDS atomics, write the segment back, and record
-// how many of its slots are occupied.  Each workgroup takes a contiguous run
-// of segments, so it meets few instances and flushes its claim count once per
-// instance.
+// One workgroup per segment.  The segment's hash slots live in LDS only: the
+// vertices the table already holds (packed at entries [0, seg_count)) are
+// re-inserted, every record of the segment is found-or-claimed and counted
+// with LDS atomics, and the occupied slots are written back packed, with the
+// new seg_count.  Each workgroup takes a contiguous run of segments, so it
+// meets few instances and flushes its claim count once per instance.
 template <uint32_t EW>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const Instance *__restrict__ inst, uint32_t m,
                                                         const uint64_t *__restrict__ pstart,
                                                         const uint64_t *__restrict__ rec2,
                                                         InstStatus *st, uint64_t parts_total) {
+    static_assert(kSegSlots % kReduceBlock == 0 && kReduceBlock % 64 == 0, "slot ranges per wavefront");
+    constexpr uint32_t kWaves = kReduceBlock / 64;
+    constexpr uint32_t kWaveSlots = kSegSlots / kWaves;  // slots compacted by one wavefront
     __shared__ uint64_t s_key[kSegSlots];
     __shared__ __align__(16) uint32_t s_cnt[kSegSlots * 4];
+    __shared__ uint32_t s_wave_n[kWaves];
     __shared__ uint32_t s_skip;
     __shared__ uint64_t s_sum;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t per_block = (parts_total + gridDim.x - 1) / gridDim.x;
     const uint64_t gp0 = (uint64_t)blockIdx.x * per_block;
     const uint64_t gp1 = min(gp0 + per_block, parts_total);
     uint32_t cur_inst = 0xffffffffu;
     uint64_t my_claims = 0;  // claims of cur_inst by this thread, not yet flushed
+    // LDS starts zeroed and every write-back leaves it zeroed again
+    for (uint32_t s = tid; s < kSegSlots; s += blockDim.x) {
+        s_key[s] = 0;
+        reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+    }
     for (uint64_t gp = gp0; gp < gp1; ++gp) {
         const uint32_t i = (uint32_t)last_le(m, gp, [&](uint64_t j) { return inst[j].part_base; });
         if (i != cur_inst) {  // uniform: gp is the same for the whole block
@@ -656,55 +692,81 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const Instance *__restr
         }
         const uint64_t seg_idx = gp - in.part_base;
         uint64_t *seg = in.table + seg_idx * (uint64_t)kSegSlots * EW;
-        if (in.fresh) {
-            for (uint32_t s = tid; s < kSegSlots; s += blockDim.x) {
-                s_key[s] = 0;
-                reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
-            }
-        } else {
-            for (uint32_t w = tid; w < kSegSlots * EW; w += blockDim.x) {
-                const uint32_t s = w / EW, f = w - s * EW;
-                const uint64_t v = seg[w];
-                if (f == 0) {
-                    s_key[s] = v;
-                } else if (f <= 2) {
-                    s_cnt[4 * s + 2 * (f - 1)] = (uint32_t)v;
-                    s_cnt[4 * s + 2 * (f - 1) + 1] = (uint32_t)(v >> 32);
+        const uint64_t a = pstart[gp], z = pstart[gp + 1];
+        // issue the first records' loads before the re-insertion below
+        uint64_t rv[kReducePrefetch];
+#pragma unroll
+        for (uint32_t c = 0; c < kReducePrefetch; ++c) {
+            const uint64_t r = a + (uint64_t)c * blockDim.x + tid;
+            rv[c] = r < z ? rec2[r] : kNoRecord;
+        }
+        const uint32_t n_old = in.fresh ? 0u : min(in.seg_count[seg_idx], kSegSlots);
+        for (uint32_t e = tid; e < n_old; e += blockDim.x) {
+            // distinct keys: each claims its own slot, and nobody else touches
+            // that slot's counters before the next barrier
+            const uint64_t tagv = seg[(uint64_t)e * EW];
+            const uint64_t c01 = seg[(uint64_t)e * EW + 1], c23 = seg[(uint64_t)e * EW + 2];
+            uint32_t s = seg_home(mix64(tagv & ~kOccupied));
+            for (uint32_t q = 0; q < kSegSlots; ++q) {
+                uint64_t expected = 0;
+                if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    reinterpret_cast<uint4 *>(s_cnt)[s] =
+                        make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
+                    break;
                 }
+                s = (s + 1) & (kSegSlots - 1);
             }
         }
         __syncthreads();
-        const uint64_t a = pstart[gp], z = pstart[gp + 1];
         bool full = false;
-        for (uint64_t base = a; base < z; base += (uint64_t)blockDim.x * kReducePrefetch) {
-            uint64_t rv[kReducePrefetch];
+        for (uint64_t base = a;;) {
+#pragma unroll
+            for (uint32_t c = 0; c < kReducePrefetch; ++c)
+                if (rv[c] != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims)) full = true;
+            base += (uint64_t)blockDim.x * kReducePrefetch;
+            if (base >= z) break;
 #pragma unroll
             for (uint32_t c = 0; c < kReducePrefetch; ++c) {
                 const uint64_t r = base + (uint64_t)c * blockDim.x + tid;
                 rv[c] = r < z ? rec2[r] : kNoRecord;
             }
-#pragma unroll
-            for (uint32_t c = 0; c < kReducePrefetch; ++c)
-                if (rv[c] != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims)) full = true;
         }
         if (full) atomic_or_u32(&st[i].err, kErrFull);
         __syncthreads();
-        uint32_t occupied = 0;
-        for (uint32_t w = tid; w < kSegSlots * EW; w += blockDim.x) {
-            const uint32_t s = w / EW, f = w - s * EW;
-            uint64_t v = 0;
-            if (f == 0) {
-                v = s_key[s];
-                occupied += v != 0;
-            } else if (f <= 2) {
-                v = (uint64_t)s_cnt[4 * s + 2 * (f - 1)] |
-                    ((uint64_t)s_cnt[4 * s + 2 * (f - 1) + 1] << 32);
-            }
-            seg[w] = v;
+        // write the occupied slots back packed: each wavefront compacts its
+        // own slot range with ballots, after one exchange of range totals
+        const uint32_t s0 = wave * kWaveSlots;
+        uint32_t mine = 0;
+        for (uint32_t c0 = 0; c0 < kWaveSlots; c0 += 64)
+            mine += (uint32_t)__popcll(__ballot(s_key[s0 + c0 + lane] != 0));
+        if (lane == 0) s_wave_n[wave] = mine;
+        __syncthreads();
+        uint32_t out = 0, total = 0;
+        for (uint32_t w2 = 0; w2 < kWaves; ++w2) {
+            const uint32_t nw = s_wave_n[w2];
+            out += w2 < wave ? nw : 0u;
+            total += nw;
         }
-        uint64_t total;
-        block_exclusive_scan(occupied, &total);
-        if (tid == 0 && in.seg_count) in.seg_count[seg_idx] = (uint32_t)total;
+        for (uint32_t c0 = 0; c0 < kWaveSlots; c0 += 64) {
+            const uint32_t s = s0 + c0 + lane;
+            const uint64_t tagv = s_key[s];
+            const uint64_t mask = __ballot(tagv != 0);
+            if (tagv) {
+                const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+                uint64_t *e = seg + (uint64_t)(out + rank) * EW;
+                const uint4 c = reinterpret_cast<const uint4 *>(s_cnt)[s];
+                e[0] = tagv;
+                e[1] = (uint64_t)c.x | ((uint64_t)c.y << 32);
+                e[2] = (uint64_t)c.z | ((uint64_t)c.w << 32);
+                if (EW == 4) e[3] = 0;
+                s_key[s] = 0;
+                reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+            }
+            out += (uint32_t)__popcll(mask);
+        }
+        if (tid == 0) in.seg_count[seg_idx] = total;
+        __syncthreads();
     }
     if (cur_inst != 0xffffffffu) flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
 }
@@ -713,8 +775,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const Instance *__restr
 
 constexpr uint32_t kExtractSegBlock = 256;
 
-// Vertices of segment gp go to [seg_off[gp], seg_off[gp + 1]).  The segment
-// is read with coalesced loads into LDS first.
+// The vertices of segment gp (packed at its first entries) go to
+// [seg_off[gp], seg_off[gp + 1]).
 template <uint32_t EW>
 __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t *__restrict__ table,
                                                                  uint32_t parts,
@@ -722,31 +784,19 @@ __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t
                                                                  uint64_t *__restrict__ okeys,
                                                                  uint32_t *__restrict__ ocnt,
                                                                  uint64_t ocap, uint64_t *out_n) {
-    __shared__ __align__(16) uint64_t s_seg[kSegSlots * EW];
-    constexpr uint32_t per = kSegSlots / kExtractSegBlock;  // slots per thread, strided
     for (uint32_t gp = blockIdx.x; gp < parts; gp += gridDim.x) {
-        const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(table + (uint64_t)gp * kSegSlots * EW);
-        ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(s_seg);
-        for (uint32_t w = threadIdx.x; w < kSegSlots * EW / 2; w += blockDim.x) dst[w] = src[w];
-        __syncthreads();
-        uint32_t mine = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < per; ++q) mine += s_seg[(q * kExtractSegBlock + threadIdx.x) * EW] != 0;
-        uint64_t total;
-        uint64_t idx = seg_off[gp] + block_exclusive_scan(mine, &total);
-#pragma unroll
-        for (uint32_t q = 0; q < per; ++q) {
-            const uint64_t *e = s_seg + (q * kExtractSegBlock + threadIdx.x) * EW;
-            if (!e[0]) continue;
-            if (idx < ocap) {
-                okeys[idx] = e[0] & ~kOccupied;
-                const uint64_t c01 = e[1], c23 = e[2];
-                *reinterpret_cast<uint4 *>(ocnt + 4 * idx) =
-                    make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
-            }
-            ++idx;
+        const uint64_t *seg = table + (uint64_t)gp * kSegSlots * EW;
+        const uint64_t base = seg_off[gp];
+        const uint32_t n = (uint32_t)min<uint64_t>(seg_off[gp + 1] - base, kSegSlots);
+        for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+            const uint64_t idx = base + e;
+            if (idx >= ocap) break;
+            const uint64_t *w = seg + (uint64_t)e * EW;
+            const uint64_t c01 = w[1], c23 = w[2];
+            okeys[idx] = w[0] & ~kOccupied;
+            *reinterpret_cast<uint4 *>(ocnt + 4 * idx) =
+                make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
         }
-        __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_n = seg_off[parts];
 }
@@ -776,17 +826,21 @@ hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packe
                          InstStatus *st, const BinBuffers &bb, uint32_t merge, int device,
                          hipStream_t s) {
     (void)merge;
-    (void)n_reads;
     hipError_t e;
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, inst, m, ws, st, bb.plan, bb.totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_reads + 255) / 256, 8192));
+        hipLaunchKernelGGL(k_tile_reads, dim3(g), dim3(256), 0, s, inst, m, ws, n_reads, bb.plan,
+                           bb.tile_read1, bb.tiles1_cap);
+    }
 
     // pass 1
     const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false), lb1 = bin_lds_bytes(bb.d1_max, true);
     const uint32_t g1c = occupancy_grid(k_bin<false>, device, kBinBlock, bb.tiles1_cap, lb0);
     const uint32_t g1s = occupancy_grid(k_bin<true>, device, kBinBlock, bb.tiles1_cap, lb1);
     hipLaunchKernelGGL((k_bin<false>), dim3(g1c), dim3(kBinBlock), lb0, s, inst, m, packed, offsets, ws,
-                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.d1_max);
+                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint64_t nb1 = (bb.hist1_cap + kFlatChunk - 1) / kFlatChunk;
     const uint64_t *len1 = &bb.totals->hist1_len;
@@ -797,17 +851,22 @@ hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packe
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb1, 1)), dim3(kFlatBlock), 0, s,
                        len1, bb.scan1, bb.partials);
     hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, inst, m, packed, offsets, ws,
-                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.d1_max);
+                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, inst, m, bb.plan, bb.scan1, bb.totals,
                        bb.buckets);
+    {
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bb.buckets_total + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_tile_buckets, dim3(g), dim3(256), 0, s, bb.buckets, bb.totals, bb.tile_bucket2,
+                           bb.tiles2_cap);
+    }
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false), lr1 = ref_lds_bytes(bb.fan_max, true);
     const uint32_t g2c = occupancy_grid(k_refine<false>, device, kRefBlock, bb.tiles2_cap, lr0);
     const uint32_t g2s = occupancy_grid(k_refine<true>, device, kRefBlock, bb.tiles2_cap, lr1);
     hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, inst, bb.buckets, bb.totals,
-                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint64_t nb2 = (bb.hist2_cap + kFlatChunk - 1) / kFlatChunk;
     const uint64_t *len2 = &bb.totals->hist2_len;
@@ -818,7 +877,7 @@ hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packe
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb2, 1)), dim3(kFlatBlock), 0, s,
                        len2, bb.scan2, bb.partials);
     hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, inst, bb.buckets, bb.totals,
-                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     // segment starts and the reduction

@@ -15,9 +15,13 @@
 //                 counter (32-bit atomic add)
 //
 // Table layout: an array of `cap` entries of `entry_words` uint64 words
-// (3 = 24 bytes, 4 = 32 bytes).  Word 0 holds the vertex key with bit 63 set
-// (0 means the slot is empty, so a zero fill empties the table); the next
-// 16 bytes hold four uint32 counters in letter-code order A, C, T, G.
+// (3 = 24 bytes, 4 = 32 bytes).  Word 0 holds the vertex key with bit 63 set,
+// the next 16 bytes four uint32 counters in letter-code order A, C, T, G.
+// Direct build: the entries are the open-addressing slots themselves (0 =
+// empty, so a zero fill empties the table).  Binned build: the table is cut
+// into segments of kSegSlots entries, and segment s holds its vertices packed
+// at entries [0, seg_count[s]) (the hash slots live in LDS only while the
+// segment is being built).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -128,6 +132,8 @@ struct BinBuffers {     // device scratch of one binned pass
     uint64_t *partials;       // for the flat scans
     uint64_t *rec1, *rec2;    // records, windows_cap each
     uint64_t *pstart;         // parts_total + 1
+    uint64_t *tile_read1;     // first read of each pass-1 tile (tiles1_cap)
+    uint32_t *tile_bucket2;   // level-1 bucket of each pass-2 tile (tiles2_cap)
     uint64_t hist1_cap, hist2_cap, partials_cap;
     uint64_t tiles1_cap, tiles2_cap, buckets_total, parts_total;
     uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)
