@@ -75,7 +75,9 @@ def main() -> int:
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--wpt", type=int, default=0)
-    ap.add_argument("--mode", choices=["direct", "binned"], default="direct")
+    ap.add_argument("--mode", choices=["direct", "binned"], default="binned")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels without HIP graphs")
+    ap.add_argument("--no-compare", action="store_true", help="skip the direct-mode comparison")
     ap.add_argument("--merge", action="store_true")
     ap.add_argument("--entry32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,49 +109,56 @@ def main() -> int:
     inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
     windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
 
-    flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
-    if args.mode == "binned":
-        flags |= dbg.F_BINNED
-    g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
-                  device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
-    st0 = g.stats()
-    cap_out = int(st0["capacity"])
-    d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
-    d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
+    def run(mode: str, steps: int, warmup: int):
+        flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
+        if mode == "binned":
+            flags |= dbg.F_BINNED
+        if not args.no_graph:
+            flags |= dbg.F_GRAPH
+        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
+                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
+        cap_out = int(g.stats()["capacity"])
+        d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
+        d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
 
-    def step():
-        g.reset()
-        g.build_device(d_reads, d_off, rs.k)
-        g.sync()
-        return g.extract_device(d_keys, d_counts)
+        def step():
+            g.reset()
+            g.build_device(d_reads, d_off, rs.k)
+            g.sync()
+            return g.extract_device(d_keys, d_counts)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    build_ms = []
-    total_ms = []
-    V = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        V = step()
-        s = g.stats()
-        build_ms.append(s["last_build_ms"])
-        total_ms.append(s["last_total_ms"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = g.stats()
-    assert st["inserts"] == inserts, (st["inserts"], inserts)
-    ms_step = dt * 1000.0 / args.steps
-    value = inserts / (dt / args.steps) / 1e9
-    kern_ms = float(np.mean(build_ms))
-    log("step %.3f ms, build kernel %.3f ms (pass %.3f ms), V=%d, cap=%d" %
-        (ms_step, kern_ms, float(np.mean(total_ms)), V, cap_out))
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        build_ms, total_ms = [], []
+        V = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            V = step()
+            s = g.stats()
+            build_ms.append(s["last_build_ms"])
+            total_ms.append(s["last_total_ms"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = g.stats()
+        assert st["inserts"] == inserts, (st["inserts"], inserts)
+        g.close()
+        del d_keys, d_counts
+        return dict(V=V, cap=cap_out, st=st, ms_step=dt * 1000.0 / steps,
+                    value=inserts / (dt / steps) / 1e9, kern_ms=float(np.mean(build_ms)),
+                    pass_ms=float(np.mean(total_ms)))
+
+    r = run(args.mode, args.steps, args.warmup)
+    V, cap_out, st, ms_step, value, kern_ms = r["V"], r["cap"], r["st"], r["ms_step"], r["value"], r["kern_ms"]
+    log("%s: step %.3f ms, build %.3f ms (pass %.3f ms), V=%d, cap=%d, graph captures %d replays %d" %
+        (args.mode, ms_step, kern_ms, r["pass_ms"], V, cap_out, st["graph_captures"], st["graph_replays"]))
 
     bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
     achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_build (persistent find-or-claim + count)",
+            "kernel": ("binned build (partition passes + LDS segment reduce)" if args.mode == "binned"
+                       else "k_build (persistent find-or-claim + count)"),
             "kernel_ms": round(kern_ms, 4), "algorithmic_bytes": bytes_alg}
 
     line = {
@@ -170,10 +179,19 @@ def main() -> int:
                    "inserts_per_step": inserts, "vertices": V, "capacity": cap_out,
                    "load_factor": args.load_factor, "entry_bytes": st["entry_bytes"],
                    "block": st["block_size"], "windows_per_thread": st["windows_per_thread"],
-                   "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode},
+                   "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode,
+                   "hip_graphs": not args.no_graph},
         "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
         "roofline": roof,
     }
+
+    if not args.no_compare:
+        other = "direct" if args.mode == "binned" else "binned"
+        o = run(other, max(3, args.steps // 2), 1)
+        line["compare_" + other] = {"value": round(o["value"], 4), "ms_per_step": round(o["ms_step"], 4),
+                                   "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
+                                   "build_ms": round(o["kern_ms"], 4)}
+        log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
 
     if not args.no_roofline:
         foot = int(st["table_bytes"])
@@ -191,7 +209,6 @@ def main() -> int:
         line["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_reads)
         log("cpu baseline %s" % json.dumps(line["cpu_baseline"]))
 
-    g.close()
     print(json.dumps(line), flush=True)
     return 0
 

@@ -63,6 +63,8 @@ extern "C" {
                               claimed and counted in LDS (k <= 31; a graph whose
                               first build has k = 32 falls back to the direct
                               build) */
+#define DBG_F_GRAPH 0x10u  /* capture each build pass as HIP graphs on first use of
+                              its size class and replay them afterwards */
 
 typedef struct dbg_graph dbg_graph;
 
@@ -100,6 +102,10 @@ typedef struct {
     uint32_t windows_per_thread;
     uint32_t grid_size;
     uint32_t entry_bytes;     /* 24 or 32 */
+    uint64_t graph_captures;  /* build passes captured as graphs (DBG_F_GRAPH) */
+    uint64_t graph_replays;   /* build passes replayed from a captured graph */
+    uint32_t binned;          /* 1 if the graph uses the binned build */
+    uint32_t pad;
 } dbg_stats;
 
 /* Fill *cfg with the defaults (all zero, device -1). */

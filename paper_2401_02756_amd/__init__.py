@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
 
 OK = 0
 E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE = range(-1, -10, -1)
-F_MERGE, F_TIMING, F_ENTRY32, F_BINNED = 0x1, 0x2, 0x4, 0x8
+F_MERGE, F_TIMING, F_ENTRY32, F_BINNED, F_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
 # every symbol include/dbg.h declares
 EXPORTS = (
@@ -63,6 +63,10 @@ class Stats(ctypes.Structure):
         ("windows_per_thread", ctypes.c_uint32),
         ("grid_size", ctypes.c_uint32),
         ("entry_bytes", ctypes.c_uint32),
+        ("graph_captures", ctypes.c_uint64),
+        ("graph_replays", ctypes.c_uint64),
+        ("binned", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

@@ -127,86 +127,138 @@ uint64_t capacity_for(uint64_t vertices, double lf) {
     return std::max<uint64_t>(64, (uint64_t)c);
 }
 
-// Buffers and launch sequence of one build pass over m instances.
+// Capacity of a buffer dimension: x rounded up to a multiple of an eighth of
+// its power of two (at most 12.5 % slack), so that calls of similar size share
+// buffers and captured graphs.
+uint64_t size_class(uint64_t x, uint64_t floor) {
+    x = std::max(x, floor);
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    const uint64_t g = std::max<uint64_t>(p / 8, 1);
+    return (x + g - 1) / g * g;
+}
+
+// What a captured pass depends on besides its buffers.
+struct PassKey {
+    int binned = 0;
+    int single = 0;
+    uint32_t ew = 3;
+    uint32_t m_cap = 0, d1_cap = 0, fan_cap = 0;
+    uint64_t n_cap = 0, len_cap = 0, parts_cap = 0, buckets_cap = 0;
+    dbgk::BuildShape shape{};
+    bool operator==(const PassKey &o) const {
+        return binned == o.binned && single == o.single && ew == o.ew && m_cap == o.m_cap &&
+               d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
+               parts_cap == o.parts_cap && buckets_cap == o.buckets_cap && shape.block == o.shape.block &&
+               shape.wpt == o.shape.wpt && shape.grid == o.shape.grid && shape.merge == o.shape.merge;
+    }
+};
+
+// Buffers and launch sequence of one build pass over m instances.  With
+// graphs enabled the pass is captured as two HIP graphs (setup: arguments,
+// prepare, pack, scan; build: the build kernels and the status readback) on
+// first use of a size class and replayed afterwards; every size and input
+// pointer reaches the kernels through the PassArgs block in device memory,
+// so a replay needs no kernel argument to change.
 struct Pass {
-    DevBuf packed, ws, partials, tiles, dinst, dstatus;
+    DevBuf packed, ws, partials, tiles, dargs, dstatus;
     // binned-mode scratch
     DevBuf bplan, bbuckets, btotals, hist1, scan1, hist2, scan2, bpartials, rec1, rec2, pstart;
     DevBuf tread1, tbucket2;
-    HostBuf hinst, hstatus;
+    HostBuf hargs, hstatus;  // pinned: PassArgs + Instance[m_cap]; InstStatus[m_cap] + CallState
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+    hipStream_t cap_stream = nullptr;
     uint32_t m = 0;
     hipStream_t stream = nullptr;
     bool pending = false;
     bool timing = false;
+    bool use_graphs = false;
+    uint64_t generation = 0;  // bumped whenever a buffer moves
+    struct Cached {
+        PassKey key;
+        uint64_t generation;
+        hipGraphExec_t setup, build;
+    };
+    std::vector<Cached> graphs;
+    uint64_t captures = 0, replays = 0;
 
     hipError_t init() {
         hipError_t e = hipEventCreate(&ev_a);
         if (e == hipSuccess) e = hipEventCreate(&ev_b);
         if (e == hipSuccess) e = hipEventCreate(&ev_c);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
         return e;
     }
+    void drop_graphs() {
+        for (auto &c : graphs) {
+            if (c.setup) (void)hipGraphExecDestroy(c.setup);
+            if (c.build) (void)hipGraphExecDestroy(c.build);
+        }
+        graphs.clear();
+    }
     void release() {
-        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dinst, &dstatus, &bplan, &bbuckets,
+        drop_graphs();
+        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dargs, &dstatus, &bplan, &bbuckets,
                        &btotals, &hist1, &scan1, &hist2, &scan2, &bpartials, &rec1, &rec2, &pstart,
                        &tread1, &tbucket2};
         for (DevBuf *b : d) b->release();
-        hinst.release();
+        hargs.release();
         hstatus.release();
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
         if (ev_c) (void)hipEventDestroy(ev_c);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         ev_a = ev_b = ev_c = nullptr;
+        cap_stream = nullptr;
     }
-    hipError_t reserve_instances(uint32_t mm) {
-        hipError_t e = hinst.reserve(sizeof(Instance) * mm);
-        if (e == hipSuccess) e = dinst.reserve(sizeof(Instance) * mm);
-        if (e == hipSuccess) e = hstatus.reserve(sizeof(InstStatus) * mm + sizeof(CallState));
-        if (e == hipSuccess) e = dstatus.reserve(sizeof(InstStatus) * mm + sizeof(CallState));
+    // Grow a buffer; a move invalidates every captured graph.
+    hipError_t grow(DevBuf &b, size_t bytes) {
+        const void *old = b.p;
+        const hipError_t e = b.reserve(bytes);
+        if (b.p != old && old) ++generation;
         return e;
     }
-    Instance *host_instances() const { return hinst.as<Instance>(); }
+    hipError_t reserve_instances(uint32_t mm) {
+        const uint32_t m_cap = (uint32_t)size_class(mm, 1);
+        const void *pa = hargs.p, *ps = hstatus.p;
+        hipError_t e = hargs.reserve(dbgk::kArgsBytes + sizeof(Instance) * m_cap);
+        if (e == hipSuccess) e = hstatus.reserve(sizeof(InstStatus) * m_cap + sizeof(CallState));
+        if ((pa && hargs.p != pa) || (ps && hstatus.p != ps)) ++generation;  // graphs copy from these
+        return e;
+    }
+    dbgk::PassArgs *host_args() const { return hargs.as<dbgk::PassArgs>(); }
+    Instance *host_instances() const {
+        return reinterpret_cast<Instance *>(hargs.as<unsigned char>() + dbgk::kArgsBytes);
+    }
     const InstStatus *host_status() const { return hstatus.as<InstStatus>(); }
 
-    // Reserve the binned-mode scratch for mm instances over len bytes.
-    hipError_t reserve_binned(uint32_t mm, uint64_t len, dbgk::BinBuffers &bb) {
-        const Instance *hi = host_instances();
-        uint64_t G1 = 0, P = 0, d1max = 1, fanmax = 1;
-        bb.entry_words = 3;
-        for (uint32_t i = 0; i < mm; ++i) {
-            G1 += hi[i].d1;
-            P += hi[i].parts;
-            d1max = std::max<uint64_t>(d1max, hi[i].d1);
-            fanmax = std::max<uint64_t>(fanmax, hi[i].fan);
-            if (hi[i].parts) bb.entry_words = hi[i].entry_words;
-        }
-        bb.d1_max = (uint32_t)d1max;
-        bb.fan_max = (uint32_t)fanmax;
-        bb.tiles1_cap = len / dbgk::kBinTile + mm + 1;
-        bb.hist1_cap = d1max * bb.tiles1_cap;
-        bb.tiles2_cap = len / dbgk::kRefTile + G1 + 1;
-        bb.hist2_cap = fanmax * bb.tiles2_cap;
+    // Reserve the binned-mode scratch for the key's capacities.
+    hipError_t reserve_binned(const PassKey &k, dbgk::BinBuffers &bb) {
+        bb.tiles1_cap = k.len_cap / dbgk::kBinTile + k.m_cap + 1;
+        bb.hist1_cap = (uint64_t)k.d1_cap * bb.tiles1_cap;
+        bb.tiles2_cap = k.len_cap / dbgk::kRefTile + k.buckets_cap + 1;
+        bb.hist2_cap = (uint64_t)k.fan_cap * bb.tiles2_cap;
         const uint64_t chunk = 1024;
         bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
-        bb.buckets_total = G1;
-        bb.parts_total = P;
-        const uint64_t recs = std::max<uint64_t>(len, 1);
+        bb.buckets_cap = k.buckets_cap;
+        bb.parts_cap = k.parts_cap;
+        bb.d1_max = k.d1_cap;
+        bb.fan_max = k.fan_cap;
+        bb.entry_words = k.ew;
         hipError_t e;
-        if ((e = bplan.reserve(sizeof(dbgk::BinPlan) * mm)) != hipSuccess ||
-            (e = bbuckets.reserve(sizeof(dbgk::Bucket) * std::max<uint64_t>(G1, 1))) != hipSuccess ||
-            (e = btotals.reserve(sizeof(dbgk::BinTotals))) != hipSuccess ||
-            (e = hist1.reserve(4 * bb.hist1_cap)) != hipSuccess ||
-            (e = scan1.reserve(8 * (bb.hist1_cap + 1))) != hipSuccess ||
-            (e = hist2.reserve(4 * bb.hist2_cap)) != hipSuccess ||
-            (e = scan2.reserve(8 * (bb.hist2_cap + 1))) != hipSuccess ||
-            (e = bpartials.reserve(8 * bb.partials_cap)) != hipSuccess ||
-            (e = rec1.reserve(8 * recs)) != hipSuccess || (e = rec2.reserve(8 * recs)) != hipSuccess ||
-            (e = pstart.reserve(8 * (P + 1))) != hipSuccess ||
-            (e = tread1.reserve(8 * bb.tiles1_cap)) != hipSuccess ||
-            (e = tbucket2.reserve(4 * bb.tiles2_cap)) != hipSuccess)
+        if ((e = grow(bplan, sizeof(dbgk::BinPlan) * k.m_cap)) != hipSuccess ||
+            (e = grow(bbuckets, sizeof(dbgk::Bucket) * std::max<uint64_t>(k.buckets_cap, 1))) != hipSuccess ||
+            (e = grow(btotals, sizeof(dbgk::BinTotals))) != hipSuccess ||
+            (e = grow(hist1, 4 * bb.hist1_cap)) != hipSuccess ||
+            (e = grow(scan1, 8 * (bb.hist1_cap + 1))) != hipSuccess ||
+            (e = grow(hist2, 4 * bb.hist2_cap)) != hipSuccess ||
+            (e = grow(scan2, 8 * (bb.hist2_cap + 1))) != hipSuccess ||
+            (e = grow(bpartials, 8 * bb.partials_cap)) != hipSuccess ||
+            (e = grow(rec1, 8 * k.len_cap)) != hipSuccess || (e = grow(rec2, 8 * k.len_cap)) != hipSuccess ||
+            (e = grow(pstart, 8 * (k.parts_cap + 1))) != hipSuccess ||
+            (e = grow(tread1, 8 * bb.tiles1_cap)) != hipSuccess ||
+            (e = grow(tbucket2, 4 * bb.tiles2_cap)) != hipSuccess)
             return e;
-        bb.tile_read1 = tread1.as<uint64_t>();
-        bb.tile_bucket2 = tbucket2.as<uint32_t>();
         bb.plan = bplan.as<dbgk::BinPlan>();
         bb.buckets = bbuckets.as<dbgk::Bucket>();
         bb.totals = btotals.as<dbgk::BinTotals>();
@@ -218,51 +270,159 @@ struct Pass {
         bb.rec1 = rec1.as<uint64_t>();
         bb.rec2 = rec2.as<uint64_t>();
         bb.pstart = pstart.as<uint64_t>();
+        bb.tile_read1 = tread1.as<uint64_t>();
+        bb.tile_bucket2 = tbucket2.as<uint32_t>();
+        return hipSuccess;
+    }
+    // Grid sizes per binned key (queried once, outside any capture).
+    std::vector<std::pair<PassKey, dbgk::BinBuffers>> grid_memo;
+    void binned_grids(const PassKey &k, int device, dbgk::BinBuffers &bb) {
+        for (auto &g : grid_memo)
+            if (g.first == k) {
+                bb.grid_bin_count = g.second.grid_bin_count;
+                bb.grid_bin_scatter = g.second.grid_bin_scatter;
+                bb.grid_ref_count = g.second.grid_ref_count;
+                bb.grid_ref_scatter = g.second.grid_ref_scatter;
+                bb.grid_reduce = g.second.grid_reduce;
+                return;
+            }
+        dbgk::binned_grids(device, bb);
+        if (grid_memo.size() > 16) grid_memo.clear();
+        grid_memo.emplace_back(k, bb);
+    }
+
+    // The two halves of the pass, enqueued on `s` (directly or under capture).
+    hipError_t enqueue_setup(const PassKey &k, hipStream_t s) {
+        dbgk::PassArgs *da = dargs.as<dbgk::PassArgs>();
+        Instance *di = reinterpret_cast<Instance *>(dargs.as<unsigned char>() + dbgk::kArgsBytes);
+        InstStatus *dst = dstatus.as<InstStatus>();
+        CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
+        hipError_t e = hipMemcpyAsync(dargs.p, hargs.p, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap,
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = dbgk::launch_prepare(da, di, dst, cs, k.m_cap, s);
+        if (e == hipSuccess) e = dbgk::launch_pack(da, packed.as<uint64_t>(), di, dst, k.len_cap, s);
+        if (e == hipSuccess)
+            e = dbgk::launch_scan(da, di, dst, ws.as<uint64_t>(), partials.as<uint64_t>(),
+                                  k.binned ? nullptr : tiles.as<uint64_t>(), cs, k.n_cap, s);
+        return e;
+    }
+    hipError_t enqueue_build(const PassKey &k, const dbgk::BinBuffers &bb, int device, hipStream_t s) {
+        dbgk::PassArgs *da = dargs.as<dbgk::PassArgs>();
+        Instance *di = reinterpret_cast<Instance *>(dargs.as<unsigned char>() + dbgk::kArgsBytes);
+        InstStatus *dst = dstatus.as<InstStatus>();
+        CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
+        hipError_t e;
+        if (k.binned)
+            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s);
+        else
+            e = dbgk::launch_build(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
+                                   cs, k.shape, k.single != 0, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * k.m_cap + sizeof(CallState),
+                               hipMemcpyDeviceToHost, s);
+        return e;
+    }
+
+    hipError_t capture(const PassKey &k, const dbgk::BinBuffers &bb, int device, Cached &out) {
+        out.key = k;
+        out.generation = generation;
+        out.setup = out.build = nullptr;
+        for (int half = 0; half < 2; ++half) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            const hipError_t ee = half == 0 ? enqueue_setup(k, cap_stream) : enqueue_build(k, bb, device, cap_stream);
+            e = hipStreamEndCapture(cap_stream, &g);
+            if (ee != hipSuccess) e = ee;
+            if (e == hipSuccess) e = hipGraphInstantiate(half == 0 ? &out.setup : &out.build, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+        }
+        ++captures;
         return hipSuccess;
     }
 
-    // Enqueue the pass; hinst[0..mm) must be filled (tables, read ranges,
+    // Enqueue the pass.  hinst[0..mm) must be filled (tables, read ranges,
     // prior k-mers, k, entry words, and the segment geometry when binned).
-    // Reads are device-resident and gap-free: read i is
-    // d_reads[off[i] - off[0] .. off[i+1] - off[0]).
+    // Reads are device-resident: read i is d_reads[off[i] - off[0] ..
+    // off[i+1] - off[0]).
     hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
                        uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
                        bool time_it, hipStream_t s) {
+        PassKey k;
+        k.binned = binned ? 1 : 0;
+        k.single = mm == 1 ? 1 : 0;
+        k.shape = shape;
+        k.m_cap = (uint32_t)size_class(mm, 1);
+        k.n_cap = size_class(n, 1024);
+        k.len_cap = size_class(len, 4096);
+        const Instance *hi = host_instances();
+        uint64_t P = 0, G1 = 0;
+        uint32_t d1max = 1, fanmax = 1;
+        for (uint32_t i = 0; i < mm; ++i) {
+            P += hi[i].parts;
+            G1 += hi[i].d1;
+            d1max = std::max(d1max, hi[i].d1);
+            fanmax = std::max(fanmax, hi[i].fan);
+            if (hi[i].parts) k.ew = hi[i].entry_words;
+        }
+        if (binned) {
+            k.parts_cap = size_class(P, 64);
+            k.buckets_cap = size_class(G1, 64);
+            k.d1_cap = (uint32_t)std::min<uint64_t>(size_class(d1max, 16), dbgk::kMaxD1);
+            k.fan_cap = (uint32_t)std::min<uint64_t>(size_class(fanmax, 16), dbgk::kMaxFan);
+        }
         const uint64_t T = (uint64_t)shape.block * shape.wpt;
-        const uint64_t tile_cap = binned ? 0 : dbgk::max_tiles(len, T);
+        const uint64_t tile_cap = dbgk::max_tiles(k.len_cap, T);
         dbgk::BinBuffers bb{};
         hipError_t e;
-        if ((e = packed.reserve(dbgk::packed_words(len) * 8)) != hipSuccess ||
-            (e = ws.reserve((n + 1) * 8)) != hipSuccess ||
-            (e = partials.reserve(dbgk::scan_blocks(n) * 8 + 8)) != hipSuccess ||
-            (!binned && (e = tiles.reserve(tile_cap * 8)) != hipSuccess) ||
-            (binned && (e = reserve_binned(mm, len, bb)) != hipSuccess))
+        if ((e = grow(packed, dbgk::packed_words(k.len_cap) * 8)) != hipSuccess ||
+            (e = grow(ws, (k.n_cap + 1) * 8)) != hipSuccess ||
+            (e = grow(partials, dbgk::scan_blocks(k.n_cap) * 8 + 8)) != hipSuccess ||
+            (e = grow(dargs, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap)) != hipSuccess ||
+            (e = grow(dstatus, sizeof(InstStatus) * k.m_cap + sizeof(CallState))) != hipSuccess ||
+            (!binned && (e = grow(tiles, tile_cap * 8)) != hipSuccess) ||
+            (binned && (e = reserve_binned(k, bb)) != hipSuccess))
             return e;
-        InstStatus *dst = dstatus.as<InstStatus>();
-        CallState *cs = reinterpret_cast<CallState *>(dst + mm);
-        Instance *di = dinst.as<Instance>();
-        const uint64_t max_windows = binned ? len : (tile_cap - 1) * T;
-        if (time_it) (void)hipEventRecord(ev_a, s);
-        e = hipMemcpyAsync(di, hinst.p, sizeof(Instance) * mm, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = dbgk::launch_prepare(di, mm, dst, cs, d_off, n, s);
-        if (e == hipSuccess) e = dbgk::launch_pack(d_reads, len, packed.as<uint64_t>(), di, mm, dst, s);
-        if (e == hipSuccess)
-            e = dbgk::launch_scan(d_off, n, len, check_ends, di, mm, dst, ws.as<uint64_t>(),
-                                  partials.as<uint64_t>(), binned ? nullptr : tiles.as<uint64_t>(),
-                                  tile_cap, (uint32_t)T, max_windows, cs, s);
-        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
-        if (e == hipSuccess) {
-            if (binned)
-                e = dbgk::launch_binned(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(), n, dst,
-                                        bb, shape.merge, device, s);
-            else
-                e = dbgk::launch_build(di, mm, packed.as<uint64_t>(), d_off, ws.as<uint64_t>(),
-                                       tiles.as<uint64_t>(), n, dst, cs, shape, s);
+        if (binned) binned_grids(k, device, bb);
+
+        dbgk::PassArgs &a = *host_args();
+        std::memset(&a, 0, sizeof a);
+        a.reads = d_reads;
+        a.off = d_off;
+        a.n_reads = n;
+        a.reads_len = len;
+        a.max_windows = binned ? len : (tile_cap - 1) * T;
+        a.tile_cap = tile_cap;
+        a.parts_total = P;
+        a.m = mm;
+        a.check_ends = check_ends ? 1 : 0;
+        a.tile = (uint32_t)T;
+
+        Cached *c = nullptr;
+        if (use_graphs) {
+            for (auto &x : graphs)
+                if (x.key == k && x.generation == generation) c = &x;
+            if (!c) {
+                if (graphs.size() >= 8 || (!graphs.empty() && graphs[0].generation != generation)) drop_graphs();
+                Cached fresh{};
+                e = capture(k, bb, device, fresh);
+                if (e != hipSuccess) {
+                    if (fresh.setup) (void)hipGraphExecDestroy(fresh.setup);
+                    if (fresh.build) (void)hipGraphExecDestroy(fresh.build);
+                    return e;
+                }
+                graphs.push_back(fresh);
+                c = &graphs.back();
+            } else {
+                ++replays;
+            }
         }
+        if (time_it) (void)hipEventRecord(ev_a, s);
+        e = c ? hipGraphLaunch(c->setup, s) : enqueue_setup(k, s);
+        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
+        if (e == hipSuccess) e = c ? hipGraphLaunch(c->build, s) : enqueue_build(k, bb, device, s);
         if (time_it && e == hipSuccess) (void)hipEventRecord(ev_c, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * mm + sizeof(CallState),
-                               hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         m = mm;
         stream = s;
@@ -531,6 +691,7 @@ static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64
         if (run[i] && !g0) g0 = graphs[i];
     }
     const bool timing = (g0->flags & DBG_F_TIMING) != 0;
+    pass.use_graphs = (g0->flags & DBG_F_GRAPH) != 0;
     const uint64_t n = read_begin[m];
     e = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, mode != 0, device, check_ends,
                      timing, stream);
@@ -591,6 +752,7 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     g->cap_req = cfg.capacity;
     g->ew = (cfg.flags & DBG_F_ENTRY32) ? 4 : 3;
     g->binned = (cfg.flags & DBG_F_BINNED) != 0;
+    g->pass.use_graphs = (cfg.flags & DBG_F_GRAPH) != 0;
     g->shape.block = block;
     g->shape.wpt = wpt;
     g->shape.merge = (cfg.flags & DBG_F_MERGE) ? 1 : 0;
@@ -770,6 +932,9 @@ int dbg_get_stats(dbg_graph *g, dbg_stats *out) {
     out->windows_per_thread = g->shape.wpt;
     out->grid_size = g->shape.grid;
     out->entry_bytes = g->ew * 8;
+    out->graph_captures = g->pass.captures;
+    out->graph_replays = g->pass.replays;
+    out->binned = g->binned ? 1u : 0u;
     return DBG_OK;
 }
 

@@ -229,9 +229,10 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 // Per instance: its window range, pass-1 tiles, histogram and bucket bases.
 // An instance that failed validation (or whose k-mer total would overflow a
 // counter) gets no tiles, so it produces no records.
-__global__ void k_bin_plan(const Instance *inst, uint32_t m, const uint64_t *ws, InstStatus *st,
-                           BinPlan *plan, BinTotals *tot) {
+__global__ void k_bin_plan(const PassArgs *__restrict__ args, const Instance *inst, const uint64_t *ws,
+                           InstStatus *st, BinPlan *plan, BinTotals *tot) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t m = args->m;
     uint64_t tiles = 0, hist = 0, buckets = 0;
     for (uint32_t i = 0; i < m; ++i) {
         const Instance &in = inst[i];
@@ -263,9 +264,11 @@ __global__ void k_bin_plan(const Instance *inst, uint32_t m, const uint64_t *ws,
 
 // First read of every pass-1 tile: read r writes the tiles whose first
 // window falls among its windows.
-__global__ void k_tile_reads(const Instance *__restrict__ inst, uint32_t m, const uint64_t *__restrict__ ws,
-                             uint64_t n, const BinPlan *__restrict__ plan, uint64_t *__restrict__ tile_read1,
-                             uint64_t tiles_cap) {
+__global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *__restrict__ inst,
+                             const uint64_t *__restrict__ ws, const BinPlan *__restrict__ plan,
+                             uint64_t *__restrict__ tile_read1, uint64_t tiles_cap) {
+    const uint32_t m = args->m;
+    const uint64_t n = args->n_reads;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         const uint64_t a = ws[r], z = ws[r + 1];
@@ -293,9 +296,9 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter)
 // finds their read once, loads three packed words, and slides through them,
 // so a window costs a few shifts instead of a search and two loads.
 template <bool SCATTER>
-__global__ __launch_bounds__(kBinBlock) void k_bin(const Instance *__restrict__ inst, uint32_t m,
+__global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ args,
+                                                  const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
-                                                  const uint64_t *__restrict__ off,
                                                   const uint64_t *__restrict__ ws,
                                                   const BinPlan *__restrict__ plan,
                                                   const BinTotals *__restrict__ tot,
@@ -311,6 +314,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const Instance *__restrict__ 
     uint64_t *s_rec = s_gbase + d1_max;
     uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);
     const uint32_t tid = threadIdx.x;
+    const uint32_t m = args->m;
+    const uint64_t *__restrict__ off = args->off;
     const uint64_t tiles = tot->tiles1;
     const uint64_t off0 = off[0];
     for (XcdTiles it(tiles); it.valid(); it.advance()) {
@@ -448,10 +453,12 @@ __global__ __launch_bounds__(kFlatBlock) void k_flat_add(const uint64_t *len_ptr
 // ---------------------------------------------------------------- pass 2
 
 // Per level-1 bucket: its record range, pass-2 tiles and histogram base.
-__global__ __launch_bounds__(1024) void k_refine_plan(const Instance *__restrict__ inst, uint32_t m,
+__global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict__ args,
+                                                     const Instance *__restrict__ inst,
                                                      const BinPlan *__restrict__ plan,
                                                      const uint64_t *__restrict__ scan1,
                                                      BinTotals *tot, Bucket *__restrict__ buckets) {
+    const uint32_t m = args->m;
     const uint64_t G = tot->buckets;
     uint64_t carry_t = 0, carry_h = 0;
     for (uint64_t base = 0; base < G; base += blockDim.x) {
@@ -583,10 +590,12 @@ __global__ void k_tile_buckets(const Bucket *__restrict__ buckets, const BinTota
 }
 
 // First record of every segment (and the total after the last).
-__global__ void k_part_starts(const Instance *__restrict__ inst, uint32_t m,
+__global__ void k_part_starts(const PassArgs *__restrict__ args, const Instance *__restrict__ inst,
                               const BinPlan *__restrict__ plan, const Bucket *__restrict__ buckets,
                               const uint64_t *__restrict__ scan2, const BinTotals *__restrict__ tot,
-                              uint64_t *__restrict__ pstart, uint64_t parts_total) {
+                              uint64_t *__restrict__ pstart) {
+    const uint32_t m = args->m;
+    const uint64_t parts_total = args->parts_total;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t gp = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < parts_total; gp += stride) {
         const uint32_t i = (uint32_t)last_le(m, gp, [&](uint64_t j) { return inst[j].part_base; });
@@ -652,10 +661,13 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
 // new seg_count.  Each workgroup takes a contiguous run of segments, so it
 // meets few instances and flushes its claim count once per instance.
 template <uint32_t EW>
-__global__ __launch_bounds__(kReduceBlock) void k_reduce(const Instance *__restrict__ inst, uint32_t m,
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restrict__ args,
+                                                        const Instance *__restrict__ inst,
                                                         const uint64_t *__restrict__ pstart,
                                                         const uint64_t *__restrict__ rec2,
-                                                        InstStatus *st, uint64_t parts_total) {
+                                                        InstStatus *st) {
+    const uint32_t m = args->m;
+    const uint64_t parts_total = args->parts_total;
     static_assert(kSegSlots % kReduceBlock == 0 && kReduceBlock % 64 == 0, "slot ranges per wavefront");
     constexpr uint32_t kWaves = kReduceBlock / 64;
     constexpr uint32_t kWaveSlots = kSegSlots / kWaves;  // slots compacted by one wavefront
@@ -821,81 +833,78 @@ uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint
 
 }  // namespace
 
-hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packed,
-                         const uint64_t *offsets, const uint64_t *ws, uint64_t n_reads,
-                         InstStatus *st, const BinBuffers &bb, uint32_t merge, int device,
-                         hipStream_t s) {
-    (void)merge;
+hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                         const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
+                         int device, hipStream_t s) {
     hipError_t e;
-    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, inst, m, ws, st, bb.plan, bb.totals);
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
-        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_reads + 255) / 256, 8192));
-        hipLaunchKernelGGL(k_tile_reads, dim3(g), dim3(256), 0, s, inst, m, ws, n_reads, bb.plan,
-                           bb.tile_read1, bb.tiles1_cap);
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
+        hipLaunchKernelGGL(k_tile_reads, dim3(g), dim3(256), 0, s, args, inst, ws, bb.plan, bb.tile_read1,
+                           bb.tiles1_cap);
     }
 
     // pass 1
     const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false), lb1 = bin_lds_bytes(bb.d1_max, true);
-    const uint32_t g1c = occupancy_grid(k_bin<false>, device, kBinBlock, bb.tiles1_cap, lb0);
-    const uint32_t g1s = occupancy_grid(k_bin<true>, device, kBinBlock, bb.tiles1_cap, lb1);
-    hipLaunchKernelGGL((k_bin<false>), dim3(g1c), dim3(kBinBlock), lb0, s, inst, m, packed, offsets, ws,
-                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
+    hipLaunchKernelGGL((k_bin<false>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
+                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const uint64_t nb1 = (bb.hist1_cap + kFlatChunk - 1) / kFlatChunk;
+    const uint64_t nb1 = std::max<uint64_t>((bb.hist1_cap + kFlatChunk - 1) / kFlatChunk, 1);
     const uint64_t *len1 = &bb.totals->hist1_len;
-    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)std::max<uint64_t>(nb1, 1)), dim3(kFlatBlock), 0, s,
-                       bb.hist1, len1, bb.scan1, bb.partials);
-    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, std::max<uint64_t>(nb1, 1),
-                       len1, bb.scan1);
-    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb1, 1)), dim3(kFlatBlock), 0, s,
-                       len1, bb.scan1, bb.partials);
-    hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, inst, m, packed, offsets, ws,
-                       bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, bb.hist1, len1, bb.scan1,
+                       bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
+    hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
+                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     // pass 2
-    hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, inst, m, bb.plan, bb.scan1, bb.totals,
+    hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
                        bb.buckets);
     {
-        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bb.buckets_total + 255) / 256, 4096));
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bb.buckets_cap + 255) / 256, 4096));
         hipLaunchKernelGGL(k_tile_buckets, dim3(g), dim3(256), 0, s, bb.buckets, bb.totals, bb.tile_bucket2,
                            bb.tiles2_cap);
     }
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false), lr1 = ref_lds_bytes(bb.fan_max, true);
-    const uint32_t g2c = occupancy_grid(k_refine<false>, device, kRefBlock, bb.tiles2_cap, lr0);
-    const uint32_t g2s = occupancy_grid(k_refine<true>, device, kRefBlock, bb.tiles2_cap, lr1);
+    const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
     hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, inst, bb.buckets, bb.totals,
                        bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const uint64_t nb2 = (bb.hist2_cap + kFlatChunk - 1) / kFlatChunk;
+    const uint64_t nb2 = std::max<uint64_t>((bb.hist2_cap + kFlatChunk - 1) / kFlatChunk, 1);
     const uint64_t *len2 = &bb.totals->hist2_len;
-    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)std::max<uint64_t>(nb2, 1)), dim3(kFlatBlock), 0, s,
-                       bb.hist2, len2, bb.scan2, bb.partials);
-    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, std::max<uint64_t>(nb2, 1),
-                       len2, bb.scan2);
-    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)std::max<uint64_t>(nb2, 1)), dim3(kFlatBlock), 0, s,
-                       len2, bb.scan2, bb.partials);
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, bb.hist2, len2, bb.scan2,
+                       bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
     hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, inst, bb.buckets, bb.totals,
                        bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     // segment starts and the reduction
-    const uint64_t P = bb.parts_total;
-    const uint32_t gs = (uint32_t)std::min<uint64_t>((P + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, inst, m, bb.plan, bb.buckets, bb.scan2,
-                       bb.totals, bb.pstart, P);
+    const uint64_t P = bb.parts_cap;
+    const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, args, inst, bb.plan, bb.buckets, bb.scan2,
+                       bb.totals, bb.pstart);
     // every instance of a binned launch has the same entry width
-    if (bb.entry_words == 4) {
-        const uint32_t gr = occupancy_grid(k_reduce<4>, device, kReduceBlock, P, 0);
-        hipLaunchKernelGGL((k_reduce<4>), dim3(gr), dim3(kReduceBlock), 0, s, inst, m, bb.pstart, bb.rec2,
-                           st, P);
-    } else {
-        const uint32_t gr = occupancy_grid(k_reduce<3>, device, kReduceBlock, P, 0);
-        hipLaunchKernelGGL((k_reduce<3>), dim3(gr), dim3(kReduceBlock), 0, s, inst, m, bb.pstart, bb.rec2,
-                           st, P);
-    }
+    const uint32_t gr = bb.grid_reduce;
+    if (bb.entry_words == 4)
+        hipLaunchKernelGGL((k_reduce<4>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
+    else
+        hipLaunchKernelGGL((k_reduce<3>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
     return hipGetLastError();
+}
+
+void binned_grids(int device, BinBuffers &bb) {
+    bb.grid_bin_count = occupancy_grid(k_bin<false>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, false));
+    bb.grid_bin_scatter = occupancy_grid(k_bin<true>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true));
+    bb.grid_ref_count = occupancy_grid(k_refine<false>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, false));
+    bb.grid_ref_scatter = occupancy_grid(k_refine<true>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, true));
+    bb.grid_reduce = bb.entry_words == 4 ? occupancy_grid(k_reduce<4>, device, kReduceBlock, bb.parts_cap, 0)
+                                         : occupancy_grid(k_reduce<3>, device, kReduceBlock, bb.parts_cap, 0);
 }
 
 hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t parts,

@@ -61,6 +61,26 @@ struct Instance {
     uint32_t pad;
 };
 
+// Per-call sizes and inputs, read by every kernel of a pass from device
+// memory, so that one captured graph serves every call whose sizes fit the
+// capacities the graph was captured for.  Stored at the start of the device
+// instance buffer, followed (at kArgsBytes) by the Instance array.
+struct PassArgs {
+    const uint8_t *reads;   // ASCII bases; read i is reads[off[i]-off[0] .. off[i+1]-off[0])
+    const uint64_t *off;    // n_reads + 1 offsets
+    uint64_t n_reads;
+    uint64_t reads_len;     // bytes (off[n] - off[0] when valid)
+    uint64_t max_windows;   // more windows than this flags every instance invalid
+    uint64_t tile_cap;      // direct build: tile map entries
+    uint64_t parts_total;   // binned build: segments over all instances
+    uint32_t m;             // instances
+    uint32_t check_ends;    // require off[n] - off[0] == reads_len
+    uint32_t tile;          // direct build: windows per tile
+    uint32_t pad;
+};
+constexpr uint32_t kArgsBytes = 128;
+static_assert(sizeof(PassArgs) <= kArgsBytes, "PassArgs grew");
+
 struct InstStatus {
     uint32_t err;       // kErr* bits
     uint32_t pad;
@@ -135,36 +155,40 @@ struct BinBuffers {     // device scratch of one binned pass
     uint64_t *tile_read1;     // first read of each pass-1 tile (tiles1_cap)
     uint32_t *tile_bucket2;   // level-1 bucket of each pass-2 tile (tiles2_cap)
     uint64_t hist1_cap, hist2_cap, partials_cap;
-    uint64_t tiles1_cap, tiles2_cap, buckets_total, parts_total;
+    uint64_t tiles1_cap, tiles2_cap, buckets_cap, parts_cap;
     uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)
     uint32_t entry_words;      // of every instance in the launch
+    // persistent grids (binned_grids fills them; no query happens while a
+    // launch is being captured)
+    uint32_t grid_bin_count, grid_bin_scatter, grid_ref_count, grid_ref_scatter, grid_reduce;
 };
+
+// Fill the grid sizes of bb from occupancy and its capacities.
+void binned_grids(int device, BinBuffers &bb);
 
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanPerThread = 4;
 constexpr uint32_t kScanReads = kScanBlock * kScanPerThread;  // reads per scan block
 constexpr uint32_t kMapReads = 256;  // reads of one tile staged in LDS
 
-inline uint64_t packed_words(uint64_t bytes) { return (bytes + 31) / 32 + 2; }
+__host__ __device__ inline uint64_t packed_words(uint64_t bytes) { return (bytes + 31) / 32 + 2; }
 inline uint64_t scan_blocks(uint64_t n_reads) { return (n_reads + kScanReads - 1) / kScanReads; }
 inline uint64_t max_tiles(uint64_t bytes, uint64_t tile) { return bytes / tile + 2; }
 
-// Launchers (all stream-ordered; they only enqueue).
-hipError_t launch_prepare(Instance *inst, uint32_t m, InstStatus *st, CallState *cs,
-                          const uint64_t *offsets, uint64_t n_reads, hipStream_t s);
+// Launchers (all stream-ordered; they only enqueue).  `args` and `inst` are
+// device pointers; *_cap values are host upper bounds that size grids.
+hipError_t launch_prepare(const PassArgs *args, Instance *inst, InstStatus *st, CallState *cs,
+                          uint32_t m_cap, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *words, uint64_t n_words, hipStream_t s);
-hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bytes, uint64_t *packed,
-                       const Instance *inst, uint32_t m, InstStatus *st, hipStream_t s);
-// tile_read may be null (no tile map); max_windows bounds the total window
-// count (valid offsets give at most one window per byte).
-hipError_t launch_scan(const uint64_t *offsets, uint64_t n_reads, uint64_t reads_len,
-                       bool check_ends, const Instance *inst, uint32_t m, InstStatus *st,
-                       uint64_t *ws, uint64_t *partials, uint64_t *tile_read, uint64_t tile_cap,
-                       uint32_t tile, uint64_t max_windows, CallState *cs, hipStream_t s);
-hipError_t launch_build(const Instance *inst, uint32_t m, const uint64_t *packed,
-                        const uint64_t *offsets, const uint64_t *ws, const uint64_t *tile_read,
-                        uint64_t n_reads, InstStatus *st, CallState *cs, BuildShape shape,
-                        hipStream_t s);
+hipError_t launch_pack(const PassArgs *args, uint64_t *packed, const Instance *inst, InstStatus *st,
+                       uint64_t len_cap, hipStream_t s);
+// tile_read may be null (no tile map).
+hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *st, uint64_t *ws,
+                       uint64_t *partials, uint64_t *tile_read, CallState *cs, uint64_t n_cap,
+                       hipStream_t s);
+hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                        const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
+                        BuildShape shape, bool single, hipStream_t s);
 hipError_t launch_extract(const uint64_t *table, uint32_t entry_words, uint64_t cap,
                           uint64_t *out_keys, uint32_t *out_counts, uint64_t out_cap,
                           uint64_t *out_n, hipStream_t s);
@@ -173,10 +197,9 @@ hipError_t launch_count(const uint64_t *table, uint32_t entry_words, uint64_t ca
 hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32_t kind,
                            uint64_t seed, uint32_t block, uint64_t *sink, hipStream_t s);
 
-hipError_t launch_binned(const Instance *inst, uint32_t m, const uint64_t *packed,
-                         const uint64_t *offsets, const uint64_t *ws, uint64_t n_reads,
-                         InstStatus *st, const BinBuffers &bb, uint32_t merge, int device,
-                         hipStream_t s);
+hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                         const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
+                         int device, hipStream_t s);
 
 // Extraction of a binned table: seg_count (parts entries) is scanned into
 // seg_off (parts + 1 entries, using `partials` of ceil(parts / 1024) + 1

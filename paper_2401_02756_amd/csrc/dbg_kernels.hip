@@ -27,8 +27,11 @@ namespace dbgk {
 namespace {
 // ---------------------------------------------------------------- prepare
 
-__global__ void k_prepare(Instance *inst, uint32_t m, InstStatus *st, CallState *cs,
-                          const uint64_t *off, uint64_t n) {
+__global__ void k_prepare(const PassArgs *__restrict__ args, Instance *inst, InstStatus *st,
+                          CallState *cs) {
+    const uint32_t m = args->m;
+    const uint64_t n = args->n_reads;
+    const uint64_t *off = args->off;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) {
         st[i].err = inst[i].skip ? kErrSkip : 0u;
@@ -64,10 +67,13 @@ __global__ void k_fill_zero(uint64_t *__restrict__ words, uint64_t n_words) {
 // One thread per output word: 32 bases, letter code (c >> 1) & 3, first base
 // in bits 63..62.  Words past the input are zero (the build reads one word
 // beyond the last base of a window).
-__global__ __launch_bounds__(256) void k_pack(const uint8_t *__restrict__ ascii, uint64_t n,
-                                             uint64_t *__restrict__ packed, uint64_t n_words,
-                                             const Instance *__restrict__ inst, uint32_t m,
-                                             InstStatus *st) {
+__global__ __launch_bounds__(256) void k_pack(const PassArgs *__restrict__ args,
+                                             uint64_t *__restrict__ packed,
+                                             const Instance *__restrict__ inst, InstStatus *st) {
+    const uint8_t *__restrict__ ascii = args->reads;
+    const uint64_t n = args->reads_len;
+    const uint64_t n_words = packed_words(n);
+    const uint32_t m = args->m;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const bool aligned = (reinterpret_cast<uintptr_t>(ascii) & 15) == 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words; w += stride) {
@@ -133,12 +139,18 @@ __device__ __forceinline__ ReadCount count_read(const uint64_t *off, uint64_t of
 // k-mers and windows of each instance (one atomic per block when the block's
 // reads all belong to one instance, as they almost always do).
 __global__ __launch_bounds__(kScanBlock) void k_scan_local(
-    const uint64_t *__restrict__ off, uint64_t n, uint64_t len, int check_ends,
-    const Instance *__restrict__ inst, uint32_t m, InstStatus *st, uint64_t *__restrict__ ws,
-    uint64_t *__restrict__ partials) {
+    const PassArgs *__restrict__ args, const Instance *__restrict__ inst, InstStatus *st,
+    uint64_t *__restrict__ ws, uint64_t *__restrict__ partials) {
     __shared__ uint32_t s_t0, s_t1;
-    const uint64_t off0 = off[0];
+    const uint64_t *__restrict__ off = args->off;
+    const uint64_t n = args->n_reads, len = args->reads_len;
+    const uint32_t m = args->m, check_ends = args->check_ends;
     const uint64_t rb = (uint64_t)blockIdx.x * kScanReads;
+    if (rb >= n) {  // grid sized for the capacity: blocks past the reads add nothing
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0;
+        return;
+    }
+    const uint64_t off0 = off[0];
     const uint64_t r0 = rb + (uint64_t)threadIdx.x * kScanPerThread;
     if (threadIdx.x == 0) {
         s_t0 = m == 1 ? 0u : instance_of_read(inst, m, rb);
@@ -199,9 +211,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(
 // per byte, which is what the tile map is sized for; overlapping (malformed)
 // offsets can exceed that, and then every instance is flagged invalid and no
 // window is processed.
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *partials, uint64_t nb,
-                                                       CallState *cs, uint64_t max_windows,
-                                                       InstStatus *st, uint32_t m) {
+__global__ __launch_bounds__(1024) void k_scan_partials(const PassArgs *__restrict__ args,
+                                                       uint64_t *partials, uint64_t nb,
+                                                       CallState *cs, InstStatus *st) {
+    const uint64_t max_windows = args->max_windows;
+    const uint32_t m = args->m;
     uint64_t carry = 0;
     for (uint64_t base = 0; base < nb; base += blockDim.x) {
         const uint64_t i = base + threadIdx.x;
@@ -219,10 +233,12 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *partials, uint
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_add(
-    const uint64_t *__restrict__ off, uint64_t n, uint64_t len, int check_ends,
-    const Instance *__restrict__ inst, uint32_t m, uint64_t *__restrict__ ws,
-    const uint64_t *__restrict__ partials, uint64_t *__restrict__ tile_read, uint64_t tile_cap,
-    uint32_t tile) {
+    const PassArgs *__restrict__ args, const Instance *__restrict__ inst, uint64_t *__restrict__ ws,
+    const uint64_t *__restrict__ partials, uint64_t *__restrict__ tile_read) {
+    const uint64_t *__restrict__ off = args->off;
+    const uint64_t n = args->n_reads, len = args->reads_len, tile_cap = args->tile_cap;
+    const uint32_t m = args->m, check_ends = args->check_ends, tile = args->tile;
+    if ((uint64_t)blockIdx.x * kScanReads >= n) return;
     const uint64_t r0 = (uint64_t)blockIdx.x * kScanReads + (uint64_t)threadIdx.x * kScanPerThread;
     const uint64_t add = partials[blockIdx.x];
     const uint64_t off0 = off[0];
@@ -319,12 +335,15 @@ __device__ __forceinline__ uint32_t instance_state(const Instance *inst, uint32_
 }
 
 template <bool SINGLE, bool MERGE>
-__global__ __launch_bounds__(1024) void k_build(const Instance *__restrict__ inst, uint32_t m,
+__global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ args,
+                                               const Instance *__restrict__ inst,
                                                const uint64_t *__restrict__ packed,
-                                               const uint64_t *__restrict__ off,
                                                const uint64_t *__restrict__ ws,
-                                               const uint64_t *__restrict__ tile_read, uint64_t n,
+                                               const uint64_t *__restrict__ tile_read,
                                                InstStatus *st, CallState *cs, uint32_t wpt) {
+    const uint64_t *__restrict__ off = args->off;
+    const uint64_t n = args->n_reads;
+    const uint32_t m = args->m;
     __shared__ uint64_t s_ws[kMapReads + 1];
     __shared__ uint64_t s_delta[kMapReads];
     __shared__ uint32_t s_inst[kMapReads];  // instance index, bit 31 = skip
@@ -633,12 +652,11 @@ uint32_t grid_for(K kernel, int device, uint32_t block) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_prepare(Instance *inst, uint32_t m, InstStatus *st, CallState *cs,
-                          const uint64_t *offsets, uint64_t n_reads, hipStream_t s) {
+hipError_t launch_prepare(const PassArgs *args, Instance *inst, InstStatus *st, CallState *cs,
+                          uint32_t m_cap, hipStream_t s) {
     const uint32_t threads = 256;
-    const uint32_t blocks = (m + threads - 1) / threads;
-    hipLaunchKernelGGL(k_prepare, dim3(blocks ? blocks : 1), dim3(threads), 0, s, inst, m, st, cs,
-                       offsets, n_reads);
+    const uint32_t blocks = (m_cap + threads - 1) / threads;
+    hipLaunchKernelGGL(k_prepare, dim3(blocks ? blocks : 1), dim3(threads), 0, s, args, inst, st, cs);
     return hipGetLastError();
 }
 
@@ -651,56 +669,49 @@ hipError_t launch_fill_zero(uint64_t *words, uint64_t n_words, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const uint8_t *ascii, uint64_t n_bytes, uint64_t *packed, const Instance *inst,
-                       uint32_t m, InstStatus *st, hipStream_t s) {
-    const uint64_t n_words = packed_words(n_bytes);
+hipError_t launch_pack(const PassArgs *args, uint64_t *packed, const Instance *inst, InstStatus *st,
+                       uint64_t len_cap, hipStream_t s) {
+    const uint64_t n_words = packed_words(len_cap);
     const uint64_t want = (n_words + 255) / 256;
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256 * 64);
-    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, ascii, n_bytes, packed, n_words, inst,
-                       m, st);
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 256 * 64));
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, args, packed, inst, st);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const uint64_t *offsets, uint64_t n_reads, uint64_t reads_len, bool check_ends,
-                       const Instance *inst, uint32_t m, InstStatus *st, uint64_t *ws,
-                       uint64_t *partials, uint64_t *tile_read, uint64_t tile_cap, uint32_t tile,
-                       uint64_t max_windows, CallState *cs, hipStream_t s) {
-    if (n_reads == 0) return hipSuccess;
-    const uint64_t nb = scan_blocks(n_reads);
-    hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, offsets, n_reads,
-                       reads_len, check_ends ? 1 : 0, inst, m, st, ws, partials);
+hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *st, uint64_t *ws,
+                       uint64_t *partials, uint64_t *tile_read, CallState *cs, uint64_t n_cap,
+                       hipStream_t s) {
+    const uint64_t nb = std::max<uint64_t>(1, scan_blocks(n_cap));
+    hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, args, inst, st, ws,
+                       partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb, cs, max_windows,
-                       st, m);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, args, partials, nb, cs, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, offsets, n_reads,
-                       reads_len, check_ends ? 1 : 0, inst, m, ws, partials, tile_read, tile_cap,
-                       tile);
+    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, args, inst, ws, partials,
+                       tile_read);
     return hipGetLastError();
 }
 
-hipError_t launch_build(const Instance *inst, uint32_t m, const uint64_t *packed,
-                        const uint64_t *offsets, const uint64_t *ws, const uint64_t *tile_read,
-                        uint64_t n_reads, InstStatus *st, CallState *cs, BuildShape shape,
-                        hipStream_t s) {
-    if (n_reads == 0) return hipSuccess;
+hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                        const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
+                        BuildShape shape, bool single, hipStream_t s) {
     const dim3 g(shape.grid), b(shape.block);
-    if (m == 1) {
+    if (single) {
         if (shape.merge)
-            hipLaunchKernelGGL((k_build<true, true>), g, b, 0, s, inst, m, packed, offsets, ws,
-                               tile_read, n_reads, st, cs, shape.wpt);
+            hipLaunchKernelGGL((k_build<true, true>), g, b, 0, s, args, inst, packed, ws, tile_read, st, cs,
+                               shape.wpt);
         else
-            hipLaunchKernelGGL((k_build<true, false>), g, b, 0, s, inst, m, packed, offsets, ws,
-                               tile_read, n_reads, st, cs, shape.wpt);
+            hipLaunchKernelGGL((k_build<true, false>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
+                               cs, shape.wpt);
     } else {
         if (shape.merge)
-            hipLaunchKernelGGL((k_build<false, true>), g, b, 0, s, inst, m, packed, offsets, ws,
-                               tile_read, n_reads, st, cs, shape.wpt);
+            hipLaunchKernelGGL((k_build<false, true>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
+                               cs, shape.wpt);
         else
-            hipLaunchKernelGGL((k_build<false, false>), g, b, 0, s, inst, m, packed, offsets, ws,
-                               tile_read, n_reads, st, cs, shape.wpt);
+            hipLaunchKernelGGL((k_build<false, false>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
+                               cs, shape.wpt);
     }
     return hipGetLastError();
 }

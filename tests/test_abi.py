@@ -45,7 +45,7 @@ def test_binding_codes_match_header():
 def test_struct_layouts_match_header():
     # dbg_config: 2 x u64, double, i32, 3 x u32, pointer -> 48 bytes on LP64
     assert ctypes.sizeof(dbg.Config) == 48
-    assert ctypes.sizeof(dbg.Stats) == 6 * 8 + 8 + 16 + 16
+    assert ctypes.sizeof(dbg.Stats) == 6 * 8 + 8 + 16 + 16 + 16 + 8
     assert ctypes.sizeof(dbg.Input) == 32
 
 

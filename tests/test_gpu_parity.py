@@ -413,6 +413,51 @@ def test_batch_device_matches_plain_device(mode):
             g.close()
 
 
+# ---------------------------------------------------------------- graph capture and replay
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_graph_replays_match_eager(mode):
+    say("graph capture + replays vs eager, mode %d" % mode)
+    a = readsim.make_config(1)
+    b = readsim.simulate(10_000, 100, 10.0, 0.005, 21, 77)  # same size class, other data
+    want_a, want_b = oracle_of(a), oracle_of(b)
+    eager = gpu_build(a, flags=mode)
+    assert_same(eager, want_a, "eager")
+    da = (torch.from_numpy(a.reads).cuda(), torch.from_numpy(a.offsets.astype(np.int64)).cuda())
+    db = (torch.from_numpy(b.reads).cuda(), torch.from_numpy(b.offsets.astype(np.int64)).cuda())
+    with dbg.Graph(flags=mode | dbg.F_GRAPH, expected_vertices=20000) as g:
+        for rep in range(4):
+            for (dr, do), rs, want in ((da, a, want_a), (db, b, want_b)):
+                g.reset()
+                g.build_device(dr, do, rs.k)
+                g.sync()
+                assert_same(g.extract_sorted(), want, "replay %d" % rep)
+                # eager work and a sync between replays
+                x = torch.arange(1 << 20, device="cuda", dtype=torch.int64).sum()
+                torch.cuda.synchronize()
+                assert int(x) == (1 << 20) * ((1 << 20) - 1) // 2
+        st = g.stats()
+    assert st["graph_captures"] >= 1 and st["graph_replays"] >= 6, st
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_graph_batch_replays(mode):
+    say("batched build through graphs, mode %d" % mode)
+    sets = [readsim.make_instance(4, j) for j in range(3)]
+    sets = [s for s in sets if s.total_bases < 30_000_000]
+    wants = [oracle_of(s) for s in sets]
+    for rep in range(3):
+        graphs = [dbg.Graph(flags=mode | dbg.F_GRAPH) for _ in sets]
+        try:
+            st = dbg.build_batch(graphs, [(s.reads, s.offsets, s.k) for s in sets])
+            assert st == [0] * len(sets)
+            for g, want in zip(graphs, wants):
+                assert_same(g.extract_sorted(), want, "batch replay %d" % rep)
+        finally:
+            for g in graphs:
+                g.close()
+
+
 # ---------------------------------------------------------------- measurement kernel
 
 def test_roofline_kernel_runs():
