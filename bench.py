@@ -43,11 +43,27 @@ def log(msg: str) -> None:
 
 def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int,
                       vertices_new: int) -> int:
-    """Bytes the build kernel must move per launch, by its algorithm:
+    """Bytes the direct build kernel must move per launch, by its algorithm:
     one 8-byte key read per window looked up, one 4-byte counter read and
     written per k-mer, one 8-byte key written per vertex claimed, the packed
     reads (2 bits per base) and, per read, its offset and window prefix."""
     return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
+
+
+def binned_phase_bytes(n_reads: int, total_bases: int, windows: int, vertices: int) -> dict:
+    """Algorithmic bytes of each phase of a binned build into an empty table
+    (8-byte window records, 24-byte vertex entries):
+      setup       ASCII in, packed reads out, offsets in, window prefix out;
+      partition1  packed reads read by the count and the scatter kernel,
+                  records written;
+      partition2  records read by the count and the scatter kernel, written;
+      reduce      records read, packed vertex entries written;
+      extract     vertex entries read, keys and counters written."""
+    return {"setup": total_bases + total_bases // 4 + 24 * n_reads,
+            "partition1": 2 * (total_bases // 4) + 8 * windows,
+            "partition2": 3 * 8 * windows,
+            "reduce": 8 * windows + 24 * vertices,
+            "extract": 2 * 24 * vertices}
 
 
 def cpu_baseline(rs, sample_reads: int) -> dict:
@@ -83,6 +99,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=250_000)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a 1 GiB read (sum) and a 1 GiB write (zero fill) of known size, "
+                         "to scale hardware traffic counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,11 +128,11 @@ def main() -> int:
     inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
     windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
 
-    def run(mode: str, steps: int, warmup: int):
+    def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
         flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
         if mode == "binned":
             flags |= dbg.F_BINNED
-        if not args.no_graph:
+        if graphs:
             flags |= dbg.F_GRAPH
         g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
                       device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
@@ -130,7 +149,7 @@ def main() -> int:
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        build_ms, total_ms = [], []
+        build_ms, total_ms, phases = [], [], []
         V = 0
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -138,28 +157,55 @@ def main() -> int:
             s = g.stats()
             build_ms.append(s["last_build_ms"])
             total_ms.append(s["last_total_ms"])
+            phases.append(g.phase_times())
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        tx = []
+        for _ in range(3):  # extraction alone, host-timed around the synchronous call
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g.extract_device(d_keys, d_counts)
+            tx.append((time.perf_counter() - t1) * 1000.0)
         st = g.stats()
         assert st["inserts"] == inserts, (st["inserts"], inserts)
         g.close()
         del d_keys, d_counts
         return dict(V=V, cap=cap_out, st=st, ms_step=dt * 1000.0 / steps,
                     value=inserts / (dt / steps) / 1e9, kern_ms=float(np.mean(build_ms)),
-                    pass_ms=float(np.mean(total_ms)))
+                    pass_ms=float(np.mean(total_ms)),
+                    phases=[float(x) for x in np.mean(np.array(phases), axis=0)] if phases else [],
+                    extract_ms=float(np.median(tx)))
+
+    if args.calibrate:
+        # k_stream_copy: reads 1 GiB and writes 1 GiB with 16-byte accesses
+        # (run twice: one warm-up, one timed launch)
+        dbg.atomic_roofline(dbg.ROOF_COPY, 2 << 30, 0, 256, 1)
+        log("calibration: streaming copy of 1 GiB")
 
     r = run(args.mode, args.steps, args.warmup)
     V, cap_out, st, ms_step, value, kern_ms = r["V"], r["cap"], r["st"], r["ms_step"], r["value"], r["kern_ms"]
     log("%s: step %.3f ms, build %.3f ms (pass %.3f ms), V=%d, cap=%d, graph captures %d replays %d" %
         (args.mode, ms_step, kern_ms, r["pass_ms"], V, cap_out, st["graph_captures"], st["graph_replays"]))
 
-    bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
-    achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
+    phase_table = None
+    if args.mode == "binned":
+        # phase times from an uncaptured timed run (events between the phases)
+        pr = r if args.no_graph else run("binned", 5, 1, graphs=False)
+        names = ["setup", "partition1", "partition2", "reduce"]
+        pb = binned_phase_bytes(rs.n_reads, rs.total_bases, windows, V)
+        phase_table = []
+        for name, ms in list(zip(names, pr["phases"])) + [("extract", pr["extract_ms"])]:
+            phase_table.append({"phase": name, "ms": round(ms, 4), "algorithmic_bytes": pb[name],
+                                "gbs": round(pb[name] / (ms * 1e-3) / 1e9, 1)})
+        red = phase_table[3]
+        bytes_alg, k_ms, kname = red["algorithmic_bytes"], red["ms"], "k_reduce (binned segment reduce)"
+    else:
+        bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
+        k_ms, kname = kern_ms, "k_build (direct find-or-claim + count)"
+    achieved = bytes_alg / (k_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": ("binned build (partition passes + LDS segment reduce)" if args.mode == "binned"
-                       else "k_build (persistent find-or-claim + count)"),
-            "kernel_ms": round(kern_ms, 4), "algorithmic_bytes": bytes_alg}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "kernel_ms": round(k_ms, 4), "algorithmic_bytes": bytes_alg}
 
     line = {
         "metric": "k-mer inserts/sec (G/s)",
@@ -184,6 +230,8 @@ def main() -> int:
         "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
         "roofline": roof,
     }
+    if phase_table:
+        line["phases"] = phase_table
 
     if not args.no_compare:
         other = "direct" if args.mode == "binned" else "binned"

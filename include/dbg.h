@@ -166,6 +166,13 @@ int dbg_reset(dbg_graph *g);
 /* Counters and launch shape of the handle (synchronises first). */
 int dbg_get_stats(dbg_graph *g, dbg_stats *out);
 
+/* Device time of each phase of the handle's last timed build (DBG_F_TIMING),
+ * in ms, in this order: setup (argument copy, prepare, pack, window scan),
+ * then, for a binned build launched without a graph, partition pass 1,
+ * partition pass 2 and segment reduce, else the whole build.  Writes
+ * min(cap, *n_phases) values; *n_phases is 0 before any timed build. */
+int dbg_get_phase_times(dbg_graph *g, double *ms, uint32_t cap, uint32_t *n_phases);
+
 /* Release all device memory of the handle.  NULL is ignored. */
 void dbg_destroy(dbg_graph *g);
 
@@ -207,7 +214,10 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
  * a 64-bit mixer over a footprint of footprint_bytes (no index array is
  * read).  kind: 0 = 64-bit load, 1 = 32-bit atomic add (no return),
  * 2 = 64-bit atomic compare-and-swap (returning), 3 = 64-bit load then a
- * 32-bit atomic add into the same 24-byte entry.  Returns the median kernel
+ * 32-bit atomic add into the same 24-byte entry, 4 = streaming copy of the
+ * first half of the footprint onto the second with 16-byte loads and stores
+ * (n_ops ignored; a copy of known size for scaling traffic counters).
+ * Returns the median kernel
  * time over `repeats` timed launches (after one warm-up) in *ms.  Allocates
  * and frees its own footprint. */
 int dbg_atomic_roofline(int32_t device, uint32_t kind, uint64_t footprint_bytes, uint64_t n_ops,

@@ -31,6 +31,7 @@ EXPORTS = (
     "dbg_config_init", "dbg_create", "dbg_build", "dbg_build_device", "dbg_sync",
     "dbg_extract", "dbg_extract_device", "dbg_reset", "dbg_get_stats", "dbg_destroy",
     "dbg_strerror", "dbg_build_batch", "dbg_build_batch_device", "dbg_atomic_roofline",
+    "dbg_get_phase_times",
 )
 
 
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
             "dbg_build_batch_device": (ctypes.c_int, [vp, u32, vp, vp, vp, u64, vp, vp, vp]),
             "dbg_atomic_roofline": (ctypes.c_int, [i32, u32, u64, u64, u32, u32,
                                                    ctypes.POINTER(ctypes.c_double)]),
+            "dbg_get_phase_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), u32,
+                                                   ctypes.POINTER(u32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -238,6 +241,13 @@ class Graph:
         _check(rc, "dbg_extract_device")
         return int(n.value)
 
+    def phase_times(self) -> list[float]:
+        """Per-phase device ms of the last timed build (see dbg_get_phase_times)."""
+        buf = (ctypes.c_double * 8)()
+        n = ctypes.c_uint32(0)
+        _check(lib().dbg_get_phase_times(self.handle, buf, 8, ctypes.byref(n)), "dbg_get_phase_times")
+        return [float(buf[i]) for i in range(min(8, n.value))]
+
     def reset(self) -> None:
         _check(lib().dbg_reset(self.handle), "dbg_reset")
 
@@ -281,7 +291,7 @@ def build_batch_device(graphs: list[Graph], read_begin, ks, d_reads, d_offsets,
     return [int(st[i]) for i in range(m)]
 
 
-ROOF_LOAD64, ROOF_ADD32, ROOF_CAS64, ROOF_LOAD_ADD = 0, 1, 2, 3
+ROOF_LOAD64, ROOF_ADD32, ROOF_CAS64, ROOF_LOAD_ADD, ROOF_COPY = 0, 1, 2, 3, 4
 
 
 def atomic_roofline(kind: int, footprint_bytes: int, n_ops: int, block_size: int = 256,

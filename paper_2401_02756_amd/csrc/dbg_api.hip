@@ -167,6 +167,8 @@ struct Pass {
     DevBuf tread1, tbucket2;
     HostBuf hargs, hstatus;  // pinned: PassArgs + Instance[m_cap]; InstStatus[m_cap] + CallState
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+    hipEvent_t marks[2] = {nullptr, nullptr};  // binned phase boundaries (timed, uncaptured)
+    bool marked = false;
     hipStream_t cap_stream = nullptr;
     uint32_t m = 0;
     hipStream_t stream = nullptr;
@@ -187,6 +189,8 @@ struct Pass {
         if (e == hipSuccess) e = hipEventCreate(&ev_b);
         if (e == hipSuccess) e = hipEventCreate(&ev_c);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&marks[0]);
+        if (e == hipSuccess) e = hipEventCreate(&marks[1]);
         return e;
     }
     void drop_graphs() {
@@ -207,6 +211,8 @@ struct Pass {
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
         if (ev_c) (void)hipEventDestroy(ev_c);
+        for (hipEvent_t &x : marks)
+            if (x) (void)hipEventDestroy(x), x = nullptr;
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         ev_a = ev_b = ev_c = nullptr;
         cap_stream = nullptr;
@@ -306,14 +312,16 @@ struct Pass {
                                   k.binned ? nullptr : tiles.as<uint64_t>(), cs, k.n_cap, s);
         return e;
     }
-    hipError_t enqueue_build(const PassKey &k, const dbgk::BinBuffers &bb, int device, hipStream_t s) {
+    hipError_t enqueue_build(const PassKey &k, const dbgk::BinBuffers &bb, int device, hipStream_t s,
+                             bool mark = false) {
         dbgk::PassArgs *da = dargs.as<dbgk::PassArgs>();
         Instance *di = reinterpret_cast<Instance *>(dargs.as<unsigned char>() + dbgk::kArgsBytes);
         InstStatus *dst = dstatus.as<InstStatus>();
         CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
         hipError_t e;
         if (k.binned)
-            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s);
+            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s,
+                                    mark ? marks : nullptr);
         else
             e = dbgk::launch_build(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
                                    cs, k.shape, k.single != 0, s);
@@ -421,7 +429,8 @@ struct Pass {
         if (time_it) (void)hipEventRecord(ev_a, s);
         e = c ? hipGraphLaunch(c->setup, s) : enqueue_setup(k, s);
         if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
-        if (e == hipSuccess) e = c ? hipGraphLaunch(c->build, s) : enqueue_build(k, bb, device, s);
+        marked = !c && time_it && binned;
+        if (e == hipSuccess) e = c ? hipGraphLaunch(c->build, s) : enqueue_build(k, bb, device, s, marked);
         if (time_it && e == hipSuccess) (void)hipEventRecord(ev_c, s);
         if (e != hipSuccess) return e;
         m = mm;
@@ -431,15 +440,29 @@ struct Pass {
         return hipSuccess;
     }
 
+    // Phase times of the last timed pass, in ms: setup, then (binned,
+    // uncaptured) partition 1, partition 2, reduce, or (otherwise) build.
+    double phase_ms[4] = {0, 0, 0, 0};
+    uint32_t n_phases = 0;
+
     // Wait for the enqueued pass; times in ms when it was timed.
     hipError_t wait(double *build_ms, double *total_ms) {
         if (!pending) return hipSuccess;
         pending = false;
         hipError_t e = hipStreamSynchronize(stream);
         if (e == hipSuccess && timing) {
-            float a = 0, b = 0;
+            float a = 0, b = 0, x = 0;
             if (hipEventElapsedTime(&a, ev_b, ev_c) == hipSuccess && build_ms) *build_ms = a;
             if (hipEventElapsedTime(&b, ev_a, ev_c) == hipSuccess && total_ms) *total_ms = b;
+            n_phases = 0;
+            if (hipEventElapsedTime(&x, ev_a, ev_b) == hipSuccess) phase_ms[n_phases++] = x;
+            if (marked) {
+                if (hipEventElapsedTime(&x, ev_b, marks[0]) == hipSuccess) phase_ms[n_phases++] = x;
+                if (hipEventElapsedTime(&x, marks[0], marks[1]) == hipSuccess) phase_ms[n_phases++] = x;
+                if (hipEventElapsedTime(&x, marks[1], ev_c) == hipSuccess) phase_ms[n_phases++] = x;
+            } else {
+                phase_ms[n_phases++] = a;
+            }
         }
         return e;
     }
@@ -951,6 +974,18 @@ void dbg_destroy(dbg_graph *g) {
     delete g;
 }
 
+int dbg_get_phase_times(dbg_graph *g, double *ms, uint32_t cap, uint32_t *n_phases) {
+    if (!g || !n_phases || (cap && !ms)) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    *n_phases = g->pass.n_phases;
+    for (uint32_t i = 0; i < g->pass.n_phases && i < cap; ++i) ms[i] = g->pass.phase_ms[i];
+    return DBG_OK;
+}
+
 const char *dbg_strerror(int code) {
     switch (code) {
     case DBG_OK: return "ok";
@@ -1094,7 +1129,7 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
 
 int dbg_atomic_roofline(int32_t device, uint32_t kind, uint64_t footprint_bytes, uint64_t n_ops,
                         uint32_t block_size, uint32_t repeats, double *ms) {
-    if (!ms || kind > 3 || footprint_bytes < 64 || block_size == 0 || block_size % 64 ||
+    if (!ms || kind > 4 || footprint_bytes < 64 || block_size == 0 || block_size % 64 ||
         block_size > 1024)
         return DBG_E_INVAL;
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;

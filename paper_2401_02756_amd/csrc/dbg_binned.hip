@@ -835,7 +835,8 @@ uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint
 
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                          const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
-                         int device, hipStream_t s) {
+                         int device, hipStream_t s, hipEvent_t *marks) {
+    (void)device;
     hipError_t e;
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -860,6 +861,7 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
                        bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks) (void)hipEventRecord(marks[0], s);
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
@@ -889,6 +891,7 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P + 255) / 256, 4096));
     hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, args, inst, bb.plan, bb.buckets, bb.scan2,
                        bb.totals, bb.pstart);
+    if (marks) (void)hipEventRecord(marks[1], s);
     // every instance of a binned launch has the same entry width
     const uint32_t gr = bb.grid_reduce;
     if (bb.entry_words == 4)

@@ -197,9 +197,11 @@ hipError_t launch_count(const uint64_t *table, uint32_t entry_words, uint64_t ca
 hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32_t kind,
                            uint64_t seed, uint32_t block, uint64_t *sink, hipStream_t s);
 
+// marks, when not null, are two events recorded after the first partition
+// pass and before the segment reduce (phase timing; never under capture).
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                          const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
-                         int device, hipStream_t s);
+                         int device, hipStream_t s, hipEvent_t *marks);
 
 // Extraction of a binned table: seg_count (parts entries) is scanned into
 // seg_off (parts + 1 entries, using `partials` of ceil(parts / 1024) + 1

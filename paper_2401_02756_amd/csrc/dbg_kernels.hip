@@ -636,6 +636,16 @@ __global__ __launch_bounds__(1024) void k_roofline(uint64_t *mem, uint64_t words
     if (acc == 0x5eed5eed5eed5eedull) sink[0] = acc;
 }
 
+// Streaming copy of the first half of mem onto the second, 16 bytes per
+// load and store: a plain copy of known size for scaling traffic counters.
+__global__ __launch_bounds__(1024) void k_stream_copy(uint64_t *mem, uint64_t words) {
+    const uint64_t half = (words / 2) & ~1ull;
+    const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(mem);
+    ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(mem + half);
+    const uint64_t n = half / 2, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 template <typename K>
 uint32_t grid_for(K kernel, int device, uint32_t block) {
     int cus = 0, per = 0;
@@ -738,6 +748,11 @@ hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32
                            uint32_t block, uint64_t *sink, hipStream_t s) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (kind == 4) {
+        const uint32_t grid = grid_for(k_stream_copy, dev, block);
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(block), 0, s, mem, words);
+        return hipGetLastError();
+    }
     const uint32_t grid = grid_for(k_roofline, dev, block);
     hipLaunchKernelGGL(k_roofline, dim3(grid), dim3(block), 0, s, mem, words, n_ops, kind, seed, sink);
     return hipGetLastError();
