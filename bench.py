@@ -50,6 +50,27 @@ def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int
     return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
 
 
+def committed_traffic(profile: str, sources: list) -> int | None:
+    """HBM bytes per launch recorded by the counter runs in `profile`, or
+    None when any of the kernel sources changed since they were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in fields.get("sources", "").split():
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if not fields.get("sources") or h.hexdigest() != fields.get("source_sha256"):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def binned_phase_bytes(n_reads: int, total_bases: int, windows: int, vertices: int) -> dict:
     """Algorithmic bytes of each phase of a binned build into an empty table
     (8-byte window records, 24-byte vertex entries):
@@ -64,6 +85,70 @@ def binned_phase_bytes(n_reads: int, total_bases: int, windows: int, vertices: i
             "partition2": 3 * 8 * windows,
             "reduce": 8 * windows + 24 * vertices,
             "extract": 2 * 24 * vertices}
+
+
+def batched_bench(dbg, torch, dev, n_inst: int, reps: int, graphs_on: bool) -> dict:
+    """256 independent read sets (genomes log-uniform in [10 kbp, 2 Mbp],
+    coverage U[10, 50], L in {100, 150}, substitutions U[0.5, 1] %, k in
+    {21, 31}) built (a) in one batched call over one device-resident
+    concatenation and (b) one plain build per set on slices of the same
+    buffers, into the same per-set tables.  Aggregate k-mer inserts/s of each,
+    with build passes only (tables reset lazily between repetitions)."""
+    import concurrent.futures
+    import readsim
+
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        sets = list(ex.map(lambda j: readsim.make_instance(4, j), range(n_inst)))
+    gen_s = time.perf_counter() - t0
+    lens = np.concatenate([x.lengths() for x in sets])
+    offs = np.zeros(lens.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    rb = np.zeros(n_inst + 1, np.uint64)
+    np.cumsum([x.n_reads for x in sets], out=rb[1:])
+    ks = [x.k for x in sets]
+    inserts = int(sum(int(np.maximum(x.lengths() - x.k + 1, 0).sum()) for x in sets))
+    d_reads = torch.from_numpy(np.concatenate([x.reads for x in sets])).to(dev)
+    d_off = torch.from_numpy(offs).to(dev)
+    del sets
+    flags = dbg.F_BINNED | (dbg.F_GRAPH if graphs_on else 0)
+    gs = []
+    for j in range(n_inst):
+        p = readsim.instance_params(4, j)
+        gs.append(dbg.Graph(expected_vertices=p["expected_vertices"], load_factor=0.5, device=0, flags=flags))
+
+    def batched():
+        for g in gs:
+            g.reset()
+        st = dbg.build_batch_device(gs, rb, ks, d_reads, d_off)
+        assert st == [0] * n_inst, st
+
+    def plain():
+        for j, g in enumerate(gs):
+            g.reset()
+            a, z = int(rb[j]), int(rb[j + 1])
+            g.build_device(d_reads[int(offs[a]):int(offs[z])], d_off[a:z + 1], ks[j])
+            g.sync()
+
+    out = {"workload": "batched: %d read sets, %d k-mer inserts, %.2f Gbp" % (n_inst, inserts, offs[-1] / 1e9),
+           "generation_s": round(gen_s, 1)}
+    for name, fn in (("batched", batched), ("plain_per_instance", plain)):
+        fn()  # warm-up (allocates scratch, captures graphs)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t1)
+        best = float(np.median(t))
+        out[name] = {"ms": round(best * 1e3, 3), "ginserts_s": round(inserts / best / 1e9, 4)}
+    vb = sum(g.vertex_count() for g in gs)
+    out["vertices"] = vb
+    out["batched_over_plain"] = round(out["batched"]["ginserts_s"] / out["plain_per_instance"]["ginserts_s"], 3)
+    for g in gs:
+        g.close()
+    return out
 
 
 def cpu_baseline(rs, sample_reads: int) -> dict:
@@ -99,6 +184,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=250_000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-build comparison")
+    ap.add_argument("--batched-sets", type=int, default=256)
+    ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB read (sum) and a 1 GiB write (zero fill) of known size, "
                          "to scale hardware traffic counters")
@@ -199,12 +287,14 @@ def main() -> int:
                                 "gbs": round(pb[name] / (ms * 1e-3) / 1e9, 1)})
         red = phase_table[3]
         bytes_alg, k_ms, kname = red["algorithmic_bytes"], red["ms"], "k_reduce (binned segment reduce)"
+        traffic = committed_traffic("k_reduce_traffic_bacterial_c2.md", []) if args.config == 2 else None
     else:
         bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
         k_ms, kname = kern_ms, "k_build (direct find-or-claim + count)"
+        traffic = None
     achieved = bytes_alg / (k_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
             "kernel_ms": round(k_ms, 4), "algorithmic_bytes": bytes_alg}
 
     line = {
@@ -240,6 +330,11 @@ def main() -> int:
                                    "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
                                    "build_ms": round(o["kern_ms"], 4)}
         log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
+
+    if not args.no_batched:
+        line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps,
+                                        not args.no_graph)
+        log("batched %s" % json.dumps(line["batched"]))
 
     if not args.no_roofline:
         foot = int(st["table_bytes"])
