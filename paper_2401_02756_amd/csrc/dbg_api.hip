@@ -1,745 +1,15 @@
-// Host runtime and C ABI of libdbg: table sizing and allocation, input
-// staging, the stream-ordered build pass, status readback, extraction, the
-// batched build and the random-access roofline.
+// C ABI of libdbg (the declarations and their contracts are in dbg.h).
 //
 // The paper's constructor takes k, the thread count, the hash table size and
 // the genome size (Methods, "Code organization"); here a handle takes the
 // table size (capacity, or expected vertices and a load factor) and the launch
 // shape; k is fixed by the first build.
-#include "dbg.h"
-#include "dbg_kernels.h"
+#include "dbg_runtime.h"
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdlib>
-#include <cstring>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <vector>
-
+using namespace dbgrt;
 using dbgk::CallState;
 using dbgk::Instance;
 using dbgk::InstStatus;
-
-namespace {
-
-constexpr uint64_t kCounterLimit = 0xffffffffull;
-
-// Grow-only device buffer.
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t reserve(size_t want) {
-        if (want <= bytes) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-        }
-        p = nullptr;
-        bytes = 0;
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) bytes = want;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-// Grow-only pinned host buffer.
-struct HostBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t reserve(size_t want) {
-        if (want <= bytes) return hipSuccess;
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        bytes = 0;
-        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
-        if (e == hipSuccess) bytes = want;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-// Makes `device` current for the scope of a call and restores the caller's.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int device) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (device >= 0 && device != prev) ok = hipSetDevice(device) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-int err_code_of(uint32_t bits) {
-    if (bits & dbgk::kErrInval) return DBG_E_INVAL;
-    if (bits & dbgk::kErrBase) return DBG_E_BASE;
-    if (bits & dbgk::kErrRange) return DBG_E_RANGE;
-    if (bits & dbgk::kErrFull) return DBG_E_FULL;
-    return DBG_OK;
-}
-
-bool validation_error(uint32_t bits) {
-    return bits & (dbgk::kErrInval | dbgk::kErrBase | dbgk::kErrRange);
-}
-
-int hip_code(hipError_t e) {
-    if (e == hipSuccess) return DBG_OK;
-    return e == hipErrorOutOfMemory ? DBG_E_NOMEM : DBG_E_DEVICE;
-}
-
-// Windows and k-mers of host-resident offsets; false if offsets decrease.
-bool host_counts(const uint64_t *off, uint64_t n, uint32_t k, uint64_t *windows, uint64_t *kmers) {
-    uint64_t w = 0, e = 0;
-    for (uint64_t i = 0; i < n; ++i) {
-        if (off[i + 1] < off[i]) return false;
-        const uint64_t L = off[i + 1] - off[i];
-        if (L >= k) {
-            w += L - k + 2;
-            e += L - k + 1;
-        }
-    }
-    *windows = w;
-    *kmers = e;
-    return true;
-}
-
-uint64_t capacity_for(uint64_t vertices, double lf) {
-    const double c = std::ceil((double)vertices / lf);
-    return std::max<uint64_t>(64, (uint64_t)c);
-}
-
-// Capacity of a buffer dimension: x rounded up to a multiple of an eighth of
-// its power of two (at most 12.5 % slack), so that calls of similar size share
-// buffers and captured graphs.
-uint64_t size_class(uint64_t x, uint64_t floor) {
-    x = std::max(x, floor);
-    uint64_t p = 1;
-    while (p < x) p <<= 1;
-    const uint64_t g = std::max<uint64_t>(p / 8, 1);
-    return (x + g - 1) / g * g;
-}
-
-// What a captured pass depends on besides its buffers.
-struct PassKey {
-    int binned = 0;
-    int single = 0;
-    uint32_t ew = 3;
-    uint32_t m_cap = 0, d1_cap = 0, fan_cap = 0;
-    uint64_t n_cap = 0, len_cap = 0, parts_cap = 0, buckets_cap = 0;
-    dbgk::BuildShape shape{};
-    bool operator==(const PassKey &o) const {
-        return binned == o.binned && single == o.single && ew == o.ew && m_cap == o.m_cap &&
-               d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
-               parts_cap == o.parts_cap && buckets_cap == o.buckets_cap && shape.block == o.shape.block &&
-               shape.wpt == o.shape.wpt && shape.grid == o.shape.grid && shape.merge == o.shape.merge;
-    }
-};
-
-// Buffers and launch sequence of one build pass over m instances.  With
-// graphs enabled the pass is captured as two HIP graphs (setup: arguments,
-// prepare, pack, scan; build: the build kernels and the status readback) on
-// first use of a size class and replayed afterwards; every size and input
-// pointer reaches the kernels through the PassArgs block in device memory,
-// so a replay needs no kernel argument to change.
-struct Pass {
-    DevBuf packed, ws, partials, tiles, dargs, dstatus;
-    // binned-mode scratch
-    DevBuf bplan, bbuckets, btotals, hist1, scan1, hist2, scan2, bpartials, rec1, rec2, pstart;
-    DevBuf tread1, tbucket2;
-    HostBuf hargs, hstatus;  // pinned: PassArgs + Instance[m_cap]; InstStatus[m_cap] + CallState
-    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
-    hipEvent_t marks[2] = {nullptr, nullptr};  // binned phase boundaries (timed, uncaptured)
-    bool marked = false;
-    hipStream_t cap_stream = nullptr;
-    uint32_t m = 0;
-    hipStream_t stream = nullptr;
-    bool pending = false;
-    bool timing = false;
-    bool use_graphs = false;
-    uint64_t generation = 0;  // bumped whenever a buffer moves
-    struct Cached {
-        PassKey key;
-        uint64_t generation;
-        hipGraphExec_t setup, build;
-    };
-    std::vector<Cached> graphs;
-    uint64_t captures = 0, replays = 0;
-
-    hipError_t init() {
-        hipError_t e = hipEventCreate(&ev_a);
-        if (e == hipSuccess) e = hipEventCreate(&ev_b);
-        if (e == hipSuccess) e = hipEventCreate(&ev_c);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreate(&marks[0]);
-        if (e == hipSuccess) e = hipEventCreate(&marks[1]);
-        return e;
-    }
-    void drop_graphs() {
-        for (auto &c : graphs) {
-            if (c.setup) (void)hipGraphExecDestroy(c.setup);
-            if (c.build) (void)hipGraphExecDestroy(c.build);
-        }
-        graphs.clear();
-    }
-    void release() {
-        drop_graphs();
-        DevBuf *d[] = {&packed, &ws, &partials, &tiles, &dargs, &dstatus, &bplan, &bbuckets,
-                       &btotals, &hist1, &scan1, &hist2, &scan2, &bpartials, &rec1, &rec2, &pstart,
-                       &tread1, &tbucket2};
-        for (DevBuf *b : d) b->release();
-        hargs.release();
-        hstatus.release();
-        if (ev_a) (void)hipEventDestroy(ev_a);
-        if (ev_b) (void)hipEventDestroy(ev_b);
-        if (ev_c) (void)hipEventDestroy(ev_c);
-        for (hipEvent_t &x : marks)
-            if (x) (void)hipEventDestroy(x), x = nullptr;
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        ev_a = ev_b = ev_c = nullptr;
-        cap_stream = nullptr;
-    }
-    // Grow a buffer; a move invalidates every captured graph.
-    hipError_t grow(DevBuf &b, size_t bytes) {
-        const void *old = b.p;
-        const hipError_t e = b.reserve(bytes);
-        if (b.p != old && old) ++generation;
-        return e;
-    }
-    hipError_t reserve_instances(uint32_t mm) {
-        const uint32_t m_cap = (uint32_t)size_class(mm, 1);
-        const void *pa = hargs.p, *ps = hstatus.p;
-        hipError_t e = hargs.reserve(dbgk::kArgsBytes + sizeof(Instance) * m_cap);
-        if (e == hipSuccess) e = hstatus.reserve(sizeof(InstStatus) * m_cap + sizeof(CallState));
-        if ((pa && hargs.p != pa) || (ps && hstatus.p != ps)) ++generation;  // graphs copy from these
-        return e;
-    }
-    dbgk::PassArgs *host_args() const { return hargs.as<dbgk::PassArgs>(); }
-    Instance *host_instances() const {
-        return reinterpret_cast<Instance *>(hargs.as<unsigned char>() + dbgk::kArgsBytes);
-    }
-    const InstStatus *host_status() const { return hstatus.as<InstStatus>(); }
-
-    // Reserve the binned-mode scratch for the key's capacities.
-    hipError_t reserve_binned(const PassKey &k, dbgk::BinBuffers &bb) {
-        bb.tiles1_cap = k.len_cap / dbgk::kBinTile + k.m_cap + 1;
-        bb.hist1_cap = (uint64_t)k.d1_cap * bb.tiles1_cap;
-        bb.tiles2_cap = k.len_cap / dbgk::kRefTile + k.buckets_cap + 1;
-        bb.hist2_cap = (uint64_t)k.fan_cap * bb.tiles2_cap;
-        const uint64_t chunk = 1024;
-        bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
-        bb.buckets_cap = k.buckets_cap;
-        bb.parts_cap = k.parts_cap;
-        bb.d1_max = k.d1_cap;
-        bb.fan_max = k.fan_cap;
-        bb.entry_words = k.ew;
-        hipError_t e;
-        if ((e = grow(bplan, sizeof(dbgk::BinPlan) * k.m_cap)) != hipSuccess ||
-            (e = grow(bbuckets, sizeof(dbgk::Bucket) * std::max<uint64_t>(k.buckets_cap, 1))) != hipSuccess ||
-            (e = grow(btotals, sizeof(dbgk::BinTotals))) != hipSuccess ||
-            (e = grow(hist1, 4 * bb.hist1_cap)) != hipSuccess ||
-            (e = grow(scan1, 8 * (bb.hist1_cap + 1))) != hipSuccess ||
-            (e = grow(hist2, 4 * bb.hist2_cap)) != hipSuccess ||
-            (e = grow(scan2, 8 * (bb.hist2_cap + 1))) != hipSuccess ||
-            (e = grow(bpartials, 8 * bb.partials_cap)) != hipSuccess ||
-            (e = grow(rec1, 8 * k.len_cap)) != hipSuccess || (e = grow(rec2, 8 * k.len_cap)) != hipSuccess ||
-            (e = grow(pstart, 8 * (k.parts_cap + 1))) != hipSuccess ||
-            (e = grow(tread1, 8 * bb.tiles1_cap)) != hipSuccess ||
-            (e = grow(tbucket2, 4 * bb.tiles2_cap)) != hipSuccess)
-            return e;
-        bb.plan = bplan.as<dbgk::BinPlan>();
-        bb.buckets = bbuckets.as<dbgk::Bucket>();
-        bb.totals = btotals.as<dbgk::BinTotals>();
-        bb.hist1 = hist1.as<uint32_t>();
-        bb.scan1 = scan1.as<uint64_t>();
-        bb.hist2 = hist2.as<uint32_t>();
-        bb.scan2 = scan2.as<uint64_t>();
-        bb.partials = bpartials.as<uint64_t>();
-        bb.rec1 = rec1.as<uint64_t>();
-        bb.rec2 = rec2.as<uint64_t>();
-        bb.pstart = pstart.as<uint64_t>();
-        bb.tile_read1 = tread1.as<uint64_t>();
-        bb.tile_bucket2 = tbucket2.as<uint32_t>();
-        return hipSuccess;
-    }
-    // Grid sizes per binned key (queried once, outside any capture).
-    std::vector<std::pair<PassKey, dbgk::BinBuffers>> grid_memo;
-    void binned_grids(const PassKey &k, int device, dbgk::BinBuffers &bb) {
-        for (auto &g : grid_memo)
-            if (g.first == k) {
-                bb.grid_bin_count = g.second.grid_bin_count;
-                bb.grid_bin_scatter = g.second.grid_bin_scatter;
-                bb.grid_ref_count = g.second.grid_ref_count;
-                bb.grid_ref_scatter = g.second.grid_ref_scatter;
-                bb.grid_reduce = g.second.grid_reduce;
-                return;
-            }
-        dbgk::binned_grids(device, bb);
-        if (grid_memo.size() > 16) grid_memo.clear();
-        grid_memo.emplace_back(k, bb);
-    }
-
-    // The two halves of the pass, enqueued on `s` (directly or under capture).
-    hipError_t enqueue_setup(const PassKey &k, hipStream_t s) {
-        dbgk::PassArgs *da = dargs.as<dbgk::PassArgs>();
-        Instance *di = reinterpret_cast<Instance *>(dargs.as<unsigned char>() + dbgk::kArgsBytes);
-        InstStatus *dst = dstatus.as<InstStatus>();
-        CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
-        hipError_t e = hipMemcpyAsync(dargs.p, hargs.p, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap,
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = dbgk::launch_prepare(da, di, dst, cs, k.m_cap, s);
-        if (e == hipSuccess) e = dbgk::launch_pack(da, packed.as<uint64_t>(), di, dst, k.len_cap, s);
-        if (e == hipSuccess)
-            e = dbgk::launch_scan(da, di, dst, ws.as<uint64_t>(), partials.as<uint64_t>(),
-                                  k.binned ? nullptr : tiles.as<uint64_t>(), cs, k.n_cap, s);
-        return e;
-    }
-    hipError_t enqueue_build(const PassKey &k, const dbgk::BinBuffers &bb, int device, hipStream_t s,
-                             bool mark = false) {
-        dbgk::PassArgs *da = dargs.as<dbgk::PassArgs>();
-        Instance *di = reinterpret_cast<Instance *>(dargs.as<unsigned char>() + dbgk::kArgsBytes);
-        InstStatus *dst = dstatus.as<InstStatus>();
-        CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
-        hipError_t e;
-        if (k.binned)
-            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s,
-                                    mark ? marks : nullptr);
-        else
-            e = dbgk::launch_build(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
-                                   cs, k.shape, k.single != 0, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * k.m_cap + sizeof(CallState),
-                               hipMemcpyDeviceToHost, s);
-        return e;
-    }
-
-    hipError_t capture(const PassKey &k, const dbgk::BinBuffers &bb, int device, Cached &out) {
-        out.key = k;
-        out.generation = generation;
-        out.setup = out.build = nullptr;
-        for (int half = 0; half < 2; ++half) {
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return e;
-            const hipError_t ee = half == 0 ? enqueue_setup(k, cap_stream) : enqueue_build(k, bb, device, cap_stream);
-            e = hipStreamEndCapture(cap_stream, &g);
-            if (ee != hipSuccess) e = ee;
-            if (e == hipSuccess) e = hipGraphInstantiate(half == 0 ? &out.setup : &out.build, g, nullptr, nullptr, 0);
-            if (g) (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return e;
-        }
-        ++captures;
-        return hipSuccess;
-    }
-
-    // Enqueue the pass.  hinst[0..mm) must be filled (tables, read ranges,
-    // prior k-mers, k, entry words, and the segment geometry when binned).
-    // Reads are device-resident: read i is d_reads[off[i] - off[0] ..
-    // off[i+1] - off[0]).
-    hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
-                       uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
-                       bool time_it, hipStream_t s) {
-        PassKey k;
-        k.binned = binned ? 1 : 0;
-        k.single = mm == 1 ? 1 : 0;
-        k.shape = shape;
-        k.m_cap = (uint32_t)size_class(mm, 1);
-        k.n_cap = size_class(n, 1024);
-        k.len_cap = size_class(len, 4096);
-        const Instance *hi = host_instances();
-        uint64_t P = 0, G1 = 0;
-        uint32_t d1max = 1, fanmax = 1;
-        for (uint32_t i = 0; i < mm; ++i) {
-            P += hi[i].parts;
-            G1 += hi[i].d1;
-            d1max = std::max(d1max, hi[i].d1);
-            fanmax = std::max(fanmax, hi[i].fan);
-            if (hi[i].parts) k.ew = hi[i].entry_words;
-        }
-        if (binned) {
-            k.parts_cap = size_class(P, 64);
-            k.buckets_cap = size_class(G1, 64);
-            k.d1_cap = (uint32_t)std::min<uint64_t>(size_class(d1max, 16), dbgk::kMaxD1);
-            k.fan_cap = (uint32_t)std::min<uint64_t>(size_class(fanmax, 16), dbgk::kMaxFan);
-        }
-        const uint64_t T = (uint64_t)shape.block * shape.wpt;
-        const uint64_t tile_cap = dbgk::max_tiles(k.len_cap, T);
-        dbgk::BinBuffers bb{};
-        hipError_t e;
-        if ((e = grow(packed, dbgk::packed_words(k.len_cap) * 8)) != hipSuccess ||
-            (e = grow(ws, (k.n_cap + 1) * 8)) != hipSuccess ||
-            (e = grow(partials, dbgk::scan_blocks(k.n_cap) * 8 + 8)) != hipSuccess ||
-            (e = grow(dargs, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap)) != hipSuccess ||
-            (e = grow(dstatus, sizeof(InstStatus) * k.m_cap + sizeof(CallState))) != hipSuccess ||
-            (!binned && (e = grow(tiles, tile_cap * 8)) != hipSuccess) ||
-            (binned && (e = reserve_binned(k, bb)) != hipSuccess))
-            return e;
-        if (binned) binned_grids(k, device, bb);
-
-        dbgk::PassArgs &a = *host_args();
-        std::memset(&a, 0, sizeof a);
-        a.reads = d_reads;
-        a.off = d_off;
-        a.n_reads = n;
-        a.reads_len = len;
-        a.max_windows = binned ? len : (tile_cap - 1) * T;
-        a.tile_cap = tile_cap;
-        a.parts_total = P;
-        a.m = mm;
-        a.check_ends = check_ends ? 1 : 0;
-        a.tile = (uint32_t)T;
-
-        Cached *c = nullptr;
-        if (use_graphs) {
-            for (auto &x : graphs)
-                if (x.key == k && x.generation == generation) c = &x;
-            if (!c) {
-                if (graphs.size() >= 8 || (!graphs.empty() && graphs[0].generation != generation)) drop_graphs();
-                Cached fresh{};
-                e = capture(k, bb, device, fresh);
-                if (e != hipSuccess) {
-                    if (fresh.setup) (void)hipGraphExecDestroy(fresh.setup);
-                    if (fresh.build) (void)hipGraphExecDestroy(fresh.build);
-                    return e;
-                }
-                graphs.push_back(fresh);
-                c = &graphs.back();
-            } else {
-                ++replays;
-            }
-        }
-        if (time_it) (void)hipEventRecord(ev_a, s);
-        e = c ? hipGraphLaunch(c->setup, s) : enqueue_setup(k, s);
-        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_b, s);
-        marked = !c && time_it && binned;
-        if (e == hipSuccess) e = c ? hipGraphLaunch(c->build, s) : enqueue_build(k, bb, device, s, marked);
-        if (time_it && e == hipSuccess) (void)hipEventRecord(ev_c, s);
-        if (e != hipSuccess) return e;
-        m = mm;
-        stream = s;
-        pending = true;
-        timing = time_it;
-        return hipSuccess;
-    }
-
-    // Phase times of the last timed pass, in ms: setup, then (binned,
-    // uncaptured) partition 1, partition 2, reduce, or (otherwise) build.
-    double phase_ms[4] = {0, 0, 0, 0};
-    uint32_t n_phases = 0;
-
-    // Wait for the enqueued pass; times in ms when it was timed.
-    hipError_t wait(double *build_ms, double *total_ms) {
-        if (!pending) return hipSuccess;
-        pending = false;
-        hipError_t e = hipStreamSynchronize(stream);
-        if (e == hipSuccess && timing) {
-            float a = 0, b = 0, x = 0;
-            if (hipEventElapsedTime(&a, ev_b, ev_c) == hipSuccess && build_ms) *build_ms = a;
-            if (hipEventElapsedTime(&b, ev_a, ev_c) == hipSuccess && total_ms) *total_ms = b;
-            n_phases = 0;
-            if (hipEventElapsedTime(&x, ev_a, ev_b) == hipSuccess) phase_ms[n_phases++] = x;
-            if (marked) {
-                if (hipEventElapsedTime(&x, ev_b, marks[0]) == hipSuccess) phase_ms[n_phases++] = x;
-                if (hipEventElapsedTime(&x, marks[0], marks[1]) == hipSuccess) phase_ms[n_phases++] = x;
-                if (hipEventElapsedTime(&x, marks[1], ev_c) == hipSuccess) phase_ms[n_phases++] = x;
-            } else {
-                phase_ms[n_phases++] = a;
-            }
-        }
-        return e;
-    }
-};
-
-}  // namespace
-
-struct dbg_graph {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    uint32_t flags = 0;
-    double lf = 0.5;
-    uint64_t expected = 0, cap_req = 0;
-    dbgk::BuildShape shape{256, 4, 0, 0};
-
-    uint64_t cap = 0;
-    uint32_t ew = 3;
-    DevBuf table;
-    bool binned = false;     // table cut into segments, built by the binned kernels
-    bool fresh = true;       // binned: logically empty (contents need not be zero)
-    uint32_t parts = 0, d1 = 0, fan = 0;
-    DevBuf seg_count, seg_off, seg_partials, seg_len;  // binned: per-segment occupancy
-
-    uint32_t k = 0;
-    int32_t poisoned = DBG_OK;
-    int32_t unreported = DBG_OK;
-
-    Pass pass;
-    uint32_t pending_k = 0;
-    DevBuf reads, offsets;   // staging of host input
-    DevBuf xkeys, xcnt, xn;  // extraction staging
-
-    uint64_t vertices = 0, inserts = 0, windows = 0, builds = 0;
-    double last_build_ms = 0, last_total_ms = 0;
-
-    hipStream_t pick(void *s) const { return s ? static_cast<hipStream_t>(s) : stream; }
-    uint64_t table_words() const { return cap * ew; }
-};
-
-namespace {
-
-// Segment geometry of a binned table of `parts` segments: d1 level-1 buckets
-// of `fan` segments each (about the square root, so both partition passes
-// write runs of similar length).
-bool binned_geometry(uint64_t parts, uint32_t *d1, uint32_t *fan) {
-    uint64_t target = (uint64_t)std::ceil(std::sqrt((double)parts));
-    target = std::max<uint64_t>(1, std::min<uint64_t>(target, dbgk::kMaxD1));
-    uint64_t f = (parts + target - 1) / target;
-    if (f > dbgk::kMaxFan) return false;
-    *fan = (uint32_t)f;
-    *d1 = (uint32_t)((parts + f - 1) / f);
-    return true;
-}
-
-hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
-    if (g->binned) {
-        const uint64_t parts = (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots;
-        if (parts > 0xffffffffull || !binned_geometry(parts, &g->d1, &g->fan)) return hipErrorInvalidValue;
-        g->parts = (uint32_t)parts;
-        cap = parts * dbgk::kSegSlots;
-        hipError_t e;
-        if ((e = g->seg_count.reserve(4 * parts)) != hipSuccess ||
-            (e = g->seg_off.reserve(8 * (parts + 1))) != hipSuccess ||
-            (e = g->seg_partials.reserve(8 * ((parts + 1023) / 1024 + 2))) != hipSuccess ||
-            (e = g->seg_len.reserve(8)) != hipSuccess)
-            return e;
-    }
-    g->cap = cap;
-    hipError_t e = g->table.reserve(g->table_words() * sizeof(uint64_t));
-    if (e != hipSuccess) {
-        g->cap = 0;
-        return e;
-    }
-    e = dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    return e;
-}
-
-int ensure_table(dbg_graph *g, uint64_t windows_bound) {
-    if (g->cap) return DBG_OK;
-    uint64_t cap = g->cap_req;
-    if (!cap) cap = capacity_for(g->expected ? g->expected : std::max<uint64_t>(windows_bound, 1), g->lf);
-    const hipError_t e = allocate_table(g, cap);
-    if (e == hipErrorInvalidValue) return DBG_E_INVAL;
-    g->fresh = true;
-    return hip_code(e);
-}
-
-// A binned graph whose first build has k = 32 (keys too wide for the 8-byte
-// records) becomes a direct one; its table must then hold zeros.
-int settle_mode(dbg_graph *g, uint32_t k) {
-    if (!g->binned || k <= 31) return DBG_OK;
-    if (g->k || g->vertices) return DBG_E_K;
-    g->binned = false;
-    if (g->cap && dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) != hipSuccess)
-        return DBG_E_DEVICE;
-    return DBG_OK;
-}
-
-void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint64_t read_end, uint32_t k) {
-    in.table = g->table.as<uint64_t>();
-    in.cap = g->cap;
-    in.read_begin = read_begin;
-    in.read_end = read_end;
-    in.byte_begin = 0;
-    in.byte_end = 0;
-    in.prior_inserts = g->inserts;
-    in.k = k;
-    in.entry_words = g->ew;
-    in.skip = 0;
-    in.part_base = 0;
-    in.parts = g->binned ? g->parts : 0;
-    in.d1 = g->binned ? g->d1 : 0;
-    in.fan = g->binned ? g->fan : 0;
-    in.fresh = (g->binned && g->fresh) ? 1u : 0u;
-    in.seg_count = g->binned ? g->seg_count.as<uint32_t>() : nullptr;
-    // Lemire, Kaser, Kurz, "Faster remainder by direct computation" (2019):
-    // for 32-bit n, n / d is the high 64 bits of ceil(2^64 / d) * n
-    in.fan_magic = (g->binned && g->fan > 1) ? (~0ull / g->fan + 1) : 0;
-    in.pad = 0;
-}
-
-// Fold one instance's status of a finished pass into its graph.
-int fold_status(dbg_graph *g, const InstStatus &st, uint32_t k) {
-    if (validation_error(st.err)) return err_code_of(st.err);  // nothing was modified
-    g->k = k;
-    g->fresh = false;
-    g->vertices += st.claimed;
-    g->inserts += st.inserts;
-    g->windows += st.windows;
-    g->builds += 1;
-    if (st.err & dbgk::kErrFull) {
-        g->poisoned = DBG_E_FULL;
-        return DBG_E_FULL;
-    }
-    return DBG_OK;
-}
-
-// Waits for the handle's own enqueued build and folds its status.
-int harvest(dbg_graph *g) {
-    if (!g->pass.pending) return DBG_OK;
-    if (g->pass.wait(&g->last_build_ms, &g->last_total_ms) != hipSuccess) return DBG_E_DEVICE;
-    return fold_status(g, g->pass.host_status()[0], g->pending_k);
-}
-
-int check_common(dbg_graph *g, uint32_t k) {
-    if (!g) return DBG_E_INVAL;
-    if (g->poisoned) return DBG_E_STATE;
-    if (k < 2 || k > 32) return DBG_E_K;
-    if (g->k && g->k != k) return DBG_E_K;
-    return DBG_OK;
-}
-
-int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
-                   uint64_t n, uint32_t k, hipStream_t s) {
-    hipError_t e = g->pass.reserve_instances(1);
-    if (e != hipSuccess) return hip_code(e);
-    fill_instance(g->pass.host_instances()[0], g, 0, n, k);
-    e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, g->binned, g->device, true,
-                        (g->flags & DBG_F_TIMING) != 0, s);
-    if (e != hipSuccess) return hip_code(e);
-    g->pending_k = k;
-    return DBG_OK;
-}
-
-// ---------------------------------------------------------------- batch context
-
-// Per-device scratch of batched builds (one batched call at a time per
-// device; calls are serialised by the mutex).
-struct BatchCtx {
-    std::mutex mu;
-    hipStream_t stream = nullptr;
-    Pass pass;
-    DevBuf reads, offsets;
-    std::vector<uint64_t> hoff;
-    bool ready = false;
-};
-
-std::mutex g_ctx_mu;
-std::map<int, std::unique_ptr<BatchCtx>> g_ctx;
-
-BatchCtx *batch_ctx(int device) {
-    std::lock_guard<std::mutex> lk(g_ctx_mu);
-    auto &p = g_ctx[device];
-    if (!p) p.reset(new BatchCtx());
-    return p.get();
-}
-
-}  // namespace
-
-// Shared by the host- and device-input batched calls: graphs[i] takes reads
-// [read_begin[i], read_begin[i+1]) of the device-resident concatenation.  A
-// graph that fails a host-side check stays in the launch as a skipped
-// instance, so its reads are attributed to it and never touched.
-static void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
-                              const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
-                              const uint64_t *d_offsets, int32_t *statuses, hipStream_t stream,
-                              BatchCtx *ctx, bool check_ends) {
-    const int device = graphs[0]->device;
-    std::vector<uint8_t> run(m, 0);
-    uint32_t n_run = 0;
-    int mode = -1;  // direct (0) or binned with 3/4-word entries: the first graph that runs decides
-    for (uint32_t i = 0; i < m; ++i) {
-        dbg_graph *g = graphs[i];
-        int rc = check_common(g, ks[i]);
-        if (rc == DBG_OK && g->device != device) rc = DBG_E_INVAL;
-        if (rc == DBG_OK && read_begin[i + 1] < read_begin[i]) rc = DBG_E_INVAL;
-        for (uint32_t j = 0; rc == DBG_OK && j < i; ++j)
-            if (graphs[j] == g) rc = DBG_E_INVAL;  // one graph per instance
-        if (rc == DBG_OK && g->pass.pending) rc = harvest(g);
-        if (rc == DBG_OK && read_begin[i + 1] > read_begin[i]) {
-            // a graph never sized takes the whole input's byte count as bound
-            rc = ensure_table(g, std::max<uint64_t>(reads_len, 1));
-            if (rc == DBG_OK) rc = settle_mode(g, ks[i]);
-            const int gm = g->binned ? (int)g->ew : 0;  // binned launches share one entry width
-            if (rc == DBG_OK && mode < 0) mode = gm;
-            if (rc == DBG_OK && gm != mode) rc = DBG_E_INVAL;  // one mode per launch
-            if (rc == DBG_OK) {
-                run[i] = 1;
-                ++n_run;
-            }
-        }
-        statuses[i] = rc;
-    }
-    if (!n_run) return;
-
-    Pass &pass = ctx->pass;
-    hipError_t e = pass.reserve_instances(m);
-    if (e != hipSuccess) {
-        for (uint32_t i = 0; i < m; ++i)
-            if (run[i]) statuses[i] = hip_code(e);
-        return;
-    }
-    Instance *hi = pass.host_instances();
-    const dbg_graph *g0 = nullptr;
-    uint64_t part_base = 0;
-    for (uint32_t i = 0; i < m; ++i) {
-        fill_instance(hi[i], graphs[i], read_begin[i], read_begin[i + 1], run[i] ? ks[i] : 31u);
-        hi[i].skip = run[i] ? 0u : 1u;
-        if (mode == 0 || !run[i]) {
-            // segments only for the graphs a binned launch builds
-            hi[i].parts = hi[i].d1 = hi[i].fan = 0;
-            hi[i].fresh = 0;
-            hi[i].fan_magic = 0;
-        }
-        hi[i].part_base = part_base;
-        part_base += hi[i].parts;
-        if (run[i] && !g0) g0 = graphs[i];
-    }
-    const bool timing = (g0->flags & DBG_F_TIMING) != 0;
-    pass.use_graphs = (g0->flags & DBG_F_GRAPH) != 0;
-    const uint64_t n = read_begin[m];
-    e = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, mode != 0, device, check_ends,
-                     timing, stream);
-    double bms = 0, tms = 0;
-    if (e == hipSuccess) e = pass.wait(&bms, &tms);
-    const InstStatus *st = pass.host_status();
-    for (uint32_t i = 0; i < m; ++i) {
-        if (!run[i]) continue;
-        if (e != hipSuccess) {
-            statuses[i] = DBG_E_DEVICE;
-            continue;
-        }
-        statuses[i] = fold_status(graphs[i], st[i], ks[i]);
-        if (timing) {
-            graphs[i]->last_build_ms = bms;
-            graphs[i]->last_total_ms = tms;
-        }
-    }
-}
-
-static int first_error(const int32_t *statuses, uint32_t m) {
-    for (uint32_t i = 0; i < m; ++i)
-        if (statuses[i] != DBG_OK) return statuses[i];
-    return DBG_OK;
-}
 
 extern "C" {
 
