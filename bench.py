@@ -151,6 +151,99 @@ def batched_bench(dbg, torch, dev, n_inst: int, reps: int, graphs_on: bool) -> d
     return out
 
 
+def served_bench(dbg, torch, dev, n_payloads: int, n_requests: int, loads, ref_gips: float,
+                 budget: int = 200_000_000_000) -> dict:
+    """Serving: a pool of n_payloads device-resident read sets of the served
+    workload (genomes log-uniform in [10 kbp, 20 Mbp], coverage U[10, 50], L
+    in {100, 150}, substitutions U[0.5, 1] %, k in {21, 31}); n_requests
+    requests, each carrying a seeded random payload of the pool, arrive as a
+    Poisson process whose insert rate is `load` x ref_gips; tables are
+    admitted against `budget` bytes of HBM; a client thread releases each
+    request when it finishes.  Latency = finish - arrival on the server's
+    clock; aggregate rate = inserts of all requests / (last finish - first
+    arrival)."""
+    import concurrent.futures
+    import threading
+    import readsim
+
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        pool = list(ex.map(lambda j: readsim.make_instance(5, j), range(n_payloads)))
+    gen_s = time.perf_counter() - t0
+    pay = []
+    for rs in pool:
+        pay.append(dict(d_reads=torch.from_numpy(rs.reads).to(dev),
+                        d_off=torch.from_numpy(rs.offsets.astype(np.int64)).to(dev),
+                        k=rs.k, ev=rs.meta["expected_vertices"],
+                        inserts=int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())))
+    del pool
+    rng = np.random.default_rng(0x5E4E)
+    choice = rng.integers(0, n_payloads, n_requests)
+    ins = np.array([pay[c]["inserts"] for c in choice], dtype=np.float64)
+    out = {"workload": "served: %d requests over a pool of %d read sets, %.1f M k-mer inserts per request "
+                       "(mean), %.0f GB table budget" % (n_requests, n_payloads, ins.mean() / 1e6, budget / 1e9),
+           "generation_s": round(gen_s, 1), "reference_ginserts_s": round(ref_gips, 3), "runs": []}
+
+    srv = dbg.Server(hbm_budget=budget, flags=dbg.F_BINNED)
+    # warm-up: every payload once (scratch sized, tables pooled); its vertex
+    # count is what every later request with that payload must reproduce
+    ids = [srv.submit_device(p["d_reads"], p["d_off"], p["k"], p["ev"]) for p in pay]
+    want_v = []
+    for rid in ids:
+        assert srv.wait(rid) == dbg.OK
+        want_v.append(srv.graph(rid).vertex_count())
+        srv.release(rid)
+    for load in loads:
+        rate = load * ref_gips * 1e9 / ins.mean()  # requests per second
+        arrive = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+        s0 = srv.stats()
+        rids = [None] * n_requests
+        got = threading.Semaphore(0)
+        lat, first_t, last_t, bad = [], [float("inf")], [0.0], []
+
+        def reaper():
+            for i in range(n_requests):
+                got.acquire()
+                rid = rids[i]
+                st = srv.wait(rid)
+                ts, _, td = srv.times(rid)
+                if st != dbg.OK or srv.graph(rid).vertex_count() != want_v[choice[i]]:
+                    bad.append((i, st))
+                srv.release(rid)
+                lat.append(td - ts)
+                first_t[0] = min(first_t[0], ts)
+                last_t[0] = max(last_t[0], td)
+
+        th = threading.Thread(target=reaper)
+        th.start()
+        t_start = time.perf_counter()
+        for i in range(n_requests):
+            wait_s = t_start + arrive[i] - time.perf_counter()
+            if wait_s > 0:
+                time.sleep(wait_s)
+            p = pay[choice[i]]
+            rids[i] = srv.submit_device(p["d_reads"], p["d_off"], p["k"], p["ev"])
+            got.release()
+        th.join()
+        s1 = srv.stats()
+        assert not bad, bad[:5]
+        lat_ms = np.array(lat) * 1e3
+        span = last_t[0] - first_t[0]
+        passes = s1["passes"] - s0["passes"]
+        run = {"load": load, "offered_requests_s": round(rate, 1),
+               "offered_ginserts_s": round(load * ref_gips, 3),
+               "achieved_ginserts_s": round(ins.sum() / span / 1e9, 3),
+               "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+               "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+               "mean_ms": round(float(lat_ms.mean()), 2), "max_ms": round(float(lat_ms.max()), 2),
+               "passes": passes, "mean_batch": round(n_requests / max(passes, 1), 2),
+               "max_in_flight": s1["max_in_flight"], "span_s": round(span, 3)}
+        out["runs"].append(run)
+        log("served load %.2f: %s" % (load, json.dumps(run)))
+    srv.close()
+    return out
+
+
 def cpu_baseline(rs, sample_reads: int) -> dict:
     import oracle
 
@@ -187,6 +280,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batched-sets", type=int, default=256)
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--no-served", action="store_true", help="skip the serving benchmark")
+    ap.add_argument("--served-payloads", type=int, default=64)
+    ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB read (sum) and a 1 GiB write (zero fill) of known size, "
                          "to scale hardware traffic counters")
@@ -335,6 +431,11 @@ def main() -> int:
         line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps,
                                         not args.no_graph)
         log("batched %s" % json.dumps(line["batched"]))
+
+    if not args.no_served:
+        ref = line["batched"]["batched"]["ginserts_s"] if "batched" in line else value
+        line["served"] = served_bench(dbg, torch, dev, args.served_payloads, args.served_requests,
+                                      (0.7, 0.5, 0.9), ref)
 
     if not args.no_roofline:
         foot = int(st["table_bytes"])

@@ -209,6 +209,85 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
                            const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
                            const uint64_t *d_offsets, int32_t *statuses, void *stream);
 
+/* ---- serving ----------------------------------------------------------
+ * A build server: requests (read sets) are admitted first come, first served
+ * while the table bytes of the admitted, unreleased requests stay within an
+ * HBM budget; admitted requests are built by continuous batching -- every
+ * pass of the server's worker thread takes the requests admitted since the
+ * previous one, and up to `slots` passes run on separate streams at once, so
+ * requests that arrive while others are on the GPU overlap with them.  Each
+ * request's graph is built exactly as dbg_build would build it alone, and
+ * stays resident on the device until the client releases it.
+ * Thread safety: every dbg_server_* call may come from any client thread. */
+#define DBG_PENDING 1 /* positive: the request has not finished yet */
+
+typedef struct dbg_server dbg_server;
+
+typedef struct {
+    uint64_t hbm_budget;      /* table bytes admitted at once; 0 = 200 GB */
+    uint64_t max_batch_bytes; /* read bytes per batched pass; 0 = 1 GiB */
+    uint32_t max_batch;       /* requests per batched pass; 0 = 64 */
+    uint32_t flags;           /* DBG_F_* of the request graphs; 0 = DBG_F_BINNED */
+    double load_factor;       /* table sizing; 0 = 0.5 */
+    int32_t device;           /* HIP device; -1 = current */
+    uint32_t slots;           /* passes in flight at once (one stream each); 0 = 2 */
+} dbg_server_config;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, released, rejected;
+    uint64_t queued;          /* waiting for admission */
+    uint64_t running;         /* admitted, not completed */
+    uint64_t resident_bytes;  /* table bytes of admitted, unreleased requests */
+    uint64_t passes;          /* batched passes launched */
+    uint64_t max_in_flight;   /* most passes on the device at once */
+} dbg_server_stats;
+
+/* Start a server and its worker thread.  Errors: DBG_E_INVAL, DBG_E_DEVICE. */
+int dbg_server_create(const dbg_server_config *cfg, dbg_server **out);
+
+/* Submit host-resident reads (copied; the caller may free them on return).
+ * expected_vertices sizes the request's table as dbg_config does (0 = bound
+ * from the input).  *id identifies the request.  Errors (nothing queued):
+ * DBG_E_INVAL (NULL pointers, decreasing offsets), DBG_E_K, DBG_E_RANGE,
+ * DBG_E_NOMEM (its table alone exceeds the budget). */
+int dbg_server_submit(dbg_server *s, const char *reads, const uint64_t *offsets, uint64_t n_reads,
+                      uint32_t k, uint64_t expected_vertices, uint64_t *id);
+
+/* Submit device-resident reads (read i is d_reads[d_offsets[i] - d_offsets[0]
+ * .. d_offsets[i+1] - d_offsets[0]), reads_len bytes).  The buffers must stay
+ * valid and unchanged until the request has finished.  Errors as above;
+ * offset consistency is checked on the device and reported as the request's
+ * status. */
+int dbg_server_submit_device(dbg_server *s, const uint8_t *d_reads, uint64_t reads_len,
+                             const uint64_t *d_offsets, uint64_t n_reads, uint32_t k,
+                             uint64_t expected_vertices, uint64_t *id);
+
+/* DBG_PENDING while the request is queued or running; DBG_OK once finished,
+ * with *status its build result (DBG_OK or a DBG_E_* code).  DBG_E_INVAL for
+ * an unknown id. */
+int dbg_server_poll(dbg_server *s, uint64_t id, int32_t *status);
+
+/* Wait up to timeout_s seconds (negative: forever) for the request; returns
+ * as dbg_server_poll. */
+int dbg_server_wait(dbg_server *s, uint64_t id, double timeout_s, int32_t *status);
+
+/* The finished request's graph (owned by the server until release): extract
+ * it with dbg_extract / dbg_extract_device.  DBG_PENDING if not finished. */
+int dbg_server_graph(dbg_server *s, uint64_t id, dbg_graph **g);
+
+/* Seconds on the server's steady clock at which the request was submitted,
+ * started on the device (its pass was enqueued) and finished. */
+int dbg_server_times(dbg_server *s, uint64_t id, double *t_submit, double *t_start, double *t_done);
+
+/* Free a finished request's graph, returning its bytes to the budget.
+ * DBG_PENDING if it has not finished. */
+int dbg_server_release(dbg_server *s, uint64_t id);
+
+int dbg_server_get_stats(dbg_server *s, dbg_server_stats *out);
+
+/* Finish every admitted request, drop queued ones, free everything. */
+void dbg_server_destroy(dbg_server *s);
+
 /* ---- measurement -----------------------------------------------------
  * Random-access roofline of the device: n_ops operations at indices drawn by
  * a 64-bit mixer over a footprint of footprint_bytes (no index array is

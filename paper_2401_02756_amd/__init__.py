@@ -23,6 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
 
 OK = 0
+PENDING = 1
 E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE = range(-1, -10, -1)
 F_MERGE, F_TIMING, F_ENTRY32, F_BINNED, F_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -31,7 +32,9 @@ EXPORTS = (
     "dbg_config_init", "dbg_create", "dbg_build", "dbg_build_device", "dbg_sync",
     "dbg_extract", "dbg_extract_device", "dbg_reset", "dbg_get_stats", "dbg_destroy",
     "dbg_strerror", "dbg_build_batch", "dbg_build_batch_device", "dbg_atomic_roofline",
-    "dbg_get_phase_times",
+    "dbg_get_phase_times", "dbg_server_create", "dbg_server_submit", "dbg_server_submit_device",
+    "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
+    "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy",
 )
 
 
@@ -83,6 +86,27 @@ class Input(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_uint64),
+        ("max_batch_bytes", ctypes.c_uint64),
+        ("max_batch", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("load_factor", ctypes.c_double),
+        ("device", ctypes.c_int32),
+        ("slots", ctypes.c_uint32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "admitted", "completed", "released", "rejected", "queued", "running",
+        "resident_bytes", "passes", "max_in_flight")]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -112,6 +136,19 @@ def lib() -> ctypes.CDLL:
                                                    ctypes.POINTER(ctypes.c_double)]),
             "dbg_get_phase_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), u32,
                                                    ctypes.POINTER(u32)]),
+            "dbg_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+            "dbg_server_submit": (ctypes.c_int, [vp, vp, vp, u64, u32, u64, ctypes.POINTER(u64)]),
+            "dbg_server_submit_device": (ctypes.c_int, [vp, vp, u64, vp, u64, u32, u64,
+                                                        ctypes.POINTER(u64)]),
+            "dbg_server_poll": (ctypes.c_int, [vp, u64, ctypes.POINTER(i32)]),
+            "dbg_server_wait": (ctypes.c_int, [vp, u64, ctypes.c_double, ctypes.POINTER(i32)]),
+            "dbg_server_graph": (ctypes.c_int, [vp, u64, ctypes.POINTER(vp)]),
+            "dbg_server_times": (ctypes.c_int, [vp, u64, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double)]),
+            "dbg_server_release": (ctypes.c_int, [vp, u64]),
+            "dbg_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
+            "dbg_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -159,7 +196,11 @@ class Graph:
 
     def __init__(self, expected_vertices: int = 0, capacity: int = 0, load_factor: float = 0.0,
                  device: int = -1, flags: int = 0, block_size: int = 0,
-                 windows_per_thread: int = 0, stream=None):
+                 windows_per_thread: int = 0, stream=None, _borrowed=None):
+        self._owned = _borrowed is None
+        if not self._owned:
+            self._h = ctypes.c_void_p(_borrowed)
+            return
         cfg = Config()
         lib().dbg_config_init(ctypes.byref(cfg))
         cfg.expected_vertices = int(expected_vertices)
@@ -182,7 +223,8 @@ class Graph:
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            lib().dbg_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().dbg_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -302,3 +344,109 @@ def atomic_roofline(kind: int, footprint_bytes: int, n_ops: int, block_size: int
                                    int(block_size), int(repeats), ctypes.byref(ms))
     _check(rc, "dbg_atomic_roofline")
     return float(ms.value)
+
+
+class Server:
+    """A build server (``dbg_server_create`` .. ``dbg_server_destroy``): FIFO
+    admission against an HBM budget for tables, continuous batching of the
+    admitted requests, tables resident until ``release``."""
+
+    def __init__(self, hbm_budget: int = 0, max_batch: int = 0, max_batch_bytes: int = 0,
+                 flags: int = 0, load_factor: float = 0.0, device: int = -1, slots: int = 0):
+        cfg = ServerConfig()
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_batch_bytes = int(max_batch_bytes)
+        cfg.max_batch = int(max_batch)
+        cfg.flags = int(flags)
+        cfg.load_factor = float(load_factor)
+        cfg.device = int(device)
+        cfg.slots = int(slots)
+        h = ctypes.c_void_p()
+        _check(lib().dbg_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dbg_server_create")
+        self._h = h
+        self._keep = {}
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("server is closed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().dbg_server_destroy(self._h)
+            self._h = None
+            self._keep = {}
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, reads, offsets, k: int, expected_vertices: int = 0) -> int:
+        """Queue host-resident reads (copied); returns the request id."""
+        reads, offsets = _host_inputs(reads, offsets)
+        n = max(0, offsets.shape[0] - 1)
+        rid = ctypes.c_uint64(0)
+        rc = lib().dbg_server_submit(self.handle, reads.ctypes.data if reads.size else None,
+                                     offsets.ctypes.data if offsets.size else None, n, int(k),
+                                     int(expected_vertices), ctypes.byref(rid))
+        _check(rc, "dbg_server_submit")
+        return int(rid.value)
+
+    def submit_device(self, d_reads, d_offsets, k: int, expected_vertices: int = 0,
+                      n_reads: int | None = None, reads_len: int | None = None) -> int:
+        """Queue device-resident reads; the tensors are kept alive until the
+        request is released."""
+        n = int(d_offsets.numel() - 1) if n_reads is None else int(n_reads)
+        ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+        rid = ctypes.c_uint64(0)
+        rc = lib().dbg_server_submit_device(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
+                                            int(expected_vertices), ctypes.byref(rid))
+        _check(rc, "dbg_server_submit_device")
+        self._keep[int(rid.value)] = (d_reads, d_offsets)
+        return int(rid.value)
+
+    def poll(self, rid: int) -> int | None:
+        """None while pending, else the request's build status."""
+        st = ctypes.c_int32(0)
+        rc = lib().dbg_server_poll(self.handle, int(rid), ctypes.byref(st))
+        if rc == PENDING:
+            return None
+        _check(rc, "dbg_server_poll")
+        return int(st.value)
+
+    def wait(self, rid: int, timeout: float = -1.0) -> int | None:
+        """The request's build status; None if the timeout passed first."""
+        st = ctypes.c_int32(0)
+        rc = lib().dbg_server_wait(self.handle, int(rid), float(timeout), ctypes.byref(st))
+        if rc == PENDING:
+            return None
+        _check(rc, "dbg_server_wait")
+        return int(st.value)
+
+    def graph(self, rid: int) -> Graph:
+        """The finished request's graph (owned by the server until release)."""
+        h = ctypes.c_void_p()
+        _check(lib().dbg_server_graph(self.handle, int(rid), ctypes.byref(h)), "dbg_server_graph")
+        return Graph(_borrowed=h.value)
+
+    def times(self, rid: int) -> tuple[float, float, float]:
+        """(submitted, started, finished) in seconds on the server's clock."""
+        a, b, c = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        rc = lib().dbg_server_times(self.handle, int(rid), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        if rc not in (OK, PENDING):
+            _check(rc, "dbg_server_times")
+        return float(a.value), float(b.value), float(c.value)
+
+    def release(self, rid: int) -> None:
+        _check(lib().dbg_server_release(self.handle, int(rid)), "dbg_server_release")
+        self._keep.pop(int(rid), None)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().dbg_server_get_stats(self.handle, ctypes.byref(s)), "dbg_server_get_stats")
+        return s.as_dict()

@@ -60,6 +60,8 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
         rc = DBG_E_DEVICE;
     }
     if (rc == DBG_OK && g->pass.init() != hipSuccess) rc = DBG_E_DEVICE;
+    if (rc == DBG_OK && hipEventCreateWithFlags(&g->zero_ev, hipEventDisableTiming) != hipSuccess)
+        rc = DBG_E_DEVICE;
     if (rc == DBG_OK && (g->cap_req || g->expected)) rc = ensure_table(g, 0);
     if (rc != DBG_OK) {
         dbg_destroy(g);
@@ -198,9 +200,7 @@ int dbg_reset(dbg_graph *g) {
     // A binned build rewrites every slot of a fresh table, so its reset only
     // marks the table empty; the direct build needs the zeros.
     if (!g->cap || g->binned) return DBG_OK;
-    return dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) == hipSuccess
-               ? DBG_OK
-               : DBG_E_DEVICE;
+    return zero_table(g) == hipSuccess ? DBG_OK : DBG_E_DEVICE;
 }
 
 int dbg_get_stats(dbg_graph *g, dbg_stats *out) {
@@ -240,6 +240,7 @@ void dbg_destroy(dbg_graph *g) {
                       &g->xn,       &g->seg_count, &g->seg_off, &g->seg_partials, &g->seg_len};
     for (DevBuf *b : bufs) b->release();
     g->pass.release();
+    if (g->zero_ev) (void)hipEventDestroy(g->zero_ev);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

@@ -485,6 +485,11 @@ struct dbg_graph {
     uint32_t parts = 0, d1 = 0, fan = 0;
     dbgrt::DevBuf seg_count, seg_off, seg_partials, seg_len;  // binned: per-segment occupancy
 
+    // A zero fill enqueued on `stream` (direct tables) that a build enqueued
+    // on another stream must wait for.
+    hipEvent_t zero_ev = nullptr;
+    bool zero_wait = false;
+
     uint32_t k = 0;
     int32_t poisoned = DBG_OK;
     int32_t unreported = DBG_OK;
@@ -516,6 +521,21 @@ inline bool binned_geometry(uint64_t parts, uint32_t *d1, uint32_t *fan) {
     return true;
 }
 
+// Zero the whole table on the graph's stream; builds on other streams are
+// ordered after it by order_after_zero.
+inline hipError_t zero_table(dbg_graph *g) {
+    hipError_t e = dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream);
+    if (e == hipSuccess && g->zero_ev) e = hipEventRecord(g->zero_ev, g->stream);
+    if (e == hipSuccess) g->zero_wait = g->zero_ev != nullptr;
+    return e;
+}
+
+inline hipError_t order_after_zero(dbg_graph *g, hipStream_t s) {
+    if (!g->zero_wait) return hipSuccess;
+    g->zero_wait = false;
+    return s == g->stream ? hipSuccess : hipStreamWaitEvent(s, g->zero_ev, 0);
+}
+
 inline hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
     if (g->binned) {
         const uint64_t parts = (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots;
@@ -535,9 +555,8 @@ inline hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
         g->cap = 0;
         return e;
     }
-    e = dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    return e;
+    // a binned build rewrites every segment of a fresh table: no zeros needed
+    return g->binned ? hipSuccess : zero_table(g);
 }
 
 inline int ensure_table(dbg_graph *g, uint64_t windows_bound) {
@@ -556,8 +575,7 @@ inline int settle_mode(dbg_graph *g, uint32_t k) {
     if (!g->binned || k <= 31) return DBG_OK;
     if (g->k || g->vertices) return DBG_E_K;
     g->binned = false;
-    if (g->cap && dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream) != hipSuccess)
-        return DBG_E_DEVICE;
+    if (g->cap && zero_table(g) != hipSuccess) return DBG_E_DEVICE;
     return DBG_OK;
 }
 
@@ -620,6 +638,7 @@ inline int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, co
     hipError_t e = g->pass.reserve_instances(1);
     if (e != hipSuccess) return hip_code(e);
     fill_instance(g->pass.host_instances()[0], g, 0, n, k);
+    if ((e = order_after_zero(g, s)) != hipSuccess) return hip_code(e);
     e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, g->binned, g->device, true,
                         (g->flags & DBG_F_TIMING) != 0, s);
     if (e != hipSuccess) return hip_code(e);
@@ -643,7 +662,7 @@ struct BatchCtx {
 inline std::mutex g_ctx_mu;
 inline std::map<int, std::unique_ptr<BatchCtx>> g_ctx;
 
-BatchCtx *batch_ctx(int device) {
+inline BatchCtx *batch_ctx(int device) {
     std::lock_guard<std::mutex> lk(g_ctx_mu);
     auto &p = g_ctx[device];
     if (!p) p.reset(new BatchCtx());
@@ -725,6 +744,13 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
         hi[i].part_base = part_base;
         part_base += hi[i].parts;
         if (br.run[i] && !g0) g0 = graphs[i];
+    }
+    for (uint32_t i = 0; i < m && e == hipSuccess; ++i)
+        if (br.run[i]) e = order_after_zero(graphs[i], stream);
+    if (e != hipSuccess) {
+        for (uint32_t i = 0; i < m; ++i)
+            if (br.run[i]) statuses[i] = hip_code(e);
+        return;
     }
     br.timing = (g0->flags & DBG_F_TIMING) != 0;
     pass.use_graphs = (g0->flags & DBG_F_GRAPH) != 0;

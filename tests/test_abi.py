@@ -4,6 +4,7 @@ arguments on the host before touching a device.  Runs without a GPU."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -40,13 +41,36 @@ def test_binding_codes_match_header():
     assert codes["E_FULL"] == dbg.E_FULL and codes["E_SPACE"] == dbg.E_SPACE
     assert codes["E_DEVICE"] == dbg.E_DEVICE and codes["E_RANGE"] == dbg.E_RANGE
     assert codes["E_STATE"] == dbg.E_STATE
+    text = open(os.path.join(ROOT, "include", "dbg.h")).read()
+    assert int(re.search(r"#define DBG_PENDING (\d+)", text).group(1)) == dbg.PENDING
 
 
-def test_struct_layouts_match_header():
-    # dbg_config: 2 x u64, double, i32, 3 x u32, pointer -> 48 bytes on LP64
-    assert ctypes.sizeof(dbg.Config) == 48
-    assert ctypes.sizeof(dbg.Stats) == 6 * 8 + 8 + 16 + 16 + 16 + 8
-    assert ctypes.sizeof(dbg.Input) == 32
+def _c_layout(tmp_path, structs):
+    """sizeof and field offsets of header structs, from a C program that
+    includes dbg.h, built with gcc."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dbg.h"', "int main(void) {"]
+    for cname, py in structs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for field, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, field, cname, field))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {a: int(b) for a, b in (line.split() for line in out.splitlines())}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = [("dbg_config", dbg.Config), ("dbg_stats", dbg.Stats), ("dbg_input", dbg.Input),
+               ("dbg_server_config", dbg.ServerConfig), ("dbg_server_stats", dbg.ServerStats)]
+    got = _c_layout(tmp_path, structs)
+    for cname, py in structs:
+        assert got[cname] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got["%s.%s" % (cname, field)] == getattr(py, field).offset, (cname, field)
 
 
 def test_strerror_and_config_init():
@@ -86,6 +110,23 @@ def test_host_side_argument_errors_need_no_device():
     ms = ctypes.c_double()
     assert L.dbg_atomic_roofline(-1, 9, 1 << 20, 10, 256, 1, ctypes.byref(ms)) == dbg.E_INVAL
     assert L.dbg_atomic_roofline(-1, 0, 1 << 20, 10, 100, 1, ctypes.byref(ms)) == dbg.E_INVAL
+    # server: configuration and handle checks come before any device call
+    sc = dbg.ServerConfig()
+    assert L.dbg_server_create(ctypes.byref(sc), None) == dbg.E_INVAL
+    for lf in (-0.5, 1.0):
+        sc.load_factor = lf
+        assert L.dbg_server_create(ctypes.byref(sc), ctypes.byref(h)) == dbg.E_INVAL
+    sc.load_factor, sc.slots = 0.5, 9
+    assert L.dbg_server_create(ctypes.byref(sc), ctypes.byref(h)) == dbg.E_INVAL
+    rid = ctypes.c_uint64()
+    st = ctypes.c_int32()
+    assert L.dbg_server_submit(None, None, None, 0, 21, 0, ctypes.byref(rid)) == dbg.E_INVAL
+    assert L.dbg_server_submit_device(None, None, 0, None, 0, 21, 0, ctypes.byref(rid)) == dbg.E_INVAL
+    assert L.dbg_server_poll(None, 1, ctypes.byref(st)) == dbg.E_INVAL
+    assert L.dbg_server_wait(None, 1, 0.0, ctypes.byref(st)) == dbg.E_INVAL
+    assert L.dbg_server_release(None, 1) == dbg.E_INVAL
+    assert L.dbg_server_get_stats(None, None) == dbg.E_INVAL
+    L.dbg_server_destroy(None)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -1,0 +1,217 @@
+"""The build server (continuous batching with HBM admission) through the C ABI.
+
+A served request's graph must be bit-identical to the oracle's and to the same
+read set built alone, whatever else shares its passes: other read sets, other
+k, host and device inputs, rejected inputs, and rebuilds after a table
+overflow.  Admission must hold requests back while the budget is used up.
+"""
+
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import readsim
+import paper_2401_02756_amd as dbg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+
+
+def same(got, want, what):
+    gk, gc = got
+    wk, wc = want
+    assert gk.shape == wk.shape, "%s: %d vertices, oracle has %d" % (what, gk.shape[0], wk.shape[0])
+    assert np.array_equal(gk, wk), what + ": keys differ"
+    assert np.array_equal(gc, wc), what + ": counts differ"
+
+
+def small_sets(n, seed0=0):
+    """Read sets of the served workload's kind, small enough for the oracle:
+    genomes log-uniform in [2 kbp, 60 kbp], coverage U[5, 20], L in {100,
+    150}, substitutions U[0.5, 1] %, k in {21, 31, 32, 5}."""
+    rng = np.random.default_rng(0xC5 + seed0)
+    out = []
+    for j in range(n):
+        G = int(np.exp(rng.uniform(np.log(2000), np.log(60000))))
+        L = int(rng.choice([100, 150]))
+        k = int(rng.choice([21, 31, 32, 5]))
+        rs = readsim.simulate(G, L, float(rng.uniform(5, 20)), float(rng.uniform(0.005, 0.01)), k,
+                              seed=1000 + seed0 * 100 + j)
+        rs.meta["expected_vertices"] = readsim.expected_vertices(G, L, rs.n_reads, 0.0075, k)
+        out.append(rs)
+    return out
+
+
+def served(srv, rid):
+    st = srv.wait(rid, timeout=60.0)
+    assert st is not None, "request %d did not finish" % rid
+    return st
+
+
+def test_served_equals_alone_and_oracle():
+    sets = small_sets(16)
+    say("16 read sets, host and device submits, k in {5, 21, 31, 32}")
+    dev = []
+    with dbg.Server(flags=dbg.F_BINNED, max_batch=8) as srv:
+        ids = []
+        for j, rs in enumerate(sets):
+            ev = rs.meta["expected_vertices"]
+            if j % 2:
+                d_reads = torch.from_numpy(rs.reads).cuda()
+                d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
+                dev.append((d_reads, d_off))
+                ids.append(srv.submit_device(d_reads, d_off, rs.k, ev))
+            else:
+                ids.append(srv.submit(rs.reads, rs.offsets, rs.k, ev))
+        for j, (rs, rid) in enumerate(zip(sets, ids)):
+            assert served(srv, rid) == dbg.OK, j
+            got = srv.graph(rid).extract_sorted()
+            same(got, oracle.build_graph(rs.reads, rs.offsets, rs.k), "request %d vs oracle" % j)
+            with dbg.Graph(expected_vertices=rs.meta["expected_vertices"], flags=dbg.F_BINNED) as g:
+                g.build(rs.reads, rs.offsets, rs.k)
+                same(got, g.extract_sorted(), "request %d vs alone" % j)
+            t_sub, t_start, t_done = srv.times(rid)
+            assert 0 <= t_sub <= t_start <= t_done
+            srv.release(rid)
+        s = srv.stats()
+        assert s["submitted"] == s["completed"] == s["released"] == 16
+        assert s["resident_bytes"] == 0 and s["queued"] == 0
+        assert 1 <= s["passes"] <= 16
+
+
+@pytest.mark.parametrize("flags", [0, dbg.F_BINNED | dbg.F_GRAPH, dbg.F_BINNED | dbg.F_ENTRY32])
+def test_served_modes(flags):
+    sets = small_sets(6, seed0=3)
+    say("server flags %#x" % flags)
+    with dbg.Server(flags=flags) as srv:
+        ids = [srv.submit(rs.reads, rs.offsets, rs.k, rs.meta["expected_vertices"]) for rs in sets]
+        for j, (rs, rid) in enumerate(zip(sets, ids)):
+            assert served(srv, rid) == dbg.OK
+            same(srv.graph(rid).extract_sorted(), oracle.build_graph(rs.reads, rs.offsets, rs.k),
+                 "flags %#x request %d" % (flags, j))
+            srv.release(rid)
+
+
+def test_rejected_inputs_do_not_disturb_the_mix():
+    sets = small_sets(4, seed0=5)
+    say("bad base, bad device offsets, empty request among good ones")
+    bad = readsim.reads_from_strings(["ACGTACGTNACGTACGTACGTACGT"], 21)
+    with dbg.Server(flags=dbg.F_BINNED) as srv:
+        ids = {}
+        ids["good0"] = srv.submit(sets[0].reads, sets[0].offsets, sets[0].k, sets[0].meta["expected_vertices"])
+        ids["base"] = srv.submit(bad.reads, bad.offsets, 21)
+        d_reads = torch.from_numpy(sets[1].reads).cuda()
+        d_off = torch.from_numpy(sets[1].offsets.astype(np.int64)).cuda()
+        # the client claims one byte fewer than its offsets cover
+        ids["offsets"] = srv.submit_device(d_reads, d_off, sets[1].k, 0, reads_len=int(d_reads.numel()) - 1)
+        ids["good2"] = srv.submit_device(torch.from_numpy(sets[2].reads).cuda(),
+                                         torch.from_numpy(sets[2].offsets.astype(np.int64)).cuda(),
+                                         sets[2].k, sets[2].meta["expected_vertices"])
+        ids["empty"] = srv.submit(np.zeros(0, np.uint8), np.zeros(1, np.uint64), 21)
+        ids["good3"] = srv.submit(sets[3].reads, sets[3].offsets, sets[3].k, sets[3].meta["expected_vertices"])
+        assert served(srv, ids["base"]) == dbg.E_BASE
+        assert served(srv, ids["offsets"]) == dbg.E_INVAL
+        assert served(srv, ids["empty"]) == dbg.OK
+        assert srv.graph(ids["empty"]).vertex_count() == 0
+        with pytest.raises(dbg.DbgError):
+            srv.graph(ids["base"])
+        for name, rs in (("good0", sets[0]), ("good2", sets[2]), ("good3", sets[3])):
+            assert served(srv, ids[name]) == dbg.OK
+            same(srv.graph(ids[name]).extract_sorted(), oracle.build_graph(rs.reads, rs.offsets, rs.k), name)
+        for rid in ids.values():
+            srv.release(rid)
+        # host-side rejections queue nothing
+        with pytest.raises(dbg.DbgError) as e:
+            srv.submit(sets[0].reads, sets[0].offsets, 33)
+        assert e.value.code == dbg.E_K
+        assert srv.stats()["submitted"] == 6
+
+
+def test_undersized_table_is_rebuilt():
+    rs = small_sets(1, seed0=7)[0]
+    say("expected_vertices=1 for %d reads" % rs.n_reads)
+    with dbg.Server(flags=dbg.F_BINNED) as srv:
+        rid = srv.submit(rs.reads, rs.offsets, rs.k, expected_vertices=1)
+        assert served(srv, rid) == dbg.OK
+        same(srv.graph(rid).extract_sorted(), oracle.build_graph(rs.reads, rs.offsets, rs.k), "rebuilt")
+        srv.release(rid)
+
+
+def test_admission_waits_for_budget():
+    rs = small_sets(1, seed0=9)[0]
+    ev = rs.meta["expected_vertices"]
+    with dbg.Server() as probe:
+        rid = probe.submit(rs.reads, rs.offsets, rs.k, ev)
+        assert served(probe, rid) == dbg.OK
+        one = probe.stats()["resident_bytes"]
+        assert one > 0
+    say("budget for one table of %d bytes" % one)
+    with dbg.Server(hbm_budget=one + one // 2) as srv:
+        a = srv.submit(rs.reads, rs.offsets, rs.k, ev)
+        b = srv.submit(rs.reads, rs.offsets, rs.k, ev)
+        assert served(srv, a) == dbg.OK
+        assert srv.wait(b, timeout=0.5) is None  # a's table holds the budget
+        s = srv.stats()
+        assert s["queued"] == 1 and s["resident_bytes"] == one
+        want = srv.graph(a).extract_sorted()
+        srv.release(a)
+        assert served(srv, b) == dbg.OK
+        same(srv.graph(b).extract_sorted(), want, "second request on the recycled table")
+        srv.release(b)
+        with pytest.raises(dbg.DbgError) as e:
+            srv.submit(rs.reads, rs.offsets, rs.k, ev * 4)
+        assert e.value.code == dbg.E_NOMEM
+        assert srv.stats()["rejected"] == 1
+
+
+def test_many_clients():
+    sets = small_sets(24, seed0=11)
+    say("4 client threads x 6 requests")
+    want = [oracle.build_graph(rs.reads, rs.offsets, rs.k) for rs in sets]
+    errors = []
+    with dbg.Server(flags=dbg.F_BINNED, max_batch=5) as srv:
+        def client(c):
+            try:
+                for j in range(c, len(sets), 4):
+                    rs = sets[j]
+                    rid = srv.submit(rs.reads, rs.offsets, rs.k, rs.meta["expected_vertices"])
+                    assert srv.wait(rid, timeout=60.0) == dbg.OK
+                    got = srv.graph(rid).extract_sorted()
+                    srv.release(rid)
+                    if not (np.array_equal(got[0], want[j][0]) and np.array_equal(got[1], want[j][1])):
+                        errors.append(j)
+            except Exception as ex:  # reported below
+                errors.append(repr(ex))
+
+        th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        s = srv.stats()
+        assert s["completed"] == s["released"] == 24 and s["resident_bytes"] == 0
+
+
+def test_destroy_with_requests_outstanding():
+    sets = small_sets(6, seed0=13)
+    say("close with unreleased and unfinished requests")
+    srv = dbg.Server(flags=dbg.F_BINNED)
+    for rs in sets:
+        srv.submit(rs.reads, rs.offsets, rs.k, rs.meta["expected_vertices"])
+    srv.close()
