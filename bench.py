@@ -111,11 +111,14 @@ def batched_bench(dbg, torch, dev, n_inst: int, reps: int, graphs_on: bool) -> d
     d_reads = torch.from_numpy(np.concatenate([x.reads for x in sets])).to(dev)
     d_off = torch.from_numpy(offs).to(dev)
     del sets
-    flags = dbg.F_BINNED | (dbg.F_GRAPH if graphs_on else 0)
-    gs = []
-    for j in range(n_inst):
-        p = readsim.instance_params(4, j)
-        gs.append(dbg.Graph(expected_vertices=p["expected_vertices"], load_factor=0.5, device=0, flags=flags))
+    keep = dbg.F_GRAPH if graphs_on else 0
+    ev = [readsim.instance_params(4, j)["expected_vertices"] for j in range(n_inst)]
+    t1 = time.perf_counter()
+    tune = dbg.autotune(rb, ks, d_reads, d_off, ev, keep_flags=keep, force=True)
+    tune_s = time.perf_counter() - t1
+    kw = tune.graph_kwargs()
+    kw["flags"] |= keep
+    gs = [dbg.Graph(expected_vertices=e, device=0, **kw) for e in ev]
 
     def batched():
         for g in gs:
@@ -131,7 +134,8 @@ def batched_bench(dbg, torch, dev, n_inst: int, reps: int, graphs_on: bool) -> d
             g.sync()
 
     out = {"workload": "batched: %d read sets, %d k-mer inserts, %.2f Gbp" % (n_inst, inserts, offs[-1] / 1e9),
-           "generation_s": round(gen_s, 1)}
+           "generation_s": round(gen_s, 1),
+           "autotune": dict(tune.as_dict(), seconds=round(tune_s, 2))}
     for name, fn in (("batched", batched), ("plain_per_instance", plain)):
         fn()  # warm-up (allocates scratch, captures graphs)
         torch.cuda.synchronize()
@@ -244,6 +248,55 @@ def served_bench(dbg, torch, dev, n_payloads: int, n_requests: int, loads, ref_g
     return out
 
 
+def large_bench(dbg, torch, dev, steps: int, graphs_on: bool) -> dict:
+    """The large plain build (100 Mbp genome with 2 % in repeats, 150 bp reads
+    at 20x, 1 % substitutions, k=31): binned mode at load factor 0.5, steps
+    of reset + build + sync as in the headline run (extraction timed apart)."""
+    import readsim
+
+    t0 = time.perf_counter()
+    rs = readsim.make_config(3)
+    gen_s = time.perf_counter() - t0
+    d_reads = torch.from_numpy(rs.reads).to(dev)
+    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
+    inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
+    g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.5, device=0,
+                  flags=dbg.F_BINNED | dbg.F_TIMING | (dbg.F_GRAPH if graphs_on else 0))
+
+    def step():
+        g.reset()
+        g.build_device(d_reads, d_off, rs.k)
+        g.sync()
+
+    step()
+    torch.cuda.synchronize()
+    ms, kern = [], []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        step()
+        ms.append((time.perf_counter() - t1) * 1e3)
+        kern.append(g.stats()["last_build_ms"])
+    st = g.stats()
+    cap = int(st["capacity"])
+    d_keys = torch.empty(st["vertices"], dtype=torch.int64, device=dev)
+    d_counts = torch.empty((st["vertices"], 4), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    V = g.extract_device(d_keys, d_counts)
+    torch.cuda.synchronize()
+    x_ms = (time.perf_counter() - t1) * 1e3
+    assert st["inserts"] == inserts
+    g.close()
+    del d_keys, d_counts, d_reads, d_off
+    torch.cuda.empty_cache()
+    step_ms = float(np.median(ms))
+    return {"workload": "plain build, large: " + rs.meta["name"], "reads": rs.n_reads, "k": rs.k,
+            "inserts_per_step": inserts, "vertices": V, "capacity": cap,
+            "table_bytes": int(st["table_bytes"]), "generation_s": round(gen_s, 1),
+            "ms_per_step": round(step_ms, 3), "ginserts_s": round(inserts / step_ms / 1e6, 4),
+            "build_ms": round(float(np.median(kern)), 3), "extract_ms": round(x_ms, 3)}
+
+
 def cpu_baseline(rs, sample_reads: int) -> dict:
     import oracle
 
@@ -281,6 +334,9 @@ def main() -> int:
     ap.add_argument("--batched-sets", type=int, default=256)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true", help="skip the serving benchmark")
+    ap.add_argument("--no-large", action="store_true", help="skip the large (100 Mbp) plain build")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use --mode/--load-factor/--block/--wpt/--merge instead of the autotuner's choice")
     ap.add_argument("--served-payloads", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--calibrate", action="store_true",
@@ -311,6 +367,16 @@ def main() -> int:
     d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
     inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
     windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
+    tuning = None
+    if not args.no_tune:
+        t1 = time.perf_counter()
+        t = dbg.autotune([0, rs.n_reads], [rs.k], d_reads, d_off, [rs.meta["expected_vertices"]],
+                         keep_flags=0 if args.no_graph else dbg.F_GRAPH, force=True)
+        tuning = dict(t.as_dict(), seconds=round(time.perf_counter() - t1, 2))
+        args.mode = "binned" if t.flags & dbg.F_BINNED else "direct"
+        args.load_factor, args.block, args.wpt = t.load_factor, t.block_size, t.windows_per_thread
+        args.merge = bool(t.flags & dbg.F_MERGE)
+        log("autotune: %s" % json.dumps(tuning))
 
     def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
         flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
@@ -414,6 +480,7 @@ def main() -> int:
                    "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode,
                    "hip_graphs": not args.no_graph},
         "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
+        "autotune": tuning,
         "roofline": roof,
     }
     if phase_table:
@@ -431,6 +498,10 @@ def main() -> int:
         line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps,
                                         not args.no_graph)
         log("batched %s" % json.dumps(line["batched"]))
+
+    if not args.no_large:
+        line["large"] = large_bench(dbg, torch, dev, 5, not args.no_graph)
+        log("large %s" % json.dumps(line["large"]))
 
     if not args.no_served:
         ref = line["batched"]["batched"]["ginserts_s"] if "batched" in line else value

@@ -288,6 +288,44 @@ int dbg_server_get_stats(dbg_server *s, dbg_server_stats *out);
 /* Finish every admitted request, drop queued ones, free everything. */
 void dbg_server_destroy(dbg_server *s);
 
+/* ---- autotuning -------------------------------------------------------
+ * Picks the build configuration of a workload by timing complete builds of a
+ * calibration input (the workload itself, or a slice of it that the caller
+ * passes): the table mode (binned or direct), the load factor and, for the
+ * direct build, block size, windows per thread and wavefront merging.  Every
+ * candidate must produce the same vertex and k-mer totals; one that does not,
+ * or that fails (a table overflow at a high load factor), is discarded.  The
+ * graph itself never depends on the choice: only the speed does. */
+typedef struct {
+    double load_factor;
+    uint32_t flags;              /* chosen DBG_F_BINNED / DBG_F_MERGE bits (others 0) */
+    uint32_t block_size;         /* direct build launch shape (0 for binned) */
+    uint32_t windows_per_thread;
+    uint32_t candidates;         /* configurations timed (0 when served from the cache) */
+    double best_ms;              /* median build time of the choice */
+    double default_ms;           /* median build time of binned mode at load factor 0.5 */
+    uint32_t from_cache;         /* 1 when the result came from the cache */
+    uint32_t pad;
+} dbg_tuning;
+
+#define DBG_TUNE_FORCE 0x1u /* ignore the cache (and refresh it) */
+
+/* Tune for m instances given as in dbg_build_batch_device (m = 1: a plain
+ * build).  expected_vertices[i] sizes instance i's table as dbg_config does
+ * (NULL or 0 = bound from the input).  keep_flags are DBG_F_* bits every
+ * candidate keeps (DBG_F_GRAPH, DBG_F_ENTRY32, DBG_F_TIMING).  repeats timed
+ * builds per candidate (0 = 3) after one warm-up.  Results are cached per
+ * process by device, instance count, k values, input size class and flags.
+ * Errors: DBG_E_INVAL, or the error of the default configuration's build. */
+int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const uint32_t *ks,
+                 const uint64_t *expected_vertices, const uint8_t *d_reads, uint64_t reads_len,
+                 const uint64_t *d_offsets, uint32_t keep_flags, uint32_t repeats, uint32_t tune_flags,
+                 dbg_tuning *out);
+
+/* Copy a tuning into a configuration (load factor, launch shape, mode and
+ * merge bits; the configuration's other fields are left as they are). */
+void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t);
+
 /* ---- measurement -----------------------------------------------------
  * Random-access roofline of the device: n_ops operations at indices drawn by
  * a 64-bit mixer over a footprint of footprint_bytes (no index array is

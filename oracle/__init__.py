@@ -139,6 +139,33 @@ def build_graph_parallel(reads, offsets, k: int, threads: int = 0):
     return keys[order], counts[order]
 
 
+def build_graph_chunked(reads, offsets, k: int, part_count: int = 1, part_index: int = 0,
+                        chunks: int = 0):
+    """Same result as ``build_graph(reads, offsets, k, part_count, part_index)``,
+    computed over ``chunks`` contiguous read ranges in parallel threads and
+    merged.  Exact because the graph is a multiset count over reads: the
+    vertex set of the whole is the union of the ranges' vertex sets and each
+    counter is the sum of the ranges' counters."""
+    import concurrent.futures
+
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    C = max(1, min(chunks or min(16, os.cpu_count() or 1), n))
+    if C == 1:
+        return build_graph(reads, offsets, k, part_count, part_index)
+    cuts = [n * c // C for c in range(C + 1)]
+    with concurrent.futures.ThreadPoolExecutor(C) as ex:
+        parts = list(ex.map(lambda c: build_graph(reads, offsets[cuts[c]:cuts[c + 1] + 1], k,
+                                                  part_count, part_index), range(C)))
+    keys = np.concatenate([p[0] for p in parts])
+    counts = np.concatenate([p[1] for p in parts]).astype(np.uint64)
+    order = np.argsort(keys, kind="stable")
+    keys, counts = keys[order], counts[order]
+    uniq, first = np.unique(keys, return_index=True)
+    summed = np.add.reduceat(counts, first, axis=0) if keys.size else counts
+    return uniq, summed.astype(np.uint32)
+
+
 def vertex_counts(reads, offsets, k: int, key: int):
     """(present, counts[4]) of one vertex by scanning every window."""
     reads, offsets = _as_inputs(reads, offsets)

@@ -34,8 +34,10 @@ EXPORTS = (
     "dbg_strerror", "dbg_build_batch", "dbg_build_batch_device", "dbg_atomic_roofline",
     "dbg_get_phase_times", "dbg_server_create", "dbg_server_submit", "dbg_server_submit_device",
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
-    "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy",
+    "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
+    "dbg_config_apply_tuning",
 )
+TUNE_FORCE = 0x1
 
 
 class Config(ctypes.Structure):
@@ -107,6 +109,28 @@ class ServerStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("load_factor", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+        ("block_size", ctypes.c_uint32),
+        ("windows_per_thread", ctypes.c_uint32),
+        ("candidates", ctypes.c_uint32),
+        ("best_ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
+        ("from_cache", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+    def graph_kwargs(self) -> dict:
+        """Keyword arguments of ``Graph`` that apply this tuning."""
+        return dict(load_factor=self.load_factor, block_size=self.block_size,
+                    windows_per_thread=self.windows_per_thread, flags=self.flags)
+
+
 _lib = None
 
 
@@ -149,6 +173,9 @@ def lib() -> ctypes.CDLL:
             "dbg_server_release": (ctypes.c_int, [vp, u64]),
             "dbg_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
             "dbg_server_destroy": (None, [vp]),
+            "dbg_autotune": (ctypes.c_int, [i32, u32, vp, vp, vp, vp, u64, vp, u32, u32, u32,
+                                            ctypes.POINTER(Tuning)]),
+            "dbg_config_apply_tuning": (None, [ctypes.POINTER(Config), ctypes.POINTER(Tuning)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -331,6 +358,26 @@ def build_batch_device(graphs: list[Graph], read_begin, ks, d_reads, d_offsets,
     lib().dbg_build_batch_device(hs, m, rb.ctypes.data, kk.ctypes.data, _ptr(d_reads), ln,
                                  _ptr(d_offsets), st, _stream(stream))
     return [int(st[i]) for i in range(m)]
+
+
+def autotune(read_begin, ks, d_reads, d_offsets, expected_vertices=None, keep_flags: int = 0,
+             repeats: int = 0, force: bool = False, reads_len: int | None = None,
+             device: int = -1) -> Tuning:
+    """``dbg_autotune`` over m instances laid out as in ``build_batch_device``
+    (m = 1: a plain build).  Returns the chosen ``Tuning``; apply it with
+    ``Graph(**t.graph_kwargs())`` (OR in the flags you keep)."""
+    rb = np.ascontiguousarray(read_begin, dtype=np.uint64)
+    kk = np.ascontiguousarray(ks, dtype=np.uint32)
+    m = kk.shape[0]
+    assert rb.shape[0] == m + 1
+    ev = None if expected_vertices is None else np.ascontiguousarray(expected_vertices, dtype=np.uint64)
+    t = Tuning()
+    ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+    rc = lib().dbg_autotune(int(device), m, rb.ctypes.data, kk.ctypes.data,
+                            None if ev is None else ev.ctypes.data, _ptr(d_reads), ln, _ptr(d_offsets),
+                            int(keep_flags), int(repeats), TUNE_FORCE if force else 0, ctypes.byref(t))
+    _check(rc, "dbg_autotune")
+    return t
 
 
 ROOF_LOAD64, ROOF_ADD32, ROOF_CAS64, ROOF_LOAD_ADD, ROOF_COPY = 0, 1, 2, 3, 4

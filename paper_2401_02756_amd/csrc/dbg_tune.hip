@@ -1,0 +1,227 @@
+// Autotuner: times complete builds of a calibration input under candidate
+// configurations and keeps the fastest.  The search is coordinate-wise:
+// binned mode over load factors, then (unless binned mode is already far
+// ahead) the direct build over launch shapes, wavefront merging and load
+// factors.  Choices are cached per process.
+#include "dbg_runtime.h"
+
+#include <chrono>
+#include <cstdio>
+#include <string>
+
+using namespace dbgrt;
+
+namespace {
+
+struct Cand {
+    bool binned;
+    double lf;
+    uint32_t block, wpt;
+    bool merge;
+};
+
+struct Workload {
+    int device;
+    uint32_t m;
+    const uint64_t *read_begin;
+    const uint32_t *ks;
+    const uint64_t *expected;
+    const uint8_t *d_reads;
+    uint64_t reads_len;
+    const uint64_t *d_offsets;
+    uint32_t keep_flags;
+    uint32_t repeats;
+};
+
+struct Outcome {
+    int rc = DBG_OK;
+    double ms = 0;
+    uint64_t vertices = 0, inserts = 0;
+};
+
+uint32_t cand_flags(const Cand &c, uint32_t keep) {
+    return (keep & (DBG_F_GRAPH | DBG_F_ENTRY32 | DBG_F_TIMING)) | (c.binned ? DBG_F_BINNED : 0u) |
+           (c.merge ? DBG_F_MERGE : 0u);
+}
+
+// Build the workload repeats + 1 times under `c`; the median host time of
+// the timed builds (tables reset between them), and the graph totals.
+Outcome time_candidate(const Workload &w, const Cand &c) {
+    Outcome o;
+    std::vector<dbg_graph *> gs(w.m, nullptr);
+    for (uint32_t i = 0; i < w.m && o.rc == DBG_OK; ++i) {
+        dbg_config cfg;
+        dbg_config_init(&cfg);
+        cfg.expected_vertices = w.expected ? w.expected[i] : 0;
+        cfg.load_factor = c.lf;
+        cfg.device = w.device;
+        cfg.flags = cand_flags(c, w.keep_flags);
+        cfg.block_size = c.block;
+        cfg.windows_per_thread = c.wpt;
+        o.rc = dbg_create(&cfg, &gs[i]);
+    }
+    std::vector<int32_t> st(w.m, DBG_OK);
+    std::vector<double> t;
+    for (uint32_t r = 0; r <= w.repeats && o.rc == DBG_OK; ++r) {
+        // a build starts from an empty table: the reset (lazy for binned
+        // tables, a zero fill for direct ones) is part of its cost
+        const auto t0 = std::chrono::steady_clock::now();
+        for (dbg_graph *g : gs) dbg_reset(g);
+        if (w.m == 1) {
+            const uint64_t *off = w.d_offsets;
+            o.rc = dbg_build_device(gs[0], w.d_reads, w.reads_len, off, w.read_begin[1], w.ks[0], nullptr);
+            if (o.rc == DBG_OK) o.rc = dbg_sync(gs[0]);
+        } else {
+            o.rc = dbg_build_batch_device(gs.data(), w.m, w.read_begin, w.ks, w.d_reads, w.reads_len, w.d_offsets,
+                                          st.data(), nullptr);
+        }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (r) t.push_back(ms);
+    }
+    if (o.rc == DBG_OK) {
+        std::sort(t.begin(), t.end());
+        o.ms = t[t.size() / 2];
+        for (dbg_graph *g : gs) {
+            dbg_stats s;
+            dbg_get_stats(g, &s);
+            o.vertices += s.vertices;
+            o.inserts += s.inserts;
+        }
+    }
+    for (dbg_graph *g : gs) dbg_destroy(g);
+    return o;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, dbg_tuning> g_tune_cache;
+
+int size_bucket(uint64_t x) {  // half-octaves
+    if (!x) return -1;
+    return (int)std::floor(2.0 * std::log2((double)x));
+}
+
+std::string cache_key(const Workload &w) {
+    uint32_t kmask_lo = 0, kmask_hi = 0;
+    uint64_t ev = 0;
+    for (uint32_t i = 0; i < w.m; ++i) {
+        (w.ks[i] < 32 ? kmask_lo : kmask_hi) |= 1u << (w.ks[i] & 31);
+        ev += w.expected ? w.expected[i] : 0;
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%d/%u/%x.%x/%d/%d/%d/%x", w.device, w.m, kmask_lo, kmask_hi,
+                  size_bucket(w.reads_len), size_bucket(w.read_begin[w.m]), size_bucket(ev), w.keep_flags);
+    return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t) {
+    if (!cfg || !t) return;
+    cfg->load_factor = t->load_factor;
+    cfg->block_size = t->block_size;
+    cfg->windows_per_thread = t->windows_per_thread;
+    cfg->flags = (cfg->flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)) | (t->flags & (DBG_F_BINNED | DBG_F_MERGE));
+}
+
+int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const uint32_t *ks,
+                 const uint64_t *expected_vertices, const uint8_t *d_reads, uint64_t reads_len,
+                 const uint64_t *d_offsets, uint32_t keep_flags, uint32_t repeats, uint32_t tune_flags,
+                 dbg_tuning *out) {
+    if (!out || m == 0 || !read_begin || !ks || !d_offsets || (!d_reads && reads_len) || read_begin[0] != 0)
+        return DBG_E_INVAL;
+    bool all_binnable = true;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (ks[i] < 2 || ks[i] > 32 || read_begin[i + 1] < read_begin[i]) return DBG_E_INVAL;
+        if (ks[i] > 31) all_binnable = false;
+    }
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
+    DeviceGuard guard(device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    Workload w{device, m, read_begin, ks, expected_vertices, d_reads, reads_len, d_offsets, keep_flags,
+               repeats ? repeats : 3u};
+    const std::string key = cache_key(w);
+    if (!(tune_flags & DBG_TUNE_FORCE)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            out->candidates = 0;
+            out->from_cache = 1;
+            return DBG_OK;
+        }
+    }
+
+    dbg_tuning best{};
+    best.best_ms = 1e300;
+    uint32_t n = 0;
+    bool have_ref = false;
+    uint64_t ref_v = 0, ref_i = 0;
+    int first_rc = DBG_OK;
+    auto consider = [&](const Cand &c) -> double {
+        const Outcome o = time_candidate(w, c);
+        ++n;
+        if (!have_ref && o.rc != DBG_OK && first_rc == DBG_OK) first_rc = o.rc;
+        if (o.rc != DBG_OK) return 1e300;
+        if (!have_ref) {
+            have_ref = true;
+            ref_v = o.vertices;
+            ref_i = o.inserts;
+        } else if (o.vertices != ref_v || o.inserts != ref_i) {
+            return 1e300;  // never chosen: its graph differs from the reference candidate's
+        }
+        if (o.ms < best.best_ms) {
+            best.best_ms = o.ms;
+            best.load_factor = c.lf;
+            best.flags = (c.binned ? DBG_F_BINNED : 0u) | (c.merge ? DBG_F_MERGE : 0u);
+            best.block_size = c.binned ? 0 : c.block;
+            best.windows_per_thread = c.binned ? 0 : c.wpt;
+        }
+        return o.ms;
+    };
+
+    double binned_best = 1e300;
+    if (all_binnable) {
+        for (double lf : {0.5, 0.4, 0.6, 0.7}) {
+            const double ms = consider(Cand{true, lf, 256, 4, false});
+            if (lf == 0.5) best.default_ms = ms;
+            binned_best = std::min(binned_best, ms);
+        }
+    }
+    // direct build: launch shape, then merging, then load factor
+    Cand dc{false, 0.5, 256, 4, false};
+    double dbest = consider(dc);
+    if (!all_binnable) best.default_ms = dbest;
+    if (dbest < 1.5 * binned_best) {
+        for (uint32_t block : {256u, 512u, 1024u})
+            for (uint32_t wpt : {2u, 4u, 8u}) {
+                if (block == 256 && wpt == 4) continue;
+                const Cand c{false, 0.5, block, wpt, false};
+                const double ms = consider(c);
+                if (ms < dbest) dbest = ms, dc = c;
+            }
+        Cand mc = dc;
+        mc.merge = true;
+        const double mms = consider(mc);
+        if (mms < dbest) dbest = mms, dc = mc;
+        for (double lf : {0.4, 0.6, 0.7}) {
+            Cand c = dc;
+            c.lf = lf;
+            const double ms = consider(c);
+            if (ms < dbest) dbest = ms, dc = c;
+        }
+    }
+    if (best.best_ms >= 1e300) return first_rc != DBG_OK ? first_rc : DBG_E_DEVICE;
+    if (best.default_ms >= 1e300) best.default_ms = 0;
+    best.candidates = n;
+    best.from_cache = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
+    return DBG_OK;
+}
+
+}  // extern "C"

@@ -65,7 +65,8 @@ def _c_layout(tmp_path, structs):
 
 def test_struct_layouts_match_header(tmp_path):
     structs = [("dbg_config", dbg.Config), ("dbg_stats", dbg.Stats), ("dbg_input", dbg.Input),
-               ("dbg_server_config", dbg.ServerConfig), ("dbg_server_stats", dbg.ServerStats)]
+               ("dbg_server_config", dbg.ServerConfig), ("dbg_server_stats", dbg.ServerStats),
+               ("dbg_tuning", dbg.Tuning)]
     got = _c_layout(tmp_path, structs)
     for cname, py in structs:
         assert got[cname] == ctypes.sizeof(py), cname
@@ -127,6 +128,18 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_server_release(None, 1) == dbg.E_INVAL
     assert L.dbg_server_get_stats(None, None) == dbg.E_INVAL
     L.dbg_server_destroy(None)
+    t = dbg.Tuning()
+    assert L.dbg_autotune(-1, 0, None, None, None, None, 0, None, 0, 0, 0, ctypes.byref(t)) == dbg.E_INVAL
+    rb = (ctypes.c_uint64 * 2)(0, 1)
+    ks = (ctypes.c_uint32 * 1)(33)
+    off = (ctypes.c_uint64 * 2)(0, 0)
+    assert L.dbg_autotune(-1, 1, rb, ks, None, None, 0, off, 0, 0, 0, ctypes.byref(t)) == dbg.E_INVAL
+    cfg = dbg.Config()
+    L.dbg_config_init(ctypes.byref(cfg))
+    cfg.flags = dbg.F_GRAPH | dbg.F_MERGE
+    t.load_factor, t.flags, t.block_size, t.windows_per_thread = 0.6, dbg.F_BINNED, 0, 0
+    L.dbg_config_apply_tuning(ctypes.byref(cfg), ctypes.byref(t))
+    assert cfg.flags == dbg.F_GRAPH | dbg.F_BINNED and cfg.load_factor == 0.6
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -1,0 +1,163 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (binned build with captured passes, load factor 0.5; the
+served runs through the server's defaults).
+
+  * bacterial scale (5 Mbp, 120M k-mers): every vertex against the oracle;
+  * large (100 Mbp, 1.6G k-mers): totals for the whole graph, and every
+    vertex of two of 256 key-space partitions against the oracle (the
+    oracle restricted to a partition is exact for it);
+  * batched (256 read sets): totals of every set, every vertex of a seeded
+    sample of sets (plus the largest and smallest) against the oracle;
+  * served: a seeded sample of requests from the served workload's pool,
+    built in a mix with other requests, against the oracle.
+"""
+
+import concurrent.futures
+
+import numpy as np
+import pytest
+
+import oracle
+import readsim
+import paper_2401_02756_amd as dbg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+THREADS = 16  # host threads of the oracle
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+
+
+def same(got, want, what):
+    gk, gc = got
+    wk, wc = want
+    assert gk.shape == wk.shape, "%s: %d vertices, oracle has %d" % (what, gk.shape[0], wk.shape[0])
+    assert np.array_equal(gk, wk), what + ": keys differ"
+    bad = int(np.count_nonzero(np.any(gc != wc, axis=1)))
+    assert bad == 0, "%s: %d vertices have different counts" % (what, bad)
+
+
+def kmers(rs):
+    return int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
+
+
+def test_bacterial_full_exact():
+    rs = readsim.make_config(2)
+    say("bacterial scale: %d reads, k=%d" % (rs.n_reads, rs.k))
+    d_reads = torch.from_numpy(rs.reads).cuda()
+    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
+    with dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.5,
+                   flags=dbg.F_BINNED | dbg.F_GRAPH) as g:
+        for _ in range(2):  # the second build replays the captured pass
+            g.reset()
+            g.build_device(d_reads, d_off, rs.k)
+            g.sync()
+        got = g.extract_sorted()
+    same(got, oracle.build_graph_parallel(rs.reads, rs.offsets, rs.k, threads=THREADS), "bacterial")
+
+
+@pytest.mark.timeout(600)
+def test_large_totals_and_sampled_partitions():
+    rs = readsim.make_config(3)
+    say("large: %d reads, %d bases, k=%d" % (rs.n_reads, rs.total_bases, rs.k))
+    d_reads = torch.from_numpy(rs.reads).cuda()
+    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
+    with dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.5,
+                   flags=dbg.F_BINNED | dbg.F_GRAPH) as g:
+        g.build_device(d_reads, d_off, rs.k)
+        g.sync()
+        st = g.stats()
+        keys, counts = g.extract()
+    del d_reads, d_off
+    torch.cuda.empty_cache()
+    say("large: %d vertices" % keys.shape[0])
+    assert st["inserts"] == kmers(rs)
+    assert int(counts.sum(dtype=np.uint64)) == kmers(rs)
+    assert keys.shape[0] == st["vertices"]
+    assert np.unique(keys).shape[0] == keys.shape[0]
+    part = oracle.partition_of(keys, 256)
+    for p in (0, 1):
+        sel = part == p
+        order = np.argsort(keys[sel])
+        got = (keys[sel][order], counts[sel][order])
+        want = oracle.build_graph_chunked(rs.reads, rs.offsets, rs.k, 256, p, chunks=THREADS)
+        same(got, want, "large, partition %d of 256" % p)
+
+
+def _batch_layout(sets):
+    lens = np.concatenate([x.lengths() for x in sets])
+    offs = np.zeros(lens.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    rb = np.zeros(len(sets) + 1, np.uint64)
+    np.cumsum([x.n_reads for x in sets], out=rb[1:])
+    return offs, rb
+
+
+def test_batched_full_totals_and_sampled_sets():
+    n = 256
+    with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+        sets = list(ex.map(lambda j: readsim.make_instance(4, j), range(n)))
+    offs, rb = _batch_layout(sets)
+    ks = [x.k for x in sets]
+    say("batched: %d sets, %d reads" % (n, int(rb[-1])))
+    d_reads = torch.from_numpy(np.concatenate([x.reads for x in sets])).cuda()
+    d_off = torch.from_numpy(offs).cuda()
+    gs = [dbg.Graph(expected_vertices=readsim.instance_params(4, j)["expected_vertices"], load_factor=0.5,
+                    flags=dbg.F_BINNED | dbg.F_GRAPH) for j in range(n)]
+    try:
+        assert dbg.build_batch_device(gs, rb, ks, d_reads, d_off) == [0] * n
+        for j, (g, x) in enumerate(zip(gs, sets)):
+            assert g.stats()["inserts"] == kmers(x), j
+        sizes = np.array([x.total_bases for x in sets])
+        rng = np.random.default_rng(0xB4)
+        sample = sorted(set(rng.choice(n, 10, replace=False).tolist()) |
+                        {int(sizes.argmax()), int(sizes.argmin())})
+        say("batched: exact check of sets %s" % sample)
+        for j in sample:
+            x = sets[j]
+            got = gs[j].extract_sorted()
+            assert int(got[1].sum(dtype=np.uint64)) == kmers(x)
+            same(got, oracle.build_graph_parallel(x.reads, x.offsets, x.k, threads=THREADS), "set %d" % j)
+    finally:
+        for g in gs:
+            g.close()
+
+
+@pytest.mark.timeout(600)
+def test_served_sampled_requests():
+    pool = [readsim.instance_params(5, j) for j in range(64)]
+    rng = np.random.default_rng(0xC5)
+    small = [j for j in range(64) if pool[j]["inserts"] < 150_000_000]
+    checked = sorted(rng.choice(small, 5, replace=False).tolist())
+    others = sorted(rng.choice([j for j in small if j not in checked], 7, replace=False).tolist())
+    with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+        sets = dict(zip(checked + others, ex.map(lambda j: readsim.make_instance(5, j), checked + others)))
+    say("served: checking requests of payloads %s among %s" % (checked, others))
+    dev = {j: (torch.from_numpy(x.reads).cuda(), torch.from_numpy(x.offsets.astype(np.int64)).cuda())
+           for j, x in sets.items()}
+    order = list(rng.permutation(checked + others))
+    with dbg.Server() as srv:
+        ids = {}
+        for j in order:
+            x = sets[j]
+            ids[j] = srv.submit_device(dev[j][0], dev[j][1], x.k, x.meta["expected_vertices"])
+        for j in order:
+            assert srv.wait(ids[j], timeout=120.0) == dbg.OK, j
+        for j in checked:
+            x = sets[j]
+            got = srv.graph(ids[j]).extract_sorted()
+            same(got, oracle.build_graph_parallel(x.reads, x.offsets, x.k, threads=THREADS), "payload %d" % j)
+        for j in order:
+            srv.release(ids[j])

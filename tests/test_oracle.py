@@ -206,6 +206,19 @@ def test_partitions_union_is_the_whole():
         assert np.all(oracle.partition_of(pk, 5) == p)
 
 
+def test_chunked_and_parallel_builds_equal_the_plain_one():
+    rs = readsim.make_config(2, scale=0.01)
+    keys, counts = oracle.build_graph(rs.reads, rs.offsets, rs.k)
+    for chunks in (2, 7):
+        ck, cc = oracle.build_graph_chunked(rs.reads, rs.offsets, rs.k, chunks=chunks)
+        assert np.array_equal(ck, keys) and np.array_equal(cc, counts)
+    pk, pc = oracle.build_graph(rs.reads, rs.offsets, rs.k, 16, 3)
+    ck, cc = oracle.build_graph_chunked(rs.reads, rs.offsets, rs.k, 16, 3, chunks=5)
+    assert np.array_equal(ck, pk) and np.array_equal(cc, pc)
+    qk, qc = oracle.build_graph_parallel(rs.reads, rs.offsets, rs.k, threads=4)
+    assert np.array_equal(qk, keys) and np.array_equal(qc, counts)
+
+
 def test_vertex_counts_one_by_one():
     rs = readsim.make_config(1)
     keys, counts = oracle.build_graph(rs.reads, rs.offsets, rs.k)
