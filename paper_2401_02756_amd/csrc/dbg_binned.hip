@@ -44,21 +44,47 @@ __device__ __forceinline__ uint32_t lds_add32(uint32_t *p, uint32_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Segment of a key within its instance (top bits of the hash).
-__device__ __forceinline__ uint32_t segment_of(uint64_t h, uint32_t parts) {
-    return (uint32_t)home_slot(h, parts);
+// Binned tables and records hold a key's image under a bijection of the
+// 60-bit key space (keys of k <= 31 have at most 60 bits): a multiply by an
+// odd constant modulo 2^60, then an xorshift by 30, which undoes itself on 60
+// bits.  A window's key is hashed once, in pass 1; everything after works on
+// the image: the segment is a pair of mixed-radix digits of its top 32 bits
+// (the level-1 bucket, then the segment inside the bucket), the home slot
+// inside the segment is its low bits, and extraction maps it back.
+constexpr uint64_t kKey60 = (1ull << 60) - 1;
+constexpr uint64_t kKeyMul = 0x0E3779B97F4A7C15ull;  // odd; the golden-ratio constant's low 60 bits
+
+constexpr uint64_t inverse_mod_2_64(uint64_t a) {  // Newton's iteration, 6 steps
+    uint64_t x = a;
+    for (int i = 0; i < 6; ++i) x *= 2 - a * x;
+    return x;
+}
+constexpr uint64_t kKeyMulInv = inverse_mod_2_64(kKeyMul);
+static_assert(kKeyMul * kKeyMulInv == 1, "inverse of the key multiplier");
+
+__device__ __forceinline__ uint64_t key_image(uint64_t key) {
+    const uint64_t x = (key * kKeyMul) & kKey60;
+    return x ^ (x >> 30);
 }
 
-// Level-1 bucket of a segment: seg / fan, by multiply-high with the
-// instance's precomputed ceil(2^64 / fan) (exact for 32-bit seg).
-__device__ __forceinline__ uint32_t bucket_of(uint32_t seg, uint32_t fan, uint64_t magic) {
-    return fan == 1 ? seg : (uint32_t)__umul64hi(magic, (uint64_t)seg);
+__device__ __forceinline__ uint64_t key_of_image(uint64_t x) {
+    x ^= x >> 30;
+    return (x * kKeyMulInv) & kKey60;
 }
 
-// Home slot inside a segment (low 32 bits of the hash).
-__device__ __forceinline__ uint32_t seg_home(uint64_t h) {
-    return (uint32_t)(((h & 0xffffffffull) * kSegSlots) >> 32);
+// Top 32 bits of an image: the digits of its segment.
+__device__ __forceinline__ uint32_t image_top(uint64_t x) { return (uint32_t)(x >> 28); }
+
+// Level-1 bucket of an image: the first digit, in [0, d1).
+__device__ __forceinline__ uint32_t bucket_of(uint32_t top, uint32_t d1) { return __umulhi(top, d1); }
+
+// Segment inside its bucket: the second digit, in [0, fan).
+__device__ __forceinline__ uint32_t child_of(uint32_t top, uint32_t d1, uint32_t fan) {
+    return __umulhi(top * d1, fan);
 }
+
+// Home slot inside a segment: the image's low bits.
+__device__ __forceinline__ uint32_t seg_home(uint64_t x) { return (uint32_t)x & (kSegSlots - 1); }
 
 // Last index i in [0, n) with base(i) <= x, for a non-decreasing base.
 template <typename F>
@@ -135,38 +161,6 @@ __device__ __forceinline__ uint32_t staged_read(const ReadStage &S, uint64_t w) 
         if (S.ws[mid] <= w) lo = mid; else hi = mid;
     }
     return lo;
-}
-
-// Record (key << 3 | sink << 2 | letter) of window w (ws[S.r0] <= w <
-// ws[re]).  `hint` is a staged read at or before w's read (the read of the
-// wavefront's first window): consecutive windows of a wavefront lie in one or
-// two reads, so walking forward from it replaces a search per lane.
-__device__ __forceinline__ uint64_t decode_record(const ReadStage &S, const uint64_t *ws,
-                                                  const uint64_t *off, uint64_t off0, uint64_t re,
-                                                  const uint64_t *packed, uint32_t km1, uint64_t w,
-                                                  uint32_t hint) {
-    uint64_t wr1, delta;
-    const uint32_t R = S.R;
-    uint32_t lo = hint;
-    if (lo <= kMapReads)
-        while (lo < R && S.ws[lo + 1] <= w) ++lo;
-    if (lo < R) {
-        wr1 = S.ws[lo + 1];
-        delta = S.delta[lo];
-    } else {
-        uint64_t glo = S.r0 + R, ghi = re;  // ws[glo] <= w < ws[ghi]
-        while (ghi - glo > 1) {
-            const uint64_t mid = (glo + ghi) >> 1;
-            if (ws[mid] <= w) glo = mid; else ghi = mid;
-        }
-        wr1 = ws[glo + 1];
-        delta = off[glo] - off0 - ws[glo];
-    }
-    const uint64_t b = bases_at(packed, w + delta);
-    const uint64_t key = b >> (64 - 2 * km1);
-    const uint32_t letter = (uint32_t)(b >> (62 - 2 * km1)) & 3u;
-    const uint32_t sink = (w + 1 == wr1) ? 4u : 0u;
-    return (key << 3) | sink | letter;
 }
 
 // Window range end and base delta (position = window + delta) of the read
@@ -326,8 +320,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
         const uint64_t tl = t - pl.tile_base;
         const uint64_t w0 = pl.w_begin + tl * kBinTile;
         const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, pl.w_end) - w0);
-        const uint32_t d1 = in.d1, fan = in.fan, parts = in.parts;
-        const uint64_t magic = in.fan_magic;
+        const uint32_t d1 = in.d1;
         const uint32_t kshift = 64 - 2 * (in.k - 1), lshift = 62 - 2 * (in.k - 1);
         for (uint32_t j = tid; j < d1; j += blockDim.x) s_cnt[j] = 0;
         stage_reads(S, ws, off, off0, tile_read1[t], in.read_end);
@@ -355,9 +348,9 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
                     c = packed[wbase + 2];
                 }
                 const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
-                const uint64_t key = v >> kshift;
-                rec[q] = (key << 3) | (w + 1 == rp.wr1 ? 4u : 0u) | ((uint32_t)(v >> lshift) & 3u);
-                const uint32_t bk = bucket_of(segment_of(mix64(key), parts), fan, magic);
+                const uint64_t img = key_image(v >> kshift);
+                rec[q] = (img << 3) | (w + 1 == rp.wr1 ? 4u : 0u) | ((uint32_t)(v >> lshift) & 3u);
+                const uint32_t bk = bucket_of(image_top(img), d1);
                 if (SCATTER) {
                     tag[q] = (bk << 12) | lds_add32(&s_cnt[bk], 1u);
                 } else {
@@ -529,7 +522,7 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict
         const uint64_t tl = t - B.tile_base;
         const uint64_t r0 = B.start + tl * kRefTile;
         const uint64_t r1 = min(r0 + kRefTile, B.start + B.size);
-        const uint32_t first = B.b * in.fan;
+        const uint32_t d1 = in.d1, fan = in.fan;
         for (uint32_t j = tid; j < B.fan; j += blockDim.x) s_cnt[j] = 0;
         __syncthreads();
         uint64_t rec[kRefPerThread];
@@ -544,7 +537,7 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict
             const uint64_t r = r0 + (uint64_t)it * blockDim.x + tid;
             tag[it] = 0xffffffffu;
             if (r < r1) {
-                const uint32_t c = segment_of(mix64(rec[it] >> 3), in.parts) - first;
+                const uint32_t c = child_of(image_top(rec[it] >> 3), d1, fan);
                 if (SCATTER) {
                     tag[it] = (c << 12) | lds_add32(&s_cnt[c], 1u);
                 } else {
@@ -629,9 +622,9 @@ constexpr uint64_t kNoRecord = ~0ull;     // no record value: keys stay below 2^
 // Returns false when the segment has no free slot for it.
 __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uint32_t *s_cnt,
                                               uint64_t &claims) {
-    const uint64_t key = rec >> 3;
-    const uint64_t tagv = key | kOccupied;
-    uint32_t s = seg_home(mix64(key));
+    const uint64_t img = rec >> 3;
+    const uint64_t tagv = img | kOccupied;
+    uint32_t s = seg_home(img);
     for (uint32_t q = 0; q < kSegSlots; ++q) {
         const uint64_t cur = lds_load64(&s_key[s]);
         bool hit = cur == tagv;
@@ -718,7 +711,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             // that slot's counters before the next barrier
             const uint64_t tagv = seg[(uint64_t)e * EW];
             const uint64_t c01 = seg[(uint64_t)e * EW + 1], c23 = seg[(uint64_t)e * EW + 2];
-            uint32_t s = seg_home(mix64(tagv & ~kOccupied));
+            uint32_t s = seg_home(tagv);
             for (uint32_t q = 0; q < kSegSlots; ++q) {
                 uint64_t expected = 0;
                 if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
@@ -805,7 +798,7 @@ __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t
             if (idx >= ocap) break;
             const uint64_t *w = seg + (uint64_t)e * EW;
             const uint64_t c01 = w[1], c23 = w[2];
-            okeys[idx] = w[0] & ~kOccupied;
+            okeys[idx] = key_of_image(w[0] & ~kOccupied);
             *reinterpret_cast<uint4 *>(ocnt + 4 * idx) =
                 make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
         }

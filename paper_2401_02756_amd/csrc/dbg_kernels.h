@@ -50,7 +50,7 @@ struct Instance {
     uint64_t prior_inserts; // k-mers already counted into the table
     uint64_t part_base;     // binned: global index of its first table segment
     uint32_t *seg_count;    // binned: occupied slots per segment (written by the build)
-    uint64_t fan_magic;     // binned: ceil(2^64 / fan) for fan > 1 (division by multiply-high)
+    uint64_t reserved;
     uint32_t k;
     uint32_t entry_words;
     uint32_t skip;          // nonzero: the host left this instance out

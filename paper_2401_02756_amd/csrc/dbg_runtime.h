@@ -508,16 +508,20 @@ struct dbg_graph {
 
 namespace dbgrt {
 
-// Segment geometry of a binned table of `parts` segments: d1 level-1 buckets
-// of `fan` segments each (about the square root, so both partition passes
-// write runs of similar length).
-inline bool binned_geometry(uint64_t parts, uint32_t *d1, uint32_t *fan) {
-    uint64_t target = (uint64_t)std::ceil(std::sqrt((double)parts));
+// Segment geometry of a binned table of at least `cap` slots: d1 level-1
+// buckets of `fan` segments each (about the square root, so both partition
+// passes write runs of similar length), d1 * fan segments of kSegSlots slots
+// in all (a segment is a pair of digits of the key image).  False if the
+// table is too large for the two levels.
+inline bool binned_geometry(uint64_t cap, uint32_t *d1, uint32_t *fan, uint64_t *parts) {
+    const uint64_t want = std::max<uint64_t>(1, (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots);
+    uint64_t target = (uint64_t)std::ceil(std::sqrt((double)want));
     target = std::max<uint64_t>(1, std::min<uint64_t>(target, dbgk::kMaxD1));
-    uint64_t f = (parts + target - 1) / target;
+    const uint64_t f = (want + target - 1) / target;
     if (f > dbgk::kMaxFan) return false;
     *fan = (uint32_t)f;
-    *d1 = (uint32_t)((parts + f - 1) / f);
+    *d1 = (uint32_t)((want + f - 1) / f);
+    *parts = (uint64_t)*d1 * f;
     return true;
 }
 
@@ -538,8 +542,8 @@ inline hipError_t order_after_zero(dbg_graph *g, hipStream_t s) {
 
 inline hipError_t allocate_table(dbg_graph *g, uint64_t cap) {
     if (g->binned) {
-        const uint64_t parts = (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots;
-        if (parts > 0xffffffffull || !binned_geometry(parts, &g->d1, &g->fan)) return hipErrorInvalidValue;
+        uint64_t parts = 0;
+        if (!binned_geometry(cap, &g->d1, &g->fan, &parts)) return hipErrorInvalidValue;
         g->parts = (uint32_t)parts;
         cap = parts * dbgk::kSegSlots;
         hipError_t e;
@@ -596,9 +600,7 @@ inline void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint6
     in.fan = g->binned ? g->fan : 0;
     in.fresh = (g->binned && g->fresh) ? 1u : 0u;
     in.seg_count = g->binned ? g->seg_count.as<uint32_t>() : nullptr;
-    // Lemire, Kaser, Kurz, "Faster remainder by direct computation" (2019):
-    // for 32-bit n, n / d is the high 64 bits of ceil(2^64 / d) * n
-    in.fan_magic = (g->binned && g->fan > 1) ? (~0ull / g->fan + 1) : 0;
+    in.reserved = 0;
     in.pad = 0;
 }
 
@@ -739,7 +741,6 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
             // segments only for the graphs a binned launch builds
             hi[i].parts = hi[i].d1 = hi[i].fan = 0;
             hi[i].fresh = 0;
-            hi[i].fan_magic = 0;
         }
         hi[i].part_base = part_base;
         part_base += hi[i].parts;

@@ -183,8 +183,9 @@ void size_request(const dbg_server_config &cfg, uint64_t vertices, Request &r) {
     r.slots = size_class(capacity_for(vertices, cfg.load_factor), 4096);
     const uint64_t ew = (cfg.flags & DBG_F_ENTRY32) ? 4 : 3;
     uint64_t cap = r.slots, extra = 0;
-    if (r.binned) {
-        const uint64_t parts = (cap + dbgk::kSegSlots - 1) / dbgk::kSegSlots;
+    uint32_t d1 = 0, fan = 0;
+    uint64_t parts = 0;
+    if (r.binned && binned_geometry(cap, &d1, &fan, &parts)) {
         cap = parts * dbgk::kSegSlots;
         extra = 4 * parts + 8 * (parts + 1) + 8 * ((parts + 1023) / 1024 + 2) + 8;
     }
