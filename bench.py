@@ -297,6 +297,16 @@ def large_bench(dbg, torch, dev, steps: int, graphs_on: bool) -> dict:
             "build_ms": round(float(np.median(kern)), 3), "extract_ms": round(x_ms, 3)}
 
 
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(rs, sample_reads: int) -> dict:
     import oracle
 
@@ -308,9 +318,19 @@ def cpu_baseline(rs, sample_reads: int) -> dict:
     keys, counts = oracle.build_graph(reads, offs, rs.k)
     dt = time.perf_counter() - t0
     ins = int(counts.sum())
-    return {"value": ins / dt / 1e9, "unit": "G k-mer inserts/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d reads (%d k-mer inserts, %d vertices), single-threaded C "
-                      "oracle, %.1f s" % (n, rs.n_reads, ins, keys.shape[0], dt)}
+    out = {"value": ins / dt / 1e9, "unit": "G k-mer inserts/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d of %d reads (%d k-mer inserts, %d vertices), single-threaded C "
+                     "oracle, %.1f s" % (n, rs.n_reads, ins, keys.shape[0], dt),
+           "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+    # the oracle's key-partitioned mode on the host's cores (each partition
+    # scans every read, so it scales with threads but not perfectly)
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    pk, pc = oracle.build_graph_parallel(reads, offs, rs.k, threads=threads)
+    dtp = time.perf_counter() - t0
+    assert pk.shape[0] == keys.shape[0]
+    out["parallel"] = {"value": ins / dtp / 1e9, "cores": threads, "seconds": round(dtp, 2)}
+    return out
 
 
 def main() -> int:
@@ -377,6 +397,25 @@ def main() -> int:
         args.load_factor, args.block, args.wpt = t.load_factor, t.block_size, t.windows_per_thread
         args.merge = bool(t.flags & dbg.F_MERGE)
         log("autotune: %s" % json.dumps(tuning))
+
+    def host_input_rate(reps: int = 3) -> dict:
+        """dbg_build from host memory: the ASCII reads and offsets cross PCIe
+        inside each timed build (pageable numpy buffers)."""
+        flags = dbg.F_BINNED if args.mode == "binned" else 0
+        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
+                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
+        g.build(rs.reads, rs.offsets, rs.k)  # warm-up
+        t = []
+        for _ in range(reps):
+            g.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build(rs.reads, rs.offsets, rs.k)
+            t.append(time.perf_counter() - t0)
+        g.close()
+        ms = float(np.median(t)) * 1e3
+        return {"ms": round(ms, 3), "ginserts_s": round(inserts / ms / 1e6, 4),
+                "bytes_over_pcie": int(rs.total_bases + 8 * (rs.n_reads + 1))}
 
     def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
         flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
@@ -493,6 +532,9 @@ def main() -> int:
                                    "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
                                    "build_ms": round(o["kern_ms"], 4)}
         log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
+
+    line["host_input"] = host_input_rate()
+    log("host input %s" % json.dumps(line["host_input"]))
 
     if not args.no_batched:
         line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps,

@@ -163,8 +163,7 @@ __device__ __forceinline__ uint32_t staged_read(const ReadStage &S, uint64_t w) 
     return lo;
 }
 
-// Window range end and base delta (position = window + delta) of the read
-// holding window w (ws[S.r0] <= w < ws[re]).
+// Window range end and base delta (position = window + delta) of a read.
 struct ReadPos {
     uint64_t wr1;    // one past the read's last window
     uint64_t delta;  // off[r] - off[0] - ws[r]
@@ -183,7 +182,7 @@ __device__ __forceinline__ ReadPos locate_read(const ReadStage &S, const uint64_
     return ReadPos{ws[glo + 1], off[glo] - off0 - ws[glo]};
 }
 
-// 64 bases starting `o` bits into the 192-bit big-endian word triple.
+// 64 bits starting `o` bits into the 192-bit big-endian word triple (o < 128).
 __device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, uint32_t o) {
     if (o >= 64) {
         a = b;
@@ -193,24 +192,53 @@ __device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, 
     return o ? (a << o) | (b >> (64 - o)) : a;
 }
 
-// Exclusive prefix of s_cnt[0..n) in place (whole block); returns nothing,
-// leaves the starts in s_cnt.  For each bucket j, gbase(j, start) is stored in
-// s_gbase[j].
+// Scatter tiles count with tagged counters: s_cnt[j] starts at j << 12, so
+// the value a record's fetch-add returns is its tag, bucket << 12 | rank, and
+// bucket j's count is s_cnt[j] - (j << 12) (at most the 4096 records of a
+// tile).  Records past the end of a tile add into one extra counter, so the
+// adds of a thread's records issue without branches.
+//
+// Exclusive prefix of the counts of s_cnt[0..n) in place (whole block): the
+// starts are left in s_cnt, and s_gbase[j] = gbase(j) - start.
 template <typename G>
 __device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, G gbase) {
     const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
     const uint32_t j0 = threadIdx.x * per;
     uint64_t sum = 0;
     for (uint32_t q = 0; q < per; ++q)
-        if (j0 + q < n) sum += s_cnt[j0 + q];
+        if (j0 + q < n) sum += s_cnt[j0 + q] - ((j0 + q) << 12);
     uint64_t total;
     uint64_t pre = block_exclusive_scan(sum, &total);
     for (uint32_t q = 0; q < per; ++q) {
         const uint32_t j = j0 + q;
         if (j < n) {
-            const uint32_t c = s_cnt[j];
+            const uint32_t c = s_cnt[j] - (j << 12);
             s_cnt[j] = (uint32_t)pre;
             s_gbase[j] = gbase(j) - pre;
+            pre += c;
+        }
+    }
+}
+
+// The same, with the global bases already loaded: g[q] holds the base of
+// bucket threadIdx.x * per + q, per = ceil(n / blockDim.x) <= N.
+template <uint32_t N>
+__device__ void bucket_starts_pre(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, const uint64_t (&g)[N]) {
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t j0 = threadIdx.x * per;
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < N; ++q)
+        if (q < per && j0 + q < n) sum += s_cnt[j0 + q] - ((j0 + q) << 12);
+    uint64_t total;
+    uint64_t pre = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (uint32_t q = 0; q < N; ++q) {
+        const uint32_t j = j0 + q;
+        if (q < per && j < n) {
+            const uint32_t c = s_cnt[j] - (j << 12);
+            s_cnt[j] = (uint32_t)pre;
+            s_gbase[j] = g[q] - pre;
             pre += c;
         }
     }
@@ -278,19 +306,22 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 
 // ---------------------------------------------------------------- pass 1
 
-// Dynamic LDS of the pass-1 kernels: s_cnt[d1_max] (+ s_gbase[d1_max],
+// Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max],
 // s_rec[kBinTile], s_bin[kBinTile] when scattering).
 __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter) {
-    uint32_t b = align16(4 * d1_max);
+    uint32_t b = align16(4 * (d1_max + 1));
     if (scatter) b += align16(8 * d1_max) + 8 * kBinTile + 2 * kBinTile;
     return b;
 }
 
 // Pass 1.  A thread takes kBinPerThread consecutive windows of the tile: it
 // finds their read once, loads three packed words, and slides through them,
-// so a window costs a few shifts instead of a search and two loads.
+// so a window costs a few shifts instead of a search and two loads.  The
+// next read's bases follow the current read's in the packed array, so a
+// window that starts another read (k - 2 bases further on) is found in the
+// staged reads and mostly stays inside the three words.
 template <bool SCATTER>
-__global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ args,
+__global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -304,7 +335,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
     __shared__ ReadStage S;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
-    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * d1_max));
+    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (d1_max + 1)));
     uint64_t *s_rec = s_gbase + d1_max;
     uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);
     const uint32_t tid = threadIdx.x;
@@ -322,14 +353,14 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
         const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, pl.w_end) - w0);
         const uint32_t d1 = in.d1;
         const uint32_t kshift = 64 - 2 * (in.k - 1), lshift = 62 - 2 * (in.k - 1);
-        for (uint32_t j = tid; j < d1; j += blockDim.x) s_cnt[j] = 0;
+        for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = SCATTER ? j << 12 : 0u;
         stage_reads(S, ws, off, off0, tile_read1[t], in.read_end);
 
         uint64_t rec[kBinPerThread];
-        uint32_t tag[kBinPerThread];  // bucket << 12 | rank within the bucket
+        uint32_t tag[kBinPerThread];  // scatter: bucket << 12 | rank (bucket d1: past the end)
         const uint32_t j0 = tid * kBinPerThread;
 #pragma unroll
-        for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = 0xffffffffu;
+        for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = d1 << 12;
         if (j0 < n_in) {
             uint64_t w = w0 + j0;
             ReadPos rp = locate_read(S, ws, off, off0, in.read_end, w);
@@ -342,17 +373,22 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
                 if (w >= rp.wr1) {  // the next window starts another read
                     rp = locate_read(S, ws, off, off0, in.read_end, w);
                     p = w + rp.delta;
-                    wbase = p >> 5;
-                    a = packed[wbase];
-                    b = packed[wbase + 1];
-                    c = packed[wbase + 2];
+                    // the words must hold this and the remaining windows' first
+                    // bases at offsets below 64 (without a crossing a thread's
+                    // offsets stay below 32 + kBinPerThread)
+                    if (p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
+                        wbase = p >> 5;
+                        a = packed[wbase];
+                        b = packed[wbase + 1];
+                        c = packed[wbase + 2];
+                    }
                 }
                 const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
                 const uint64_t img = key_image(v >> kshift);
                 rec[q] = (img << 3) | (w + 1 == rp.wr1 ? 4u : 0u) | ((uint32_t)(v >> lshift) & 3u);
                 const uint32_t bk = bucket_of(image_top(img), d1);
                 if (SCATTER) {
-                    tag[q] = (bk << 12) | lds_add32(&s_cnt[bk], 1u);
+                    tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
                 } else {
                     __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -372,8 +408,8 @@ __global__ __launch_bounds__(kBinBlock) void k_bin(const PassArgs *__restrict__ 
         __syncthreads();
 #pragma unroll
         for (uint32_t q = 0; q < kBinPerThread; ++q) {
-            if (tag[q] == 0xffffffffu) continue;
             const uint32_t bk = tag[q] >> 12;
+            if (bk == d1) continue;  // past the tile's end
             const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
             s_rec[pos] = rec[q];
             s_bin[pos] = (uint16_t)bk;
@@ -493,92 +529,121 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 // Dynamic LDS of the pass-2 kernels: s_cnt[fan_max] (+ s_gbase[fan_max],
 // s_rec[kRefTile], s_child[kRefTile] when scattering).
 __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter) {
-    uint32_t b = align16(4 * fan_max);
+    uint32_t b = align16(4 * (fan_max + 1));
     if (scatter) b += align16(8 * fan_max) + 8 * kRefTile + 2 * kRefTile;
     return b;
 }
 
-template <bool SCATTER>
-__global__ __launch_bounds__(kRefBlock) void k_refine(const Instance *__restrict__ inst,
-                                                     const Bucket *__restrict__ buckets,
-                                                     const BinTotals *__restrict__ tot,
-                                                     const uint64_t *__restrict__ rec1,
-                                                     uint32_t *__restrict__ hist2,
-                                                     const uint64_t *__restrict__ scan2,
-                                                     uint64_t *__restrict__ rec2,
-                                                     const uint32_t *__restrict__ tile_bucket2,
-                                                     uint32_t fan_max) {
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
-    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * fan_max));
-    uint64_t *s_rec = s_gbase + fan_max;
-    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);
-    const uint32_t tid = threadIdx.x;
-    const uint64_t tiles = tot->tiles2;
-    for (XcdTiles xt(tiles); xt.valid(); xt.advance()) {
-        const uint64_t t = xt.next;
-        const Bucket B = buckets[tile_bucket2[t]];
-        const Instance &in = inst[B.inst];
-        const uint64_t tl = t - B.tile_base;
-        const uint64_t r0 = B.start + tl * kRefTile;
-        const uint64_t r1 = min(r0 + kRefTile, B.start + B.size);
-        const uint32_t d1 = in.d1, fan = in.fan;
-        for (uint32_t j = tid; j < B.fan; j += blockDim.x) s_cnt[j] = 0;
-        __syncthreads();
-        uint64_t rec[kRefPerThread];
-        uint32_t tag[kRefPerThread];
+constexpr uint32_t kRefMaxPer = (kMaxFan + kRefBlock - 1) / kRefBlock;  // segments per thread in a scan
+
+// Load a pass-2 tile's records.
+__device__ __forceinline__ void refine_load(const RefTile &T, const uint64_t *__restrict__ rec1,
+                                            uint64_t (&rec)[kRefPerThread]) {
 #pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread; ++it) {
-            const uint64_t r = r0 + (uint64_t)it * blockDim.x + tid;
-            rec[it] = r < r1 ? rec1[r] : 0;
-        }
-#pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread; ++it) {
-            const uint64_t r = r0 + (uint64_t)it * blockDim.x + tid;
-            tag[it] = 0xffffffffu;
-            if (r < r1) {
-                const uint32_t c = child_of(image_top(rec[it] >> 3), d1, fan);
-                if (SCATTER) {
-                    tag[it] = (c << 12) | lds_add32(&s_cnt[c], 1u);
-                } else {
-                    __hip_atomic_fetch_add(&s_cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-        }
-        __syncthreads();
-        if (!SCATTER) {
-            for (uint32_t j = tid; j < B.fan; j += blockDim.x)
-                hist2[B.hist_base + (uint64_t)j * B.tiles + tl] = s_cnt[j];
-            __syncthreads();
-            continue;
-        }
-        bucket_starts(s_cnt, s_gbase, B.fan,
-                      [&](uint32_t j) { return scan2[B.hist_base + (uint64_t)j * B.tiles + tl]; });
-        __syncthreads();
-#pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread; ++it) {
-            if (tag[it] == 0xffffffffu) continue;
-            const uint32_t c = tag[it] >> 12;
-            const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
-            s_rec[pos] = rec[it];
-            s_child[pos] = (uint16_t)c;
-        }
-        __syncthreads();
-        const uint32_t n_in = (uint32_t)(r1 - r0);
-        for (uint32_t j = tid; j < n_in; j += blockDim.x) rec2[s_gbase[s_child[j]] + j] = s_rec[j];
-        __syncthreads();
+    for (uint32_t it = 0; it < kRefPerThread; ++it) {
+        const uint32_t j = it * blockDim.x + threadIdx.x;
+        rec[it] = j < T.n ? rec1[T.r0 + j] : 0;
     }
 }
 
-// Level-1 bucket of every pass-2 tile.
-__global__ void k_tile_buckets(const Bucket *__restrict__ buckets, const BinTotals *__restrict__ tot,
-                               uint32_t *__restrict__ tile_bucket2, uint64_t tiles_cap) {
+// Pass 2, per tile of records of one level-1 bucket: count (or, with
+// SCATTER, place) each record by its segment inside the bucket.  The next
+// tile's descriptor is read while this one is counted and its records are
+// loaded while this one is written; a scatter tile's global bases load while
+// its records are counted.  So a tile's global loads never wait on the
+// previous tile.
+template <bool SCATTER>
+__global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
+                                                     const RefTile *__restrict__ tile2,
+                                                     const uint64_t *__restrict__ rec1,
+                                                     uint32_t *__restrict__ hist2,
+                                                     const uint64_t *__restrict__ scan2,
+                                                     uint64_t *__restrict__ rec2, uint32_t fan_max) {
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
+    uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (fan_max + 1)));
+    uint64_t *s_rec = s_gbase + fan_max;
+    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);
+    const uint32_t tid = threadIdx.x;
+    XcdTiles xt(tot->tiles2);
+    if (!xt.valid()) return;
+    RefTile T = tile2[xt.next];
+    uint64_t rec[kRefPerThread];
+    refine_load(T, rec1, rec);
+    for (;;) {
+        xt.advance();
+        const bool more = xt.valid();
+        RefTile N{};
+        if (more) N = tile2[xt.next];
+        const uint32_t fan = T.fan, d1 = T.d1;
+        // scatter: this tile's segment bases (thread t: segments t * per ..
+        // t * per + per - 1), first used after the count
+        uint64_t gb[kRefMaxPer];
+        if (SCATTER) {
+            const uint32_t per = (fan + blockDim.x - 1) / blockDim.x;
+#pragma unroll
+            for (uint32_t q = 0; q < kRefMaxPer; ++q) {
+                const uint32_t j = tid * per + q;
+                gb[q] = (q < per && j < fan) ? scan2[T.hcol + (uint64_t)j * T.stride] : 0;
+            }
+        }
+        for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = SCATTER ? j << 12 : 0u;
+        __syncthreads();
+        uint32_t tag[kRefPerThread];  // scatter: segment << 12 | rank (segment fan: past the end)
+#pragma unroll
+        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            const uint32_t j = it * blockDim.x + tid;
+            const uint32_t c = j < T.n ? child_of(image_top(rec[it] >> 3), d1, fan) : fan;
+            if (SCATTER)
+                tag[it] = lds_add32(&s_cnt[c], 1u);
+            else
+                __hip_atomic_fetch_add(&s_cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        if (!SCATTER) {
+            for (uint32_t j = tid; j < fan; j += blockDim.x) hist2[T.hcol + (uint64_t)j * T.stride] = s_cnt[j];
+            if (more) refine_load(N, rec1, rec);
+            __syncthreads();
+        } else {
+            bucket_starts_pre(s_cnt, s_gbase, fan, gb);
+            __syncthreads();
+#pragma unroll
+            for (uint32_t it = 0; it < kRefPerThread; ++it) {
+                const uint32_t c = tag[it] >> 12;
+                if (c == fan) continue;  // past the tile's end
+                const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
+                s_rec[pos] = rec[it];
+                s_child[pos] = (uint16_t)c;
+            }
+            if (more) refine_load(N, rec1, rec);
+            __syncthreads();
+            for (uint32_t j = tid; j < T.n; j += blockDim.x) rec2[s_gbase[s_child[j]] + j] = s_rec[j];
+            __syncthreads();
+        }
+        if (!more) break;
+        T = N;
+    }
+}
+
+// Descriptor of every pass-2 tile: a block per level-1 bucket, a thread per tile.
+__global__ void k_tile_descs(const Instance *__restrict__ inst, const Bucket *__restrict__ buckets,
+                             const BinTotals *__restrict__ tot, RefTile *__restrict__ tile2,
+                             uint64_t tiles_cap) {
     const uint64_t G = tot->buckets;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += stride) {
+    for (uint64_t g = blockIdx.x; g < G; g += gridDim.x) {
         const Bucket B = buckets[g];
-        for (uint64_t t = B.tile_base; t < B.tile_base + B.tiles && t < tiles_cap; ++t)
-            tile_bucket2[t] = (uint32_t)g;
+        const uint32_t d1 = inst[B.inst].d1;
+        for (uint64_t tl = threadIdx.x; tl < B.tiles && B.tile_base + tl < tiles_cap; tl += blockDim.x) {
+            RefTile T;
+            T.r0 = B.start + tl * kRefTile;
+            T.hcol = B.hist_base + tl;
+            T.stride = B.tiles;
+            T.n = (uint32_t)min<uint64_t>(kRefTile, B.size - tl * kRefTile);
+            T.fan = B.fan;
+            T.d1 = d1;
+            T.pad = 0;
+            tile2[B.tile_base + tl] = T;
+        }
     }
 }
 
@@ -653,6 +718,13 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
 // with LDS atomics, and the occupied slots are written back packed, with the
 // new seg_count.  Each workgroup takes a contiguous run of segments, so it
 // meets few instances and flushes its claim count once per instance.
+//
+// Nothing global sits on the path from one segment to the next: segment
+// starts are read 256 at a time into LDS, the instance (and whether it is
+// skipped) is kept until the run crosses an instance boundary, and the next
+// segment's first records are loaded while this one is written back.
+constexpr uint32_t kStartsChunk = 256;  // segment starts staged per LDS refill
+
 template <uint32_t EW>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restrict__ args,
                                                         const Instance *__restrict__ inst,
@@ -666,46 +738,62 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     constexpr uint32_t kWaveSlots = kSegSlots / kWaves;  // slots compacted by one wavefront
     __shared__ uint64_t s_key[kSegSlots];
     __shared__ __align__(16) uint32_t s_cnt[kSegSlots * 4];
+    __shared__ uint64_t s_start[kStartsChunk + 2];
     __shared__ uint32_t s_wave_n[kWaves];
-    __shared__ uint32_t s_skip;
     __shared__ uint64_t s_sum;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t per_block = (parts_total + gridDim.x - 1) / gridDim.x;
-    const uint64_t gp0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t gp0 = min((uint64_t)blockIdx.x * per_block, parts_total);
     const uint64_t gp1 = min(gp0 + per_block, parts_total);
-    uint32_t cur_inst = 0xffffffffu;
-    uint64_t my_claims = 0;  // claims of cur_inst by this thread, not yet flushed
+    if (gp0 >= gp1) return;
     // LDS starts zeroed and every write-back leaves it zeroed again
     for (uint32_t s = tid; s < kSegSlots; s += blockDim.x) {
         s_key[s] = 0;
         reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
     }
-    for (uint64_t gp = gp0; gp < gp1; ++gp) {
-        const uint32_t i = (uint32_t)last_le(m, gp, [&](uint64_t j) { return inst[j].part_base; });
-        if (i != cur_inst) {  // uniform: gp is the same for the whole block
-            if (cur_inst != 0xffffffffu) flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
-            my_claims = 0;
-            cur_inst = i;
-        }
-        const Instance &in = inst[i];
-        if (tid == 0)
-            s_skip = __hip_atomic_load(&st[i].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kSkipMask;
+    // s_start[j] = pstart[c0 + j] for j <= kStartsChunk + 1 (within range)
+    uint64_t c0 = gp0;
+    auto stage_starts = [&]() {
+        for (uint32_t j = tid; j < kStartsChunk + 2; j += blockDim.x)
+            s_start[j] = c0 + j <= parts_total ? pstart[c0 + j] : 0;
         __syncthreads();
-        if (s_skip) {  // rejected input: the table is left untouched
-            __syncthreads();
-            continue;
-        }
-        const uint64_t seg_idx = gp - in.part_base;
-        uint64_t *seg = in.table + seg_idx * (uint64_t)kSegSlots * EW;
-        const uint64_t a = pstart[gp], z = pstart[gp + 1];
-        // issue the first records' loads before the re-insertion below
-        uint64_t rv[kReducePrefetch];
+    };
+    stage_starts();
+    uint32_t cur_inst = (uint32_t)last_le(m, gp0, [&](uint64_t j) { return inst[j].part_base; });
+    uint64_t next_base = cur_inst + 1 < m ? inst[cur_inst + 1].part_base : ~0ull;
+    bool skip = __hip_atomic_load(&st[cur_inst].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kSkipMask;
+    uint64_t my_claims = 0;  // claims of cur_inst by this thread, not yet flushed
+
+    uint64_t rv[kReducePrefetch];  // first records of the current segment
+    {
+        const uint64_t a = s_start[0], z = s_start[1];
 #pragma unroll
         for (uint32_t c = 0; c < kReducePrefetch; ++c) {
             const uint64_t r = a + (uint64_t)c * blockDim.x + tid;
             rv[c] = r < z ? rec2[r] : kNoRecord;
         }
-        const uint32_t n_old = in.fresh ? 0u : min(in.seg_count[seg_idx], kSegSlots);
+    }
+    for (uint64_t gp = gp0; gp < gp1; ++gp) {
+        if (gp >= next_base) {  // uniform: the run enters the next instance
+            flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
+            my_claims = 0;
+            while (gp >= next_base) {
+                ++cur_inst;
+                next_base = cur_inst + 1 < m ? inst[cur_inst + 1].part_base : ~0ull;
+            }
+            skip = __hip_atomic_load(&st[cur_inst].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kSkipMask;
+        }
+        if (gp - c0 == kStartsChunk) {
+            __syncthreads();  // every thread is done with the old starts
+            c0 = gp;
+            stage_starts();
+        }
+        const uint64_t a = s_start[gp - c0], z = s_start[gp - c0 + 1];
+        const Instance &in = inst[cur_inst];
+        const uint64_t seg_idx = gp - in.part_base;
+        uint64_t *seg = in.table + seg_idx * (uint64_t)kSegSlots * EW;
+        // a skipped (rejected) instance has no records and its table is left untouched
+        const uint32_t n_old = (skip || in.fresh) ? 0u : min(in.seg_count[seg_idx], kSegSlots);
         for (uint32_t e = tid; e < n_old; e += blockDim.x) {
             // distinct keys: each claims its own slot, and nobody else touches
             // that slot's counters before the next barrier
@@ -737,14 +825,24 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
                 rv[c] = r < z ? rec2[r] : kNoRecord;
             }
         }
-        if (full) atomic_or_u32(&st[i].err, kErrFull);
+        // the next segment's first records load while this one is written back
+        {
+            const uint64_t na = z, nz = gp + 1 < gp1 ? s_start[gp - c0 + 2] : z;
+#pragma unroll
+            for (uint32_t c = 0; c < kReducePrefetch; ++c) {
+                const uint64_t r = na + (uint64_t)c * blockDim.x + tid;
+                rv[c] = r < nz ? rec2[r] : kNoRecord;
+            }
+        }
+        if (full) atomic_or_u32(&st[cur_inst].err, kErrFull);
         __syncthreads();
+        if (skip) continue;  // uniform; LDS is still all zero
         // write the occupied slots back packed: each wavefront compacts its
         // own slot range with ballots, after one exchange of range totals
         const uint32_t s0 = wave * kWaveSlots;
         uint32_t mine = 0;
-        for (uint32_t c0 = 0; c0 < kWaveSlots; c0 += 64)
-            mine += (uint32_t)__popcll(__ballot(s_key[s0 + c0 + lane] != 0));
+        for (uint32_t c0w = 0; c0w < kWaveSlots; c0w += 64)
+            mine += (uint32_t)__popcll(__ballot(s_key[s0 + c0w + lane] != 0));
         if (lane == 0) s_wave_n[wave] = mine;
         __syncthreads();
         uint32_t out = 0, total = 0;
@@ -753,8 +851,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             out += w2 < wave ? nw : 0u;
             total += nw;
         }
-        for (uint32_t c0 = 0; c0 < kWaveSlots; c0 += 64) {
-            const uint32_t s = s0 + c0 + lane;
+        for (uint32_t c0w = 0; c0w < kWaveSlots; c0w += 64) {
+            const uint32_t s = s0 + c0w + lane;
             const uint64_t tagv = s_key[s];
             const uint64_t mask = __ballot(tagv != 0);
             if (tagv) {
@@ -773,7 +871,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         if (tid == 0) in.seg_count[seg_idx] = total;
         __syncthreads();
     }
-    if (cur_inst != 0xffffffffu) flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
+    flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
 }
 
 // ---------------------------------------------------------------- extract
@@ -860,14 +958,14 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
                        bb.buckets);
     {
-        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((bb.buckets_cap + 255) / 256, 4096));
-        hipLaunchKernelGGL(k_tile_buckets, dim3(g), dim3(256), 0, s, bb.buckets, bb.totals, bb.tile_bucket2,
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
+        hipLaunchKernelGGL(k_tile_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.tile2,
                            bb.tiles2_cap);
     }
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false), lr1 = ref_lds_bytes(bb.fan_max, true);
     const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
-    hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, inst, bb.buckets, bb.totals,
-                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
+    hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.tile2, bb.rec1,
+                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint64_t nb2 = std::max<uint64_t>((bb.hist2_cap + kFlatChunk - 1) / kFlatChunk, 1);
     const uint64_t *len2 = &bb.totals->hist2_len;
@@ -875,8 +973,8 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
                        bb.partials);
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
-    hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, inst, bb.buckets, bb.totals,
-                       bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.tile_bucket2, bb.fan_max);
+    hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.tile2, bb.rec1,
+                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     // segment starts and the reduction

@@ -137,6 +137,16 @@ struct Bucket {         // per level-1 bucket
     uint32_t pad;
 };
 
+struct RefTile {        // per pass-2 tile: everything its kernels need, in one load
+    uint64_t r0;              // first record (level-1 output)
+    uint64_t hcol;            // histogram entry of the bucket's first segment for this tile
+    uint64_t stride;          // histogram entries from one segment to the next (the bucket's tiles)
+    uint32_t n;               // records
+    uint32_t fan;             // segments in the bucket
+    uint32_t d1;              // level-1 buckets of the instance (first digit's radix)
+    uint32_t pad;
+};
+
 struct BinTotals {
     uint64_t tiles1, hist1_len, buckets, tiles2, hist2_len, records;
 };
@@ -153,7 +163,7 @@ struct BinBuffers {     // device scratch of one binned pass
     uint64_t *rec1, *rec2;    // records, windows_cap each
     uint64_t *pstart;         // parts_total + 1
     uint64_t *tile_read1;     // first read of each pass-1 tile (tiles1_cap)
-    uint32_t *tile_bucket2;   // level-1 bucket of each pass-2 tile (tiles2_cap)
+    RefTile *tile2;           // pass-2 tiles (tiles2_cap)
     uint64_t hist1_cap, hist2_cap, partials_cap;
     uint64_t tiles1_cap, tiles2_cap, buckets_cap, parts_cap;
     uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)

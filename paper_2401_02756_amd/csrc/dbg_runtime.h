@@ -261,7 +261,7 @@ struct Pass {
             (e = grow(rec1, 8 * k.len_cap)) != hipSuccess || (e = grow(rec2, 8 * k.len_cap)) != hipSuccess ||
             (e = grow(pstart, 8 * (k.parts_cap + 1))) != hipSuccess ||
             (e = grow(tread1, 8 * bb.tiles1_cap)) != hipSuccess ||
-            (e = grow(tbucket2, 4 * bb.tiles2_cap)) != hipSuccess)
+            (e = grow(tbucket2, sizeof(dbgk::RefTile) * bb.tiles2_cap)) != hipSuccess)
             return e;
         bb.plan = bplan.as<dbgk::BinPlan>();
         bb.buckets = bbuckets.as<dbgk::Bucket>();
@@ -275,7 +275,7 @@ struct Pass {
         bb.rec2 = rec2.as<uint64_t>();
         bb.pstart = pstart.as<uint64_t>();
         bb.tile_read1 = tread1.as<uint64_t>();
-        bb.tile_bucket2 = tbucket2.as<uint32_t>();
+        bb.tile2 = tbucket2.as<dbgk::RefTile>();
         return hipSuccess;
     }
     // Grid sizes per binned key (queried once, outside any capture).
