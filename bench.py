@@ -50,9 +50,11 @@ def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int
     return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
 
 
-def committed_traffic(profile: str, sources: list) -> int | None:
+def committed_traffic(profile: str, workload: dict) -> int | None:
     """HBM bytes per launch recorded by the counter runs in `profile`, or
-    None when any of the kernel sources changed since they were taken."""
+    None when any of the kernel sources changed since they were taken or the
+    run's workload parameters (`workload`, e.g. load factor and mode) differ
+    from the ones recorded there."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", profile)
@@ -68,6 +70,9 @@ def committed_traffic(profile: str, sources: list) -> int | None:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if not fields.get("sources") or h.hexdigest() != fields.get("source_sha256"):
         return None
+    for k, v in workload.items():
+        if fields.get(k) != str(v):
+            return None
     return int(fields["traffic_bytes_per_launch"])
 
 
@@ -488,7 +493,9 @@ def main() -> int:
                                 "gbs": round(pb[name] / (ms * 1e-3) / 1e9, 1)})
         red = phase_table[3]
         bytes_alg, k_ms, kname = red["algorithmic_bytes"], red["ms"], "k_reduce (binned segment reduce)"
-        traffic = committed_traffic("k_reduce_traffic_bacterial_c2.md", []) if args.config == 2 else None
+        traffic = (committed_traffic("k_reduce_traffic_bacterial_c2.md",
+                                     {"load_factor": args.load_factor, "mode": args.mode, "entry_bytes": st["entry_bytes"]})
+                   if args.config == 2 else None)
     else:
         bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
         k_ms, kname = kern_ms, "k_build (direct find-or-claim + count)"
