@@ -71,6 +71,12 @@ def lib() -> ctypes.CDLL:
         L.oracle_partition_many.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                             ctypes.c_void_p]
         L.oracle_partition_many.restype = None
+        L.oracle_contigs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_contigs.restype = ctypes.c_int
+        L.oracle_strings_digest.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
+        L.oracle_strings_digest.restype = ctypes.c_uint64
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_free.restype = None
         _lib = L
@@ -164,6 +170,43 @@ def build_graph_chunked(reads, offsets, k: int, part_count: int = 1, part_index:
     uniq, first = np.unique(keys, return_index=True)
     summed = np.add.reduceat(counts, first, axis=0) if keys.size else counts
     return uniq, summed.astype(np.uint32)
+
+
+def contigs(keys, counts, k: int):
+    """Contigs of the graph ``(keys ascending, counts[V, 4])`` as the paper's
+    findContigs defines them (see ``oracle_contigs``): ``(seq uint8[],
+    offsets uint64[n + 1])``, contig i being ``seq[offsets[i]:offsets[i+1]]``."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    n = keys.shape[0]
+    ps, po = ctypes.c_void_p(), ctypes.c_void_p()
+    nc, sl = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    rc = lib().oracle_contigs(keys.ctypes.data if n else None, counts.ctypes.data if n else None, n, int(k),
+                              ctypes.byref(ps), ctypes.byref(po), ctypes.byref(nc), ctypes.byref(sl))
+    if rc != OK:
+        raise OracleError(rc)
+    try:
+        seq = (np.ctypeslib.as_array(ctypes.cast(ps, ctypes.POINTER(ctypes.c_uint8)), shape=(sl.value,)).copy()
+               if sl.value else np.zeros(0, np.uint8))
+        off = np.ctypeslib.as_array(ctypes.cast(po, ctypes.POINTER(ctypes.c_uint64)), shape=(nc.value + 1,)).copy()
+    finally:
+        lib().oracle_free(ps)
+        lib().oracle_free(po)
+    return seq, off
+
+
+def contig_strings(seq, off) -> list:
+    """The contigs as a sorted list of bytes (for small sets)."""
+    seq = np.asarray(seq, dtype=np.uint8)
+    return sorted(seq[off[i]:off[i + 1]].tobytes() for i in range(len(off) - 1))
+
+
+def strings_digest(seq, off) -> int:
+    """Order-free 64-bit digest of a set of strings (``oracle_strings_digest``)."""
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    return int(lib().oracle_strings_digest(seq.ctypes.data if seq.size else None, off.ctypes.data,
+                                           off.shape[0] - 1))
 
 
 def vertex_counts(reads, offsets, k: int, key: int):

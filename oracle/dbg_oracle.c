@@ -262,3 +262,155 @@ int oracle_vertex_counts(const unsigned char *reads, const uint64_t *offsets, ui
 }
 
 void oracle_free(void *p) { free(p); }
+
+/* ---------------------------------------------------------------- contigs
+ *
+ * Contigs of a graph (Methods, "Finding contigs", Algorithm 5), computed from
+ * the graph's records (keys ascending, four counters each), as this oracle
+ * reads the passage:
+ *
+ *   - first(v) holds when v was only ever added as a left vertex, i.e. no
+ *     k-mer ends in v: in-degree 0 (the flag is cleared whenever v is added
+ *     as a right vertex);
+ *   - v has an out-edge for every letter whose counter is non-zero;
+ *   - a contig starts at every vertex with first(v) or with more than one
+ *     out-edge, one contig per out-edge, and spells v followed by the letter
+ *     of each edge it takes;
+ *   - from the edge's target it keeps going while the vertex it stands on has
+ *     exactly one out-edge; it stops on a vertex with zero or several
+ *     out-edges, and (a case the passage leaves open: a loop of one-edge
+ *     vertices would never end) on a vertex it has already stood on.  The
+ *     vertex it stops on is part of the contig.
+ *
+ * Contigs are produced in the order of their start key, then letter code;
+ * comparisons sort them.  Vertices are found by binary search over the keys.
+ */
+static int64_t find_key(const uint64_t *keys, uint64_t n, uint64_t key) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && keys[lo] == key) ? (int64_t)lo : -1;
+}
+
+static uint32_t out_degree(const uint32_t *counts, uint64_t i) {
+    uint32_t d = 0;
+    for (int c = 0; c < 4; ++c) d += counts[4 * i + c] ? 1u : 0u;
+    return d;
+}
+
+typedef struct {
+    unsigned char *seq;
+    uint64_t len, cap;
+    uint64_t *off;
+    uint64_t n, off_cap;
+} ocontigs;
+
+static int push_base(ocontigs *o, unsigned char b) {
+    if (o->len == o->cap) {
+        const uint64_t cap = o->cap ? 2 * o->cap : 1 << 16;
+        unsigned char *p = (unsigned char *)realloc(o->seq, cap);
+        if (!p) return ORACLE_E_NOMEM;
+        o->seq = p;
+        o->cap = cap;
+    }
+    o->seq[o->len++] = b;
+    return ORACLE_OK;
+}
+
+static int push_offset(ocontigs *o, uint64_t v) {
+    if (o->n + 1 >= o->off_cap) {
+        const uint64_t cap = o->off_cap ? 2 * o->off_cap : 1 << 12;
+        uint64_t *p = (uint64_t *)realloc(o->off, cap * sizeof(uint64_t));
+        if (!p) return ORACLE_E_NOMEM;
+        o->off = p;
+        o->off_cap = cap;
+    }
+    o->off[o->n] = v;
+    return ORACLE_OK;
+}
+
+/* Output: *seq_out (ASCII, contigs back to back) and *off_out (n_contigs + 1
+ * offsets into it); both freed with oracle_free. */
+int oracle_contigs(const uint64_t *keys, const uint32_t *counts, uint64_t n, uint32_t k,
+                   unsigned char **seq_out, uint64_t **off_out, uint64_t *n_contigs, uint64_t *seq_len) {
+    static const unsigned char letters[4] = {'A', 'C', 'T', 'G'};
+    if (!seq_out || !off_out || !n_contigs || !seq_len || (n && (!keys || !counts))) return ORACLE_E_INVAL;
+    if (k < 2 || k > 32) return ORACLE_E_K;
+    *seq_out = NULL;
+    *off_out = NULL;
+    *n_contigs = 0;
+    *seq_len = 0;
+    const uint32_t km1 = k - 1;
+    const uint64_t mask = (1ull << (2 * km1)) - 1;
+    ocontigs o = {0};
+    uint64_t *stamp = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t)); /* walk id + 1 of the last visit */
+    if (!stamp) return ORACLE_E_NOMEM;
+    int rc = ORACLE_OK;
+    uint64_t walk = 0;
+    for (uint64_t i = 0; i < n && rc == ORACLE_OK; ++i) {
+        const uint64_t v = keys[i];
+        const uint32_t deg = out_degree(counts, i);
+        if (deg == 0) continue;
+        int has_in = 0;
+        for (uint64_t x = 0; x < 4 && !has_in; ++x) {
+            const uint64_t pred = (x << (2 * (km1 - 1))) | (v >> 2);
+            const int64_t j = find_key(keys, n, pred);
+            if (j >= 0 && counts[4 * (uint64_t)j + (v & 3)]) has_in = 1;
+        }
+        if (!(deg >= 2 || !has_in)) continue;
+        for (uint32_t c = 0; c < 4 && rc == ORACLE_OK; ++c) {
+            if (!counts[4 * i + c]) continue;
+            ++walk;
+            rc = push_offset(&o, o.len);
+            for (uint32_t b = 0; b < km1 && rc == ORACLE_OK; ++b)
+                rc = push_base(&o, letters[(v >> (2 * (km1 - 1 - b))) & 3]);
+            if (rc == ORACLE_OK) rc = push_base(&o, letters[c]);
+            stamp[i] = walk;
+            uint64_t cur = ((v << 2) | c) & mask;
+            while (rc == ORACLE_OK) {
+                const int64_t j = find_key(keys, n, cur);
+                if (j < 0) { rc = ORACLE_E_INVAL; break; } /* a target is always a vertex */
+                if (out_degree(counts, (uint64_t)j) != 1 || stamp[j] == walk) break;
+                stamp[j] = walk;
+                uint32_t only = 0;
+                while (!counts[4 * (uint64_t)j + only]) ++only;
+                rc = push_base(&o, letters[only]);
+                cur = ((cur << 2) | only) & mask;
+            }
+            ++o.n;
+        }
+    }
+    free(stamp);
+    if (rc == ORACLE_OK) rc = push_offset(&o, o.len);
+    if (rc != ORACLE_OK) {
+        free(o.seq);
+        free(o.off);
+        return rc;
+    }
+    *seq_out = o.seq;
+    *off_out = o.off;
+    *n_contigs = o.n;
+    *seq_len = o.len;
+    return ORACLE_OK;
+}
+
+/* Order-free digest of a set of strings (for comparing very large contig
+ * sets): the sum, modulo 2^64, of a 64-bit FNV-1a hash of each string passed
+ * through the SplitMix64 finalizer. */
+uint64_t oracle_strings_digest(const unsigned char *seq, const uint64_t *off, uint64_t n) {
+    uint64_t sum = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = 0xcbf29ce484222325ull;
+        for (uint64_t p = off[i]; p < off[i + 1]; ++p) h = (h ^ seq[p]) * 0x100000001b3ull;
+        h ^= h >> 30;
+        h *= 0xbf58476d1ce4e5b9ull;
+        h ^= h >> 27;
+        h *= 0x94d049bb133111ebull;
+        h ^= h >> 31;
+        sum += h;
+    }
+    return sum;
+}
