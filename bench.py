@@ -422,6 +422,26 @@ def main() -> int:
         return {"ms": round(ms, 3), "ginserts_s": round(inserts / ms / 1e6, 4),
                 "bytes_over_pcie": int(rs.total_bases + 8 * (rs.n_reads + 1))}
 
+    def contig_rate(reps: int = 3) -> dict:
+        """Contigs (findContigs, Algorithm 5) of the built graph, on the
+        device: extraction, walk table, starts, walks, layout, spelling."""
+        flags = dbg.F_BINNED if args.mode == "binned" else 0
+        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
+                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
+        t = []
+        n = ln = 0
+        for _ in range(reps + 1):
+            g.reset()
+            g.build_device(d_reads, d_off, rs.k)
+            g.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n, ln = g.contig_sizes()
+            t.append(time.perf_counter() - t0)
+        g.close()
+        ms = float(np.median(t[1:])) * 1e3
+        return {"ms": round(ms, 3), "contigs": n, "bases": ln, "vertices_per_s": round(V / ms * 1e3, 1)}
+
     def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
         flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
         if mode == "binned":
@@ -539,6 +559,9 @@ def main() -> int:
                                    "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
                                    "build_ms": round(o["kern_ms"], 4)}
         log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
+
+    line["contigs"] = contig_rate()
+    log("contigs %s" % json.dumps(line["contigs"]))
 
     line["host_input"] = host_input_rate()
     log("host input %s" % json.dumps(line["host_input"]))

@@ -209,6 +209,31 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
                            const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
                            const uint64_t *d_offsets, int32_t *statuses, void *stream);
 
+/* ---- contigs ----------------------------------------------------------
+ * Contigs of the graph (Methods, "Finding contigs", Algorithm 5): a vertex is
+ * marked `first` when no k-mer ends in it (the paper clears the flag whenever
+ * the vertex is added as a right vertex); a contig starts at every vertex that
+ * is `first` or has more than one out-edge, once per out-edge, spells the
+ * vertex and the letter of each edge it takes, and goes on while the vertex
+ * it reaches has exactly one out-edge.  It stops on a vertex with zero or
+ * several out-edges, or on a vertex it has already passed (loops of one-edge
+ * vertices, which the paper's walk would follow forever); the vertex it stops
+ * on is part of the contig.  Loops without a start vertex yield no contig.
+ *
+ * Output: ASCII contigs back to back in seq, contig i being
+ * seq[offsets[i] .. offsets[i+1]); n_contigs + 1 offsets.  The set is unique;
+ * the order is unspecified.  With seq and offsets NULL only *n_contigs and
+ * *seq_len are set (the result is kept on the device until the next build or
+ * reset, so a second call to fetch it does not recompute).  Errors:
+ * DBG_E_INVAL, DBG_E_STATE (graph poisoned), DBG_E_SPACE (a buffer is too
+ * small; the sizes are set), DBG_E_NOMEM, DBG_E_DEVICE. */
+int dbg_contigs(dbg_graph *g, char *seq, uint64_t seq_cap, uint64_t *offsets, uint64_t offsets_cap,
+                uint64_t *n_contigs, uint64_t *seq_len);
+
+/* The same into device buffers, ordered on `stream` (NULL: the handle's). */
+int dbg_contigs_device(dbg_graph *g, uint8_t *d_seq, uint64_t seq_cap, uint64_t *d_offsets,
+                       uint64_t offsets_cap, uint64_t *n_contigs, uint64_t *seq_len, void *stream);
+
 /* ---- serving ----------------------------------------------------------
  * A build server: requests (read sets) are admitted first come, first served
  * while the table bytes of the admitted, unreleased requests stay within an

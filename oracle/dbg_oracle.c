@@ -282,17 +282,35 @@ void oracle_free(void *p) { free(p); }
  *     vertices would never end) on a vertex it has already stood on.  The
  *     vertex it stops on is part of the contig.
  *
- * Contigs are produced in the order of their start key, then letter code;
- * comparisons sort them.  Vertices are found by binary search over the keys.
+ * first(v) is computed the way the paper maintains it: it starts true for
+ * every vertex and is cleared on the target of every edge.  Contigs are
+ * produced in the order of their start key, then letter code; comparisons
+ * sort them.  Vertices are found through a chained index over the keys.
  */
-static int64_t find_key(const uint64_t *keys, uint64_t n, uint64_t key) {
-    uint64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (keys[mid] < key) lo = mid + 1;
-        else hi = mid;
+typedef struct {
+    int64_t *head, *next;
+    int bits;
+} oindex;
+
+static int oindex_build(oindex *x, const uint64_t *keys, uint64_t n) {
+    x->bits = 1;
+    while ((1ull << x->bits) < 2 * n) ++x->bits;
+    x->head = (int64_t *)malloc((1ull << x->bits) * sizeof(int64_t));
+    x->next = (int64_t *)malloc((n ? n : 1) * sizeof(int64_t));
+    if (!x->head || !x->next) return ORACLE_E_NOMEM;
+    for (uint64_t b = 0; b < (1ull << x->bits); ++b) x->head[b] = -1;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t b = bucket_of(keys[i], x->bits);
+        x->next[i] = x->head[b];
+        x->head[b] = (int64_t)i;
     }
-    return (lo < n && keys[lo] == key) ? (int64_t)lo : -1;
+    return ORACLE_OK;
+}
+
+static int64_t oindex_find(const oindex *x, const uint64_t *keys, uint64_t key) {
+    for (int64_t i = x->head[bucket_of(key, x->bits)]; i >= 0; i = x->next[i])
+        if (keys[i] == key) return i;
+    return -1;
 }
 
 static uint32_t out_degree(const uint32_t *counts, uint64_t i) {
@@ -346,21 +364,24 @@ int oracle_contigs(const uint64_t *keys, const uint32_t *counts, uint64_t n, uin
     const uint32_t km1 = k - 1;
     const uint64_t mask = (1ull << (2 * km1)) - 1;
     ocontigs o = {0};
-    uint64_t *stamp = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t)); /* walk id + 1 of the last visit */
-    if (!stamp) return ORACLE_E_NOMEM;
-    int rc = ORACLE_OK;
+    oindex ix = {0};
+    uint64_t *stamp = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t)); /* walk id of the last visit */
+    unsigned char *first = (unsigned char *)malloc(n ? n : 1);
+    int rc = (stamp && first) ? oindex_build(&ix, keys, n) : ORACLE_E_NOMEM;
+    for (uint64_t i = 0; i < n && rc == ORACLE_OK; ++i) first[i] = 1;
+    for (uint64_t i = 0; i < n && rc == ORACLE_OK; ++i)
+        for (uint64_t c = 0; c < 4; ++c) {
+            if (!counts[4 * i + c]) continue;
+            const int64_t j = oindex_find(&ix, keys, ((keys[i] << 2) | c) & mask);
+            if (j < 0) { rc = ORACLE_E_INVAL; break; } /* a target is always a vertex */
+            first[j] = 0;
+        }
     uint64_t walk = 0;
     for (uint64_t i = 0; i < n && rc == ORACLE_OK; ++i) {
         const uint64_t v = keys[i];
         const uint32_t deg = out_degree(counts, i);
         if (deg == 0) continue;
-        int has_in = 0;
-        for (uint64_t x = 0; x < 4 && !has_in; ++x) {
-            const uint64_t pred = (x << (2 * (km1 - 1))) | (v >> 2);
-            const int64_t j = find_key(keys, n, pred);
-            if (j >= 0 && counts[4 * (uint64_t)j + (v & 3)]) has_in = 1;
-        }
-        if (!(deg >= 2 || !has_in)) continue;
+        if (!(deg >= 2 || first[i])) continue;
         for (uint32_t c = 0; c < 4 && rc == ORACLE_OK; ++c) {
             if (!counts[4 * i + c]) continue;
             ++walk;
@@ -371,8 +392,8 @@ int oracle_contigs(const uint64_t *keys, const uint32_t *counts, uint64_t n, uin
             stamp[i] = walk;
             uint64_t cur = ((v << 2) | c) & mask;
             while (rc == ORACLE_OK) {
-                const int64_t j = find_key(keys, n, cur);
-                if (j < 0) { rc = ORACLE_E_INVAL; break; } /* a target is always a vertex */
+                const int64_t j = oindex_find(&ix, keys, cur);
+                if (j < 0) { rc = ORACLE_E_INVAL; break; }
                 if (out_degree(counts, (uint64_t)j) != 1 || stamp[j] == walk) break;
                 stamp[j] = walk;
                 uint32_t only = 0;
@@ -384,6 +405,9 @@ int oracle_contigs(const uint64_t *keys, const uint32_t *counts, uint64_t n, uin
         }
     }
     free(stamp);
+    free(first);
+    free(ix.head);
+    free(ix.next);
     if (rc == ORACLE_OK) rc = push_offset(&o, o.len);
     if (rc != ORACLE_OK) {
         free(o.seq);
@@ -399,17 +423,17 @@ int oracle_contigs(const uint64_t *keys, const uint32_t *counts, uint64_t n, uin
 
 /* Order-free digest of a set of strings (for comparing very large contig
  * sets): the sum, modulo 2^64, of a 64-bit FNV-1a hash of each string passed
- * through the SplitMix64 finalizer. */
+ * through MurmurHash3's 64-bit finalizer (fmix64). */
 uint64_t oracle_strings_digest(const unsigned char *seq, const uint64_t *off, uint64_t n) {
     uint64_t sum = 0;
     for (uint64_t i = 0; i < n; ++i) {
         uint64_t h = 0xcbf29ce484222325ull;
         for (uint64_t p = off[i]; p < off[i + 1]; ++p) h = (h ^ seq[p]) * 0x100000001b3ull;
-        h ^= h >> 30;
-        h *= 0xbf58476d1ce4e5b9ull;
-        h ^= h >> 27;
-        h *= 0x94d049bb133111ebull;
-        h ^= h >> 31;
+        h ^= h >> 33;
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 33;
+        h *= 0xc4ceb9fe1a85ec53ull;
+        h ^= h >> 33;
         sum += h;
     }
     return sum;

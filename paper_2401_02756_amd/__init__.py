@@ -35,7 +35,7 @@ EXPORTS = (
     "dbg_get_phase_times", "dbg_server_create", "dbg_server_submit", "dbg_server_submit_device",
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
     "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
-    "dbg_config_apply_tuning",
+    "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device",
 )
 TUNE_FORCE = 0x1
 
@@ -176,6 +176,9 @@ def lib() -> ctypes.CDLL:
             "dbg_autotune": (ctypes.c_int, [i32, u32, vp, vp, vp, vp, u64, vp, u32, u32, u32,
                                             ctypes.POINTER(Tuning)]),
             "dbg_config_apply_tuning": (None, [ctypes.POINTER(Config), ctypes.POINTER(Tuning)]),
+            "dbg_contigs": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+            "dbg_contigs_device": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64),
+                                                  ctypes.POINTER(u64), vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -309,6 +312,31 @@ class Graph:
                                       int(d_keys.numel()), ctypes.byref(n), _stream(stream))
         _check(rc, "dbg_extract_device")
         return int(n.value)
+
+    def contig_sizes(self) -> tuple[int, int]:
+        """(number of contigs, total bases) -- computes the contigs."""
+        n, ln = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(lib().dbg_contigs(self.handle, None, 0, None, 0, ctypes.byref(n), ctypes.byref(ln)),
+               "dbg_contigs")
+        return int(n.value), int(ln.value)
+
+    def contigs(self):
+        """(seq uint8[total], offsets uint64[n + 1]): contig i is seq[offsets[i]:offsets[i+1]]."""
+        n, ln = self.contig_sizes()
+        seq = np.empty(max(ln, 1), dtype=np.uint8)
+        off = np.empty(n + 1, dtype=np.uint64)
+        nn, ll = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(lib().dbg_contigs(self.handle, seq.ctypes.data, seq.shape[0], off.ctypes.data, off.shape[0],
+                                 ctypes.byref(nn), ctypes.byref(ll)), "dbg_contigs")
+        return seq[:ln], off
+
+    def contigs_device(self, d_seq, d_offsets, stream=None) -> tuple[int, int]:
+        """Contigs into device tensors (uint8, int64/uint64); returns (n, total bases)."""
+        n, ln = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        rc = lib().dbg_contigs_device(self.handle, _ptr(d_seq), int(d_seq.numel()), _ptr(d_offsets),
+                                      int(d_offsets.numel()), ctypes.byref(n), ctypes.byref(ln), _stream(stream))
+        _check(rc, "dbg_contigs_device")
+        return int(n.value), int(ln.value)
 
     def phase_times(self) -> list[float]:
         """Per-phase device ms of the last timed build (see dbg_get_phase_times)."""

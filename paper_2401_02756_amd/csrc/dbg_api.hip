@@ -196,6 +196,7 @@ int dbg_reset(dbg_graph *g) {
     g->poisoned = DBG_OK;
     g->unreported = DBG_OK;
     g->vertices = g->inserts = g->windows = g->builds = 0;
+    ++g->epoch;
     g->fresh = true;
     // A binned build rewrites every slot of a fresh table, so its reset only
     // marks the table empty; the direct build needs the zeros.
@@ -240,6 +241,7 @@ void dbg_destroy(dbg_graph *g) {
                       &g->xn,       &g->seg_count, &g->seg_off, &g->seg_partials, &g->seg_len};
     for (DevBuf *b : bufs) b->release();
     g->pass.release();
+    dbg_contigs_free(g->contigs);
     if (g->zero_ev) (void)hipEventDestroy(g->zero_ev);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

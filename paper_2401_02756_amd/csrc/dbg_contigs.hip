@@ -1,0 +1,403 @@
+// Contigs of a built graph (Methods, "Finding contigs", Algorithm 5).
+//
+// The paper keeps a `first` flag per vertex, cleared whenever the vertex is
+// added as a right vertex, so it marks vertices no k-mer ends in (in-degree
+// 0).  Contigs start at every vertex with `first` or with more than one
+// out-edge, one per out-edge, and go on while the vertex reached has exactly
+// one out-edge.  The passage leaves loops of one-edge vertices open (the walk
+// would never end); here a walk also stops on the first vertex it has already
+// passed.  The vertex a walk stops on is part of its contig.
+//
+// On the device: the graph's vertices are extracted and inserted into a walk
+// table (key, out-letter mask); a start pass finds the start vertices (the
+// in-degree test looks up the four possible predecessors) and lists one walk
+// per start edge; a length pass follows every walk (Brent's cycle detection
+// finds the loops, then the first revisit is located exactly); a scan lays
+// the contigs out; a write pass spells them.  Every loop is bounded, so a
+// walk that cannot end reports an error instead of running forever.
+#include "dbg_runtime.h"
+#include "dbg_device.h"
+
+using namespace dbgrt;
+using dbgk::block_exclusive_scan;
+using dbgk::home_slot;
+using dbgk::kOccupied;
+using dbgk::mix64;
+
+namespace {
+
+constexpr uint32_t kWalkBlock = 256;
+
+struct WalkTable {
+    uint64_t *keys;   // key | kOccupied, 0 = empty
+    uint8_t *masks;   // bit c: the vertex has an out-edge for letter code c
+    uint64_t cap;     // power of two
+    uint64_t kmask;   // (k-1)-mer key mask
+    uint32_t km1;
+};
+
+// Slot of `key`, or ~0 when absent (after at most cap probes).
+__device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key) {
+    const uint64_t tagv = key | kOccupied;
+    uint64_t s = home_slot(mix64(key), T.cap);
+    for (uint64_t q = 0; q < T.cap; ++q) {
+        const uint64_t cur = T.keys[s];
+        if (cur == tagv) return s;
+        if (cur == 0) return ~0ull;
+        s = (s + 1) & (T.cap - 1);
+    }
+    return ~0ull;
+}
+
+__global__ __launch_bounds__(kWalkBlock) void k_walk_insert(WalkTable T, const uint64_t *__restrict__ keys,
+                                                            const uint32_t *__restrict__ counts, uint64_t n,
+                                                            uint32_t *err) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = keys[i];
+        const uint4 c = *reinterpret_cast<const uint4 *>(counts + 4 * i);
+        const uint8_t m = (uint8_t)((c.x ? 1u : 0u) | (c.y ? 2u : 0u) | (c.z ? 4u : 0u) | (c.w ? 8u : 0u));
+        uint64_t s = home_slot(mix64(key), T.cap);
+        bool placed = false;
+        for (uint64_t q = 0; q < T.cap && !placed; ++q) {
+            unsigned long long expected = 0;
+            if (__hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(&T.keys[s]), &expected,
+                                                     (unsigned long long)(key | kOccupied), __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                T.masks[s] = m;
+                placed = true;
+            } else {
+                s = (s + 1) & (T.cap - 1);
+            }
+        }
+        if (!placed) atomicOr(err, 1u);
+    }
+}
+
+// Walks (slot << 2 | letter) of the start vertices, appended in any order.
+__global__ __launch_bounds__(kWalkBlock) void k_walk_starts(WalkTable T, uint64_t *__restrict__ items,
+                                                            uint64_t items_cap, unsigned long long *n_items,
+                                                            uint32_t *err) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t lane = threadIdx.x & 63;
+    // the loop runs the same number of times on every lane of a wavefront
+    const uint64_t rounds = (T.cap + stride - 1) / stride;
+    for (uint64_t r = 0; r < rounds; ++r) {
+        const uint64_t s = r * stride + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        uint32_t m = 0;
+        uint64_t key = 0;
+        if (s < T.cap) {
+            const uint64_t tagv = T.keys[s];
+            if (tagv) {
+                key = tagv & ~kOccupied;
+                m = T.masks[s];
+            }
+        }
+        const uint32_t deg = __popc(m);
+        bool start = deg >= 2;
+        if (deg == 1) {
+            bool has_in = false;
+            const uint32_t last = (uint32_t)(key & 3);
+            for (uint64_t x = 0; x < 4 && !has_in; ++x) {
+                const uint64_t pred = (x << (2 * (T.km1 - 1))) | (key >> 2);
+                const uint64_t ps = walk_find(T, pred);
+                if (ps != ~0ull && ((T.masks[ps] >> last) & 1u)) has_in = true;
+            }
+            start = !has_in;
+        }
+        const uint32_t mine = start ? deg : 0u;
+        // one atomic per wavefront: lane offsets by prefix of the counts
+        uint32_t pre = mine;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(pre, d, 64);
+            if (lane >= d) pre += o;
+        }
+        const uint32_t total = __shfl(pre, 63, 64);
+        unsigned long long base = 0;
+        if (lane == 63 && total) base = atomicAdd(n_items, (unsigned long long)total);
+        base = __shfl(base, 63, 64);
+        uint64_t at = base + pre - mine;
+        for (uint32_t c = 0; c < 4 && mine; ++c) {
+            if (!((m >> c) & 1u)) continue;
+            if (at < items_cap) items[at] = (s << 2) | c;
+            else atomicOr(err, 2u);
+            ++at;
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t succ(const WalkTable &T, uint64_t key, uint32_t m) {
+    return ((key << 2) | (uint32_t)__builtin_ctz(m)) & T.kmask;
+}
+
+// Edges of every walk: x0 (the start) -> x1 -> ..., stopping on the first
+// x_m with other than one out-edge or equal to an earlier x_j.  x0 is never
+// passed again (it has no in-edge or several out-edges), so a revisit can
+// only happen on a loop of one-edge vertices, which Brent's method finds;
+// then the loop's length lam and entry mu give m = mu + lam exactly.
+__global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const uint64_t *__restrict__ items,
+                                                            const unsigned long long *n_items,
+                                                            uint64_t *__restrict__ edges, uint64_t limit,
+                                                            uint32_t *err) {
+    const uint64_t n = *n_items;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t it = items[i];
+        const uint64_t key0 = T.keys[it >> 2] & ~kOccupied;
+        const uint64_t x1 = ((key0 << 2) | (it & 3)) & T.kmask;
+        uint64_t hare = x1, tort = x1, power = 1, lam = 1, idx = 1;
+        bool loop = false, bad = false;
+        for (;;) {
+            const uint64_t s = walk_find(T, hare);
+            if (s == ~0ull || idx > limit) { bad = true; break; }
+            const uint32_t m = T.masks[s];
+            if (__popc(m) != 1) break;  // stops on x_idx
+            hare = succ(T, hare, m);
+            ++idx;
+            if (hare == tort) { loop = true; break; }
+            if (power == lam) {
+                tort = hare;
+                power <<= 1;
+                lam = 0;
+            }
+            ++lam;
+        }
+        if (loop) {
+            // x_{mu} is the first vertex of the loop: walk a from x1 and b from
+            // x_{1+lam} together until they meet
+            uint64_t a = x1, b = x1;
+            for (uint64_t q = 0; q < lam && !bad; ++q) {
+                const uint64_t s = walk_find(T, b);
+                if (s == ~0ull) bad = true;
+                else b = succ(T, b, T.masks[s]);
+            }
+            uint64_t mu = 1;
+            while (!bad && a != b) {
+                const uint64_t sa = walk_find(T, a), sb = walk_find(T, b);
+                if (sa == ~0ull || sb == ~0ull || mu > limit) { bad = true; break; }
+                a = succ(T, a, T.masks[sa]);
+                b = succ(T, b, T.masks[sb]);
+                ++mu;
+            }
+            idx = mu + lam;
+        }
+        if (bad) {
+            atomicOr(err, 4u);
+            idx = 1;
+        }
+        edges[i] = idx;
+    }
+}
+
+// Contig lengths in bases (k - 1 + edges), for the scan.
+__global__ void k_walk_bases(const uint64_t *__restrict__ edges, const unsigned long long *n_items, uint32_t km1,
+                             uint64_t *__restrict__ len) {
+    const uint64_t n = *n_items;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) len[i] = km1 + edges[i];
+}
+
+// Exclusive scan of n (device count) uint64 values in place, in one block;
+// out[n] = total.  Contig counts are in the millions, so one block suffices.
+__global__ __launch_bounds__(1024) void k_walk_scan(uint64_t *v, const unsigned long long *n_items) {
+    const uint64_t n = *n_items;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < n; base += blockDim.x) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t x = i < n ? v[i] : 0;
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan(x, &total);
+        if (i < n) v[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) v[n] = carry;
+}
+
+__global__ __launch_bounds__(kWalkBlock) void k_walk_write(WalkTable T, const uint64_t *__restrict__ items,
+                                                           const unsigned long long *n_items,
+                                                           const uint64_t *__restrict__ edges,
+                                                           const uint64_t *__restrict__ off, uint8_t *__restrict__ seq,
+                                                           uint32_t *err) {
+    const uint8_t letters[4] = {'A', 'C', 'T', 'G'};
+    const uint64_t n = *n_items;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t it = items[i];
+        const uint64_t key0 = T.keys[it >> 2] & ~kOccupied;
+        uint8_t *o = seq + off[i];
+        for (uint32_t b = 0; b < T.km1; ++b) *o++ = letters[(key0 >> (2 * (T.km1 - 1 - b))) & 3];
+        *o++ = letters[it & 3];
+        uint64_t cur = ((key0 << 2) | (it & 3)) & T.kmask;
+        const uint64_t m = edges[i];
+        for (uint64_t e = 1; e < m; ++e) {
+            const uint64_t s = walk_find(T, cur);
+            if (s == ~0ull) {
+                atomicOr(err, 8u);
+                break;
+            }
+            const uint32_t c = (uint32_t)__builtin_ctz(T.masks[s]);
+            *o++ = letters[c];
+            cur = ((cur << 2) | c) & T.kmask;
+        }
+    }
+}
+
+__global__ void k_walk_clear(uint64_t *keys, uint64_t cap) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) keys[i] = 0;
+}
+
+uint32_t grid_for(uint64_t n, uint32_t block) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + block - 1) / block, 65536));
+}
+
+}  // namespace
+
+struct dbg_contig_state {
+    DevBuf keys, masks, items, edges, off, seq, xkeys, xcnt, xn, scalars;
+    uint64_t epoch = ~0ull;  // the graph's epoch the contigs were made for
+    uint64_t n = 0, len = 0;
+};
+
+namespace {
+
+// Compute (or reuse) the contigs of g on stream s: counts in cs->n / cs->len,
+// contigs in cs->seq / cs->off on the device.
+int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
+    if (cs->epoch == g->epoch) return DBG_OK;
+    const uint64_t V = g->vertices;
+    cs->n = cs->len = 0;
+    if (V == 0 || g->k == 0) {
+        cs->epoch = g->epoch;
+        return DBG_OK;
+    }
+    hipError_t e;
+    uint64_t cap = 64;
+    while (cap < 2 * V) cap <<= 1;
+    if ((e = cs->xkeys.reserve(V * 8)) != hipSuccess || (e = cs->xcnt.reserve(V * 16)) != hipSuccess ||
+        (e = cs->xn.reserve(8)) != hipSuccess || (e = cs->keys.reserve(cap * 8)) != hipSuccess ||
+        (e = cs->masks.reserve(cap)) != hipSuccess || (e = cs->scalars.reserve(32)) != hipSuccess)
+        return hip_code(e);
+    uint64_t *xn = cs->xn.as<uint64_t>();
+    e = dbgk::launch_fill_zero(xn, 1, s);
+    if (e == hipSuccess && g->binned)
+        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, g->parts, g->seg_count.as<uint32_t>(),
+                                        g->seg_off.as<uint64_t>(), g->seg_partials.as<uint64_t>(),
+                                        g->seg_len.as<uint64_t>(), cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(),
+                                        V, xn, g->device, s);
+    else if (e == hipSuccess)
+        e = dbgk::launch_extract(g->table.as<uint64_t>(), g->ew, g->cap, cs->xkeys.as<uint64_t>(),
+                                 cs->xcnt.as<uint32_t>(), V, xn, s);
+    // scalars: [0] walk count, [1] error bits
+    unsigned long long *n_items = cs->scalars.as<unsigned long long>();
+    uint32_t *err = reinterpret_cast<uint32_t *>(cs->scalars.as<uint64_t>() + 1);
+    if (e == hipSuccess) e = dbgk::launch_fill_zero(cs->scalars.as<uint64_t>(), 2, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_walk_clear, dim3(grid_for(cap, 256)), dim3(256), 0, s, cs->keys.as<uint64_t>(), cap);
+        e = hipGetLastError();
+    }
+    WalkTable T{cs->keys.as<uint64_t>(), cs->masks.as<uint8_t>(), cap, (1ull << (2 * (g->k - 1))) - 1, g->k - 1};
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_walk_insert, dim3(grid_for(V, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                           cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
+        e = hipGetLastError();
+    }
+    // walks are at most the edges, at most 4 per vertex
+    const uint64_t items_cap = 4 * V;
+    if (e == hipSuccess && (e = cs->items.reserve(items_cap * 8)) == hipSuccess) {
+        hipLaunchKernelGGL(k_walk_starts, dim3(grid_for(cap, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                           cs->items.as<uint64_t>(), items_cap, n_items, err);
+        e = hipGetLastError();
+    }
+    uint64_t hs[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, cs->scalars.p, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_code(e);
+    if ((uint32_t)hs[1]) return DBG_E_DEVICE;
+    const uint64_t n = hs[0];
+    if ((e = cs->edges.reserve(std::max<uint64_t>(n, 1) * 8)) != hipSuccess ||
+        (e = cs->off.reserve((n + 1) * 8)) != hipSuccess)
+        return hip_code(e);
+    // a walk passes each vertex at most once before its loop closes, and
+    // finding the loop takes at most twice its length more
+    const uint64_t limit = 4 * V + 16;
+    hipLaunchKernelGGL(k_walk_length, dim3(grid_for(n, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                       cs->items.as<uint64_t>(), n_items, cs->edges.as<uint64_t>(), limit, err);
+    hipLaunchKernelGGL(k_walk_bases, dim3(grid_for(n, 256)), dim3(256), 0, s, cs->edges.as<uint64_t>(), n_items,
+                       g->k - 1, cs->off.as<uint64_t>());
+    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, cs->off.as<uint64_t>(), n_items);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_code(e);
+    uint64_t total = 0;
+    if ((e = hipMemcpyAsync(&total, cs->off.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_code(e);
+    if ((e = cs->seq.reserve(std::max<uint64_t>(total, 1))) != hipSuccess) return hip_code(e);
+    hipLaunchKernelGGL(k_walk_write, dim3(grid_for(n, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                       cs->items.as<uint64_t>(), n_items, cs->edges.as<uint64_t>(), cs->off.as<uint64_t>(),
+                       cs->seq.as<uint8_t>(), err);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_code(e);
+    uint32_t herr = 0;
+    if ((e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_code(e);
+    if (herr) return DBG_E_DEVICE;
+    cs->n = n;
+    cs->len = total;
+    cs->epoch = g->epoch;
+    return DBG_OK;
+}
+
+int contigs_common(dbg_graph *g, void *seq, uint64_t seq_cap, uint64_t *offsets, uint64_t offsets_cap,
+                   uint64_t *n_contigs, uint64_t *seq_len, bool device_out, hipStream_t s) {
+    if (!g || !n_contigs || !seq_len) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    if (g->poisoned) return DBG_E_STATE;
+    if (!g->contigs) g->contigs = new dbg_contig_state();
+    dbg_contig_state *cs = g->contigs;
+    const int rc = compute_contigs(g, cs, s);
+    if (rc != DBG_OK) {
+        cs->epoch = ~0ull;
+        return rc;
+    }
+    *n_contigs = cs->n;
+    *seq_len = cs->len;
+    if (!seq && !offsets) return DBG_OK;
+    if (!seq || !offsets) return DBG_E_INVAL;
+    if (seq_cap < cs->len || offsets_cap < cs->n + 1) return DBG_E_SPACE;
+    const hipMemcpyKind kind = device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipError_t e = hipSuccess;
+    if (cs->len) e = hipMemcpyAsync(seq, cs->seq.p, cs->len, kind, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(offsets, cs->off.p, (cs->n + 1) * 8, kind, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? DBG_OK : DBG_E_DEVICE;
+}
+
+}  // namespace
+
+void dbg_contigs_free(dbg_contig_state *cs) {
+    if (!cs) return;
+    DevBuf *b[] = {&cs->keys, &cs->masks, &cs->items, &cs->edges, &cs->off, &cs->seq, &cs->xkeys, &cs->xcnt,
+                   &cs->xn, &cs->scalars};
+    for (DevBuf *x : b) x->release();
+    delete cs;
+}
+
+extern "C" {
+
+int dbg_contigs(dbg_graph *g, char *seq, uint64_t seq_cap, uint64_t *offsets, uint64_t offsets_cap,
+                uint64_t *n_contigs, uint64_t *seq_len) {
+    return contigs_common(g, seq, seq_cap, offsets, offsets_cap, n_contigs, seq_len, false, g ? g->stream : nullptr);
+}
+
+int dbg_contigs_device(dbg_graph *g, uint8_t *d_seq, uint64_t seq_cap, uint64_t *d_offsets, uint64_t offsets_cap,
+                       uint64_t *n_contigs, uint64_t *seq_len, void *stream) {
+    return contigs_common(g, d_seq, seq_cap, d_offsets, offsets_cap, n_contigs, seq_len, true,
+                          g ? g->pick(stream) : nullptr);
+}
+
+}  // extern "C"

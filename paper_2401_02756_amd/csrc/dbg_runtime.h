@@ -468,6 +468,11 @@ struct Pass {
 
 }  // namespace dbgrt
 
+// Contigs of a graph (dbg_contigs.hip): device buffers kept until the next
+// build or reset.
+struct dbg_contig_state;
+void dbg_contigs_free(dbg_contig_state *cs);
+
 struct dbg_graph {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -500,7 +505,9 @@ struct dbg_graph {
     dbgrt::DevBuf xkeys, xcnt, xn;  // extraction staging
 
     uint64_t vertices = 0, inserts = 0, windows = 0, builds = 0;
+    uint64_t epoch = 0;  // advanced by every build and reset
     double last_build_ms = 0, last_total_ms = 0;
+    dbg_contig_state *contigs = nullptr;
 
     hipStream_t pick(void *s) const { return s ? static_cast<hipStream_t>(s) : stream; }
     uint64_t table_words() const { return cap * ew; }
@@ -609,6 +616,7 @@ inline int fold_status(dbg_graph *g, const InstStatus &st, uint32_t k) {
     if (validation_error(st.err)) return err_code_of(st.err);  // nothing was modified
     g->k = k;
     g->fresh = false;
+    ++g->epoch;
     g->vertices += st.claimed;
     g->inserts += st.inserts;
     g->windows += st.windows;
