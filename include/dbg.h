@@ -209,6 +209,22 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
                            const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
                            const uint64_t *d_offsets, int32_t *statuses, void *stream);
 
+/* ---- normalization ----------------------------------------------------
+ * Normalized counters (Methods, "Normalization of graph"): the paper divides
+ * every counter by the number of times a k-mer of the genome is expected to
+ * be read, reads * (read length - k + 1) / genome size.  Here the numerator
+ * is the graph's total k-mer count (the same number for reads of one length,
+ * and defined for any mix of lengths), so each counter c becomes
+ * c * genome_size / total_kmers rounded half up, computed exactly in integer
+ * arithmetic and saturated at 2^32 - 1.  genome_size = 0 leaves the counters
+ * as they are.  With DBG_NORM_U8 the counters are written as uint8 saturated
+ * at 255, the paper's 8-bit counter (counts then points to 4 * cap bytes).
+ * Otherwise as dbg_extract: keys and counts in the same unspecified order. */
+#define DBG_NORM_U8 0x1u
+
+int dbg_extract_normalized(dbg_graph *g, uint64_t genome_size, uint32_t flags, uint64_t *keys, void *counts,
+                           uint64_t cap, uint64_t *n_vertices);
+
 /* ---- contigs ----------------------------------------------------------
  * Contigs of the graph (Methods, "Finding contigs", Algorithm 5): a vertex is
  * marked `first` when no k-mer ends in it (the paper clears the flag whenever

@@ -77,6 +77,9 @@ def lib() -> ctypes.CDLL:
         L.oracle_contigs.restype = ctypes.c_int
         L.oracle_strings_digest.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
         L.oracle_strings_digest.restype = ctypes.c_uint64
+        L.oracle_normalize.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_normalize.restype = None
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_free.restype = None
         _lib = L
@@ -207,6 +210,18 @@ def strings_digest(seq, off) -> int:
     off = np.ascontiguousarray(off, dtype=np.uint64)
     return int(lib().oracle_strings_digest(seq.ctypes.data if seq.size else None, off.ctypes.data,
                                            off.shape[0] - 1))
+
+
+def normalize(counts, genome_size: int, total_kmers: int):
+    """Normalized counters (``oracle_normalize``): (uint32 array, uint8 array
+    saturated at 255) of the same shape as ``counts``."""
+    c = np.ascontiguousarray(counts, dtype=np.uint32)
+    o32 = np.empty_like(c)
+    o8 = np.empty(c.shape, dtype=np.uint8)
+    if c.size:
+        lib().oracle_normalize(c.ctypes.data, c.size, int(genome_size), int(total_kmers), o32.ctypes.data,
+                               o8.ctypes.data)
+    return o32, o8
 
 
 def vertex_counts(reads, offsets, k: int, key: int):

@@ -438,3 +438,28 @@ uint64_t oracle_strings_digest(const unsigned char *seq, const uint64_t *off, ui
     }
     return sum;
 }
+
+/* ---------------------------------------------------------------- normalization
+ *
+ * Normalized counters (Methods, "Normalization of graph"): every counter is
+ * divided by the number of times a k-mer of the genome is expected to be
+ * read, reads * (read length - k + 1) / genome size.  With reads of any
+ * length the numerator is the total number of k-mers read, `total`, so
+ *   normalized(c) = c * genome / total, rounded half up,
+ * computed exactly in 128-bit integers; saturated at 2^32 - 1.  With
+ * genome = 0 the counters are left as they are.  out8 (if not NULL) receives
+ * the same values saturated at 255, the paper's 8-bit counter.
+ */
+void oracle_normalize(const uint32_t *counts, uint64_t n, uint64_t genome, uint64_t total,
+                      uint32_t *out32, unsigned char *out8) {
+    for (uint64_t i = 0; i < n; ++i) {
+        unsigned __int128 v = counts[i];
+        if (genome && total) {
+            const unsigned __int128 num = 2 * (unsigned __int128)counts[i] * genome + total;
+            v = num / (2 * (unsigned __int128)total);
+        }
+        const uint32_t v32 = v > 0xffffffffu ? 0xffffffffu : (uint32_t)v;
+        if (out32) out32[i] = v32;
+        if (out8) out8[i] = v32 > 255 ? 255 : (unsigned char)v32;
+    }
+}

@@ -35,8 +35,9 @@ EXPORTS = (
     "dbg_get_phase_times", "dbg_server_create", "dbg_server_submit", "dbg_server_submit_device",
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
     "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
-    "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device",
+    "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device", "dbg_extract_normalized",
 )
+NORM_U8 = 0x1
 TUNE_FORCE = 0x1
 
 
@@ -176,6 +177,7 @@ def lib() -> ctypes.CDLL:
             "dbg_autotune": (ctypes.c_int, [i32, u32, vp, vp, vp, vp, u64, vp, u32, u32, u32,
                                             ctypes.POINTER(Tuning)]),
             "dbg_config_apply_tuning": (None, [ctypes.POINTER(Config), ctypes.POINTER(Tuning)]),
+            "dbg_extract_normalized": (ctypes.c_int, [vp, u64, u32, vp, vp, u64, ctypes.POINTER(u64)]),
             "dbg_contigs": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
             "dbg_contigs_device": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64),
                                                   ctypes.POINTER(u64), vp]),
@@ -312,6 +314,20 @@ class Graph:
                                       int(d_keys.numel()), ctypes.byref(n), _stream(stream))
         _check(rc, "dbg_extract_device")
         return int(n.value)
+
+    def extract_normalized(self, genome_size: int, u8: bool = False):
+        """(keys uint64[V], counts[V, 4]) with every counter normalized by the
+        expected k-mer duplication (dbg_extract_normalized); uint32 counts,
+        or uint8 saturated at 255 with u8=True."""
+        V = self.vertex_count()
+        keys = np.empty(V, dtype=np.uint64)
+        counts = np.empty((V, 4), dtype=np.uint8 if u8 else np.uint32)
+        n = ctypes.c_uint64(0)
+        if V:
+            rc = lib().dbg_extract_normalized(self.handle, int(genome_size), NORM_U8 if u8 else 0,
+                                              keys.ctypes.data, counts.ctypes.data, V, ctypes.byref(n))
+            _check(rc, "dbg_extract_normalized")
+        return keys, counts
 
     def contig_sizes(self) -> tuple[int, int]:
         """(number of contigs, total bases) -- computes the contigs."""

@@ -188,6 +188,39 @@ int dbg_extract_device(dbg_graph *g, uint64_t *d_keys, uint32_t *d_counts, uint6
     return extract_impl(g, d_keys, d_counts, cap, n_vertices, true, g ? g->pick(stream) : nullptr);
 }
 
+int dbg_extract_normalized(dbg_graph *g, uint64_t genome_size, uint32_t flags, uint64_t *keys, void *counts,
+                           uint64_t cap, uint64_t *n_vertices) {
+    if (!g || !n_vertices || (flags & ~DBG_NORM_U8)) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    const uint64_t V = g->vertices;
+    *n_vertices = V;
+    if (!keys) return DBG_OK;
+    if (cap < V) return DBG_E_SPACE;
+    if (!counts) return DBG_E_INVAL;
+    if (V == 0) return DBG_OK;
+    hipError_t e;
+    if ((e = g->nkeys.reserve(V * 8)) != hipSuccess || (e = g->ncnt.reserve(V * 16)) != hipSuccess ||
+        (e = g->n8.reserve(V * 4)) != hipSuccess)
+        return hip_code(e);
+    uint64_t n = 0;
+    int rc = extract_impl(g, g->nkeys.as<uint64_t>(), g->ncnt.as<uint32_t>(), V, &n, true, g->stream);
+    if (rc != DBG_OK) return rc;
+    hipStream_t s = g->stream;
+    const bool u8 = (flags & DBG_NORM_U8) != 0;
+    e = dbgk::launch_normalize(g->ncnt.as<uint32_t>(), 4 * V, genome_size, g->inserts,
+                               u8 ? g->n8.as<uint8_t>() : nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(keys, g->nkeys.p, V * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts, u8 ? g->n8.p : g->ncnt.p, u8 ? V * 4 : V * 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? DBG_OK : DBG_E_DEVICE;
+}
+
 int dbg_reset(dbg_graph *g) {
     if (!g) return DBG_E_INVAL;
     DeviceGuard guard(g->device);
@@ -237,8 +270,9 @@ void dbg_destroy(dbg_graph *g) {
     DeviceGuard guard(g->device);
     if (g->pass.pending) (void)g->pass.wait(nullptr, nullptr);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
-    DevBuf *bufs[] = {&g->table,    &g->reads,  &g->offsets,      &g->xkeys,  &g->xcnt,
-                      &g->xn,       &g->seg_count, &g->seg_off, &g->seg_partials, &g->seg_len};
+    DevBuf *bufs[] = {&g->table, &g->reads,     &g->offsets, &g->xkeys,        &g->xcnt,    &g->xn,
+                      &g->nkeys, &g->ncnt,      &g->n8,      &g->seg_count,    &g->seg_off, &g->seg_partials,
+                      &g->seg_len};
     for (DevBuf *b : bufs) b->release();
     g->pass.release();
     dbg_contigs_free(g->contigs);

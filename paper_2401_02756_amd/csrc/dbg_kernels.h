@@ -202,6 +202,12 @@ hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64
 hipError_t launch_extract(const uint64_t *table, uint32_t entry_words, uint64_t cap,
                           uint64_t *out_keys, uint32_t *out_counts, uint64_t out_cap,
                           uint64_t *out_n, hipStream_t s);
+// Normalized counters (Methods, "Normalization of graph"): counts[i] becomes
+// round-half-up(counts[i] * genome / total), saturated at 2^32 - 1, in place,
+// or into out8 saturated at 255 when out8 is not NULL (genome = 0: no
+// division, saturation only).
+hipError_t launch_normalize(uint32_t *counts, uint64_t n, uint64_t genome, uint64_t total, uint8_t *out8,
+                            hipStream_t s);
 hipError_t launch_count(const uint64_t *table, uint32_t entry_words, uint64_t cap,
                         uint64_t *out_n, hipStream_t s);
 hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32_t kind,

@@ -726,6 +726,54 @@ hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64
     return hipGetLastError();
 }
 
+namespace {
+
+// round-half-up(c * genome / total) = floor((2 c genome + total) / (2 total)),
+// exactly: the 128-bit numerator is divided 16 bits at a time (the divisor
+// 2 total is below 2^34, so a partial remainder shifted by 16 stays below
+// 2^50); saturated at 2^32 - 1.
+__device__ __forceinline__ uint32_t normalized(uint32_t c, uint64_t genome, uint64_t total) {
+    if (!genome || !total) return c;
+    uint64_t lo = (uint64_t)c * genome;
+    uint64_t hi = __umul64hi((uint64_t)c, genome);
+    hi = (hi << 1) | (lo >> 63);
+    lo <<= 1;
+    const uint64_t lo2 = lo + total;
+    hi += lo2 < lo ? 1u : 0u;
+    lo = lo2;
+    const uint64_t d = 2 * total;
+    uint64_t q = 0, r = 0;
+    for (int i = 7; i >= 0; --i) {
+        const uint64_t limb = (i >= 4 ? hi >> (16 * (i - 4)) : lo >> (16 * i)) & 0xffffu;
+        const uint64_t cur = (r << 16) | limb;
+        const uint64_t qd = cur / d;
+        r = cur - qd * d;
+        if (q >> 48) return 0xffffffffu;
+        q = (q << 16) | qd;
+    }
+    return q > 0xffffffffull ? 0xffffffffu : (uint32_t)q;
+}
+
+__global__ __launch_bounds__(256) void k_normalize(uint32_t *counts, uint64_t n, uint64_t genome, uint64_t total,
+                                                   uint8_t *out8) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t v = normalized(counts[i], genome, total);
+        if (out8) out8[i] = (uint8_t)(v > 255u ? 255u : v);
+        else counts[i] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_normalize(uint32_t *counts, uint64_t n, uint64_t genome, uint64_t total, uint8_t *out8,
+                            hipStream_t s) {
+    if (!n) return hipSuccess;
+    const uint32_t g = (uint32_t)std::min<uint64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_normalize, dim3(g), dim3(256), 0, s, counts, n, genome, total, out8);
+    return hipGetLastError();
+}
+
 hipError_t launch_extract(const uint64_t *table, uint32_t ew, uint64_t cap, uint64_t *okeys,
                           uint32_t *ocnt, uint64_t ocap, uint64_t *out_n, hipStream_t s) {
     const uint64_t chunk = (uint64_t)kExtractBlock * kExtractPerThread;

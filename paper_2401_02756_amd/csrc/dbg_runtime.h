@@ -503,6 +503,7 @@ struct dbg_graph {
     uint32_t pending_k = 0;
     dbgrt::DevBuf reads, offsets;   // staging of host input
     dbgrt::DevBuf xkeys, xcnt, xn;  // extraction staging
+    dbgrt::DevBuf nkeys, ncnt, n8;  // normalized extraction staging
 
     uint64_t vertices = 0, inserts = 0, windows = 0, builds = 0;
     uint64_t epoch = 0;  // advanced by every build and reset

@@ -129,6 +129,7 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_server_get_stats(None, None) == dbg.E_INVAL
     L.dbg_server_destroy(None)
     n64 = ctypes.c_uint64()
+    assert L.dbg_extract_normalized(None, 1, 0, None, None, 0, ctypes.byref(n64)) == dbg.E_INVAL
     assert L.dbg_contigs(None, None, 0, None, 0, ctypes.byref(n64), ctypes.byref(n64)) == dbg.E_INVAL
     assert L.dbg_contigs_device(None, None, 0, None, 0, ctypes.byref(n64), ctypes.byref(n64), None) == dbg.E_INVAL
     t = dbg.Tuning()
