@@ -338,6 +338,28 @@ def cpu_baseline(rs, sample_reads: int) -> dict:
     return out
 
 
+def cpu_lfdbg_scaling(rs, sample_reads: int) -> dict:
+    """The paper's own design (chained buckets, CAS on list heads, per-thread
+    node pools, two find-or-adds per k-mer) on the host's CPU threads, on the
+    same sample as the oracle baseline: the thread-scaling context the paper's
+    missing figures held."""
+    import oracle
+
+    n = min(sample_reads, rs.n_reads)
+    reads = rs.reads[:int(rs.offsets[n])]
+    offs = rs.offsets[:n + 1]
+    ins = int(np.maximum(np.diff(offs.astype(np.int64)) - rs.k + 1, 0).sum())
+    out = {"kind": "paper design on CPU threads (oracle/lfdbg_cpu.cpp)", "unit": "G k-mer inserts/s",
+           "sample": "first %d reads (%d k-mer inserts), table of one bucket per window" % (n, ins),
+           "host_cpu": host_cpu(), "rates": {}}
+    t = 1
+    while t <= min(16, os.cpu_count() or 1):
+        _, _, sec = oracle.lfdbg_build(reads, offs, rs.k, t)
+        out["rates"][str(t)] = round(ins / sec / 1e9, 5)
+        t *= 2
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -595,6 +617,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_reads)
         log("cpu baseline %s" % json.dumps(line["cpu_baseline"]))
+        line["cpu_lfdbg"] = cpu_lfdbg_scaling(rs, args.cpu_sample_reads)
+        log("cpu lfdbg %s" % json.dumps(line["cpu_lfdbg"]))
 
     print(json.dumps(line), flush=True)
     return 0

@@ -30,6 +30,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dbg_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+_LFDBG_SRC = os.path.join(_HERE, "lfdbg_cpu.cpp")
+_LFDBG_PATH = os.path.join(_HERE, "_liblfdbg.so")
 
 OK, E_INVAL, E_K, E_BASE, E_NOMEM = 0, -1, -2, -3, -4
 
@@ -40,12 +42,18 @@ _lib = None
 
 
 def compile_oracle(force: bool = False) -> str:
-    """Compile the C core with gcc into ``oracle/_liboracle.so``."""
+    """Compile the C core with gcc into ``oracle/_liboracle.so`` (and the
+    CPU baseline of the paper's threaded build into ``oracle/_liblfdbg.so``)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared",
                                "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_LFDBG_PATH):
+        tmp = _LFDBG_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-pthread", "-shared",
+                               "-fPIC", "-o", tmp, _LFDBG_SRC])
+        os.replace(tmp, _LFDBG_PATH)
     return _LIB_PATH
 
 
@@ -222,6 +230,49 @@ def normalize(counts, genome_size: int, total_kmers: int):
         lib().oracle_normalize(c.ctypes.data, c.size, int(genome_size), int(total_kmers), o32.ctypes.data,
                                o8.ctypes.data)
     return o32, o8
+
+
+_lfdbg = None
+
+
+def lfdbg_build(reads, offsets, k: int, threads: int, buckets: int = 0):
+    """The paper's lock-free build on CPU threads (``oracle/lfdbg_cpu.cpp``):
+    ``(keys ascending, counts[V, 4], seconds of the threaded build)``.
+    ``buckets`` is the paper's table size (default: the number of windows)."""
+    global _lfdbg
+    if _lfdbg is None:
+        if not os.path.exists(_LFDBG_PATH):
+            compile_oracle()
+        L = ctypes.CDLL(_LFDBG_PATH)
+        L.lfdbg_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_double)]
+        L.lfdbg_build.restype = ctypes.c_int
+        L.lfdbg_free.argtypes = [ctypes.c_void_p]
+        L.lfdbg_free.restype = None
+        _lfdbg = L
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    if not buckets:
+        buckets = max(1, int(np.maximum(np.diff(offsets.astype(np.int64)) - k + 2, 0).sum()))
+    pk, pc = ctypes.c_void_p(), ctypes.c_void_p()
+    nv, sec = ctypes.c_uint64(0), ctypes.c_double(0)
+    rc = _lfdbg.lfdbg_build(reads.ctypes.data if reads.size else None, offsets.ctypes.data if offsets.size else None,
+                            n, int(k), int(threads), int(buckets), ctypes.byref(pk), ctypes.byref(pc),
+                            ctypes.byref(nv), ctypes.byref(sec))
+    if rc != 0:
+        raise OracleError(rc)
+    V = int(nv.value)
+    try:
+        keys = (np.ctypeslib.as_array(ctypes.cast(pk, ctypes.POINTER(ctypes.c_uint64)), shape=(V,)).copy()
+                if V else np.zeros(0, np.uint64))
+        counts = (np.ctypeslib.as_array(ctypes.cast(pc, ctypes.POINTER(ctypes.c_uint32)), shape=(V * 4,))
+                  .copy().reshape(V, 4) if V else np.zeros((0, 4), np.uint32))
+    finally:
+        _lfdbg.lfdbg_free(pk)
+        _lfdbg.lfdbg_free(pc)
+    return keys, counts, float(sec.value)
 
 
 def vertex_counts(reads, offsets, k: int, key: int):
