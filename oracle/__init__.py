@@ -88,6 +88,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_normalize.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_normalize.restype = None
+        L.oracle_build_wide.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_build_wide.restype = ctypes.c_int
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_free.restype = None
         _lib = L
@@ -273,6 +277,37 @@ def lfdbg_build(reads, offsets, k: int, threads: int, buckets: int = 0):
         _lfdbg.lfdbg_free(pk)
         _lfdbg.lfdbg_free(pc)
     return keys, counts, float(sec.value)
+
+
+def build_graph_wide(reads, offsets, k: int):
+    """Graph for 2 <= k <= 64: ``(hi uint64[V], lo uint64[V], counts[V, 4])``
+    sorted by (hi, lo); the (k-1)-mer key is hi * 2^64 + lo."""
+    reads, offsets = _as_inputs(reads, offsets)
+    n = max(0, offsets.shape[0] - 1)
+    ph, pl, pc = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    nv = ctypes.c_uint64(0)
+    rc = lib().oracle_build_wide(reads.ctypes.data if reads.size else None,
+                                 offsets.ctypes.data if offsets.size else None, n, int(k),
+                                 ctypes.byref(ph), ctypes.byref(pl), ctypes.byref(pc), ctypes.byref(nv))
+    if rc != OK:
+        raise OracleError(rc)
+    V = int(nv.value)
+    u64p, u32p = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32)
+    try:
+        hi = np.ctypeslib.as_array(ctypes.cast(ph, u64p), shape=(V,)).copy() if V else np.zeros(0, np.uint64)
+        lo = np.ctypeslib.as_array(ctypes.cast(pl, u64p), shape=(V,)).copy() if V else np.zeros(0, np.uint64)
+        counts = (np.ctypeslib.as_array(ctypes.cast(pc, u32p), shape=(V * 4,)).copy().reshape(V, 4)
+                  if V else np.zeros((0, 4), np.uint32))
+    finally:
+        for p in (ph, pl, pc):
+            lib().oracle_free(p)
+    return hi, lo, counts
+
+
+def decode_wide_key(hi: int, lo: int, k: int) -> str:
+    """The (k-1)-mer string of a two-word key."""
+    v = (int(hi) << 64) | int(lo)
+    return "".join("ACTG"[(v >> (2 * (k - 2 - i))) & 3] for i in range(k - 1))
 
 
 def vertex_counts(reads, offsets, k: int, key: int):

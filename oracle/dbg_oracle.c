@@ -28,7 +28,9 @@
  *
  * Vertex key: the (k-1)-mer written as 2-bit codes, first base most
  * significant, right-aligned in a uint64 (k <= 32).  Each key is packed from
- * the bases directly, window by window, with no rolling update.
+ * the bases directly, window by window, with no rolling update.  For longer k
+ * (up to 64, the paper's runs use k = 51) oracle_build_wide keeps the same
+ * packing in a 128-bit integer and reports it as a high and a low word.
  *
  * The store is a separately chained hash map, as in the paper's structure, but
  * single threaded (no atomics are needed: the result is a multiset count and
@@ -462,4 +464,108 @@ void oracle_normalize(const uint32_t *counts, uint64_t n, uint64_t genome, uint6
         if (out32) out32[i] = v32;
         if (out8) out8[i] = v32 > 255 ? 255 : (unsigned char)v32;
     }
+}
+
+/* ---------------------------------------------------------------- long k
+ *
+ * The same graph for 2 <= k <= 64: a (k-1)-mer of up to 63 bases is packed
+ * from scratch into a 128-bit integer (first base most significant), split
+ * into a high and a low 64-bit word.  A separately chained map of its own;
+ * output sorted by (high, low).
+ */
+typedef unsigned __int128 u128;
+
+typedef struct {
+    u128 key;
+    uint32_t cnt[4];
+    int64_t next;
+} wrec;
+
+static uint64_t wide_bucket(u128 key, int bits) {
+    const uint64_t x = (uint64_t)(key >> 64) * 0xC2B2AE3D27D4EB4Full ^ (uint64_t)key;
+    return (x * 0x9E3779B97F4A7C15ull) >> (64 - bits);
+}
+
+static int cmp_wrec(const void *a, const void *b) {
+    const u128 x = ((const wrec *)a)->key, y = ((const wrec *)b)->key;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int oracle_build_wide(const unsigned char *reads, const uint64_t *offsets, uint64_t n_reads, uint32_t k,
+                      uint64_t **out_hi, uint64_t **out_lo, uint32_t **out_counts, uint64_t *out_n) {
+    if (!out_hi || !out_lo || !out_counts || !out_n) return ORACLE_E_INVAL;
+    *out_hi = *out_lo = NULL;
+    *out_counts = NULL;
+    *out_n = 0;
+    if (k < 2 || k > 64) return ORACLE_E_K;
+    if (n_reads && !offsets) return ORACLE_E_INVAL;
+    for (uint64_t i = 0; i < n_reads; ++i)
+        if (offsets[i + 1] < offsets[i]) return ORACLE_E_INVAL;
+    if (n_reads && offsets[n_reads] > offsets[0] && !reads) return ORACLE_E_INVAL;
+    for (uint64_t p = n_reads ? offsets[0] : 0; n_reads && p < offsets[n_reads]; ++p)
+        if (letter_index(reads[p]) < 0) return ORACLE_E_BASE;
+
+    int bits = 16;
+    uint64_t cap = 1024, n = 0;
+    int64_t *head = (int64_t *)malloc((1ull << bits) * sizeof(int64_t));
+    wrec *rec = (wrec *)malloc(cap * sizeof(wrec));
+    if (!head || !rec) { free(head); free(rec); return ORACLE_E_NOMEM; }
+    for (uint64_t b = 0; b < (1ull << bits); ++b) head[b] = -1;
+    for (uint64_t r = 0; r < n_reads; ++r) {
+        const unsigned char *s = reads + offsets[r];
+        const uint64_t L = offsets[r + 1] - offsets[r];
+        if (L < k) continue;
+        for (uint64_t j = 0; j + k - 1 <= L; ++j) {
+            u128 key = 0;
+            for (uint32_t i = 0; i < k - 1; ++i) key = (key << 2) | (u128)letter_index(s[j + i]);
+            int64_t at = -1;
+            for (int64_t i = head[wide_bucket(key, bits)]; i >= 0; i = rec[i].next)
+                if (rec[i].key == key) { at = i; break; }
+            if (at < 0) {
+                if (n == cap) {
+                    wrec *x = (wrec *)realloc(rec, 2 * cap * sizeof(wrec));
+                    if (!x) { free(head); free(rec); return ORACLE_E_NOMEM; }
+                    rec = x;
+                    cap *= 2;
+                }
+                if (n >= (1ull << bits)) { /* keep chains short: double the buckets */
+                    ++bits;
+                    int64_t *h = (int64_t *)malloc((1ull << bits) * sizeof(int64_t));
+                    if (!h) { free(head); free(rec); return ORACLE_E_NOMEM; }
+                    for (uint64_t b = 0; b < (1ull << bits); ++b) h[b] = -1;
+                    for (uint64_t i = 0; i < n; ++i) {
+                        const uint64_t b = wide_bucket(rec[i].key, bits);
+                        rec[i].next = h[b];
+                        h[b] = (int64_t)i;
+                    }
+                    free(head);
+                    head = h;
+                }
+                const uint64_t b = wide_bucket(key, bits);
+                rec[n].key = key;
+                rec[n].cnt[0] = rec[n].cnt[1] = rec[n].cnt[2] = rec[n].cnt[3] = 0;
+                rec[n].next = head[b];
+                head[b] = (int64_t)n;
+                at = (int64_t)n++;
+            }
+            if (j + k <= L) rec[at].cnt[letter_index(s[j + k - 1])] += 1;
+        }
+    }
+    free(head);
+    qsort(rec, n, sizeof(wrec), cmp_wrec);
+    uint64_t *hi = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t *lo = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint32_t *cnts = (uint32_t *)malloc((n ? n : 1) * 4 * sizeof(uint32_t));
+    if (!hi || !lo || !cnts) { free(hi); free(lo); free(cnts); free(rec); return ORACLE_E_NOMEM; }
+    for (uint64_t i = 0; i < n; ++i) {
+        hi[i] = (uint64_t)(rec[i].key >> 64);
+        lo[i] = (uint64_t)rec[i].key;
+        memcpy(&cnts[4 * i], rec[i].cnt, 4 * sizeof(uint32_t));
+    }
+    free(rec);
+    *out_hi = hi;
+    *out_lo = lo;
+    *out_counts = cnts;
+    *out_n = n;
+    return ORACLE_OK;
 }
