@@ -20,7 +20,11 @@
  *   - Letter code (Methods, "Graph data structure"): (c >> 1) & 3, so A=0,
  *     C=1, T=2, G=3.
  *   - Vertex key: the (k-1)-mer as 2-bit letter codes, first base most
- *     significant, right-aligned in a uint64.  2 <= k <= 32.
+ *     significant, right-aligned in a uint64, for 2 <= k <= 32.  Longer k
+ *     (33 <= k <= 64; the paper's runs use k = 51) is taken by dbg_build and
+ *     dbg_build_device: the key K then has up to 126 bits and is given as two
+ *     uint64 words, K >> 64 then K mod 2^64, so every key array holds two
+ *     words per vertex.  Batches, the server and contigs take k <= 32.
  *   - Counts: four uint32 per vertex in letter-code order (A, C, T, G).
  *     Sink vertices (no out-edge) are vertices with four zero counters.
  *   - Return values: DBG_OK (0) or a negative DBG_E_* code.
@@ -46,7 +50,8 @@ extern "C" {
 /* ---- error codes ---------------------------------------------------- */
 #define DBG_OK 0
 #define DBG_E_INVAL (-1)  /* NULL pointer, bad offsets, bad configuration */
-#define DBG_E_K (-2)      /* k outside [2, 32], or differs from the handle's k */
+#define DBG_E_K (-2)      /* k outside [2, 64] ([2, 32] for batches, the server and
+                             contigs), or differs from the handle's k */
 #define DBG_E_BASE (-3)   /* a read byte outside ACGTacgt */
 #define DBG_E_NOMEM (-4)  /* device allocation refused */
 #define DBG_E_FULL (-5)   /* table capacity exhausted; the handle is poisoned */
@@ -61,7 +66,7 @@ extern "C" {
 #define DBG_F_ENTRY32 0x4u /* 32-byte table entries (default 24 bytes) */
 #define DBG_F_BINNED 0x8u  /* binned build: records partitioned by table segment,
                               claimed and counted in LDS (k <= 31; a graph whose
-                              first build has k = 32 falls back to the direct
+                              first build has k >= 32 falls back to the direct
                               build) */
 #define DBG_F_GRAPH 0x10u  /* capture each build pass as HIP graphs on first use of
                               its size class and replay them afterwards */
@@ -121,7 +126,9 @@ int dbg_create(const dbg_config *cfg, dbg_graph **out);
 /* Add the k-mers of host-resident reads (makeGraph over all reads).  The
  * input is copied; the caller may free it on return.  Synchronous: returns
  * after the device work and the status readback.  Builds on one handle
- * accumulate (counts add), and all must use the same k.
+ * accumulate (counts add), and all must use the same k.  2 <= k <= 64; the
+ * first build with k > 32 re-allocates the table with 32-byte entries (two
+ * key words) and builds it directly (no binned mode, no wavefront merging).
  * Errors: DBG_E_INVAL (NULL pointers, decreasing offsets), DBG_E_K,
  * DBG_E_BASE, DBG_E_RANGE -- in all of these nothing was modified;
  * DBG_E_FULL (counts are partial, handle poisoned), DBG_E_NOMEM,
@@ -146,14 +153,16 @@ int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
 int dbg_sync(dbg_graph *g);
 
 /* Copy the graph out as records in unspecified order: keys[i] and
- * counts[4*i .. 4*i+3] for i < *n_vertices.  With keys == NULL only
+ * counts[4*i .. 4*i+3] for i < *n_vertices; for k > 32 the key of record i
+ * is keys[2*i] (high word) and keys[2*i+1] (low word), and keys must hold
+ * 2 * cap words.  With keys == NULL only
  * *n_vertices is set.  Synchronous.  Errors: DBG_E_SPACE when cap is smaller
  * than the vertex count (*n_vertices is still set, nothing is written),
  * DBG_E_INVAL, DBG_E_DEVICE.  Allowed on a poisoned handle (partial counts). */
 int dbg_extract(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap,
                 uint64_t *n_vertices);
 
-/* Same into device buffers d_keys (cap entries) and d_counts (4 * cap),
+/* Same into device buffers d_keys (cap entries, 2 * cap for k > 32) and d_counts (4 * cap),
  * stream-ordered up to the vertex count, which the call reads back
  * (synchronising on the stream). */
 int dbg_extract_device(dbg_graph *g, uint64_t *d_keys, uint32_t *d_counts, uint64_t cap,
@@ -241,7 +250,7 @@ int dbg_extract_normalized(dbg_graph *g, uint64_t genome_size, uint32_t flags, u
  * the order is unspecified.  With seq and offsets NULL only *n_contigs and
  * *seq_len are set (the result is kept on the device until the next build or
  * reset, so a second call to fetch it does not recompute).  Errors:
- * DBG_E_INVAL, DBG_E_STATE (graph poisoned), DBG_E_SPACE (a buffer is too
+ * DBG_E_INVAL, DBG_E_K (k > 32), DBG_E_STATE (graph poisoned), DBG_E_SPACE (a buffer is too
  * small; the sizes are set), DBG_E_NOMEM, DBG_E_DEVICE. */
 int dbg_contigs(dbg_graph *g, char *seq, uint64_t seq_cap, uint64_t *offsets, uint64_t offsets_cap,
                 uint64_t *n_contigs, uint64_t *seq_len);
@@ -357,6 +366,8 @@ typedef struct {
  * candidate keeps (DBG_F_GRAPH, DBG_F_ENTRY32, DBG_F_TIMING).  repeats timed
  * builds per candidate (0 = 3) after one warm-up.  Results are cached per
  * process by device, instance count, k values, input size class and flags.
+ * k may exceed 32 (up to 64) only for m = 1; such a graph is tuned over the
+ * direct build's launch shape and load factor.
  * Errors: DBG_E_INVAL, or the error of the default configuration's build. */
 int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const uint32_t *ks,
                  const uint64_t *expected_vertices, const uint8_t *d_reads, uint64_t reads_len,

@@ -291,10 +291,15 @@ class Graph:
         _check(lib().dbg_extract(self.handle, None, None, 0, ctypes.byref(n)), "dbg_extract")
         return int(n.value)
 
+    def key_words(self) -> int:
+        """uint64 words per extracted key: 2 for k > 32 (high word, low word)."""
+        return 2 if self.stats()["k"] > 32 else 1
+
     def extract(self):
-        """(keys uint64[V], counts uint32[V, 4]) in unspecified order."""
+        """(keys uint64[V], counts uint32[V, 4]) in unspecified order; for
+        k > 32 keys is uint64[V, 2] (high word, low word)."""
         V = self.vertex_count()
-        keys = np.empty(V, dtype=np.uint64)
+        keys = np.empty((V, 2) if self.key_words() == 2 else V, dtype=np.uint64)
         counts = np.empty((V, 4), dtype=np.uint32)
         n = ctypes.c_uint64(0)
         if V:
@@ -305,13 +310,16 @@ class Graph:
 
     def extract_sorted(self):
         keys, counts = self.extract()
-        order = np.argsort(keys, kind="stable")
+        if keys.ndim == 2:
+            order = np.lexsort((keys[:, 1], keys[:, 0]))
+        else:
+            order = np.argsort(keys, kind="stable")
         return keys[order], counts[order]
 
     def extract_device(self, d_keys, d_counts, stream=None) -> int:
         n = ctypes.c_uint64(0)
         rc = lib().dbg_extract_device(self.handle, _ptr(d_keys), _ptr(d_counts),
-                                      int(d_keys.numel()), ctypes.byref(n), _stream(stream))
+                                      int(d_keys.numel()) // self.key_words(), ctypes.byref(n), _stream(stream))
         _check(rc, "dbg_extract_device")
         return int(n.value)
 
@@ -320,7 +328,7 @@ class Graph:
         expected k-mer duplication (dbg_extract_normalized); uint32 counts,
         or uint8 saturated at 255 with u8=True."""
         V = self.vertex_count()
-        keys = np.empty(V, dtype=np.uint64)
+        keys = np.empty((V, 2) if self.key_words() == 2 else V, dtype=np.uint64)
         counts = np.empty((V, 4), dtype=np.uint8 if u8 else np.uint32)
         n = ctypes.c_uint64(0)
         if V:

@@ -50,6 +50,7 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     g->shape.wpt = wpt;
     g->shape.merge = (cfg.flags & DBG_F_MERGE) ? 1 : 0;
     g->shape.grid = dbgk::build_grid(device, block);
+    g->grid_wide = dbgk::build_grid_wide(device, block);
 
     int rc = DBG_OK;
     if (cfg.stream) {
@@ -73,7 +74,7 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
 
 int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
                      const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, void *stream) {
-    int rc = check_common(g, k);
+    int rc = check_common(g, k, kMaxK);
     if (rc != DBG_OK) return rc;
     if (n_reads == 0) return DBG_OK;
     if (!d_offsets || (!d_reads && reads_len)) return DBG_E_INVAL;
@@ -99,7 +100,7 @@ int dbg_sync(dbg_graph *g) {
 }
 
 int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t n_reads, uint32_t k) {
-    int rc = check_common(g, k);
+    int rc = check_common(g, k, kMaxK);
     if (rc != DBG_OK) return rc;
     if (n_reads == 0) return DBG_OK;
     if (!offsets) return DBG_E_INVAL;
@@ -148,12 +149,13 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
     if (cap < V) return DBG_E_SPACE;
     if (!counts) return DBG_E_INVAL;
     if (V == 0) return DBG_OK;
+    const uint64_t kw = key_words(g);
 
     uint64_t *okeys = keys;
     uint32_t *ocnt = counts;
     hipError_t e;
     if (!device_out) {
-        if ((e = g->xkeys.reserve(V * 8)) != hipSuccess || (e = g->xcnt.reserve(V * 16)) != hipSuccess)
+        if ((e = g->xkeys.reserve(V * 8 * kw)) != hipSuccess || (e = g->xcnt.reserve(V * 16)) != hipSuccess)
             return hip_code(e);
         okeys = g->xkeys.as<uint64_t>();
         ocnt = g->xcnt.as<uint32_t>();
@@ -161,7 +163,9 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
     if (g->xn.reserve(8) != hipSuccess) return DBG_E_DEVICE;
     uint64_t found = 0;
     e = dbgk::launch_fill_zero(g->xn.as<uint64_t>(), 1, s);
-    if (e == hipSuccess && g->binned)
+    if (e == hipSuccess && kw == 2)
+        e = dbgk::launch_extract_wide(g->table.as<uint64_t>(), g->cap, okeys, ocnt, V, g->xn.as<uint64_t>(), s);
+    else if (e == hipSuccess && g->binned)
         e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, g->parts,
                                         g->seg_count.as<uint32_t>(), g->seg_off.as<uint64_t>(),
                                         g->seg_partials.as<uint64_t>(), g->seg_len.as<uint64_t>(), okeys,
@@ -171,7 +175,7 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
                                  g->xn.as<uint64_t>(), s);
     if (e == hipSuccess) e = hipMemcpyAsync(&found, g->xn.p, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && !device_out) {
-        e = hipMemcpyAsync(keys, okeys, V * 8, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(keys, okeys, V * 8 * kw, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(counts, ocnt, V * 16, hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -203,8 +207,9 @@ int dbg_extract_normalized(dbg_graph *g, uint64_t genome_size, uint32_t flags, u
     if (cap < V) return DBG_E_SPACE;
     if (!counts) return DBG_E_INVAL;
     if (V == 0) return DBG_OK;
+    const uint64_t kw = key_words(g);
     hipError_t e;
-    if ((e = g->nkeys.reserve(V * 8)) != hipSuccess || (e = g->ncnt.reserve(V * 16)) != hipSuccess ||
+    if ((e = g->nkeys.reserve(V * 8 * kw)) != hipSuccess || (e = g->ncnt.reserve(V * 16)) != hipSuccess ||
         (e = g->n8.reserve(V * 4)) != hipSuccess)
         return hip_code(e);
     uint64_t n = 0;
@@ -214,7 +219,7 @@ int dbg_extract_normalized(dbg_graph *g, uint64_t genome_size, uint32_t flags, u
     const bool u8 = (flags & DBG_NORM_U8) != 0;
     e = dbgk::launch_normalize(g->ncnt.as<uint32_t>(), 4 * V, genome_size, g->inserts,
                                u8 ? g->n8.as<uint8_t>() : nullptr, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(keys, g->nkeys.p, V * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(keys, g->nkeys.p, V * 8 * kw, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(counts, u8 ? g->n8.p : g->ncnt.p, u8 ? V * 4 : V * 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -297,7 +302,7 @@ const char *dbg_strerror(int code) {
     switch (code) {
     case DBG_OK: return "ok";
     case DBG_E_INVAL: return "invalid argument (NULL pointer, bad offsets or configuration)";
-    case DBG_E_K: return "k outside [2, 32] or different from the graph's k";
+    case DBG_E_K: return "k outside [2, 64] (outside [2, 32] for batches, the server and contigs) or different from the graph's k";
     case DBG_E_BASE: return "read byte outside ACGTacgt";
     case DBG_E_NOMEM: return "device memory allocation refused";
     case DBG_E_FULL: return "table capacity exhausted; graph poisoned";

@@ -357,6 +357,7 @@ int contigs_common(dbg_graph *g, void *seq, uint64_t seq_cap, uint64_t *offsets,
         if (rc != DBG_OK) g->unreported = rc;
     }
     if (g->poisoned) return DBG_E_STATE;
+    if (g->k > 32) return DBG_E_K;  // walks use one-word keys
     if (!g->contigs) g->contigs = new dbg_contig_state();
     dbg_contig_state *cs = g->contigs;
     const int rc = compute_contigs(g, cs, s);

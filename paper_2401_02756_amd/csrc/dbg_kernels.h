@@ -17,6 +17,9 @@
 // Table layout: an array of `cap` entries of `entry_words` uint64 words
 // (3 = 24 bytes, 4 = 32 bytes).  Word 0 holds the vertex key with bit 63 set,
 // the next 16 bytes four uint32 counters in letter-code order A, C, T, G.
+// Long k (32 < k <= 64, direct build only): 32-byte entries whose words 0
+// and 1 hold the upper and lower 63 bits of the key, each with bit 63 set,
+// and whose words 2-3 hold the counters.
 // Direct build: the entries are the open-addressing slots themselves (0 =
 // empty, so a zero fill empties the table).  Binned build: the table is cut
 // into segments of kSegSlots entries, and segment s holds its vertices packed
@@ -199,6 +202,13 @@ hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *s
 hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                         const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
                         BuildShape shape, bool single, hipStream_t s);
+// Plain build for 32 < k <= 64 (one instance, direct table of 32-byte entries).
+hipError_t launch_build_wide(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                             const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
+                             BuildShape shape, hipStream_t s);
+// Records of a long-k table: two key words per record, (K >> 64, K mod 2^64).
+hipError_t launch_extract_wide(const uint64_t *table, uint64_t cap, uint64_t *out_keys, uint32_t *out_counts,
+                               uint64_t out_cap, uint64_t *out_n, hipStream_t s);
 hipError_t launch_extract(const uint64_t *table, uint32_t entry_words, uint64_t cap,
                           uint64_t *out_keys, uint32_t *out_counts, uint64_t out_cap,
                           uint64_t *out_n, hipStream_t s);
@@ -229,7 +239,9 @@ hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, ui
                                  uint64_t *len, uint64_t *out_keys, uint32_t *out_counts,
                                  uint64_t out_cap, uint64_t *out_n, int device, hipStream_t s);
 
-// Occupancy-derived persistent grid for the build kernel.
+// Occupancy-derived persistent grid for the build kernel (k <= 32) and for
+// the long-k build.
 uint32_t build_grid(int device, uint32_t block);
+uint32_t build_grid_wide(int device, uint32_t block);
 
 }  // namespace dbgk

@@ -555,6 +555,180 @@ __global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ arg
     }
 }
 
+// ---------------------------------------------------------------- build, long k
+
+// For 32 < k <= 64 the (k-1)-mer K has 64 to 126 bits and takes two words of
+// a 32-byte entry: word 0 = kOccupied | K >> 63, word 1 = kWritten | (K mod
+// 2^63), then the four counters.  A slot is claimed by the CAS of word 0
+// alone; the claimer then stores word 1 once.  A lane that finds word 0
+// equal to its own but word 1 still zero has met a claim in flight and reads
+// the slot again (the claimer waits for nothing between its CAS and that
+// store, so the wait ends); a word 1 of another key sends it on to the next
+// slot.  Words are written once each, so no ordering between the two words
+// is needed beyond each word's own atomicity.
+constexpr uint64_t kWritten = 1ull << 63;
+constexpr uint64_t kLow63 = kWritten - 1;
+constexpr uint32_t kMaxInFlight = 1u << 20;  // re-reads of one claim in flight
+
+// 64 bases from base position p, first base in bits 63..62 of x0.
+__device__ __forceinline__ void bases128_at(const uint64_t *__restrict__ packed, uint64_t p,
+                                            uint64_t &x0, uint64_t &x1) {
+    const uint64_t wi = p >> 5;
+    const uint32_t sh = (uint32_t)(p & 31) * 2;
+    const uint64_t w0 = packed[wi], w1 = packed[wi + 1];
+    if (sh == 0) {
+        x0 = w0;
+        x1 = w1;
+        return;
+    }
+    const uint64_t w2 = packed[wi + 2];
+    x0 = (w0 << sh) | (w1 >> (64 - sh));
+    x1 = (w1 << sh) | (w2 >> (64 - sh));
+}
+
+__device__ __forceinline__ uint64_t find_or_claim_wide(uint64_t *table, uint64_t cap, uint64_t tag0,
+                                                       uint64_t tag1, uint64_t h, bool &claimed,
+                                                       uint32_t *err) {
+    const uint64_t limit = cap < kMaxProbe ? cap : kMaxProbe;
+    uint64_t s = home_slot(h, cap);
+    uint64_t probes = 0;
+    uint32_t waits = 0;
+    for (;;) {
+        uint64_t *e = table + s * 4;
+        uint64_t cur = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0) {
+            uint64_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(e, &expected, tag0, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(e + 1, tag1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                claimed = true;
+                return s;
+            }
+            cur = expected;
+        }
+        if (cur == tag0) {
+            const uint64_t w1 = __hip_atomic_load(e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (w1 == tag1) return s;
+            if (w1 == 0) {  // a claim in flight: read this slot again
+                if (++waits > kMaxInFlight) return kAllOnes;
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+        }
+        if (++probes >= limit) return kAllOnes;
+        s = (s + 1 == cap) ? 0 : s + 1;
+        if ((probes & 255) == 255 &&
+            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrFull))
+            return kAllOnes;
+    }
+}
+
+// Plain (one-graph) build for 32 < k <= 64; same tiles and window map as
+// k_build, one window per thread per step, no merging.
+__global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict__ args,
+                                                    const Instance *__restrict__ inst,
+                                                    const uint64_t *__restrict__ packed,
+                                                    const uint64_t *__restrict__ ws,
+                                                    const uint64_t *__restrict__ tile_read,
+                                                    InstStatus *st, CallState *cs, uint32_t wpt) {
+    const uint64_t *__restrict__ off = args->off;
+    const uint64_t n = args->n_reads;
+    __shared__ uint64_t s_ws[kMapReads + 1];
+    __shared__ uint64_t s_delta[kMapReads];
+    __shared__ uint64_t s_tile;
+    __shared__ uint64_t s_claims;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const uint64_t W = cs->windows;
+    const uint64_t off0 = n ? off[0] : 0;
+    const uint64_t T = (uint64_t)blockDim.x * wpt;
+    const uint64_t ntiles = (W + T - 1) / T;
+    uint64_t *tab = inst[0].table;
+    const uint64_t cap = inst[0].cap;
+    const uint32_t km1 = inst[0].k - 1;
+    const uint32_t r = 128 - 2 * km1;  // 2 .. 64: key bits end r bits above the 128-bit window's end
+    if (inst[0].prior_inserts + st[0].inserts > 0xffffffffull) {
+        if (tid == 0) atomic_or_u32(&st[0].err, kErrRange);
+        return;
+    }
+    if (__hip_atomic_load(&st[0].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+        (kErrBase | kErrInval | kErrRange | kErrSkip))
+        return;
+
+    uint64_t my_claims = 0;
+    if (tid == 0) s_claims = 0;
+    for (;;) {
+        if (tid == 0) {
+            s_tile = __hip_atomic_fetch_add(&cs->cursor, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(&st[0].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrFull)
+                s_tile = ntiles;
+        }
+        __syncthreads();
+        const uint64_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint64_t w0 = tile * T;
+        const uint64_t w1 = min(w0 + T, W);
+        const uint64_t r0 = tile_read[tile];
+        const uint32_t R = (uint32_t)min((uint64_t)kMapReads, n - r0);
+        for (uint32_t i = tid; i <= R; i += blockDim.x) {
+            const uint64_t rr = r0 + i;
+            const uint64_t wr = ws[rr];
+            s_ws[i] = wr;
+            if (i < R) s_delta[i] = off[rr] - off0 - wr;
+        }
+        __syncthreads();
+
+        for (uint32_t it = 0; it < wpt; ++it) {
+            const uint64_t w = w0 + (uint64_t)it * blockDim.x + tid;
+            if (w >= w1) continue;
+            uint64_t wr1, delta;
+            if (w < s_ws[R]) {
+                uint32_t lo = 0, hi = R;  // s_ws[lo] <= w < s_ws[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_ws[mid] <= w) lo = mid; else hi = mid;
+                }
+                wr1 = s_ws[lo + 1];
+                delta = s_delta[lo];
+            } else {
+                uint64_t lo = r0 + R, hi = n;  // ws[lo] <= w < ws[hi]
+                while (hi - lo > 1) {
+                    const uint64_t mid = (lo + hi) >> 1;
+                    if (ws[mid] <= w) lo = mid; else hi = mid;
+                }
+                wr1 = ws[lo + 1];
+                delta = off[lo] - off0 - ws[lo];
+            }
+            const bool sink = (w + 1 == wr1);
+            uint64_t x0, x1;
+            bases128_at(packed, w + delta, x0, x1);
+            // K = the top 2 km1 bits of x0:x1; the letter follows it
+            const uint64_t klo = r == 64 ? x0 : (x1 >> r) | (x0 << (64 - r));
+            const uint64_t khi = r == 64 ? 0 : x0 >> r;
+            const uint32_t letter = (uint32_t)(x1 >> (r - 2)) & 3u;
+            const uint64_t a = (khi << 1) | (klo >> 63);
+            const uint64_t tag0 = a | kOccupied, tag1 = (klo & kLow63) | kWritten;
+            const uint64_t h = mix64(tag1 ^ mix64(a));
+            bool claimed = false;
+            const uint64_t s = find_or_claim_wide(tab, cap, tag0, tag1, h, claimed, &st[0].err);
+            if (s == kAllOnes) {
+                atomic_or_u32(&st[0].err, kErrFull);
+                continue;
+            }
+            if (!sink)
+                __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(tab + s * 4 + 2) + letter, 1u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            my_claims += claimed ? 1u : 0u;
+        }
+        __syncthreads();
+    }
+    for (int d = 32; d >= 1; d >>= 1) my_claims += __shfl_xor(my_claims, d, 64);
+    if (lane == 0 && my_claims)
+        __hip_atomic_fetch_add(&s_claims, my_claims, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    if (tid == 0 && s_claims) atomic_add_u64(&st[0].claimed, s_claims);
+}
+
 // ---------------------------------------------------------------- extract
 
 constexpr uint32_t kExtractBlock = 256;
@@ -597,6 +771,44 @@ __global__ __launch_bounds__(kExtractBlock) void k_extract(const uint64_t *__res
                 }
                 ++idx;
             }
+        }
+        __syncthreads();
+    }
+}
+
+// Long-k table: each record's key as two words (K >> 64, K mod 2^64).
+__global__ __launch_bounds__(kExtractBlock) void k_extract_wide(const uint64_t *__restrict__ table,
+                                                               uint64_t cap, uint64_t *__restrict__ okeys,
+                                                               uint32_t *__restrict__ ocnt, uint64_t ocap,
+                                                               uint64_t *out_n) {
+    __shared__ uint64_t s_base;
+    const uint64_t chunk = (uint64_t)kExtractBlock * kExtractPerThread;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < cap; base += (uint64_t)gridDim.x * chunk) {
+        uint64_t tags[kExtractPerThread];
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kExtractPerThread; ++i) {
+            const uint64_t s = base + (uint64_t)i * kExtractBlock + threadIdx.x;
+            tags[i] = s < cap ? table[s * 4] : 0;
+            mine += tags[i] != 0;
+        }
+        uint64_t total;
+        uint64_t pre = block_exclusive_scan(mine, &total);
+        if (threadIdx.x == 0) s_base = total ? atomicAdd((unsigned long long *)out_n, (unsigned long long)total) : 0;
+        __syncthreads();
+        uint64_t idx = s_base + pre;
+#pragma unroll
+        for (uint32_t i = 0; i < kExtractPerThread; ++i) {
+            if (!tags[i]) continue;
+            const uint64_t s = base + (uint64_t)i * kExtractBlock + threadIdx.x;
+            if (idx < ocap) {
+                const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(table + s * 4);
+                const uint4 c = *reinterpret_cast<const uint4 *>(table + s * 4 + 2);
+                const uint64_t a = e.x & ~kOccupied, b = e.y & kLow63;
+                *reinterpret_cast<ulonglong2 *>(okeys + 2 * idx) = make_ulonglong2(a >> 1, (a << 63) | b);
+                *reinterpret_cast<uint4 *>(ocnt + 4 * idx) = c;
+            }
+            ++idx;
         }
         __syncthreads();
     }
@@ -726,6 +938,14 @@ hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64
     return hipGetLastError();
 }
 
+hipError_t launch_build_wide(const PassArgs *args, const Instance *inst, const uint64_t *packed,
+                             const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
+                             BuildShape shape, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_wide, dim3(shape.grid), dim3(shape.block), 0, s, args, inst, packed, ws, tile_read,
+                       st, cs, shape.wpt);
+    return hipGetLastError();
+}
+
 namespace {
 
 // round-half-up(c * genome / total) = floor((2 c genome + total) / (2 total)),
@@ -783,6 +1003,15 @@ hipError_t launch_extract(const uint64_t *table, uint32_t ew, uint64_t cap, uint
     return hipGetLastError();
 }
 
+hipError_t launch_extract_wide(const uint64_t *table, uint64_t cap, uint64_t *okeys, uint32_t *ocnt,
+                               uint64_t ocap, uint64_t *out_n, hipStream_t s) {
+    const uint64_t chunk = (uint64_t)kExtractBlock * kExtractPerThread;
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((cap + chunk - 1) / chunk, 256 * 32));
+    hipLaunchKernelGGL(k_extract_wide, dim3(blocks), dim3(kExtractBlock), 0, s, table, cap, okeys, ocnt, ocap,
+                       out_n);
+    return hipGetLastError();
+}
+
 hipError_t launch_count(const uint64_t *table, uint32_t ew, uint64_t cap, uint64_t *out_n,
                         hipStream_t s) {
     const uint64_t chunk = (uint64_t)kExtractBlock * kExtractPerThread;
@@ -805,6 +1034,8 @@ hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32
     hipLaunchKernelGGL(k_roofline, dim3(grid), dim3(block), 0, s, mem, words, n_ops, kind, seed, sink);
     return hipGetLastError();
 }
+
+uint32_t build_grid_wide(int device, uint32_t block) { return grid_for(k_build_wide, device, block); }
 
 uint32_t build_grid(int device, uint32_t block) {
     // all four instantiations share the same resource shape up to LDS; the

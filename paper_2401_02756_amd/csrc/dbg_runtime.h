@@ -140,12 +140,13 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
 struct PassKey {
     int binned = 0;
     int single = 0;
+    int wide = 0;  // one instance with 32 < k <= 64
     uint32_t ew = 3;
     uint32_t m_cap = 0, d1_cap = 0, fan_cap = 0;
     uint64_t n_cap = 0, len_cap = 0, parts_cap = 0, buckets_cap = 0;
     dbgk::BuildShape shape{};
     bool operator==(const PassKey &o) const {
-        return binned == o.binned && single == o.single && ew == o.ew && m_cap == o.m_cap &&
+        return binned == o.binned && single == o.single && wide == o.wide && ew == o.ew && m_cap == o.m_cap &&
                d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
                parts_cap == o.parts_cap && buckets_cap == o.buckets_cap && shape.block == o.shape.block &&
                shape.wpt == o.shape.wpt && shape.grid == o.shape.grid && shape.merge == o.shape.merge;
@@ -317,7 +318,10 @@ struct Pass {
         InstStatus *dst = dstatus.as<InstStatus>();
         CallState *cs = reinterpret_cast<CallState *>(dst + k.m_cap);
         hipError_t e;
-        if (k.binned)
+        if (k.wide)
+            e = dbgk::launch_build_wide(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
+                                        cs, k.shape, s);
+        else if (k.binned)
             e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s,
                                     mark ? marks : nullptr);
         else
@@ -359,6 +363,7 @@ struct Pass {
         k.binned = binned ? 1 : 0;
         k.single = mm == 1 ? 1 : 0;
         k.shape = shape;
+        k.wide = (mm == 1 && !binned && host_instances()[0].k > 32) ? 1 : 0;
         k.m_cap = (uint32_t)size_class(mm, 1);
         k.n_cap = size_class(n, 1024);
         k.len_cap = size_class(len, 4096);
@@ -481,6 +486,7 @@ struct dbg_graph {
     double lf = 0.5;
     uint64_t expected = 0, cap_req = 0;
     dbgk::BuildShape shape{256, 4, 0, 0};
+    uint32_t grid_wide = 0;  // persistent grid of the long-k build
 
     uint64_t cap = 0;
     uint32_t ew = 3;
@@ -582,11 +588,25 @@ inline int ensure_table(dbg_graph *g, uint64_t windows_bound) {
 }
 
 // A binned graph whose first build has k = 32 (keys too wide for the 8-byte
-// records) becomes a direct one; its table must then hold zeros.
+// records) becomes a direct one; its table must then hold zeros.  A build
+// with k > 32 needs 32-byte entries (two key words): the graph's table is
+// re-allocated for them before its first build.
 inline int settle_mode(dbg_graph *g, uint32_t k) {
-    if (!g->binned || k <= 31) return DBG_OK;
+    const bool wide = k > 32 && g->ew != 4;
+    if (!wide && (!g->binned || k <= 31)) return DBG_OK;
     if (g->k || g->vertices) return DBG_E_K;
     g->binned = false;
+    if (wide) {
+        g->ew = 4;
+        if (g->cap) {
+            g->table.release();
+            const hipError_t e = g->table.reserve(g->table_words() * sizeof(uint64_t));
+            if (e != hipSuccess) {
+                g->cap = 0;
+                return hip_code(e);
+            }
+        }
+    }
     if (g->cap && zero_table(g) != hipSuccess) return DBG_E_DEVICE;
     return DBG_OK;
 }
@@ -636,10 +656,18 @@ inline int harvest(dbg_graph *g) {
     return fold_status(g, g->pass.host_status()[0], g->pending_k);
 }
 
-inline int check_common(dbg_graph *g, uint32_t k) {
+// uint64 words per extracted key: two for a long-k graph.
+inline uint64_t key_words(const dbg_graph *g) { return g->k > 32 ? 2 : 1; }
+
+// Largest k of a plain build, and of every other path (batches, the
+// server, contigs), whose keys must fit one word.
+constexpr uint32_t kMaxK = 64;
+constexpr uint32_t kMaxKWord = 32;
+
+inline int check_common(dbg_graph *g, uint32_t k, uint32_t kmax = kMaxKWord) {
     if (!g) return DBG_E_INVAL;
     if (g->poisoned) return DBG_E_STATE;
-    if (k < 2 || k > 32) return DBG_E_K;
+    if (k < 2 || k > kmax) return DBG_E_K;
     if (g->k && g->k != k) return DBG_E_K;
     return DBG_OK;
 }
@@ -650,7 +678,12 @@ inline int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, co
     if (e != hipSuccess) return hip_code(e);
     fill_instance(g->pass.host_instances()[0], g, 0, n, k);
     if ((e = order_after_zero(g, s)) != hipSuccess) return hip_code(e);
-    e = g->pass.enqueue(1, d_reads, len, d_off, n, g->shape, g->binned, g->device, true,
+    dbgk::BuildShape shape = g->shape;
+    if (k > 32) {
+        shape.grid = g->grid_wide;
+        shape.merge = 0;
+    }
+    e = g->pass.enqueue(1, d_reads, len, d_off, n, shape, g->binned, g->device, true,
                         (g->flags & DBG_F_TIMING) != 0, s);
     if (e != hipSuccess) return hip_code(e);
     g->pending_k = k;

@@ -101,14 +101,14 @@ int size_bucket(uint64_t x) {  // half-octaves
 }
 
 std::string cache_key(const Workload &w) {
-    uint32_t kmask_lo = 0, kmask_hi = 0;
+    uint64_t kmask = 0;  // bit k - 1 for each k in 2 .. 64
     uint64_t ev = 0;
     for (uint32_t i = 0; i < w.m; ++i) {
-        (w.ks[i] < 32 ? kmask_lo : kmask_hi) |= 1u << (w.ks[i] & 31);
+        kmask |= 1ull << (w.ks[i] - 1);
         ev += w.expected ? w.expected[i] : 0;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%d/%u/%x.%x/%d/%d/%d/%x", w.device, w.m, kmask_lo, kmask_hi,
+    std::snprintf(buf, sizeof buf, "%d/%u/%llx/%d/%d/%d/%x", w.device, w.m, (unsigned long long)kmask,
                   size_bucket(w.reads_len), size_bucket(w.read_begin[w.m]), size_bucket(ev), w.keep_flags);
     return buf;
 }
@@ -131,10 +131,12 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
                  dbg_tuning *out) {
     if (!out || m == 0 || !read_begin || !ks || !d_offsets || (!d_reads && reads_len) || read_begin[0] != 0)
         return DBG_E_INVAL;
-    bool all_binnable = true;
+    bool all_binnable = true, wide = false;
     for (uint32_t i = 0; i < m; ++i) {
-        if (ks[i] < 2 || ks[i] > 32 || read_begin[i + 1] < read_begin[i]) return DBG_E_INVAL;
+        // k > 32 only for a single graph (batched builds take k <= 32)
+        if (ks[i] < 2 || ks[i] > (m == 1 ? 64u : 32u) || read_begin[i + 1] < read_begin[i]) return DBG_E_INVAL;
         if (ks[i] > 31) all_binnable = false;
+        if (ks[i] > 32) wide = true;
     }
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
     DeviceGuard guard(device);
@@ -201,10 +203,12 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
                 const double ms = consider(c);
                 if (ms < dbest) dbest = ms, dc = c;
             }
-        Cand mc = dc;
-        mc.merge = true;
-        const double mms = consider(mc);
-        if (mms < dbest) dbest = mms, dc = mc;
+        if (!wide) {  // the long-k build does not merge
+            Cand mc = dc;
+            mc.merge = true;
+            const double mms = consider(mc);
+            if (mms < dbest) dbest = mms, dc = mc;
+        }
         for (double lf : {0.4, 0.6, 0.7}) {
             Cand c = dc;
             c.lf = lf;

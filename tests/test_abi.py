@@ -134,10 +134,12 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_contigs_device(None, None, 0, None, 0, ctypes.byref(n64), ctypes.byref(n64), None) == dbg.E_INVAL
     t = dbg.Tuning()
     assert L.dbg_autotune(-1, 0, None, None, None, None, 0, None, 0, 0, 0, ctypes.byref(t)) == dbg.E_INVAL
-    rb = (ctypes.c_uint64 * 2)(0, 1)
-    ks = (ctypes.c_uint32 * 1)(33)
+    rb = (ctypes.c_uint64 * 3)(0, 1, 1)
+    ks = (ctypes.c_uint32 * 2)(65, 21)
     off = (ctypes.c_uint64 * 2)(0, 0)
     assert L.dbg_autotune(-1, 1, rb, ks, None, None, 0, off, 0, 0, 0, ctypes.byref(t)) == dbg.E_INVAL
+    ks[0] = 33  # long k only for a single graph
+    assert L.dbg_autotune(-1, 2, rb, ks, None, None, 0, off, 0, 0, 0, ctypes.byref(t)) == dbg.E_INVAL
     cfg = dbg.Config()
     L.dbg_config_init(ctypes.byref(cfg))
     cfg.flags = dbg.F_GRAPH | dbg.F_MERGE
