@@ -382,6 +382,8 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true", help="skip the serving benchmark")
     ap.add_argument("--no-large", action="store_true", help="skip the large (100 Mbp) plain build")
+    ap.add_argument("--no-long-k", action="store_true", help="skip the k = 51 build of the same reads")
+    ap.add_argument("--long-k", type=int, default=51)
     ap.add_argument("--no-tune", action="store_true",
                     help="use --mode/--load-factor/--block/--wpt/--merge instead of the autotuner's choice")
     ap.add_argument("--served-payloads", type=int, default=64)
@@ -463,6 +465,45 @@ def main() -> int:
         g.close()
         ms = float(np.median(t[1:])) * 1e3
         return {"ms": round(ms, 3), "contigs": n, "bases": ln, "vertices_per_s": round(V / ms * 1e3, 1)}
+
+    def long_k_rate(k: int, steps: int = 5) -> dict:
+        """The same reads at long k (two-word keys, direct build, 32-byte
+        entries): whole step (reset, build, extraction) and build kernel."""
+        kins = int(np.maximum(rs.lengths() - k + 1, 0).sum())
+        ev = readsim.expected_vertices(int(rs.meta["genome_len"]), int(rs.meta["read_len"]), rs.n_reads,
+                                       float(rs.meta["err"]), k)
+        flags = dbg.F_TIMING | (0 if args.no_graph else dbg.F_GRAPH)
+        g = dbg.Graph(expected_vertices=ev, load_factor=0.5, device=0, flags=flags)
+        g.build_device(d_reads, d_off, k)
+        g.sync()
+        cap = int(g.stats()["capacity"])
+        d_keys = torch.empty(2 * cap, dtype=torch.int64, device=dev)
+        d_counts = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+
+        def step():
+            g.reset()
+            g.build_device(d_reads, d_off, k)
+            g.sync()
+            return g.extract_device(d_keys, d_counts)
+
+        step()
+        torch.cuda.synchronize()
+        kern = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            nv = step()
+            kern.append(g.stats()["last_build_ms"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = g.stats()
+        assert st["inserts"] == kins, (st["inserts"], kins)
+        g.close()
+        del d_keys, d_counts
+        km = float(np.mean(kern))
+        return {"k": k, "inserts_per_step": kins, "vertices": nv, "capacity": cap,
+                "entry_bytes": st["entry_bytes"], "ms_per_step": round(dt * 1e3, 3),
+                "value": round(kins / dt / 1e9, 4), "build_ms": round(km, 4),
+                "build_ginserts_s": round(kins / (km * 1e-3) / 1e9, 4)}
 
     def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
         flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
@@ -581,6 +622,10 @@ def main() -> int:
                                    "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
                                    "build_ms": round(o["kern_ms"], 4)}
         log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
+
+    if not args.no_long_k:
+        line["long_k"] = long_k_rate(args.long_k)
+        log("long k %s" % json.dumps(line["long_k"]))
 
     line["contigs"] = contig_rate()
     log("contigs %s" % json.dumps(line["contigs"]))

@@ -9,11 +9,11 @@
 // passed.  The vertex a walk stops on is part of its contig.
 //
 // On the device: the graph's vertices are extracted and inserted into a walk
-// table (key, out-letter mask); a start pass finds the start vertices (the
-// in-degree test looks up the four possible predecessors) and lists one walk
-// per start edge; a length pass follows every walk (Brent's cycle detection
-// finds the loops, then the first revisit is located exactly); a scan lays
-// the contigs out; a write pass spells them.  Every loop is bounded, so a
+// table (key, out-letter mask); a mark pass follows every edge once and flags
+// its target as having an in-edge (so `first` = no flag); a start pass lists
+// one walk per out-edge of every start vertex; a length pass follows every
+// walk (Brent's cycle detection finds the loops, then the first revisit is
+// located exactly); a scan lays the contigs out; a write pass spells them.  Every loop is bounded, so a
 // walk that cannot end reports an error instead of running forever.
 #include "dbg_runtime.h"
 #include "dbg_device.h"
@@ -28,9 +28,12 @@ namespace {
 
 constexpr uint32_t kWalkBlock = 256;
 
+constexpr uint8_t kOutMask = 0x0f;  // bits 0-3: out-edges by letter code
+constexpr uint8_t kHasIn = 0x10;    // some k-mer ends in the vertex
+
 struct WalkTable {
     uint64_t *keys;   // key | kOccupied, 0 = empty
-    uint8_t *masks;   // bit c: the vertex has an out-edge for letter code c
+    uint8_t *masks;   // bit c: the vertex has an out-edge for letter code c; kHasIn
     uint64_t cap;     // power of two
     uint64_t kmask;   // (k-1)-mer key mask
     uint32_t km1;
@@ -74,55 +77,74 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_insert(WalkTable T, const u
     }
 }
 
+__device__ __forceinline__ uint32_t out_mask(const WalkTable &T, uint64_t s) { return T.masks[s] & kOutMask; }
+
+// Flag the target of every edge.  Every writer of a mask byte writes the same
+// value (its out-edges and kHasIn), so plain byte stores suffice.
+__global__ __launch_bounds__(kWalkBlock) void k_walk_mark(WalkTable T, const uint64_t *__restrict__ keys,
+                                                          const uint32_t *__restrict__ counts, uint64_t n,
+                                                          uint32_t *err) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = keys[i];
+        const uint4 c = *reinterpret_cast<const uint4 *>(counts + 4 * i);
+        const uint32_t cnt[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (uint32_t x = 0; x < 4; ++x) {
+            if (!cnt[x]) continue;
+            const uint64_t s = walk_find(T, ((key << 2) | x) & T.kmask);
+            if (s == ~0ull) {
+                atomicOr(err, 16u);  // an edge without its target vertex
+                continue;
+            }
+            const uint8_t m = T.masks[s];
+            if (!(m & kHasIn)) T.masks[s] = (uint8_t)(m | kHasIn);
+        }
+    }
+}
+
 // Walks (slot << 2 | letter) of the start vertices, appended in any order.
+// A workgroup takes kStartChunk consecutive slots and reserves its output
+// range with one atomic (an atomic per wavefront on one counter serialises
+// millions of times at this table size).
+constexpr uint32_t kStartEach = 16, kStartChunk = kWalkBlock * kStartEach;
+
 __global__ __launch_bounds__(kWalkBlock) void k_walk_starts(WalkTable T, uint64_t *__restrict__ items,
                                                             uint64_t items_cap, unsigned long long *n_items,
                                                             uint32_t *err) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint32_t lane = threadIdx.x & 63;
-    // the loop runs the same number of times on every lane of a wavefront
-    const uint64_t rounds = (T.cap + stride - 1) / stride;
-    for (uint64_t r = 0; r < rounds; ++r) {
-        const uint64_t s = r * stride + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        uint32_t m = 0;
-        uint64_t key = 0;
-        if (s < T.cap) {
-            const uint64_t tagv = T.keys[s];
-            if (tagv) {
-                key = tagv & ~kOccupied;
-                m = T.masks[s];
+    __shared__ unsigned long long s_base;
+    const uint64_t chunks = (T.cap + kStartChunk - 1) / kStartChunk;
+    for (uint64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+        const uint64_t s0 = ch * kStartChunk + threadIdx.x;
+        uint32_t outs[kStartEach];
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kStartEach; ++j) {
+            const uint64_t s = s0 + (uint64_t)j * kWalkBlock;
+            uint32_t mb = 0;
+            if (s < T.cap && T.keys[s]) mb = T.masks[s];
+            const uint32_t m = mb & kOutMask;
+            const uint32_t deg = __popc(m);
+            const bool start = deg >= 2 || (deg == 1 && !(mb & kHasIn));
+            outs[j] = start ? m : 0u;
+            mine += start ? deg : 0u;
+        }
+        uint64_t total;
+        const uint64_t pre = block_exclusive_scan(mine, &total);
+        if (threadIdx.x == 0) s_base = total ? atomicAdd(n_items, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        uint64_t at = s_base + pre;
+#pragma unroll
+        for (uint32_t j = 0; j < kStartEach; ++j) {
+            const uint64_t s = s0 + (uint64_t)j * kWalkBlock;
+            for (uint32_t c = 0; c < 4; ++c) {
+                if (!((outs[j] >> c) & 1u)) continue;
+                if (at < items_cap) items[at] = (s << 2) | c;
+                else atomicOr(err, 2u);
+                ++at;
             }
         }
-        const uint32_t deg = __popc(m);
-        bool start = deg >= 2;
-        if (deg == 1) {
-            bool has_in = false;
-            const uint32_t last = (uint32_t)(key & 3);
-            for (uint64_t x = 0; x < 4 && !has_in; ++x) {
-                const uint64_t pred = (x << (2 * (T.km1 - 1))) | (key >> 2);
-                const uint64_t ps = walk_find(T, pred);
-                if (ps != ~0ull && ((T.masks[ps] >> last) & 1u)) has_in = true;
-            }
-            start = !has_in;
-        }
-        const uint32_t mine = start ? deg : 0u;
-        // one atomic per wavefront: lane offsets by prefix of the counts
-        uint32_t pre = mine;
-        for (uint32_t d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(pre, d, 64);
-            if (lane >= d) pre += o;
-        }
-        const uint32_t total = __shfl(pre, 63, 64);
-        unsigned long long base = 0;
-        if (lane == 63 && total) base = atomicAdd(n_items, (unsigned long long)total);
-        base = __shfl(base, 63, 64);
-        uint64_t at = base + pre - mine;
-        for (uint32_t c = 0; c < 4 && mine; ++c) {
-            if (!((m >> c) & 1u)) continue;
-            if (at < items_cap) items[at] = (s << 2) | c;
-            else atomicOr(err, 2u);
-            ++at;
-        }
+        __syncthreads();
     }
 }
 
@@ -150,7 +172,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const u
         for (;;) {
             const uint64_t s = walk_find(T, hare);
             if (s == ~0ull || idx > limit) { bad = true; break; }
-            const uint32_t m = T.masks[s];
+            const uint32_t m = out_mask(T, s);
             if (__popc(m) != 1) break;  // stops on x_idx
             hare = succ(T, hare, m);
             ++idx;
@@ -169,14 +191,14 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const u
             for (uint64_t q = 0; q < lam && !bad; ++q) {
                 const uint64_t s = walk_find(T, b);
                 if (s == ~0ull) bad = true;
-                else b = succ(T, b, T.masks[s]);
+                else b = succ(T, b, out_mask(T, s));
             }
             uint64_t mu = 1;
             while (!bad && a != b) {
                 const uint64_t sa = walk_find(T, a), sb = walk_find(T, b);
                 if (sa == ~0ull || sb == ~0ull || mu > limit) { bad = true; break; }
-                a = succ(T, a, T.masks[sa]);
-                b = succ(T, b, T.masks[sb]);
+                a = succ(T, a, out_mask(T, sa));
+                b = succ(T, b, out_mask(T, sb));
                 ++mu;
             }
             idx = mu + lam;
@@ -197,20 +219,47 @@ __global__ void k_walk_bases(const uint64_t *__restrict__ edges, const unsigned 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) len[i] = km1 + edges[i];
 }
 
-// Exclusive scan of n (device count) uint64 values in place, in one block;
-// out[n] = total.  Contig counts are in the millions, so one block suffices.
-__global__ __launch_bounds__(1024) void k_walk_scan(uint64_t *v, const unsigned long long *n_items) {
-    const uint64_t n = *n_items;
+// Exclusive scan of v[0, n) in place with v[n] = total, in three launches:
+// per-block scans of kScanChunk values with the block sums in part[], one
+// block scanning part[], and the carry added back.
+constexpr uint32_t kScanThreads = 256, kScanEach = 8, kScanChunk = kScanThreads * kScanEach;
+
+__global__ __launch_bounds__(kScanThreads) void k_walk_scan_local(uint64_t *v, uint64_t n, uint64_t *part) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanEach;
+    uint64_t x[kScanEach], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanEach; ++j) {
+        x[j] = b0 + j < n ? v[b0 + j] : 0;
+        sum += x[j];
+    }
+    uint64_t total;
+    uint64_t pre = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (uint32_t j = 0; j < kScanEach; ++j) {
+        if (b0 + j < n) v[b0 + j] = pre;
+        pre += x[j];
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_walk_scan_part(uint64_t *part, uint64_t nb, uint64_t *v, uint64_t n) {
     uint64_t carry = 0;
-    for (uint64_t base = 0; base < n; base += blockDim.x) {
+    for (uint64_t base = 0; base < nb; base += blockDim.x) {
         const uint64_t i = base + threadIdx.x;
-        const uint64_t x = i < n ? v[i] : 0;
+        const uint64_t x = i < nb ? part[i] : 0;
         uint64_t total;
         const uint64_t ex = block_exclusive_scan(x, &total);
-        if (i < n) v[i] = carry + ex;
+        if (i < nb) part[i] = carry + ex;
         carry += total;
     }
     if (threadIdx.x == 0) v[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_walk_scan_add(uint64_t *v, uint64_t n, const uint64_t *part) {
+    const uint64_t add = part[blockIdx.x];
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
+    for (uint32_t j = threadIdx.x; j < kScanChunk; j += kScanThreads)
+        if (b0 + j < n) v[b0 + j] += add;
 }
 
 __global__ __launch_bounds__(kWalkBlock) void k_walk_write(WalkTable T, const uint64_t *__restrict__ items,
@@ -235,7 +284,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_write(WalkTable T, const ui
                 atomicOr(err, 8u);
                 break;
             }
-            const uint32_t c = (uint32_t)__builtin_ctz(T.masks[s]);
+            const uint32_t c = (uint32_t)__builtin_ctz(out_mask(T, s));
             *o++ = letters[c];
             cur = ((cur << 2) | c) & T.kmask;
         }
@@ -254,7 +303,7 @@ uint32_t grid_for(uint64_t n, uint32_t block) {
 }  // namespace
 
 struct dbg_contig_state {
-    DevBuf keys, masks, items, edges, off, seq, xkeys, xcnt, xn, scalars;
+    DevBuf keys, masks, items, edges, off, part, seq, xkeys, xcnt, xn, scalars;
     uint64_t epoch = ~0ull;  // the graph's epoch the contigs were made for
     uint64_t n = 0, len = 0;
 };
@@ -302,10 +351,15 @@ int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
                            cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
         e = hipGetLastError();
     }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_walk_mark, dim3(grid_for(V, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                           cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
+        e = hipGetLastError();
+    }
     // walks are at most the edges, at most 4 per vertex
     const uint64_t items_cap = 4 * V;
     if (e == hipSuccess && (e = cs->items.reserve(items_cap * 8)) == hipSuccess) {
-        hipLaunchKernelGGL(k_walk_starts, dim3(grid_for(cap, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+        hipLaunchKernelGGL(k_walk_starts, dim3(grid_for(cap, kStartChunk)), dim3(kWalkBlock), 0, s, T,
                            cs->items.as<uint64_t>(), items_cap, n_items, err);
         e = hipGetLastError();
     }
@@ -315,8 +369,9 @@ int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
     if (e != hipSuccess) return hip_code(e);
     if ((uint32_t)hs[1]) return DBG_E_DEVICE;
     const uint64_t n = hs[0];
+    const uint64_t nb = std::max<uint64_t>(1, (n + kScanChunk - 1) / kScanChunk);
     if ((e = cs->edges.reserve(std::max<uint64_t>(n, 1) * 8)) != hipSuccess ||
-        (e = cs->off.reserve((n + 1) * 8)) != hipSuccess)
+        (e = cs->off.reserve((n + 1) * 8)) != hipSuccess || (e = cs->part.reserve(nb * 8)) != hipSuccess)
         return hip_code(e);
     // a walk passes each vertex at most once before its loop closes, and
     // finding the loop takes at most twice its length more
@@ -325,7 +380,12 @@ int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
                        cs->items.as<uint64_t>(), n_items, cs->edges.as<uint64_t>(), limit, err);
     hipLaunchKernelGGL(k_walk_bases, dim3(grid_for(n, 256)), dim3(256), 0, s, cs->edges.as<uint64_t>(), n_items,
                        g->k - 1, cs->off.as<uint64_t>());
-    hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, cs->off.as<uint64_t>(), n_items);
+    hipLaunchKernelGGL(k_walk_scan_local, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, cs->off.as<uint64_t>(), n,
+                       cs->part.as<uint64_t>());
+    hipLaunchKernelGGL(k_walk_scan_part, dim3(1), dim3(1024), 0, s, cs->part.as<uint64_t>(), nb,
+                       cs->off.as<uint64_t>(), n);
+    hipLaunchKernelGGL(k_walk_scan_add, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, cs->off.as<uint64_t>(), n,
+                       cs->part.as<uint64_t>());
     if ((e = hipGetLastError()) != hipSuccess) return hip_code(e);
     uint64_t total = 0;
     if ((e = hipMemcpyAsync(&total, cs->off.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -382,8 +442,8 @@ int contigs_common(dbg_graph *g, void *seq, uint64_t seq_cap, uint64_t *offsets,
 
 void dbg_contigs_free(dbg_contig_state *cs) {
     if (!cs) return;
-    DevBuf *b[] = {&cs->keys, &cs->masks, &cs->items, &cs->edges, &cs->off, &cs->seq, &cs->xkeys, &cs->xcnt,
-                   &cs->xn, &cs->scalars};
+    DevBuf *b[] = {&cs->keys, &cs->masks, &cs->items, &cs->edges, &cs->off, &cs->part, &cs->seq, &cs->xkeys,
+                   &cs->xcnt, &cs->xn, &cs->scalars};
     for (DevBuf *x : b) x->release();
     delete cs;
 }
