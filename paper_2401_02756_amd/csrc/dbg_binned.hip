@@ -182,6 +182,39 @@ __device__ __forceinline__ ReadPos locate_read(const ReadStage &S, const uint64_
     return ReadPos{ws[glo + 1], off[glo] - off0 - ws[glo]};
 }
 
+// A thread's position among the reads: the window range end and base delta
+// of the read holding its current window, and that read's staged index
+// (kMapReads + 1 when it lies past the staged reads).
+struct ReadCursor {
+    uint64_t wr1, delta;
+    uint32_t ri;
+};
+
+__device__ __forceinline__ ReadCursor first_read(const ReadStage &S, const uint64_t *ws, const uint64_t *off,
+                                                 uint64_t off0, uint64_t re, uint64_t w) {
+    const uint32_t lo = staged_read(S, w);
+    if (lo < S.R) return ReadCursor{S.ws[lo + 1], S.delta[lo], lo};
+    const ReadPos rp = locate_read(S, ws, off, off0, re, w);
+    return ReadCursor{rp.wr1, rp.delta, kMapReads + 1};
+}
+
+// Window w (>= c.wr1) lies in a later read: the staged reads that follow are
+// stepped through (reads shorter than k have no window), so crossing into
+// the next read costs one or two LDS loads instead of a search.
+__device__ __forceinline__ void next_read(ReadCursor &c, const ReadStage &S, const uint64_t *ws,
+                                          const uint64_t *off, uint64_t off0, uint64_t re, uint64_t w) {
+    if (c.ri < S.R) {
+        uint32_t i = c.ri + 1;
+        while (i < S.R && S.ws[i + 1] <= w) ++i;
+        if (i < S.R) {
+            c = ReadCursor{S.ws[i + 1], S.delta[i], i};
+            return;
+        }
+    }
+    const ReadPos rp = locate_read(S, ws, off, off0, re, w);
+    c = ReadCursor{rp.wr1, rp.delta, kMapReads + 1};
+}
+
 // 64 bits starting `o` bits into the 192-bit big-endian word triple (o < 128).
 __device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, uint32_t o) {
     if (o >= 64) {
@@ -363,7 +396,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
         for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = d1 << 12;
         if (j0 < n_in) {
             uint64_t w = w0 + j0;
-            ReadPos rp = locate_read(S, ws, off, off0, in.read_end, w);
+            ReadCursor rp = first_read(S, ws, off, off0, in.read_end, w);
             uint64_t p = w + rp.delta;
             uint64_t wbase = p >> 5;
             uint64_t a = packed[wbase], b = packed[wbase + 1], c = packed[wbase + 2];
@@ -371,7 +404,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
             for (uint32_t q = 0; q < kBinPerThread; ++q) {
                 if (j0 + q >= n_in) break;
                 if (w >= rp.wr1) {  // the next window starts another read
-                    rp = locate_read(S, ws, off, off0, in.read_end, w);
+                    next_read(rp, S, ws, off, off0, in.read_end, w);
                     p = w + rp.delta;
                     // the words must hold this and the remaining windows' first
                     // bases at offsets below 64 (without a crossing a thread's
