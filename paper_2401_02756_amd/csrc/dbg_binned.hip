@@ -83,6 +83,16 @@ __device__ __forceinline__ uint32_t child_of(uint32_t top, uint32_t d1, uint32_t
     return __umulhi(top * d1, fan);
 }
 
+// A segment of a binned table is kSegSlots entries of EW words, stored as
+// arrays: the image words (image | kOccupied) of its vertices, packed at
+// [0, seg_count), then their four counters (16 bytes each); with 32-byte
+// entries the last quarter is unused.  Each is written and read by
+// consecutive lanes as one contiguous run.
+__device__ __forceinline__ uint4 *seg_counts(uint64_t *seg) { return reinterpret_cast<uint4 *>(seg + kSegSlots); }
+__device__ __forceinline__ const uint4 *seg_counts(const uint64_t *seg) {
+    return reinterpret_cast<const uint4 *>(seg + kSegSlots);
+}
+
 // Home slot inside a segment: the image's low bits.
 __device__ __forceinline__ uint32_t seg_home(uint64_t x) { return (uint32_t)x & (kSegSlots - 1); }
 
@@ -723,26 +733,27 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
     const uint64_t img = rec >> 3;
     const uint64_t tagv = img | kOccupied;
     uint32_t s = seg_home(img);
-    for (uint32_t q = 0; q < kSegSlots; ++q) {
-        const uint64_t cur = lds_load64(&s_key[s]);
-        bool hit = cur == tagv;
-        if (!hit && cur == 0) {
+    uint64_t cur = lds_load64(&s_key[s]);
+    // probe until the slot holds this key (found, or claimed here); the count
+    // is added once, after the loop
+    for (uint32_t q = 0;;) {
+        if (cur == 0) {
             uint64_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            __hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (expected == 0) {
                 ++claims;
-                hit = true;
-            } else {
-                hit = expected == tagv;
+                break;
             }
+            cur = expected;
         }
-        if (hit) {
-            if (!(rec & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec & 3)], 1u);
-            return true;
-        }
+        if (cur == tagv) break;
+        if (++q == kSegSlots) return false;
         s = (s + 1) & (kSegSlots - 1);
+        cur = lds_load64(&s_key[s]);
     }
-    return false;
+    if (!(rec & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec & 3)], 1u);
+    return true;
 }
 
 // One workgroup per segment.  The segment's hash slots live in LDS only: the
@@ -830,15 +841,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         for (uint32_t e = tid; e < n_old; e += blockDim.x) {
             // distinct keys: each claims its own slot, and nobody else touches
             // that slot's counters before the next barrier
-            const uint64_t tagv = seg[(uint64_t)e * EW];
-            const uint64_t c01 = seg[(uint64_t)e * EW + 1], c23 = seg[(uint64_t)e * EW + 2];
+            const uint64_t tagv = seg[e];
+            const uint4 cv = seg_counts(seg)[e];
             uint32_t s = seg_home(tagv);
             for (uint32_t q = 0; q < kSegSlots; ++q) {
                 uint64_t expected = 0;
                 if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                    reinterpret_cast<uint4 *>(s_cnt)[s] =
-                        make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
+                    reinterpret_cast<uint4 *>(s_cnt)[s] = cv;
                     break;
                 }
                 s = (s + 1) & (kSegSlots - 1);
@@ -890,12 +900,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             const uint64_t mask = __ballot(tagv != 0);
             if (tagv) {
                 const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-                uint64_t *e = seg + (uint64_t)(out + rank) * EW;
-                const uint4 c = reinterpret_cast<const uint4 *>(s_cnt)[s];
-                e[0] = tagv;
-                e[1] = (uint64_t)c.x | ((uint64_t)c.y << 32);
-                e[2] = (uint64_t)c.z | ((uint64_t)c.w << 32);
-                if (EW == 4) e[3] = 0;
+                seg[out + rank] = tagv;
+                seg_counts(seg)[out + rank] = reinterpret_cast<const uint4 *>(s_cnt)[s];
                 s_key[s] = 0;
                 reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
             }
@@ -927,11 +933,8 @@ __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t
         for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
             const uint64_t idx = base + e;
             if (idx >= ocap) break;
-            const uint64_t *w = seg + (uint64_t)e * EW;
-            const uint64_t c01 = w[1], c23 = w[2];
-            okeys[idx] = key_of_image(w[0] & ~kOccupied);
-            *reinterpret_cast<uint4 *>(ocnt + 4 * idx) =
-                make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
+            okeys[idx] = key_of_image(seg[e] & ~kOccupied);
+            *reinterpret_cast<uint4 *>(ocnt + 4 * idx) = seg_counts(seg)[e];
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_n = seg_off[parts];

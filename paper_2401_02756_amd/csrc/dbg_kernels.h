@@ -23,8 +23,9 @@
 // Direct build: the entries are the open-addressing slots themselves (0 =
 // empty, so a zero fill empties the table).  Binned build: the table is cut
 // into segments of kSegSlots entries, and segment s holds its vertices packed
-// at entries [0, seg_count[s]) (the hash slots live in LDS only while the
-// segment is being built).
+// at [0, seg_count[s]), stored as two arrays: kSegSlots key words, then
+// kSegSlots groups of four counters (the hash slots live in LDS only while
+// the segment is being built).
 #pragma once
 
 #include <hip/hip_runtime.h>
