@@ -466,14 +466,14 @@ def main() -> int:
         ms = float(np.median(t[1:])) * 1e3
         return {"ms": round(ms, 3), "contigs": n, "bases": ln, "vertices_per_s": round(V / ms * 1e3, 1)}
 
-    def long_k_rate(k: int, steps: int = 5) -> dict:
-        """The same reads at long k (two-word keys, direct build, 32-byte
-        entries): whole step (reset, build, extraction) and build kernel."""
+    def long_k_rate(k: int, binned: bool, steps: int = 5) -> dict:
+        """The same reads at long k (two-word keys, 32-byte entries), binned
+        or direct: whole step (reset, build, extraction) and build pass."""
         kins = int(np.maximum(rs.lengths() - k + 1, 0).sum())
         ev = readsim.expected_vertices(int(rs.meta["genome_len"]), int(rs.meta["read_len"]), rs.n_reads,
                                        float(rs.meta["err"]), k)
-        flags = dbg.F_TIMING | (0 if args.no_graph else dbg.F_GRAPH)
-        g = dbg.Graph(expected_vertices=ev, load_factor=0.5, device=0, flags=flags)
+        flags = dbg.F_TIMING | (0 if args.no_graph else dbg.F_GRAPH) | (dbg.F_BINNED if binned else 0)
+        g = dbg.Graph(expected_vertices=ev, load_factor=args.load_factor if binned else 0.5, device=0, flags=flags)
         g.build_device(d_reads, d_off, k)
         g.sync()
         cap = int(g.stats()["capacity"])
@@ -500,7 +500,8 @@ def main() -> int:
         g.close()
         del d_keys, d_counts
         km = float(np.mean(kern))
-        return {"k": k, "inserts_per_step": kins, "vertices": nv, "capacity": cap,
+        return {"k": k, "mode": "binned" if st["binned"] else "direct", "inserts_per_step": kins,
+                "vertices": nv, "capacity": cap, "load_factor": args.load_factor if binned else 0.5,
                 "entry_bytes": st["entry_bytes"], "ms_per_step": round(dt * 1e3, 3),
                 "value": round(kins / dt / 1e9, 4), "build_ms": round(km, 4),
                 "build_ginserts_s": round(kins / (km * 1e-3) / 1e9, 4)}
@@ -624,8 +625,10 @@ def main() -> int:
         log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
 
     if not args.no_long_k:
-        line["long_k"] = long_k_rate(args.long_k)
+        line["long_k"] = long_k_rate(args.long_k, True)
         log("long k %s" % json.dumps(line["long_k"]))
+        line["long_k"]["compare_direct"] = long_k_rate(args.long_k, False)
+        log("long k direct %s" % json.dumps(line["long_k"]["compare_direct"]))
 
     line["contigs"] = contig_rate()
     log("contigs %s" % json.dumps(line["contigs"]))

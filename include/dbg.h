@@ -65,9 +65,9 @@ extern "C" {
 #define DBG_F_TIMING 0x2u  /* time each build kernel with HIP events */
 #define DBG_F_ENTRY32 0x4u /* 32-byte table entries (default 24 bytes) */
 #define DBG_F_BINNED 0x8u  /* binned build: records partitioned by table segment,
-                              claimed and counted in LDS (k <= 31; a graph whose
-                              first build has k >= 32 falls back to the direct
-                              build) */
+                              claimed and counted in LDS (k <= 31, and 33 <= k <= 63
+                              with two-word records; a graph whose first build has
+                              k = 32 or k = 64 falls back to the direct build) */
 #define DBG_F_GRAPH 0x10u  /* capture each build pass as HIP graphs on first use of
                               its size class and replay them afterwards */
 
@@ -128,7 +128,8 @@ int dbg_create(const dbg_config *cfg, dbg_graph **out);
  * after the device work and the status readback.  Builds on one handle
  * accumulate (counts add), and all must use the same k.  2 <= k <= 64; the
  * first build with k > 32 re-allocates the table with 32-byte entries (two
- * key words) and builds it directly (no binned mode, no wavefront merging).
+ * key words); binned graphs stay binned up to k = 63, and direct builds of
+ * long k do not merge within a wavefront.
  * Errors: DBG_E_INVAL (NULL pointers, decreasing offsets), DBG_E_K,
  * DBG_E_BASE, DBG_E_RANGE -- in all of these nothing was modified;
  * DBG_E_FULL (counts are partial, handle poisoned), DBG_E_NOMEM,
@@ -162,7 +163,8 @@ int dbg_sync(dbg_graph *g);
 int dbg_extract(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap,
                 uint64_t *n_vertices);
 
-/* Same into device buffers d_keys (cap entries, 2 * cap for k > 32) and d_counts (4 * cap),
+/* Same into device buffers d_keys (cap entries, 2 * cap for k > 32) and d_counts (4 * cap,
+ * 16-byte aligned: a vertex's four counters are stored with one 16-byte write),
  * stream-ordered up to the vertex count, which the call reads back
  * (synchronising on the stream). */
 int dbg_extract_device(dbg_graph *g, uint64_t *d_keys, uint32_t *d_counts, uint64_t cap,

@@ -163,10 +163,10 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
     if (g->xn.reserve(8) != hipSuccess) return DBG_E_DEVICE;
     uint64_t found = 0;
     e = dbgk::launch_fill_zero(g->xn.as<uint64_t>(), 1, s);
-    if (e == hipSuccess && kw == 2)
+    if (e == hipSuccess && kw == 2 && !g->binned)
         e = dbgk::launch_extract_wide(g->table.as<uint64_t>(), g->cap, okeys, ocnt, V, g->xn.as<uint64_t>(), s);
     else if (e == hipSuccess && g->binned)
-        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, g->parts,
+        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, (uint32_t)kw, g->parts,
                                         g->seg_count.as<uint32_t>(), g->seg_off.as<uint64_t>(),
                                         g->seg_partials.as<uint64_t>(), g->seg_len.as<uint64_t>(), okeys,
                                         ocnt, V, g->xn.as<uint64_t>(), g->device, s);

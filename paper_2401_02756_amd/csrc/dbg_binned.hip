@@ -72,6 +72,38 @@ __device__ __forceinline__ uint64_t key_of_image(uint64_t x) {
     return (x * kKeyMulInv) & kKey60;
 }
 
+// Long keys (33 <= k <= 63, so K < 2^124) as (kh = K >> 64 < 2^60, kl):
+// two Feistel rounds give the image (ih < 2^60, il): il = kl ^ mix64(kh),
+// then ih = kh ^ (il * kWideMul) >> 4.  ih takes the place of a short key's
+// image (its top bits are the segment digits) and il's low bits are the
+// home slot; each round undoes itself given the other half.
+constexpr uint64_t kWideMul = 0xD1B54A32D192ED03ull;  // odd
+
+__device__ __forceinline__ void wide_image(uint64_t kh, uint64_t kl, uint64_t &ih, uint64_t &il) {
+    il = kl ^ mix64(kh);
+    ih = kh ^ ((il * kWideMul) >> 4);
+}
+
+__device__ __forceinline__ void wide_key(uint64_t ih, uint64_t il, uint64_t &kh, uint64_t &kl) {
+    kh = ih ^ ((il * kWideMul) >> 4);
+    kl = il ^ mix64(kh);
+}
+
+// A window record: RW = 1, one word image << 3 | sink << 2 | letter; RW = 2
+// (long keys), that word built from ih, then il.  Both start with the word
+// that carries the segment digits and the flags.
+template <uint32_t RW> struct RecOf;
+template <> struct RecOf<1> {
+    using T = uint64_t;
+    static __device__ __forceinline__ uint64_t head(uint64_t r) { return r; }
+    static __device__ __forceinline__ uint64_t none() { return ~0ull; }
+};
+template <> struct RecOf<2> {
+    using T = ulonglong2;
+    static __device__ __forceinline__ uint64_t head(ulonglong2 r) { return r.x; }
+    static __device__ __forceinline__ ulonglong2 none() { return make_ulonglong2(~0ull, 0); }
+};
+
 // Top 32 bits of an image: the digits of its segment.
 __device__ __forceinline__ uint32_t image_top(uint64_t x) { return (uint32_t)(x >> 28); }
 
@@ -86,11 +118,16 @@ __device__ __forceinline__ uint32_t child_of(uint32_t top, uint32_t d1, uint32_t
 // A segment of a binned table is kSegSlots entries of EW words, stored as
 // arrays: the image words (image | kOccupied) of its vertices, packed at
 // [0, seg_count), then their four counters (16 bytes each); with 32-byte
-// entries the last quarter is unused.  Each is written and read by
+// entries of short keys the last quarter is unused.  Each is written and read by
 // consecutive lanes as one contiguous run.
-__device__ __forceinline__ uint4 *seg_counts(uint64_t *seg) { return reinterpret_cast<uint4 *>(seg + kSegSlots); }
+// Long keys: the words ih | kOccupied, then il, then the counters.
+template <uint32_t RW = 1>
+__device__ __forceinline__ uint4 *seg_counts(uint64_t *seg) {
+    return reinterpret_cast<uint4 *>(seg + RW * kSegSlots);
+}
+template <uint32_t RW = 1>
 __device__ __forceinline__ const uint4 *seg_counts(const uint64_t *seg) {
-    return reinterpret_cast<const uint4 *>(seg + kSegSlots);
+    return reinterpret_cast<const uint4 *>(seg + RW * kSegSlots);
 }
 
 // Home slot inside a segment: the image's low bits.
@@ -350,10 +387,10 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 // ---------------------------------------------------------------- pass 1
 
 // Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max],
-// s_rec[kBinTile], s_bin[kBinTile] when scattering).
-__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter) {
+// s_rec[kBinTile] and, for one-word records, s_bin[kBinTile] when scattering).
+__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + 8 * kBinTile + 2 * kBinTile;
+    if (scatter) b += align16(8 * d1_max) + 8 * rw * kBinTile + (rw == 1 ? 2 * kBinTile : 0);
     return b;
 }
 
@@ -362,9 +399,10 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter)
 // so a window costs a few shifts instead of a search and two loads.  The
 // next read's bases follow the current read's in the packed array, so a
 // window that starts another read (k - 2 bases further on) is found in the
-// staged reads and mostly stays inside the three words.
-template <bool SCATTER>
-__global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_bin(const PassArgs *__restrict__ args,
+// staged reads and mostly stays inside the three words.  Long keys (RW = 2)
+// take each window's 128 bits from the packed array directly.
+template <bool SCATTER, uint32_t RW>
+__global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -372,15 +410,17 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
                                                   const BinTotals *__restrict__ tot,
                                                   uint32_t *__restrict__ hist1,
                                                   const uint64_t *__restrict__ scan1,
-                                                  uint64_t *__restrict__ rec1,
+                                                  uint64_t *__restrict__ rec1w,
                                                   const uint64_t *__restrict__ tile_read1,
                                                   uint32_t d1_max) {
+    using R = typename RecOf<RW>::T;
     __shared__ ReadStage S;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (d1_max + 1)));
-    uint64_t *s_rec = s_gbase + d1_max;
-    uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);
+    R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (d1_max + 1)) + align16(8 * d1_max));  // 16-byte aligned
+    uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);  // RW = 1 only
+    R *rec1 = reinterpret_cast<R *>(rec1w);
     const uint32_t tid = threadIdx.x;
     const uint32_t m = args->m;
     const uint64_t *__restrict__ off = args->off;
@@ -399,7 +439,7 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
         for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = SCATTER ? j << 12 : 0u;
         stage_reads(S, ws, off, off0, tile_read1[t], in.read_end);
 
-        uint64_t rec[kBinPerThread];
+        R rec[kBinPerThread];
         uint32_t tag[kBinPerThread];  // scatter: bucket << 12 | rank (bucket d1: past the end)
         const uint32_t j0 = tid * kBinPerThread;
 #pragma unroll
@@ -409,7 +449,12 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
             ReadCursor rp = first_read(S, ws, off, off0, in.read_end, w);
             uint64_t p = w + rp.delta;
             uint64_t wbase = p >> 5;
-            uint64_t a = packed[wbase], b = packed[wbase + 1], c = packed[wbase + 2];
+            uint64_t a = 0, b = 0, c = 0;
+            if (RW == 1) {
+                a = packed[wbase];
+                b = packed[wbase + 1];
+                c = packed[wbase + 2];
+            }
 #pragma unroll
             for (uint32_t q = 0; q < kBinPerThread; ++q) {
                 if (j0 + q >= n_in) break;
@@ -419,17 +464,29 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
                     // the words must hold this and the remaining windows' first
                     // bases at offsets below 64 (without a crossing a thread's
                     // offsets stay below 32 + kBinPerThread)
-                    if (p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
+                    if (RW == 1 && p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
                         wbase = p >> 5;
                         a = packed[wbase];
                         b = packed[wbase + 1];
                         c = packed[wbase + 2];
                     }
                 }
-                const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
-                const uint64_t img = key_image(v >> kshift);
-                rec[q] = (img << 3) | (w + 1 == rp.wr1 ? 4u : 0u) | ((uint32_t)(v >> lshift) & 3u);
-                const uint32_t bk = bucket_of(image_top(img), d1);
+                const uint64_t sink = w + 1 == rp.wr1 ? 4u : 0u;
+                uint64_t head;
+                if constexpr (RW == 1) {
+                    const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
+                    head = (key_image(v >> kshift) << 3) | sink | ((uint32_t)(v >> lshift) & 3u);
+                    rec[q] = head;
+                } else {
+                    uint64_t x0, x1, kh, kl, ih, il;
+                    uint32_t letter;
+                    bases128_at(packed, p, x0, x1);
+                    wide_window(x0, x1, in.k - 1, kh, kl, letter);
+                    wide_image(kh, kl, ih, il);
+                    head = (ih << 3) | sink | letter;
+                    rec[q] = make_ulonglong2(head, il);
+                }
+                const uint32_t bk = bucket_of(image_top(head >> 3), d1);
                 if (SCATTER) {
                     tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
                 } else {
@@ -455,10 +512,14 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(6))) 
             if (bk == d1) continue;  // past the tile's end
             const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
             s_rec[pos] = rec[q];
-            s_bin[pos] = (uint16_t)bk;
+            if (RW == 1) s_bin[pos] = (uint16_t)bk;
         }
         __syncthreads();
-        for (uint32_t j = tid; j < n_in; j += blockDim.x) rec1[s_gbase[s_bin[j]] + j] = s_rec[j];
+        for (uint32_t j = tid; j < n_in; j += blockDim.x) {
+            const R r = s_rec[j];
+            const uint32_t bk = RW == 1 ? s_bin[j] : bucket_of(image_top(RecOf<RW>::head(r) >> 3), d1);
+            rec1[s_gbase[bk] + j] = r;
+        }
         __syncthreads();
     }
 }
@@ -570,22 +631,23 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 }
 
 // Dynamic LDS of the pass-2 kernels: s_cnt[fan_max] (+ s_gbase[fan_max],
-// s_rec[kRefTile], s_child[kRefTile] when scattering).
-__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter) {
+// s_rec[kRefTile] and, for one-word records, s_child[kRefTile] when
+// scattering).
+__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1) {
     uint32_t b = align16(4 * (fan_max + 1));
-    if (scatter) b += align16(8 * fan_max) + 8 * kRefTile + 2 * kRefTile;
+    if (scatter) b += align16(8 * fan_max) + 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0);
     return b;
 }
 
 constexpr uint32_t kRefMaxPer = (kMaxFan + kRefBlock - 1) / kRefBlock;  // segments per thread in a scan
 
 // Load a pass-2 tile's records.
-__device__ __forceinline__ void refine_load(const RefTile &T, const uint64_t *__restrict__ rec1,
-                                            uint64_t (&rec)[kRefPerThread]) {
+template <typename R>
+__device__ __forceinline__ void refine_load(const RefTile &T, const R *__restrict__ rec1, R (&rec)[kRefPerThread]) {
 #pragma unroll
     for (uint32_t it = 0; it < kRefPerThread; ++it) {
         const uint32_t j = it * blockDim.x + threadIdx.x;
-        rec[it] = j < T.n ? rec1[T.r0 + j] : 0;
+        rec[it] = j < T.n ? rec1[T.r0 + j] : R{};
     }
 }
 
@@ -595,23 +657,26 @@ __device__ __forceinline__ void refine_load(const RefTile &T, const uint64_t *__
 // loaded while this one is written; a scatter tile's global bases load while
 // its records are counted.  So a tile's global loads never wait on the
 // previous tile.
-template <bool SCATTER>
+template <bool SCATTER, uint32_t RW>
 __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
                                                      const RefTile *__restrict__ tile2,
-                                                     const uint64_t *__restrict__ rec1,
+                                                     const uint64_t *__restrict__ rec1w,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
-                                                     uint64_t *__restrict__ rec2, uint32_t fan_max) {
+                                                     uint64_t *__restrict__ rec2w, uint32_t fan_max) {
+    using R = typename RecOf<RW>::T;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (fan_max + 1)));
-    uint64_t *s_rec = s_gbase + fan_max;
-    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);
+    R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (fan_max + 1)) + align16(8 * fan_max));  // 16-byte aligned
+    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);  // RW = 1 only
+    const R *rec1 = reinterpret_cast<const R *>(rec1w);
+    R *rec2 = reinterpret_cast<R *>(rec2w);
     const uint32_t tid = threadIdx.x;
     XcdTiles xt(tot->tiles2);
     if (!xt.valid()) return;
     RefTile T = tile2[xt.next];
-    uint64_t rec[kRefPerThread];
+    R rec[kRefPerThread];
     refine_load(T, rec1, rec);
     for (;;) {
         xt.advance();
@@ -636,7 +701,7 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
 #pragma unroll
         for (uint32_t it = 0; it < kRefPerThread; ++it) {
             const uint32_t j = it * blockDim.x + tid;
-            const uint32_t c = j < T.n ? child_of(image_top(rec[it] >> 3), d1, fan) : fan;
+            const uint32_t c = j < T.n ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
             if (SCATTER)
                 tag[it] = lds_add32(&s_cnt[c], 1u);
             else
@@ -656,11 +721,15 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
                 if (c == fan) continue;  // past the tile's end
                 const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
                 s_rec[pos] = rec[it];
-                s_child[pos] = (uint16_t)c;
+                if (RW == 1) s_child[pos] = (uint16_t)c;
             }
             if (more) refine_load(N, rec1, rec);
             __syncthreads();
-            for (uint32_t j = tid; j < T.n; j += blockDim.x) rec2[s_gbase[s_child[j]] + j] = s_rec[j];
+            for (uint32_t j = tid; j < T.n; j += blockDim.x) {
+                const R r = s_rec[j];
+                const uint32_t c = RW == 1 ? s_child[j] : child_of(image_top(RecOf<RW>::head(r) >> 3), d1, fan);
+                rec2[s_gbase[c] + j] = r;
+            }
             __syncthreads();
         }
         if (!more) break;
@@ -756,6 +825,53 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
     return true;
 }
 
+// Long keys: a slot's key is two LDS words, hi (ih | kOccupied) and lo (il).
+// A slot is claimed by the CAS of hi; the claimer then stores lo and sets
+// kReady in hi.  A lane that finds its own hi without kReady has met a claim
+// in flight and reads the slot again (the claimer waits on nothing between
+// its CAS and those stores); with kReady set, lo decides whether the slot
+// is this key's.  Returns the slot, or kSegSlots when none is found.
+constexpr uint64_t kReady = 1ull << 62;
+constexpr uint32_t kMaxInFlightReads = 1u << 20;
+
+__device__ __forceinline__ uint32_t wide_slot(uint64_t tag, uint64_t lo, uint64_t *s_hi, uint64_t *s_lo,
+                                              bool &claimed) {
+    uint32_t s = seg_home(lo), waits = 0;
+    for (uint32_t q = 0;;) {
+        uint64_t cur = __hip_atomic_load(&s_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == 0) {
+            uint64_t expected = 0;
+            __hip_atomic_compare_exchange_strong(&s_hi[s], &expected, tag, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (expected == 0) {
+                __hip_atomic_store(&s_lo[s], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(&s_hi[s], tag | kReady, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                claimed = true;
+                return s;
+            }
+            cur = expected;
+        }
+        if ((cur & ~kReady) == tag) {
+            if (!(cur & kReady)) {  // claim in flight: read the slot again
+                if (++waits > kMaxInFlightReads) return kSegSlots;
+                continue;
+            }
+            if (lds_load64(&s_lo[s]) == lo) return s;
+        }
+        if (++q == kSegSlots) return kSegSlots;
+        s = (s + 1) & (kSegSlots - 1);
+    }
+}
+
+__device__ __forceinline__ bool reduce_record(ulonglong2 rec, uint64_t *s_key, uint32_t *s_cnt, uint64_t &claims) {
+    bool claimed = false;
+    const uint32_t s = wide_slot((rec.x >> 3) | kOccupied, rec.y, s_key, s_key + kSegSlots, claimed);
+    if (s == kSegSlots) return false;
+    claims += claimed ? 1u : 0u;
+    if (!(rec.x & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec.x & 3)], 1u);
+    return true;
+}
+
 // One workgroup per segment.  The segment's hash slots live in LDS only: the
 // vertices the table already holds (packed at entries [0, seg_count)) are
 // re-inserted, every record of the segment is found-or-claimed and counted
@@ -769,18 +885,21 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
 // segment's first records are loaded while this one is written back.
 constexpr uint32_t kStartsChunk = 256;  // segment starts staged per LDS refill
 
-template <uint32_t EW>
+template <uint32_t EW, uint32_t RW>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restrict__ args,
                                                         const Instance *__restrict__ inst,
                                                         const uint64_t *__restrict__ pstart,
-                                                        const uint64_t *__restrict__ rec2,
+                                                        const uint64_t *__restrict__ rec2w,
                                                         InstStatus *st) {
+    using R = typename RecOf<RW>::T;
+    const R *rec2 = reinterpret_cast<const R *>(rec2w);
+    static_assert(RW == 1 || EW == 4, "long keys take 32-byte entries");
     const uint32_t m = args->m;
     const uint64_t parts_total = args->parts_total;
     static_assert(kSegSlots % kReduceBlock == 0 && kReduceBlock % 64 == 0, "slot ranges per wavefront");
     constexpr uint32_t kWaves = kReduceBlock / 64;
     constexpr uint32_t kWaveSlots = kSegSlots / kWaves;  // slots compacted by one wavefront
-    __shared__ uint64_t s_key[kSegSlots];
+    __shared__ uint64_t s_key[kSegSlots * RW];  // RW = 2: hi words, then lo words
     __shared__ __align__(16) uint32_t s_cnt[kSegSlots * 4];
     __shared__ uint64_t s_start[kStartsChunk + 2];
     __shared__ uint32_t s_wave_n[kWaves];
@@ -795,6 +914,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         s_key[s] = 0;
         reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
     }
+    const R kNone = RecOf<RW>::none();
     // s_start[j] = pstart[c0 + j] for j <= kStartsChunk + 1 (within range)
     uint64_t c0 = gp0;
     auto stage_starts = [&]() {
@@ -808,13 +928,13 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     bool skip = __hip_atomic_load(&st[cur_inst].err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kSkipMask;
     uint64_t my_claims = 0;  // claims of cur_inst by this thread, not yet flushed
 
-    uint64_t rv[kReducePrefetch];  // first records of the current segment
+    R rv[kReducePrefetch];  // first records of the current segment
     {
         const uint64_t a = s_start[0], z = s_start[1];
 #pragma unroll
         for (uint32_t c = 0; c < kReducePrefetch; ++c) {
             const uint64_t r = a + (uint64_t)c * blockDim.x + tid;
-            rv[c] = r < z ? rec2[r] : kNoRecord;
+            rv[c] = r < z ? rec2[r] : kNone;
         }
     }
     for (uint64_t gp = gp0; gp < gp1; ++gp) {
@@ -842,7 +962,13 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             // distinct keys: each claims its own slot, and nobody else touches
             // that slot's counters before the next barrier
             const uint64_t tagv = seg[e];
-            const uint4 cv = seg_counts(seg)[e];
+            const uint4 cv = seg_counts<RW>(seg)[e];
+            if constexpr (RW == 2) {
+                bool claimed = false;
+                const uint32_t s = wide_slot(tagv, seg[kSegSlots + e], s_key, s_key + kSegSlots, claimed);
+                if (s < kSegSlots) reinterpret_cast<uint4 *>(s_cnt)[s] = cv;
+                continue;
+            }
             uint32_t s = seg_home(tagv);
             for (uint32_t q = 0; q < kSegSlots; ++q) {
                 uint64_t expected = 0;
@@ -859,13 +985,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         for (uint64_t base = a;;) {
 #pragma unroll
             for (uint32_t c = 0; c < kReducePrefetch; ++c)
-                if (rv[c] != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims)) full = true;
+                if (RecOf<RW>::head(rv[c]) != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims))
+                    full = true;
             base += (uint64_t)blockDim.x * kReducePrefetch;
             if (base >= z) break;
 #pragma unroll
             for (uint32_t c = 0; c < kReducePrefetch; ++c) {
                 const uint64_t r = base + (uint64_t)c * blockDim.x + tid;
-                rv[c] = r < z ? rec2[r] : kNoRecord;
+                rv[c] = r < z ? rec2[r] : kNone;
             }
         }
         // the next segment's first records load while this one is written back
@@ -874,7 +1001,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
 #pragma unroll
             for (uint32_t c = 0; c < kReducePrefetch; ++c) {
                 const uint64_t r = na + (uint64_t)c * blockDim.x + tid;
-                rv[c] = r < nz ? rec2[r] : kNoRecord;
+                rv[c] = r < nz ? rec2[r] : kNone;
             }
         }
         if (full) atomic_or_u32(&st[cur_inst].err, kErrFull);
@@ -900,8 +1027,9 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             const uint64_t mask = __ballot(tagv != 0);
             if (tagv) {
                 const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-                seg[out + rank] = tagv;
-                seg_counts(seg)[out + rank] = reinterpret_cast<const uint4 *>(s_cnt)[s];
+                seg[out + rank] = tagv & ~kReady;
+                if (RW == 2) seg[kSegSlots + out + rank] = s_key[kSegSlots + s];
+                seg_counts<RW>(seg)[out + rank] = reinterpret_cast<const uint4 *>(s_cnt)[s];
                 s_key[s] = 0;
                 reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
             }
@@ -919,7 +1047,7 @@ constexpr uint32_t kExtractSegBlock = 256;
 
 // The vertices of segment gp (packed at its first entries) go to
 // [seg_off[gp], seg_off[gp + 1]).
-template <uint32_t EW>
+template <uint32_t EW, uint32_t RW>
 __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t *__restrict__ table,
                                                                  uint32_t parts,
                                                                  const uint64_t *__restrict__ seg_off,
@@ -933,8 +1061,15 @@ __global__ __launch_bounds__(kExtractSegBlock) void k_extract_seg(const uint64_t
         for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
             const uint64_t idx = base + e;
             if (idx >= ocap) break;
-            okeys[idx] = key_of_image(seg[e] & ~kOccupied);
-            *reinterpret_cast<uint4 *>(ocnt + 4 * idx) = seg_counts(seg)[e];
+            if constexpr (RW == 1) {
+                okeys[idx] = key_of_image(seg[e] & ~kOccupied);
+            } else {  // two key words per record: K >> 64, K mod 2^64
+                uint64_t kh, kl;
+                wide_key(seg[e] & ~kOccupied, seg[kSegSlots + e], kh, kl);
+                okeys[2 * idx] = kh;
+                okeys[2 * idx + 1] = kl;
+            }
+            *reinterpret_cast<uint4 *>(ocnt + 4 * idx) = seg_counts<RW>(seg)[e];
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_n = seg_off[parts];
@@ -958,6 +1093,69 @@ uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint
     return (uint32_t)std::max<uint64_t>(1, g);
 }
 
+// The binned pass for records of RW words (enqueue only).
+template <uint32_t RW>
+hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint64_t *packed, const uint64_t *ws,
+                         InstStatus *st, const BinBuffers &bb, hipStream_t s, hipEvent_t *marks) {
+    hipError_t e;
+    // pass 1
+    const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW), lb1 = bin_lds_bytes(bb.d1_max, true, RW);
+    const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
+    hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
+                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t nb1 = std::max<uint64_t>((bb.hist1_cap + kFlatChunk - 1) / kFlatChunk, 1);
+    const uint64_t *len1 = &bb.totals->hist1_len;
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, bb.hist1, len1, bb.scan1,
+                       bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
+    hipLaunchKernelGGL((k_bin<true, RW>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
+                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks) (void)hipEventRecord(marks[0], s);
+
+    // pass 2
+    hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
+                       bb.buckets);
+    {
+        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
+        hipLaunchKernelGGL(k_tile_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.tile2,
+                           bb.tiles2_cap);
+    }
+    const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW), lr1 = ref_lds_bytes(bb.fan_max, true, RW);
+    const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
+    hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.tile2, bb.rec1,
+                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t nb2 = std::max<uint64_t>((bb.hist2_cap + kFlatChunk - 1) / kFlatChunk, 1);
+    const uint64_t *len2 = &bb.totals->hist2_len;
+    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, bb.hist2, len2, bb.scan2,
+                       bb.partials);
+    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
+    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
+    hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.tile2, bb.rec1,
+                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // segment starts and the reduction
+    const uint64_t P = bb.parts_cap;
+    const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, args, inst, bb.plan, bb.buckets, bb.scan2,
+                       bb.totals, bb.pstart);
+    if (marks) (void)hipEventRecord(marks[1], s);
+    // every instance of a binned launch has the same entry width
+    const uint32_t gr = bb.grid_reduce;
+    if (RW == 2)
+        hipLaunchKernelGGL((k_reduce<4, 2>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
+    else if (bb.entry_words == 4)
+        hipLaunchKernelGGL((k_reduce<4, 1>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
+    else
+        hipLaunchKernelGGL((k_reduce<3, 1>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
+    return hipGetLastError();
+}
+
+
 }  // namespace
 
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
@@ -973,71 +1171,35 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
                            bb.tiles1_cap);
     }
 
-    // pass 1
-    const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false), lb1 = bin_lds_bytes(bb.d1_max, true);
-    const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
-    hipLaunchKernelGGL((k_bin<false>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
-                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const uint64_t nb1 = std::max<uint64_t>((bb.hist1_cap + kFlatChunk - 1) / kFlatChunk, 1);
-    const uint64_t *len1 = &bb.totals->hist1_len;
-    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, bb.hist1, len1, bb.scan1,
-                       bb.partials);
-    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
-    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
-    hipLaunchKernelGGL((k_bin<true>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
-                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (marks) (void)hipEventRecord(marks[0], s);
-
-    // pass 2
-    hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
-                       bb.buckets);
-    {
-        const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
-        hipLaunchKernelGGL(k_tile_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.tile2,
-                           bb.tiles2_cap);
-    }
-    const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false), lr1 = ref_lds_bytes(bb.fan_max, true);
-    const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
-    hipLaunchKernelGGL((k_refine<false>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.tile2, bb.rec1,
-                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const uint64_t nb2 = std::max<uint64_t>((bb.hist2_cap + kFlatChunk - 1) / kFlatChunk, 1);
-    const uint64_t *len2 = &bb.totals->hist2_len;
-    hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, bb.hist2, len2, bb.scan2,
-                       bb.partials);
-    hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
-    hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
-    hipLaunchKernelGGL((k_refine<true>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.tile2, bb.rec1,
-                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-
-    // segment starts and the reduction
-    const uint64_t P = bb.parts_cap;
-    const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, args, inst, bb.plan, bb.buckets, bb.scan2,
-                       bb.totals, bb.pstart);
-    if (marks) (void)hipEventRecord(marks[1], s);
-    // every instance of a binned launch has the same entry width
-    const uint32_t gr = bb.grid_reduce;
-    if (bb.entry_words == 4)
-        hipLaunchKernelGGL((k_reduce<4>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
-    else
-        hipLaunchKernelGGL((k_reduce<3>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
-    return hipGetLastError();
+    if (bb.rec_words == 2) return launch_passes<2>(args, inst, packed, ws, st, bb, s, marks);
+    return launch_passes<1>(args, inst, packed, ws, st, bb, s, marks);
 }
+
+namespace {
+template <uint32_t RW>
+void grids_for(int device, BinBuffers &bb) {
+    bb.grid_bin_count =
+        occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, false, RW));
+    bb.grid_bin_scatter =
+        occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true, RW));
+    bb.grid_ref_count =
+        occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, false, RW));
+    bb.grid_ref_scatter =
+        occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, true, RW));
+    bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2>, device, kReduceBlock, bb.parts_cap, 0)
+                   : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1>, device, kReduceBlock, bb.parts_cap, 0)
+                                         : occupancy_grid(k_reduce<3, 1>, device, kReduceBlock, bb.parts_cap, 0);
+}
+}  // namespace
 
 void binned_grids(int device, BinBuffers &bb) {
-    bb.grid_bin_count = occupancy_grid(k_bin<false>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, false));
-    bb.grid_bin_scatter = occupancy_grid(k_bin<true>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true));
-    bb.grid_ref_count = occupancy_grid(k_refine<false>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, false));
-    bb.grid_ref_scatter = occupancy_grid(k_refine<true>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, true));
-    bb.grid_reduce = bb.entry_words == 4 ? occupancy_grid(k_reduce<4>, device, kReduceBlock, bb.parts_cap, 0)
-                                         : occupancy_grid(k_reduce<3>, device, kReduceBlock, bb.parts_cap, 0);
+    if (bb.rec_words == 2)
+        grids_for<2>(device, bb);
+    else
+        grids_for<1>(device, bb);
 }
 
-hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t parts,
+hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t key_words, uint32_t parts,
                                  const uint32_t *seg_count, uint64_t *seg_off, uint64_t *partials,
                                  uint64_t *len, uint64_t *out_keys, uint32_t *out_counts,
                                  uint64_t out_cap, uint64_t *out_n, int device, hipStream_t s) {
@@ -1047,13 +1209,18 @@ hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, ui
                        partials);
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, partials, nb, len, seg_off);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb), dim3(kFlatBlock), 0, s, len, seg_off, partials);
-    if (entry_words == 4) {
-        const uint32_t g = occupancy_grid(k_extract_seg<4>, device, kExtractSegBlock, parts, 0);
-        hipLaunchKernelGGL((k_extract_seg<4>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
+    if (key_words == 2) {
+        if (entry_words != 4) return hipErrorInvalidValue;
+        const uint32_t g = occupancy_grid(k_extract_seg<4, 2>, device, kExtractSegBlock, parts, 0);
+        hipLaunchKernelGGL((k_extract_seg<4, 2>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
+                           out_keys, out_counts, out_cap, out_n);
+    } else if (entry_words == 4) {
+        const uint32_t g = occupancy_grid(k_extract_seg<4, 1>, device, kExtractSegBlock, parts, 0);
+        hipLaunchKernelGGL((k_extract_seg<4, 1>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
                            out_keys, out_counts, out_cap, out_n);
     } else {
-        const uint32_t g = occupancy_grid(k_extract_seg<3>, device, kExtractSegBlock, parts, 0);
-        hipLaunchKernelGGL((k_extract_seg<3>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
+        const uint32_t g = occupancy_grid(k_extract_seg<3, 1>, device, kExtractSegBlock, parts, 0);
+        hipLaunchKernelGGL((k_extract_seg<3, 1>), dim3(g), dim3(kExtractSegBlock), 0, s, table, parts, seg_off,
                            out_keys, out_counts, out_cap, out_n);
     }
     return hipGetLastError();

@@ -330,7 +330,7 @@ int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
     uint64_t *xn = cs->xn.as<uint64_t>();
     e = dbgk::launch_fill_zero(xn, 1, s);
     if (e == hipSuccess && g->binned)
-        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, g->parts, g->seg_count.as<uint32_t>(),
+        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, 1, g->parts, g->seg_count.as<uint32_t>(),
                                         g->seg_off.as<uint64_t>(), g->seg_partials.as<uint64_t>(),
                                         g->seg_len.as<uint64_t>(), cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(),
                                         V, xn, g->device, s);

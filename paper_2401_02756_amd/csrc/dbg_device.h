@@ -67,6 +67,33 @@ __device__ __forceinline__ uint64_t bases_at(const uint64_t *__restrict__ packed
     return (hi << sh) | (lo >> (64 - sh));
 }
 
+// 64 bases from base position p, first base in bits 63..62 of x0 (reads
+// up to three words: the packed array has two words of padding).
+__device__ __forceinline__ void bases128_at(const uint64_t *__restrict__ packed, uint64_t p,
+                                            uint64_t &x0, uint64_t &x1) {
+    const uint64_t wi = p >> 5;
+    const uint32_t sh = (uint32_t)(p & 31) * 2;
+    const uint64_t w0 = packed[wi], w1 = packed[wi + 1];
+    if (sh == 0) {
+        x0 = w0;
+        x1 = w1;
+        return;
+    }
+    const uint64_t w2 = packed[wi + 2];
+    x0 = (w0 << sh) | (w1 >> (64 - sh));
+    x1 = (w1 << sh) | (w2 >> (64 - sh));
+}
+
+// The (k-1)-mer K of a window of 32 < k <= 64 as (K >> 64, K mod 2^64), and
+// the letter after it, from the window's 128 bits x0:x1.
+__device__ __forceinline__ void wide_window(uint64_t x0, uint64_t x1, uint32_t km1, uint64_t &khi,
+                                            uint64_t &klo, uint32_t &letter) {
+    const uint32_t r = 128 - 2 * km1;  // 2 .. 64: the key ends r bits above x1's end
+    klo = r == 64 ? x0 : (x1 >> r) | (x0 << (64 - r));
+    khi = r == 64 ? 0 : x0 >> r;
+    letter = (uint32_t)(x1 >> (r - 2)) & 3u;
+}
+
 __device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t v) {
     const uint32_t lane = threadIdx.x & 63;
 #pragma unroll

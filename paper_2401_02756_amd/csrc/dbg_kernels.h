@@ -164,7 +164,7 @@ struct BinBuffers {     // device scratch of one binned pass
     uint32_t *hist2;          // hist2_cap
     uint64_t *scan2;          // hist2_cap + 1
     uint64_t *partials;       // for the flat scans
-    uint64_t *rec1, *rec2;    // records, windows_cap each
+    uint64_t *rec1, *rec2;    // records (rec_words words each), windows_cap each
     uint64_t *pstart;         // parts_total + 1
     uint64_t *tile_read1;     // first read of each pass-1 tile (tiles1_cap)
     RefTile *tile2;           // pass-2 tiles (tiles2_cap)
@@ -172,6 +172,7 @@ struct BinBuffers {     // device scratch of one binned pass
     uint64_t tiles1_cap, tiles2_cap, buckets_cap, parts_cap;
     uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)
     uint32_t entry_words;      // of every instance in the launch
+    uint32_t rec_words;        // record words: 1, or 2 for long keys (33 <= k <= 63)
     // persistent grids (binned_grids fills them; no query happens while a
     // launch is being captured)
     uint32_t grid_bin_count, grid_bin_scatter, grid_ref_count, grid_ref_scatter, grid_reduce;
@@ -235,7 +236,8 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
 // entries and a device word `len` that the call fills with parts), then each
 // segment writes its vertices at its offset (segment order; unspecified
 // order within a segment).  *out_n receives the total on the device.
-hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t parts,
+// key_words = 2: long keys, written as two words per record.
+hipError_t launch_extract_binned(const uint64_t *table, uint32_t entry_words, uint32_t key_words, uint32_t parts,
                                  const uint32_t *seg_count, uint64_t *seg_off, uint64_t *partials,
                                  uint64_t *len, uint64_t *out_keys, uint32_t *out_counts,
                                  uint64_t out_cap, uint64_t *out_n, int device, hipStream_t s);

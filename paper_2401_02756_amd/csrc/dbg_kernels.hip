@@ -570,22 +570,6 @@ constexpr uint64_t kWritten = 1ull << 63;
 constexpr uint64_t kLow63 = kWritten - 1;
 constexpr uint32_t kMaxInFlight = 1u << 20;  // re-reads of one claim in flight
 
-// 64 bases from base position p, first base in bits 63..62 of x0.
-__device__ __forceinline__ void bases128_at(const uint64_t *__restrict__ packed, uint64_t p,
-                                            uint64_t &x0, uint64_t &x1) {
-    const uint64_t wi = p >> 5;
-    const uint32_t sh = (uint32_t)(p & 31) * 2;
-    const uint64_t w0 = packed[wi], w1 = packed[wi + 1];
-    if (sh == 0) {
-        x0 = w0;
-        x1 = w1;
-        return;
-    }
-    const uint64_t w2 = packed[wi + 2];
-    x0 = (w0 << sh) | (w1 >> (64 - sh));
-    x1 = (w1 << sh) | (w2 >> (64 - sh));
-}
-
 __device__ __forceinline__ uint64_t find_or_claim_wide(uint64_t *table, uint64_t cap, uint64_t tag0,
                                                        uint64_t tag1, uint64_t h, bool &claimed,
                                                        uint32_t *err) {
@@ -646,7 +630,6 @@ __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict_
     uint64_t *tab = inst[0].table;
     const uint64_t cap = inst[0].cap;
     const uint32_t km1 = inst[0].k - 1;
-    const uint32_t r = 128 - 2 * km1;  // 2 .. 64: key bits end r bits above the 128-bit window's end
     if (inst[0].prior_inserts + st[0].inserts > 0xffffffffull) {
         if (tid == 0) atomic_or_u32(&st[0].err, kErrRange);
         return;
@@ -700,12 +683,10 @@ __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict_
                 delta = off[lo] - off0 - ws[lo];
             }
             const bool sink = (w + 1 == wr1);
-            uint64_t x0, x1;
+            uint64_t x0, x1, khi, klo;
+            uint32_t letter;
             bases128_at(packed, w + delta, x0, x1);
-            // K = the top 2 km1 bits of x0:x1; the letter follows it
-            const uint64_t klo = r == 64 ? x0 : (x1 >> r) | (x0 << (64 - r));
-            const uint64_t khi = r == 64 ? 0 : x0 >> r;
-            const uint32_t letter = (uint32_t)(x1 >> (r - 2)) & 3u;
+            wide_window(x0, x1, km1, khi, klo, letter);
             const uint64_t a = (khi << 1) | (klo >> 63);
             const uint64_t tag0 = a | kOccupied, tag1 = (klo & kLow63) | kWritten;
             const uint64_t h = mix64(tag1 ^ mix64(a));
@@ -805,7 +786,8 @@ __global__ __launch_bounds__(kExtractBlock) void k_extract_wide(const uint64_t *
                 const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(table + s * 4);
                 const uint4 c = *reinterpret_cast<const uint4 *>(table + s * 4 + 2);
                 const uint64_t a = e.x & ~kOccupied, b = e.y & kLow63;
-                *reinterpret_cast<ulonglong2 *>(okeys + 2 * idx) = make_ulonglong2(a >> 1, (a << 63) | b);
+                okeys[2 * idx] = a >> 1;
+                okeys[2 * idx + 1] = (a << 63) | b;
                 *reinterpret_cast<uint4 *>(ocnt + 4 * idx) = c;
             }
             ++idx;

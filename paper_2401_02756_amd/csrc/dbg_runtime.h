@@ -140,13 +140,15 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
 struct PassKey {
     int binned = 0;
     int single = 0;
-    int wide = 0;  // one instance with 32 < k <= 64
+    int wide = 0;  // one instance with 32 < k <= 64, direct build
+    uint32_t rw = 1;  // binned record words (2: long keys)
     uint32_t ew = 3;
     uint32_t m_cap = 0, d1_cap = 0, fan_cap = 0;
     uint64_t n_cap = 0, len_cap = 0, parts_cap = 0, buckets_cap = 0;
     dbgk::BuildShape shape{};
     bool operator==(const PassKey &o) const {
-        return binned == o.binned && single == o.single && wide == o.wide && ew == o.ew && m_cap == o.m_cap &&
+        return binned == o.binned && single == o.single && wide == o.wide && rw == o.rw && ew == o.ew &&
+               m_cap == o.m_cap &&
                d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
                parts_cap == o.parts_cap && buckets_cap == o.buckets_cap && shape.block == o.shape.block &&
                shape.wpt == o.shape.wpt && shape.grid == o.shape.grid && shape.merge == o.shape.merge;
@@ -250,6 +252,7 @@ struct Pass {
         bb.d1_max = k.d1_cap;
         bb.fan_max = k.fan_cap;
         bb.entry_words = k.ew;
+        bb.rec_words = k.rw;
         hipError_t e;
         if ((e = grow(bplan, sizeof(dbgk::BinPlan) * k.m_cap)) != hipSuccess ||
             (e = grow(bbuckets, sizeof(dbgk::Bucket) * std::max<uint64_t>(k.buckets_cap, 1))) != hipSuccess ||
@@ -259,7 +262,8 @@ struct Pass {
             (e = grow(hist2, 4 * bb.hist2_cap)) != hipSuccess ||
             (e = grow(scan2, 8 * (bb.hist2_cap + 1))) != hipSuccess ||
             (e = grow(bpartials, 8 * bb.partials_cap)) != hipSuccess ||
-            (e = grow(rec1, 8 * k.len_cap)) != hipSuccess || (e = grow(rec2, 8 * k.len_cap)) != hipSuccess ||
+            (e = grow(rec1, 8 * k.rw * k.len_cap)) != hipSuccess ||
+            (e = grow(rec2, 8 * k.rw * k.len_cap)) != hipSuccess ||
             (e = grow(pstart, 8 * (k.parts_cap + 1))) != hipSuccess ||
             (e = grow(tread1, 8 * bb.tiles1_cap)) != hipSuccess ||
             (e = grow(tbucket2, sizeof(dbgk::RefTile) * bb.tiles2_cap)) != hipSuccess)
@@ -364,6 +368,7 @@ struct Pass {
         k.single = mm == 1 ? 1 : 0;
         k.shape = shape;
         k.wide = (mm == 1 && !binned && host_instances()[0].k > 32) ? 1 : 0;
+        k.rw = (mm == 1 && binned && host_instances()[0].k > 32) ? 2 : 1;  // long keys: one graph at a time
         k.m_cap = (uint32_t)size_class(mm, 1);
         k.n_cap = size_class(n, 1024);
         k.len_cap = size_class(len, 4096);
@@ -587,15 +592,18 @@ inline int ensure_table(dbg_graph *g, uint64_t windows_bound) {
     return hip_code(e);
 }
 
-// A binned graph whose first build has k = 32 (keys too wide for the 8-byte
-// records) becomes a direct one; its table must then hold zeros.  A build
-// with k > 32 needs 32-byte entries (two key words): the graph's table is
-// re-allocated for them before its first build.
+// Binned builds take k <= 31 (one-word records) and 33 <= k <= 63 (two-word
+// records).  A binned graph whose first build has k = 32 or 64 becomes a
+// direct one; its table must then hold zeros.  A build with k > 32 needs
+// 32-byte entries (two key words): the graph's table is re-allocated for
+// them before its first build.
+inline bool binnable_k(uint32_t k) { return k <= 31 || (k >= 33 && k <= 63); }
+
 inline int settle_mode(dbg_graph *g, uint32_t k) {
     const bool wide = k > 32 && g->ew != 4;
-    if (!wide && (!g->binned || k <= 31)) return DBG_OK;
+    if (!wide && (!g->binned || binnable_k(k))) return DBG_OK;
     if (g->k || g->vertices) return DBG_E_K;
-    g->binned = false;
+    if (!binnable_k(k)) g->binned = false;
     if (wide) {
         g->ew = 4;
         if (g->cap) {
@@ -607,7 +615,8 @@ inline int settle_mode(dbg_graph *g, uint32_t k) {
             }
         }
     }
-    if (g->cap && zero_table(g) != hipSuccess) return DBG_E_DEVICE;
+    // a binned table is rewritten from scratch by its first build
+    if (g->cap && !g->binned && zero_table(g) != hipSuccess) return DBG_E_DEVICE;
     return DBG_OK;
 }
 

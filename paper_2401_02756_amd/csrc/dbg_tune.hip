@@ -135,7 +135,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
     for (uint32_t i = 0; i < m; ++i) {
         // k > 32 only for a single graph (batched builds take k <= 32)
         if (ks[i] < 2 || ks[i] > (m == 1 ? 64u : 32u) || read_begin[i + 1] < read_begin[i]) return DBG_E_INVAL;
-        if (ks[i] > 31) all_binnable = false;
+        // binned passes take k <= 31, and 33 <= k <= 63 for a single graph
+        if (!(ks[i] <= 31 || (m == 1 && binnable_k(ks[i])))) all_binnable = false;
         if (ks[i] > 32) wide = true;
     }
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;

@@ -41,14 +41,20 @@ def check(got, exp):
     assert np.array_equal(gc, ec)
 
 
+MODES = [0, dbg.F_BINNED]
+MODE_IDS = ["direct", "binned"]
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("k", [33, 40, 51, 63, 64])
-def test_random_reads(k):
+def test_random_reads(k, mode):
     rs = readsim.simulate(200_000, 150, 12.0, 0.01, k, 900 + k)
-    say("long k=%d random reads" % k)
-    with dbg.Graph() as g:
+    say("long k=%d random reads, mode %d" % (k, mode))
+    with dbg.Graph(flags=mode) as g:
         g.build(rs.reads, rs.offsets, k)
         check(g.extract_sorted(), want(rs, k))
-        assert g.stats()["entry_bytes"] == 32 and g.stats()["binned"] == 0
+        # binned graphs stay binned up to k = 63
+        assert g.stats()["entry_bytes"] == 32 and g.stats()["binned"] == (1 if mode and k <= 63 else 0)
 
 
 def test_ragged_and_edge_reads():
@@ -59,22 +65,41 @@ def test_ragged_and_edge_reads():
         n = int(rng.integers(0, 200))
         reads.append(alphabet[rng.integers(0, 8, n)].tobytes())
     reads += [b"", b"A" * 50, b"C" * 51, b"G" * 52, b"ACGT" * 60]
-    for k in (33, 51, 64):
+    for k in (33, 51, 63, 64):
         rs = readsim.reads_from_strings(reads, k)
-        say("long k=%d ragged" % k)
-        with dbg.Graph() as g:
-            g.build(rs.reads, rs.offsets, k)
-            check(g.extract_sorted(), want(rs, k))
+        exp = want(rs, k)
+        for mode in MODES:
+            say("long k=%d ragged, mode %d" % (k, mode))
+            with dbg.Graph(flags=mode) as g:
+                g.build(rs.reads, rs.offsets, k)
+                check(g.extract_sorted(), exp)
 
 
-def test_one_key_everywhere():
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_one_key_everywhere(mode):
     # every window of every read is the same vertex: all lanes race for one slot
     k = 51
     rs = readsim.reads_from_strings([b"A" * 150] * 4000 + [b"AC" * 75] * 4000, k)
-    say("long k contended claims")
-    with dbg.Graph() as g:
+    say("long k contended claims, mode %d" % mode)
+    with dbg.Graph(flags=mode) as g:
         g.build(rs.reads, rs.offsets, k)
         check(g.extract_sorted(), want(rs, k))
+
+
+def test_shared_prefixes_on_a_crowded_table():
+    # keys that share their first 40 bases and differ only at the end, in a
+    # table filled to about 80 %: long probe chains over similar keys
+    rng = np.random.default_rng(17)
+    k = 45
+    stem = "".join("ACGT"[x] for x in rng.integers(0, 4, 40))
+    reads = [stem + "".join("ACGT"[x] for x in rng.integers(0, 4, 30)) for _ in range(3000)]
+    rs = readsim.reads_from_strings(reads, k)
+    exp = want(rs, k)
+    for mode in MODES:
+        say("long k shared prefixes, mode %d" % mode)
+        with dbg.Graph(flags=mode, expected_vertices=90_000, load_factor=0.9) as g:
+            g.build(rs.reads, rs.offsets, k)
+            check(g.extract_sorted(), exp)
 
 
 def test_device_input_binned_flag_and_accumulation():
@@ -106,10 +131,11 @@ def test_device_input_binned_flag_and_accumulation():
         assert e.value.code == dbg.E_SPACE
 
 
-def test_reset_to_short_k_and_back():
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_reset_to_short_k_and_back(mode):
     rs = readsim.simulate(100_000, 150, 8.0, 0.01, 21, 31)
-    say("long k then k=21 on one handle")
-    with dbg.Graph(expected_vertices=readsim.expected_vertices(100_000, 150, rs.n_reads, 0.01, 45)) as g:
+    say("long k then k=21 on one handle, mode %d" % mode)
+    with dbg.Graph(flags=mode, expected_vertices=readsim.expected_vertices(100_000, 150, rs.n_reads, 0.01, 45)) as g:
         g.build(rs.reads, rs.offsets, 45)
         check(g.extract_sorted(), want(rs, 45))
         with pytest.raises(dbg.DbgError) as e:
@@ -164,7 +190,7 @@ def test_autotune_long_k():
     d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
     say("long k autotune")
     t = dbg.autotune([0, rs.n_reads], [k], d_reads, d_off, repeats=1)
-    assert t.flags & dbg.F_BINNED == 0 and t.flags & dbg.F_MERGE == 0
+    assert t.flags & dbg.F_MERGE == 0  # the long-k direct build does not merge
     with dbg.Graph(**t.graph_kwargs()) as g:
         g.build(rs.reads, rs.offsets, k)
         check(g.extract_sorted(), want(rs, k))
@@ -178,8 +204,10 @@ def test_bacterial_k51_exact():
     exp = want(rs, k)
     d_reads = torch.from_numpy(rs.reads).cuda()
     d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
-    with dbg.Graph(expected_vertices=readsim.expected_vertices(5_000_000, 150, rs.n_reads, 0.01, k),
-                   load_factor=0.5, flags=dbg.F_GRAPH) as g:
-        g.build_device(d_reads, d_off, k)
-        g.sync()
-        check(g.extract_sorted(), exp)
+    for mode in MODES:
+        say("long k=51 bacterial scale, mode %d" % mode)
+        with dbg.Graph(expected_vertices=readsim.expected_vertices(5_000_000, 150, rs.n_reads, 0.01, k),
+                       load_factor=0.5, flags=dbg.F_GRAPH | mode) as g:
+            g.build_device(d_reads, d_off, k)
+            g.sync()
+            check(g.extract_sorted(), exp)
