@@ -3,10 +3,11 @@
 // executes past the per-XCD L2, at most ~27 G/s) into LDS.
 //
 // Each instance's table is cut into segments of kSegSlots slots; a key's
-// segment is chosen by the top bits of its hash and its home slot inside the
-// segment by the low 32 bits.  The windows of all reads become 8-byte
-// records (key << 3 | sink << 2 | letter; k <= 31) that are partitioned by
-// segment in two passes:
+// segment is chosen by the top bits of its image (a bijection of the key)
+// and its home slot inside the segment by its low bits.  The windows of all
+// reads become records (image << 3 | sink << 2 | letter: 8 bytes for
+// k <= 31; 16 bytes for 33 <= k <= 63, whose image takes two words) that are
+// partitioned by segment in two passes:
 //
 //   pass 1  windows -> records grouped by level-1 bucket (d1 buckets per
 //           instance, each covering `fan` consecutive segments)

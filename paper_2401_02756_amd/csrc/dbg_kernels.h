@@ -17,9 +17,10 @@
 // Table layout: an array of `cap` entries of `entry_words` uint64 words
 // (3 = 24 bytes, 4 = 32 bytes).  Word 0 holds the vertex key with bit 63 set,
 // the next 16 bytes four uint32 counters in letter-code order A, C, T, G.
-// Long k (32 < k <= 64, direct build only): 32-byte entries whose words 0
-// and 1 hold the upper and lower 63 bits of the key, each with bit 63 set,
-// and whose words 2-3 hold the counters.
+// Long k (32 < k <= 64), direct build: 32-byte entries whose words 0 and 1
+// hold the upper and lower 63 bits of the key, each with bit 63 set, and
+// whose words 2-3 hold the counters (the binned build of 33 <= k <= 63 keeps
+// its segments' key words and counters as arrays, as described below).
 // Direct build: the entries are the open-addressing slots themselves (0 =
 // empty, so a zero fill empties the table).  Binned build: the table is cut
 // into segments of kSegSlots entries, and segment s holds its vertices packed
