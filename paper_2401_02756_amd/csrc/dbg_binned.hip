@@ -642,14 +642,40 @@ __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter
 
 constexpr uint32_t kRefMaxPer = (kMaxFan + kRefBlock - 1) / kRefBlock;  // segments per thread in a scan
 
-// Load a pass-2 tile's records.
+// Load a pass-2 tile's records (the tile's order of records over threads is
+// free: counts and ranks only need each record once).  One-word records go
+// two per load.
 template <typename R>
 __device__ __forceinline__ void refine_load(const RefTile &T, const R *__restrict__ rec1, R (&rec)[kRefPerThread]) {
+    if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (uint32_t it = 0; it < kRefPerThread; ++it) {
-        const uint32_t j = it * blockDim.x + threadIdx.x;
-        rec[it] = j < T.n ? rec1[T.r0 + j] : R{};
+        for (uint32_t it = 0; it < kRefPerThread / 2; ++it) {
+            const uint32_t j = 2 * (it * blockDim.x + threadIdx.x);
+            if (j + 1 < T.n) {
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(rec1 + T.r0 + j);
+                rec[2 * it] = v.x;
+                rec[2 * it + 1] = v.y;
+            } else {
+                rec[2 * it] = j < T.n ? rec1[T.r0 + j] : R{};
+                rec[2 * it + 1] = R{};
+            }
+        }
+    } else {
+#pragma unroll
+        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            const uint32_t j = it * blockDim.x + threadIdx.x;
+            rec[it] = j < T.n ? rec1[T.r0 + j] : R{};
+        }
     }
+}
+
+// Whether slot it of a thread's records holds one (matches refine_load).
+template <typename R>
+__device__ __forceinline__ bool refine_has(const RefTile &T, uint32_t it) {
+    if constexpr (sizeof(R) == 8)
+        return 2 * ((it / 2) * blockDim.x + threadIdx.x) + (it & 1) < T.n;
+    else
+        return it * blockDim.x + threadIdx.x < T.n;
 }
 
 // Pass 2, per tile of records of one level-1 bucket: count (or, with
@@ -701,8 +727,7 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
         uint32_t tag[kRefPerThread];  // scatter: segment << 12 | rank (segment fan: past the end)
 #pragma unroll
         for (uint32_t it = 0; it < kRefPerThread; ++it) {
-            const uint32_t j = it * blockDim.x + tid;
-            const uint32_t c = j < T.n ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
+            const uint32_t c = refine_has<R>(T, it) ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
             if (SCATTER)
                 tag[it] = lds_add32(&s_cnt[c], 1u);
             else
