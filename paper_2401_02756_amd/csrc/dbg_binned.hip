@@ -819,7 +819,7 @@ __device__ void flush_block_sum(uint64_t v, uint64_t *dst, uint64_t *s_sum) {
 }
 
 constexpr uint32_t kReducePrefetch = 8;  // records a thread loads before using them
-constexpr uint64_t kNoRecord = ~0ull;     // no record value: keys stay below 2^61
+constexpr uint64_t kNoRecord = ~0ull;     // no record: a record's first word stays below 2^63
 
 // Find-or-claim one record's vertex in the LDS segment and count its letter.
 // Returns false when the segment has no free slot for it.
