@@ -1202,21 +1202,21 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
 }
 
 namespace {
-constexpr uint32_t kScatterWide = 384;  // digits per partition step beyond which scatters take half the grid
+constexpr uint32_t kScatterWide = 384;  // segments per bucket beyond which pass 2 takes half the grid
 
 template <uint32_t RW>
 void grids_for(int device, BinBuffers &bb) {
     bb.grid_bin_count =
         occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, false, RW));
-    // A scatter tile writes one run per bucket, and the runs of the tiles in
+    // A scatter tile writes one run per segment, and the runs of the tiles in
     // flight on an XCD meet in its L2 (they are adjacent in the output).  With
-    // many buckets those partial lines overflow the L2 before they fill, so
-    // fewer workgroups (shorter distance between the first and last tile in
-    // flight) write faster: half the resident grid above kScatterWide digits.
-    const uint32_t bin_div = bb.d1_max > kScatterWide ? 2 : 1, ref_div = bb.fan_max > kScatterWide ? 2 : 1;
-    bb.grid_bin_scatter = std::max<uint32_t>(
-        8, occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true, RW)) /
-               bin_div);
+    // many segments per bucket those partial lines overflow the L2 before
+    // they fill, so pass 2 writes faster on half the resident grid above
+    // kScatterWide digits.  (Pass 1, which also decodes windows, measured
+    // slower that way.)
+    const uint32_t ref_div = bb.fan_max > kScatterWide ? 2 : 1;
+    bb.grid_bin_scatter =
+        occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true, RW));
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, false, RW));
     bb.grid_ref_scatter = std::max<uint32_t>(
