@@ -8,21 +8,34 @@
 // would never end); here a walk also stops on the first vertex it has already
 // passed.  The vertex a walk stops on is part of its contig.
 //
-// On the device: the graph's vertices are extracted and inserted into a walk
-// table (key, out-letter mask); a mark pass follows every edge once and flags
-// its target as having an in-edge (so `first` = no flag); a start pass lists
-// one walk per out-edge of every start vertex; a length pass follows every
-// walk (Brent's cycle detection finds the loops, then the first revisit is
-// located exactly); a scan lays the contigs out; a write pass spells them.  Every loop is bounded, so a
+// On the device: the graph's vertices go into a walk table (key, out-letter
+// mask).  For a binned graph the walk table has the graph's own segments:
+// each workgroup rehashes one packed segment in LDS and writes its slots out,
+// so a key is found from its image's segment digits and home slot, with no
+// extraction and no global atomics.  For a direct graph the vertices are
+// extracted and inserted into a hash table.  Then a mark pass follows every
+// edge once and flags its target as having an in-edge (so `first` = no
+// flag); a start pass lists one walk per out-edge of every start vertex; a
+// length pass follows every walk (Brent's cycle detection finds the loops,
+// then the first revisit is located exactly); a scan lays the contigs out;
+// a write pass spells them.  Every loop is bounded, so a
 // walk that cannot end reports an error instead of running forever.
 #include "dbg_runtime.h"
 #include "dbg_device.h"
 
 using namespace dbgrt;
 using dbgk::block_exclusive_scan;
+using dbgk::bucket_of;
+using dbgk::child_of;
 using dbgk::home_slot;
+using dbgk::image_top;
+using dbgk::key_image;
+using dbgk::key_of_image;
 using dbgk::kOccupied;
+using dbgk::kSegSlots;
 using dbgk::mix64;
+using dbgk::seg_counts;
+using dbgk::seg_home;
 
 namespace {
 
@@ -32,15 +45,37 @@ constexpr uint8_t kOutMask = 0x0f;  // bits 0-3: out-edges by letter code
 constexpr uint8_t kHasIn = 0x10;    // some k-mer ends in the vertex
 
 struct WalkTable {
-    uint64_t *keys;   // key | kOccupied, 0 = empty
+    uint64_t *keys;   // key (segmented: key image) | kOccupied, 0 = empty
     uint8_t *masks;   // bit c: the vertex has an out-edge for letter code c; kHasIn
-    uint64_t cap;     // power of two
+    uint64_t cap;     // slots: a power of two, or (segmented) segments * kSegSlots
     uint64_t kmask;   // (k-1)-mer key mask
     uint32_t km1;
+    uint32_t seg;     // 1: segmented like the binned graph, d1 x fan segments
+    uint32_t d1, fan;
 };
 
-// Slot of `key`, or ~0 when absent (after at most cap probes).
+// The key stored in an occupied slot.
+__device__ __forceinline__ uint64_t slot_key(const WalkTable &T, uint64_t s) {
+    const uint64_t w = T.keys[s] & ~kOccupied;
+    return T.seg ? key_of_image(w) : w;
+}
+
+// Slot of `key`, or ~0 when absent (after at most a segment's or the
+// table's slots).
 __device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key) {
+    if (T.seg) {
+        const uint64_t img = key_image(key), tagv = img | kOccupied;
+        const uint32_t top = image_top(img);
+        const uint64_t base = ((uint64_t)bucket_of(top, T.d1) * T.fan + child_of(top, T.d1, T.fan)) * kSegSlots;
+        uint32_t s = seg_home(img);
+        for (uint32_t q = 0; q < kSegSlots; ++q) {
+            const uint64_t cur = T.keys[base + s];
+            if (cur == tagv) return base + s;
+            if (cur == 0) return ~0ull;
+            s = (s + 1) & (kSegSlots - 1);
+        }
+        return ~0ull;
+    }
     const uint64_t tagv = key | kOccupied;
     uint64_t s = home_slot(mix64(key), T.cap);
     for (uint64_t q = 0; q < T.cap; ++q) {
@@ -81,25 +116,69 @@ __device__ __forceinline__ uint32_t out_mask(const WalkTable &T, uint64_t s) { r
 
 // Flag the target of every edge.  Every writer of a mask byte writes the same
 // value (its out-edges and kHasIn), so plain byte stores suffice.
-__global__ __launch_bounds__(kWalkBlock) void k_walk_mark(WalkTable T, const uint64_t *__restrict__ keys,
-                                                          const uint32_t *__restrict__ counts, uint64_t n,
-                                                          uint32_t *err) {
+__global__ __launch_bounds__(kWalkBlock) void k_walk_mark(WalkTable T, uint32_t *err) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t key = keys[i];
-        const uint4 c = *reinterpret_cast<const uint4 *>(counts + 4 * i);
-        const uint32_t cnt[4] = {c.x, c.y, c.z, c.w};
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T.cap; i += stride) {
+        if (!T.keys[i]) continue;
+        const uint64_t key = slot_key(T, i);
+        const uint32_t m = T.masks[i] & kOutMask;
 #pragma unroll
         for (uint32_t x = 0; x < 4; ++x) {
-            if (!cnt[x]) continue;
+            if (!((m >> x) & 1u)) continue;
             const uint64_t s = walk_find(T, ((key << 2) | x) & T.kmask);
             if (s == ~0ull) {
                 atomicOr(err, 16u);  // an edge without its target vertex
                 continue;
             }
-            const uint8_t m = T.masks[s];
-            if (!(m & kHasIn)) T.masks[s] = (uint8_t)(m | kHasIn);
+            const uint8_t mt = T.masks[s];
+            if (!(mt & kHasIn)) T.masks[s] = (uint8_t)(mt | kHasIn);
         }
+    }
+}
+
+// Walk table of a binned graph: segment gp of the graph (its vertices packed
+// at [0, seg_count[gp])) is rehashed in LDS by its image's home slots and
+// written to slots [gp * kSegSlots, (gp + 1) * kSegSlots), empty ones as 0.
+template <uint32_t EW>
+__global__ __launch_bounds__(kWalkBlock) void k_walk_seg(const uint64_t *__restrict__ table,
+                                                         const uint32_t *__restrict__ seg_count, uint64_t parts,
+                                                         WalkTable T, uint32_t *err) {
+    __shared__ uint64_t s_key[kSegSlots];
+    __shared__ uint8_t s_mask[kSegSlots];
+    for (uint64_t gp = blockIdx.x; gp < parts; gp += gridDim.x) {
+        for (uint32_t j = threadIdx.x; j < kSegSlots; j += blockDim.x) {
+            s_key[j] = 0;
+            s_mask[j] = 0;
+        }
+        __syncthreads();
+        const uint64_t *seg = table + gp * kSegSlots * EW;
+        const uint32_t n = min(seg_count[gp], kSegSlots);
+        for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+            const uint64_t tagv = seg[e];
+            const uint4 c = seg_counts(seg)[e];
+            const uint8_t m = (uint8_t)((c.x ? 1u : 0u) | (c.y ? 2u : 0u) | (c.z ? 4u : 0u) | (c.w ? 8u : 0u));
+            uint32_t s = seg_home(tagv);
+            bool placed = false;
+            for (uint32_t q = 0; q < kSegSlots && !placed; ++q) {  // keys are distinct
+                uint64_t expected = 0;
+                if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    s_mask[s] = m;
+                    placed = true;
+                } else {
+                    s = (s + 1) & (kSegSlots - 1);
+                }
+            }
+            if (!placed) atomicOr(err, 1u);
+        }
+        __syncthreads();
+        uint64_t *ok = T.keys + gp * kSegSlots;
+        uint8_t *om = T.masks + gp * kSegSlots;
+        for (uint32_t j = threadIdx.x; j < kSegSlots; j += blockDim.x) {
+            ok[j] = s_key[j];
+            om[j] = s_mask[j];
+        }
+        __syncthreads();
     }
 }
 
@@ -165,7 +244,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const u
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t it = items[i];
-        const uint64_t key0 = T.keys[it >> 2] & ~kOccupied;
+        const uint64_t key0 = slot_key(T, it >> 2);
         const uint64_t x1 = ((key0 << 2) | (it & 3)) & T.kmask;
         uint64_t hare = x1, tort = x1, power = 1, lam = 1, idx = 1;
         bool loop = false, bad = false;
@@ -272,7 +351,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_write(WalkTable T, const ui
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t it = items[i];
-        const uint64_t key0 = T.keys[it >> 2] & ~kOccupied;
+        const uint64_t key0 = slot_key(T, it >> 2);
         uint8_t *o = seq + off[i];
         for (uint32_t b = 0; b < T.km1; ++b) *o++ = letters[(key0 >> (2 * (T.km1 - 1 - b))) & 3];
         *o++ = letters[it & 3];
@@ -321,45 +400,62 @@ int compute_contigs(dbg_graph *g, dbg_contig_state *cs, hipStream_t s) {
         return DBG_OK;
     }
     hipError_t e;
-    uint64_t cap = 64;
-    while (cap < 2 * V) cap <<= 1;
-    if ((e = cs->xkeys.reserve(V * 8)) != hipSuccess || (e = cs->xcnt.reserve(V * 16)) != hipSuccess ||
-        (e = cs->xn.reserve(8)) != hipSuccess || (e = cs->keys.reserve(cap * 8)) != hipSuccess ||
-        (e = cs->masks.reserve(cap)) != hipSuccess || (e = cs->scalars.reserve(32)) != hipSuccess)
-        return hip_code(e);
-    uint64_t *xn = cs->xn.as<uint64_t>();
-    e = dbgk::launch_fill_zero(xn, 1, s);
-    if (e == hipSuccess && g->binned)
-        e = dbgk::launch_extract_binned(g->table.as<uint64_t>(), g->ew, 1, g->parts, g->seg_count.as<uint32_t>(),
-                                        g->seg_off.as<uint64_t>(), g->seg_partials.as<uint64_t>(),
-                                        g->seg_len.as<uint64_t>(), cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(),
-                                        V, xn, g->device, s);
-    else if (e == hipSuccess)
-        e = dbgk::launch_extract(g->table.as<uint64_t>(), g->ew, g->cap, cs->xkeys.as<uint64_t>(),
-                                 cs->xcnt.as<uint32_t>(), V, xn, s);
     // scalars: [0] walk count, [1] error bits
+    if ((e = cs->scalars.reserve(32)) != hipSuccess) return hip_code(e);
     unsigned long long *n_items = cs->scalars.as<unsigned long long>();
     uint32_t *err = reinterpret_cast<uint32_t *>(cs->scalars.as<uint64_t>() + 1);
-    if (e == hipSuccess) e = dbgk::launch_fill_zero(cs->scalars.as<uint64_t>(), 2, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_walk_clear, dim3(grid_for(cap, 256)), dim3(256), 0, s, cs->keys.as<uint64_t>(), cap);
-        e = hipGetLastError();
+    e = dbgk::launch_fill_zero(cs->scalars.as<uint64_t>(), 2, s);
+    const uint64_t kmask = (1ull << (2 * (g->k - 1))) - 1;
+    WalkTable T{};
+    if (g->binned) {
+        // the graph's own segments, rehashed
+        const uint64_t cap = (uint64_t)g->parts * kSegSlots;
+        if (e == hipSuccess && ((e = cs->keys.reserve(cap * 8)) != hipSuccess || (e = cs->masks.reserve(cap)) != hipSuccess))
+            return hip_code(e);
+        T = WalkTable{cs->keys.as<uint64_t>(), cs->masks.as<uint8_t>(), cap, kmask, g->k - 1, 1u, g->d1, g->fan};
+        if (e == hipSuccess) {
+            const dim3 grid((uint32_t)std::min<uint64_t>(g->parts, 65536)), block(kWalkBlock);
+            if (g->ew == 4)
+                hipLaunchKernelGGL((k_walk_seg<4>), grid, block, 0, s, g->table.as<uint64_t>(),
+                                   g->seg_count.as<uint32_t>(), (uint64_t)g->parts, T, err);
+            else
+                hipLaunchKernelGGL((k_walk_seg<3>), grid, block, 0, s, g->table.as<uint64_t>(),
+                                   g->seg_count.as<uint32_t>(), (uint64_t)g->parts, T, err);
+            e = hipGetLastError();
+        }
+    } else {
+        // extracted vertices, inserted into a hash table
+        uint64_t cap = 64;
+        while (cap < 2 * V) cap <<= 1;
+        if (e == hipSuccess &&
+            ((e = cs->xkeys.reserve(V * 8)) != hipSuccess || (e = cs->xcnt.reserve(V * 16)) != hipSuccess ||
+             (e = cs->xn.reserve(8)) != hipSuccess || (e = cs->keys.reserve(cap * 8)) != hipSuccess ||
+             (e = cs->masks.reserve(cap)) != hipSuccess))
+            return hip_code(e);
+        T = WalkTable{cs->keys.as<uint64_t>(), cs->masks.as<uint8_t>(), cap, kmask, g->k - 1, 0u, 0u, 0u};
+        uint64_t *xn = cs->xn.as<uint64_t>();
+        if (e == hipSuccess) e = dbgk::launch_fill_zero(xn, 1, s);
+        if (e == hipSuccess)
+            e = dbgk::launch_extract(g->table.as<uint64_t>(), g->ew, g->cap, cs->xkeys.as<uint64_t>(),
+                                     cs->xcnt.as<uint32_t>(), V, xn, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_walk_clear, dim3(grid_for(cap, 256)), dim3(256), 0, s, cs->keys.as<uint64_t>(), cap);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_walk_insert, dim3(grid_for(V, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
+                               cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
+            e = hipGetLastError();
+        }
     }
-    WalkTable T{cs->keys.as<uint64_t>(), cs->masks.as<uint8_t>(), cap, (1ull << (2 * (g->k - 1))) - 1, g->k - 1};
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_walk_insert, dim3(grid_for(V, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
-                           cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_walk_mark, dim3(grid_for(V, kWalkBlock)), dim3(kWalkBlock), 0, s, T,
-                           cs->xkeys.as<uint64_t>(), cs->xcnt.as<uint32_t>(), V, err);
+        hipLaunchKernelGGL(k_walk_mark, dim3(grid_for(T.cap, kWalkBlock)), dim3(kWalkBlock), 0, s, T, err);
         e = hipGetLastError();
     }
     // walks are at most the edges, at most 4 per vertex
     const uint64_t items_cap = 4 * V;
     if (e == hipSuccess && (e = cs->items.reserve(items_cap * 8)) == hipSuccess) {
-        hipLaunchKernelGGL(k_walk_starts, dim3(grid_for(cap, kStartChunk)), dim3(kWalkBlock), 0, s, T,
+        hipLaunchKernelGGL(k_walk_starts, dim3(grid_for(T.cap, kStartChunk)), dim3(kWalkBlock), 0, s, T,
                            cs->items.as<uint64_t>(), items_cap, n_items, err);
         e = hipGetLastError();
     }

@@ -126,4 +126,63 @@ __device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t *total) {
 }
 
 
+// ---------------------------------------------------------------- binned key images
+
+// Binned tables and records hold a key's image under a bijection of the
+// 60-bit key space (keys of k <= 31 have at most 60 bits): a multiply by an
+// odd constant modulo 2^60, then an xorshift by 30, which undoes itself on 60
+// bits.  A window's key is hashed once, in pass 1; everything after works on
+// the image: the segment is a pair of mixed-radix digits of its top 32 bits
+// (the level-1 bucket, then the segment inside the bucket), the home slot
+// inside the segment is its low bits, and extraction maps it back.
+constexpr uint64_t kKey60 = (1ull << 60) - 1;
+constexpr uint64_t kKeyMul = 0x0E3779B97F4A7C15ull;  // odd; the golden-ratio constant's low 60 bits
+
+constexpr uint64_t inverse_mod_2_64(uint64_t a) {  // Newton's iteration, 6 steps
+    uint64_t x = a;
+    for (int i = 0; i < 6; ++i) x *= 2 - a * x;
+    return x;
+}
+constexpr uint64_t kKeyMulInv = inverse_mod_2_64(kKeyMul);
+static_assert(kKeyMul * kKeyMulInv == 1, "inverse of the key multiplier");
+
+__device__ __forceinline__ uint64_t key_image(uint64_t key) {
+    const uint64_t x = (key * kKeyMul) & kKey60;
+    return x ^ (x >> 30);
+}
+
+__device__ __forceinline__ uint64_t key_of_image(uint64_t x) {
+    x ^= x >> 30;
+    return (x * kKeyMulInv) & kKey60;
+}
+
+// Top 32 bits of an image: the digits of its segment.
+__device__ __forceinline__ uint32_t image_top(uint64_t x) { return (uint32_t)(x >> 28); }
+
+// Level-1 bucket of an image: the first digit, in [0, d1).
+__device__ __forceinline__ uint32_t bucket_of(uint32_t top, uint32_t d1) { return __umulhi(top, d1); }
+
+// Segment inside its bucket: the second digit, in [0, fan).
+__device__ __forceinline__ uint32_t child_of(uint32_t top, uint32_t d1, uint32_t fan) {
+    return __umulhi(top * d1, fan);
+}
+
+// A segment of a binned table is kSegSlots entries of EW words, stored as
+// arrays: the image words (image | kOccupied) of its vertices, packed at
+// [0, seg_count), then their four counters (16 bytes each); with 32-byte
+// entries of short keys the last quarter is unused.  Each is written and read by
+// consecutive lanes as one contiguous run.
+// Long keys: the words ih | kOccupied, then il, then the counters.
+template <uint32_t RW = 1>
+__device__ __forceinline__ uint4 *seg_counts(uint64_t *seg) {
+    return reinterpret_cast<uint4 *>(seg + RW * kSegSlots);
+}
+template <uint32_t RW = 1>
+__device__ __forceinline__ const uint4 *seg_counts(const uint64_t *seg) {
+    return reinterpret_cast<const uint4 *>(seg + RW * kSegSlots);
+}
+
+// Home slot inside a segment: the image's low bits.
+__device__ __forceinline__ uint32_t seg_home(uint64_t x) { return (uint32_t)x & (kSegSlots - 1); }
+
 }  // namespace dbgk
