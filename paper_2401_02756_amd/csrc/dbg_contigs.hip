@@ -61,8 +61,9 @@ __device__ __forceinline__ uint64_t slot_key(const WalkTable &T, uint64_t s) {
 }
 
 // Slot of `key`, or ~0 when absent (after at most a segment's or the
-// table's slots).
-__device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key) {
+// table's slots); *mb receives the slot's mask byte, loaded beside each
+// probed key so that a walk step waits on one load, not two in a row.
+__device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key, uint32_t *mb = nullptr) {
     if (T.seg) {
         const uint64_t img = key_image(key), tagv = img | kOccupied;
         const uint32_t top = image_top(img);
@@ -70,7 +71,11 @@ __device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key) 
         uint32_t s = seg_home(img);
         for (uint32_t q = 0; q < kSegSlots; ++q) {
             const uint64_t cur = T.keys[base + s];
-            if (cur == tagv) return base + s;
+            const uint32_t m = T.masks[base + s];
+            if (cur == tagv) {
+                if (mb) *mb = m;
+                return base + s;
+            }
             if (cur == 0) return ~0ull;
             s = (s + 1) & (kSegSlots - 1);
         }
@@ -80,7 +85,11 @@ __device__ __forceinline__ uint64_t walk_find(const WalkTable &T, uint64_t key) 
     uint64_t s = home_slot(mix64(key), T.cap);
     for (uint64_t q = 0; q < T.cap; ++q) {
         const uint64_t cur = T.keys[s];
-        if (cur == tagv) return s;
+        const uint32_t m = T.masks[s];
+        if (cur == tagv) {
+            if (mb) *mb = m;
+            return s;
+        }
         if (cur == 0) return ~0ull;
         s = (s + 1) & (T.cap - 1);
     }
@@ -112,7 +121,6 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_insert(WalkTable T, const u
     }
 }
 
-__device__ __forceinline__ uint32_t out_mask(const WalkTable &T, uint64_t s) { return T.masks[s] & kOutMask; }
 
 // Flag the target of every edge.  Every writer of a mask byte writes the same
 // value (its out-edges and kHasIn), so plain byte stores suffice.
@@ -125,12 +133,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_mark(WalkTable T, uint32_t 
 #pragma unroll
         for (uint32_t x = 0; x < 4; ++x) {
             if (!((m >> x) & 1u)) continue;
-            const uint64_t s = walk_find(T, ((key << 2) | x) & T.kmask);
+            uint32_t mt = 0;
+            const uint64_t s = walk_find(T, ((key << 2) | x) & T.kmask, &mt);
             if (s == ~0ull) {
                 atomicOr(err, 16u);  // an edge without its target vertex
                 continue;
             }
-            const uint8_t mt = T.masks[s];
             if (!(mt & kHasIn)) T.masks[s] = (uint8_t)(mt | kHasIn);
         }
     }
@@ -249,9 +257,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const u
         uint64_t hare = x1, tort = x1, power = 1, lam = 1, idx = 1;
         bool loop = false, bad = false;
         for (;;) {
-            const uint64_t s = walk_find(T, hare);
+            uint32_t mb = 0;
+            const uint64_t s = walk_find(T, hare, &mb);
             if (s == ~0ull || idx > limit) { bad = true; break; }
-            const uint32_t m = out_mask(T, s);
+            const uint32_t m = mb & kOutMask;
             if (__popc(m) != 1) break;  // stops on x_idx
             hare = succ(T, hare, m);
             ++idx;
@@ -268,16 +277,18 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_length(WalkTable T, const u
             // x_{1+lam} together until they meet
             uint64_t a = x1, b = x1;
             for (uint64_t q = 0; q < lam && !bad; ++q) {
-                const uint64_t s = walk_find(T, b);
+                uint32_t mb = 0;
+                const uint64_t s = walk_find(T, b, &mb);
                 if (s == ~0ull) bad = true;
-                else b = succ(T, b, out_mask(T, s));
+                else b = succ(T, b, mb & kOutMask);
             }
             uint64_t mu = 1;
             while (!bad && a != b) {
-                const uint64_t sa = walk_find(T, a), sb = walk_find(T, b);
+                uint32_t ma = 0, mbb = 0;
+                const uint64_t sa = walk_find(T, a, &ma), sb = walk_find(T, b, &mbb);
                 if (sa == ~0ull || sb == ~0ull || mu > limit) { bad = true; break; }
-                a = succ(T, a, out_mask(T, sa));
-                b = succ(T, b, out_mask(T, sb));
+                a = succ(T, a, ma & kOutMask);
+                b = succ(T, b, mbb & kOutMask);
                 ++mu;
             }
             idx = mu + lam;
@@ -358,12 +369,13 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk_write(WalkTable T, const ui
         uint64_t cur = ((key0 << 2) | (it & 3)) & T.kmask;
         const uint64_t m = edges[i];
         for (uint64_t e = 1; e < m; ++e) {
-            const uint64_t s = walk_find(T, cur);
+            uint32_t mb = 0;
+            const uint64_t s = walk_find(T, cur, &mb);
             if (s == ~0ull) {
                 atomicOr(err, 8u);
                 break;
             }
-            const uint32_t c = (uint32_t)__builtin_ctz(out_mask(T, s));
+            const uint32_t c = (uint32_t)__builtin_ctz(mb & kOutMask);
             *o++ = letters[c];
             cur = ((cur << 2) | c) & T.kmask;
         }
