@@ -63,11 +63,35 @@ def test_hand_derived(case, mode):
     assert gpu_contigs(readsim.reads_from_strings(reads, k), mode) == sorted(want)
 
 
-@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("mode", MODES + [dbg.F_BINNED | dbg.F_ENTRY32, dbg.F_ENTRY32],
+                         ids=MODE_IDS + ["binned-entry32", "direct-entry32"])
 def test_config1(mode):
     rs = readsim.make_config(1)
     say("contigs config 1 mode %d" % mode)
     assert gpu_contigs(rs, mode) == oracle_contigs(rs)
+
+
+def test_batched_graphs_and_reused_table():
+    sets = [readsim.make_config(1)] + [readsim.simulate(20_000 + 5_000 * j, 100, 12.0, 0.01, 21 + 10 * (j % 2), 70 + j)
+                                       for j in range(3)]
+    say("contigs of batch-built graphs")
+    gs = [dbg.Graph(flags=dbg.F_BINNED, expected_vertices=60_000) for _ in sets]
+    try:
+        st = dbg.build_batch(gs, [(x.reads, x.offsets, x.k) for x in sets])
+        assert st == [0] * len(sets)
+        for g, x in zip(gs, sets):
+            assert oracle.contig_strings(*g.contigs()) == oracle_contigs(x)
+    finally:
+        for g in gs:
+            g.close()
+    # a binned table that held long keys (32-byte entries) and was reset
+    rs = readsim.make_config(1)
+    with dbg.Graph(flags=dbg.F_BINNED, expected_vertices=40_000) as g:
+        g.build(rs.reads, rs.offsets, 45)
+        g.reset()
+        g.build(rs.reads, rs.offsets, rs.k)
+        assert g.stats()["entry_bytes"] == 32 and g.stats()["binned"] == 1
+        assert oracle.contig_strings(*g.contigs()) == oracle_contigs(rs)
 
 
 @pytest.mark.parametrize("k", [2, 3, 5, 17, 31, 32])
