@@ -16,7 +16,8 @@
 // among them) before trying again.  Nodes come from a per-thread pool, so no
 // allocator lock is taken (Methods, "Implementation issues").
 //
-// Departures, each a reading of the paper stated in the design doc: the (k-1)-mer
+// Departures from the paper's structure, none of which changes the work per
+// k-mer or the result: the (k-1)-mer
 // is stored packed in a 64-bit word rather than as a view into the reads;
 // counters are 32-bit (the paper's 8-bit counters wrap on repeats); the
 // explicit out-edge pointers and the `first` flag are not kept (the build's
