@@ -136,18 +136,21 @@ __device__ __forceinline__ ReadCount count_read(const uint64_t *off, uint64_t of
 }
 
 // Per-read windows, block-local exclusive prefix and block totals; also the
-// k-mers and windows of each instance (one atomic per block when the block's
-// reads all belong to one instance, as they almost always do).
+// k-mers and windows of each instance.  A single instance's totals are summed
+// from per-block partials (kpart) by k_scan_partials: an atomic per block on
+// one address would serialise about a thousand times.  In a batch, a block
+// whose reads all belong to one instance, as they almost always do, adds its
+// totals with one atomic.
 __global__ __launch_bounds__(kScanBlock) void k_scan_local(
     const PassArgs *__restrict__ args, const Instance *__restrict__ inst, InstStatus *st,
-    uint64_t *__restrict__ ws, uint64_t *__restrict__ partials) {
+    uint64_t *__restrict__ ws, uint64_t *__restrict__ partials, uint64_t *__restrict__ kpart) {
     __shared__ uint32_t s_t0, s_t1;
     const uint64_t *__restrict__ off = args->off;
     const uint64_t n = args->n_reads, len = args->reads_len;
     const uint32_t m = args->m, check_ends = args->check_ends;
     const uint64_t rb = (uint64_t)blockIdx.x * kScanReads;
     if (rb >= n) {  // grid sized for the capacity: blocks past the reads add nothing
-        if (threadIdx.x == 0) partials[blockIdx.x] = 0;
+        if (threadIdx.x == 0) partials[blockIdx.x] = kpart[blockIdx.x] = 0;
         return;
     }
     const uint64_t off0 = off[0];
@@ -197,10 +200,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(
         pre += w[i];
     }
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
-    if (uniform) {
-        uint64_t ktotal;
-        block_exclusive_scan(tk, &ktotal);
-        if (threadIdx.x == 0 && (total | ktotal)) {
+    uint64_t ktotal = 0;
+    if (uniform) block_exclusive_scan(tk, &ktotal);
+    if (threadIdx.x == 0) {
+        kpart[blockIdx.x] = m == 1 ? ktotal : 0;
+        if (m > 1 && uniform && (total | ktotal)) {
             atomic_add_u64(&st[s_t0].inserts, ktotal);
             atomic_add_u64(&st[s_t0].windows, total);
         }
@@ -212,18 +216,26 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(
 // offsets can exceed that, and then every instance is flagged invalid and no
 // window is processed.
 __global__ __launch_bounds__(1024) void k_scan_partials(const PassArgs *__restrict__ args,
-                                                       uint64_t *partials, uint64_t nb,
+                                                       uint64_t *partials, const uint64_t *kpart, uint64_t nb,
                                                        CallState *cs, InstStatus *st) {
     const uint64_t max_windows = args->max_windows;
     const uint32_t m = args->m;
-    uint64_t carry = 0;
+    uint64_t carry = 0, kcarry = 0;
     for (uint64_t base = 0; base < nb; base += blockDim.x) {
         const uint64_t i = base + threadIdx.x;
         const uint64_t v = i < nb ? partials[i] : 0;
-        uint64_t total;
+        uint64_t total, ktotal = 0;
         const uint64_t ex = block_exclusive_scan(v, &total);
         if (i < nb) partials[i] = carry + ex;
         carry += total;
+        if (m == 1) {
+            block_exclusive_scan(i < nb ? kpart[i] : 0, &ktotal);
+            kcarry += ktotal;
+        }
+    }
+    if (m == 1 && threadIdx.x == 0) {  // the single instance's totals
+        st[0].windows = carry;
+        st[0].inserts = kcarry;
     }
     if (carry > max_windows) {
         for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) atomic_or_u32(&st[i].err, kErrInval);
@@ -886,11 +898,12 @@ hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *s
                        uint64_t *partials, uint64_t *tile_read, CallState *cs, uint64_t n_cap,
                        hipStream_t s) {
     const uint64_t nb = std::max<uint64_t>(1, scan_blocks(n_cap));
+    uint64_t *kpart = partials + nb;  // the partials buffer holds 2 * nb + 1 words
     hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, args, inst, st, ws,
-                       partials);
+                       partials, kpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, args, partials, nb, cs, st);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, args, partials, kpart, nb, cs, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, args, inst, ws, partials,

@@ -394,7 +394,7 @@ struct Pass {
         hipError_t e;
         if ((e = grow(packed, dbgk::packed_words(k.len_cap) * 8)) != hipSuccess ||
             (e = grow(ws, (k.n_cap + 1) * 8)) != hipSuccess ||
-            (e = grow(partials, dbgk::scan_blocks(k.n_cap) * 8 + 8)) != hipSuccess ||
+            (e = grow(partials, std::max<uint64_t>(1, dbgk::scan_blocks(k.n_cap)) * 16 + 8)) != hipSuccess ||
             (e = grow(dargs, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap)) != hipSuccess ||
             (e = grow(dstatus, sizeof(InstStatus) * k.m_cap + sizeof(CallState))) != hipSuccess ||
             (!binned && (e = grow(tiles, tile_cap * 8)) != hipSuccess) ||
