@@ -102,8 +102,11 @@ def test_served_modes(flags):
         ids = [srv.submit(rs.reads, rs.offsets, rs.k, rs.meta["expected_vertices"]) for rs in sets]
         for j, (rs, rid) in enumerate(zip(sets, ids)):
             assert served(srv, rid) == dbg.OK
-            same(srv.graph(rid).extract_sorted(), oracle.build_graph(rs.reads, rs.offsets, rs.k),
-                 "flags %#x request %d" % (flags, j))
+            keys, counts = oracle.build_graph(rs.reads, rs.offsets, rs.k)
+            same(srv.graph(rid).extract_sorted(), (keys, counts), "flags %#x request %d" % (flags, j))
+            if j < 2:  # contigs of a served graph, from its resident table
+                want = oracle.contig_strings(*oracle.contigs(keys, counts, rs.k))
+                assert oracle.contig_strings(*srv.graph(rid).contigs()) == want
             srv.release(rid)
 
 
