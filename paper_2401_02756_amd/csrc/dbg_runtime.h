@@ -643,7 +643,12 @@ inline void fill_instance(Instance &in, dbg_graph *g, uint64_t read_begin, uint6
 
 // Fold one instance's status of a finished pass into its graph.
 inline int fold_status(dbg_graph *g, const InstStatus &st, uint32_t k) {
-    if (validation_error(st.err)) return err_code_of(st.err);  // nothing was modified
+    if (validation_error(st.err)) {  // nothing was modified
+        // an empty graph whose table was sized from this rejected input is
+        // sized again, from its input, by the next build
+        if (g->builds == 0 && !g->cap_req && !g->expected) g->cap = 0;
+        return err_code_of(st.err);
+    }
     g->k = k;
     g->fresh = false;
     ++g->epoch;

@@ -170,17 +170,23 @@ def test_errors_and_limits():
     with dbg.Graph() as g:
         st = dbg.build_batch([g], [(rs.reads, rs.offsets, 40)])
         assert st == [dbg.E_K]
-    # a table too small for the vertices: full, poisoned
-    with dbg.Graph(capacity=1000) as g:
-        with pytest.raises(dbg.DbgError) as e:
-            g.build(rs.reads, rs.offsets, 51)
-        assert e.value.code == dbg.E_FULL
     bad = readsim.reads_from_strings([b"ACGT" * 20 + b"N" + b"ACGT" * 20], 51)
-    with dbg.Graph() as g:
-        with pytest.raises(dbg.DbgError) as e:
-            g.build(bad.reads, bad.offsets, 51)
-        assert e.value.code == dbg.E_BASE
-        assert g.vertex_count() == 0
+    for mode in MODES:
+        # a table too small for the vertices (one segment when binned): full, poisoned
+        with dbg.Graph(capacity=1000, flags=mode) as g:
+            with pytest.raises(dbg.DbgError) as e:
+                g.build(rs.reads, rs.offsets, 51)
+            assert e.value.code == dbg.E_FULL
+            with pytest.raises(dbg.DbgError) as e:
+                g.build(rs.reads, rs.offsets, 51)
+            assert e.value.code == dbg.E_STATE
+        with dbg.Graph(flags=mode) as g:
+            with pytest.raises(dbg.DbgError) as e:
+                g.build(bad.reads, bad.offsets, 51)
+            assert e.value.code == dbg.E_BASE
+            assert g.vertex_count() == 0
+            g.build(rs.reads, rs.offsets, 51)  # a rejected input leaves the graph usable
+            check(g.extract_sorted(), want(rs, 51))
 
 
 def test_autotune_long_k():
