@@ -79,7 +79,8 @@ typedef struct dbg_graph dbg_graph;
  * exact number of slots; otherwise capacity = ceil(expected_vertices /
  * load_factor).  With both zero the table is sized at the first build as
  * ceil(windows / load_factor): the number of windows bounds the number of
- * distinct vertices, so that build cannot run out of slots.
+ * distinct vertices, so that build cannot run out of slots (if that first
+ * input is rejected, the next build sizes the table instead).
  */
 typedef struct {
     uint64_t expected_vertices;  /* estimate of distinct (k-1)-mers; 0 = from input */
