@@ -150,6 +150,23 @@ int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t
 int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
                      const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, void *stream);
 
+/* dbg_build_device followed by dbg_extract_device, as one call: build from
+ * device-resident input (arguments as dbg_build_device), then write every
+ * vertex of the resulting graph to d_keys / d_counts (as dbg_extract_device:
+ * cap entries, d_counts 16-byte aligned, unspecified order) and set
+ * *n_vertices.  The graph is the paper's makeGraph result (Algorithms 2-4)
+ * over all builds of the handle so far.  For a binned graph with k <= 31 the
+ * output is written by the build's last kernel, while each table segment is
+ * still on chip, instead of by a second pass over the table; otherwise the
+ * call builds and then extracts.  Synchronous (it waits for the build's
+ * status).  With d_keys == NULL only *n_vertices is set.  Errors: those of
+ * dbg_build_device (reported here, not by dbg_sync) and DBG_E_SPACE when cap
+ * is smaller than the vertex count: the graph is built, *n_vertices is set,
+ * and the output holds an unspecified subset of the vertices. */
+int dbg_build_extract_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
+                             const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, uint64_t *d_keys,
+                             uint32_t *d_counts, uint64_t cap, uint64_t *n_vertices, void *stream);
+
 /* Wait for the handle's outstanding work and return its status: DBG_OK or
  * the first error the device reported since the previous dbg_sync. */
 int dbg_sync(dbg_graph *g);

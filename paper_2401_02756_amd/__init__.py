@@ -36,6 +36,7 @@ EXPORTS = (
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
     "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
     "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device", "dbg_extract_normalized",
+    "dbg_build_extract_device",
 )
 NORM_U8 = 0x1
 TUNE_FORCE = 0x1
@@ -151,6 +152,8 @@ def lib() -> ctypes.CDLL:
             "dbg_sync": (ctypes.c_int, [vp]),
             "dbg_extract": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
             "dbg_extract_device": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
+            "dbg_build_extract_device": (ctypes.c_int, [vp, vp, u64, vp, u64, u32, vp, vp, u64,
+                                                        ctypes.POINTER(u64), vp]),
             "dbg_reset": (ctypes.c_int, [vp]),
             "dbg_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
             "dbg_destroy": (None, [vp]),
@@ -282,6 +285,23 @@ class Graph:
         rc = lib().dbg_build_device(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
                                     _stream(stream))
         _check(rc, "dbg_build_device")
+
+    def build_extract_device(self, d_reads, d_offsets, k: int, d_keys, d_counts, n_reads: int | None = None,
+                             reads_len: int | None = None, stream=None) -> int:
+        """``dbg_build_extract_device``: build from device tensors, then write
+        every vertex of the graph to d_keys / d_counts (device tensors, any
+        order).  Returns the vertex count."""
+        n = int(d_offsets.numel() - 1) if n_reads is None else int(n_reads)
+        ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+        kw = 2 if int(k) > 32 else 1
+        v = ctypes.c_uint64(0)
+        rc = lib().dbg_build_extract_device(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
+                                            _ptr(d_keys) if d_keys is not None else None,
+                                            _ptr(d_counts) if d_counts is not None else None,
+                                            int(d_keys.numel()) // kw if d_keys is not None else 0,
+                                            ctypes.byref(v), _stream(stream))
+        _check(rc, "dbg_build_extract_device")
+        return int(v.value)
 
     def sync(self) -> None:
         _check(lib().dbg_sync(self.handle), "dbg_sync")

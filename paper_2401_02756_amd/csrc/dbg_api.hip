@@ -183,6 +183,41 @@ static int extract_impl(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t
     return found == V ? DBG_OK : DBG_E_DEVICE;
 }
 
+int dbg_build_extract_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
+                             const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, uint64_t *d_keys,
+                             uint32_t *d_counts, uint64_t cap, uint64_t *n_vertices, void *stream) {
+    int rc = check_common(g, k, kMaxK);
+    if (rc != DBG_OK) return rc;
+    if (!n_vertices || (n_reads && !d_offsets) || (!d_reads && reads_len) || (d_keys && cap && !d_counts))
+        return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (!guard.ok) return DBG_E_DEVICE;
+    if (g->pass.pending) {
+        rc = harvest(g);
+        if (rc != DBG_OK) return rc;
+    }
+    hipStream_t s = g->pick(stream);
+    if (n_reads) {
+        rc = ensure_table(g, reads_len);
+        if (rc == DBG_OK) rc = settle_mode(g, k);
+        if (rc != DBG_OK) return rc;
+        // fused: binned, one-word records (the mode settle_mode chose for k)
+        const bool fuse = d_keys && g->binned && k <= 31;
+        rc = enqueue_single(g, d_reads, reads_len, d_offsets, n_reads, k, s, fuse ? d_keys : nullptr,
+                            fuse ? d_counts : nullptr, fuse ? cap : 0);
+        if (rc != DBG_OK) return rc;
+        rc = harvest(g);
+        if (rc != DBG_OK) return rc;
+        if (fuse) {
+            const uint64_t V = g->vertices;
+            *n_vertices = V;
+            if (g->pass.host_status()[0].emitted != V) return DBG_E_DEVICE;
+            return cap < V ? DBG_E_SPACE : DBG_OK;
+        }
+    }
+    return extract_impl(g, d_keys, d_counts, cap, n_vertices, true, s);
+}
+
 int dbg_extract(dbg_graph *g, uint64_t *keys, uint32_t *counts, uint64_t cap, uint64_t *n_vertices) {
     return extract_impl(g, keys, counts, cap, n_vertices, false, g ? g->stream : nullptr);
 }

@@ -866,6 +866,10 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     static_assert(RW == 1 || EW == 4, "long keys take 32-byte entries");
     const uint32_t m = args->m;
     const uint64_t parts_total = args->parts_total;
+    // fused extraction (one instance, one-word keys): see the write-back
+    uint64_t *__restrict__ xkeys = RW == 1 ? args->xkeys : nullptr;
+    uint4 *__restrict__ xcounts = reinterpret_cast<uint4 *>(args->xcounts);
+    const uint64_t xcap = args->xcap;
     static_assert(kSegSlots % kReduceBlock == 0 && kReduceBlock % 64 == 0, "slot ranges per wavefront");
     constexpr uint32_t kWaves = kReduceBlock / 64;
     constexpr uint32_t kWaveSlots = kSegSlots / kWaves;  // slots compacted by one wavefront
@@ -873,7 +877,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     __shared__ __align__(16) uint32_t s_cnt[kSegSlots * 4];
     __shared__ uint64_t s_start[kStartsChunk + 2];
     __shared__ uint32_t s_wave_n[kWaves];
-    __shared__ uint64_t s_sum;
+    __shared__ uint64_t s_sum, s_xbase;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t per_block = (parts_total + gridDim.x - 1) / gridDim.x;
     const uint64_t gp0 = min((uint64_t)blockIdx.x * per_block, parts_total);
@@ -991,6 +995,15 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             out += w2 < wave ? nw : 0u;
             total += nw;
         }
+        // Fused extraction: the segment's vertices also go to the caller's
+        // arrays at [xbase, xbase + total), reserved with one device atomic
+        // whose latency the table write-back below hides.  The order of
+        // segments in the output is whatever order the reservations land in.
+        uint64_t xbase = 0;
+        if (xkeys && tid == 0)
+            xbase = __hip_atomic_fetch_add(&st[cur_inst].emitted, (uint64_t)total, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t out0 = out;
         for (uint32_t c0w = 0; c0w < kWaveSlots; c0w += 64) {
             const uint32_t s = s0 + c0w + lane;
             const uint64_t tagv = s_key[s];
@@ -1000,10 +1013,33 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
                 seg[out + rank] = tagv & ~kReady;
                 if (RW == 2) seg[kSegSlots + out + rank] = s_key[kSegSlots + s];
                 seg_counts<RW>(seg)[out + rank] = reinterpret_cast<const uint4 *>(s_cnt)[s];
-                s_key[s] = 0;
-                reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+                if (!xkeys) {
+                    s_key[s] = 0;
+                    reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+                }
             }
             out += (uint32_t)__popcll(mask);
+        }
+        if (xkeys) {  // uniform
+            if (tid == 0) s_xbase = xbase;
+            __syncthreads();
+            const uint64_t xb = s_xbase;
+            out = out0;
+            for (uint32_t c0w = 0; c0w < kWaveSlots; c0w += 64) {
+                const uint32_t s = s0 + c0w + lane;
+                const uint64_t tagv = s_key[s];
+                const uint64_t mask = __ballot(tagv != 0);
+                if (tagv) {
+                    const uint64_t o = xb + out + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+                    if (o < xcap) {
+                        xkeys[o] = key_of_image(tagv & ~kOccupied);
+                        xcounts[o] = reinterpret_cast<const uint4 *>(s_cnt)[s];
+                    }
+                    s_key[s] = 0;
+                    reinterpret_cast<uint4 *>(s_cnt)[s] = make_uint4(0, 0, 0, 0);
+                }
+                out += (uint32_t)__popcll(mask);
+            }
         }
         if (tid == 0) in.seg_count[seg_idx] = total;
         __syncthreads();

@@ -39,6 +39,7 @@ __global__ void k_prepare(const PassArgs *__restrict__ args, Instance *inst, Ins
         st[i].claimed = 0;
         st[i].inserts = 0;
         st[i].windows = 0;
+        st[i].emitted = 0;
         // byte range of the instance, relative to the first read's first byte
         if (n) {
             const uint64_t off0 = off[0];

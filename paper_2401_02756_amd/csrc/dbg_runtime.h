@@ -360,9 +360,12 @@ struct Pass {
     // prior k-mers, k, entry words, and the segment geometry when binned).
     // Reads are device-resident: read i is d_reads[off[i] - off[0] ..
     // off[i+1] - off[0]).
+    // xkeys / xcounts / xcap: the fused extraction of a one-instance binned
+    // pass with one-word keys (PassArgs); null otherwise.
     hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
                        uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
-                       bool time_it, hipStream_t s) {
+                       bool time_it, hipStream_t s, uint64_t *xkeys = nullptr, uint32_t *xcounts = nullptr,
+                       uint64_t xcap = 0) {
         PassKey k;
         k.binned = binned ? 1 : 0;
         k.single = mm == 1 ? 1 : 0;
@@ -414,6 +417,11 @@ struct Pass {
         a.m = mm;
         a.check_ends = check_ends ? 1 : 0;
         a.tile = (uint32_t)T;
+        if (binned && mm == 1 && k.rw == 1 && xkeys) {
+            a.xkeys = xkeys;
+            a.xcounts = xcounts;
+            a.xcap = xcap;
+        }
 
         Cached *c = nullptr;
         if (use_graphs) {
@@ -687,7 +695,8 @@ inline int check_common(dbg_graph *g, uint32_t k, uint32_t kmax = kMaxKWord) {
 }
 
 inline int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
-                   uint64_t n, uint32_t k, hipStream_t s) {
+                   uint64_t n, uint32_t k, hipStream_t s, uint64_t *xkeys = nullptr, uint32_t *xcounts = nullptr,
+                   uint64_t xcap = 0) {
     hipError_t e = g->pass.reserve_instances(1);
     if (e != hipSuccess) return hip_code(e);
     fill_instance(g->pass.host_instances()[0], g, 0, n, k);
@@ -698,7 +707,7 @@ inline int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, co
         shape.merge = 0;
     }
     e = g->pass.enqueue(1, d_reads, len, d_off, n, shape, g->binned, g->device, true,
-                        (g->flags & DBG_F_TIMING) != 0, s);
+                        (g->flags & DBG_F_TIMING) != 0, s, xkeys, xcounts, xcap);
     if (e != hipSuccess) return hip_code(e);
     g->pending_k = k;
     return DBG_OK;
