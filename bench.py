@@ -258,7 +258,7 @@ def served_bench(dbg, torch, dev, n_payloads: int, n_requests: int, loads, ref_g
 def large_bench(dbg, torch, dev, steps: int, graphs_on: bool) -> dict:
     """The large plain build (100 Mbp genome with 2 % in repeats, 150 bp reads
     at 20x, 1 % substitutions, k=31): binned mode at load factor 0.5, steps
-    of reset + build + sync as in the headline run (extraction timed apart)."""
+    of reset + build + sync, without an output (extraction timed apart)."""
     import readsim
 
     t0 = time.perf_counter()

@@ -846,8 +846,10 @@ __device__ __forceinline__ bool reduce_record(ulonglong2 rec, uint64_t *s_key, u
 // vertices the table already holds (packed at entries [0, seg_count)) are
 // re-inserted, every record of the segment is found-or-claimed and counted
 // with LDS atomics, and the occupied slots are written back packed, with the
-// new seg_count.  Each workgroup takes a contiguous run of segments, so it
-// meets few instances and flushes its claim count once per instance.
+// new seg_count.  With a fused extraction (PassArgs.xkeys) they are also
+// written, as keys and counters, to the caller's output arrays.  Each
+// workgroup takes a contiguous run of segments, so it meets few instances
+// and flushes its claim count once per instance.
 //
 // Nothing global sits on the path from one segment to the next: segment
 // starts are read 256 at a time into LDS, the instance (and whether it is
