@@ -1,11 +1,12 @@
 """Different handles used from several host threads at once.
 
 The C ABI lets each handle be driven by its own thread (one handle is never
-shared between threads).  Here five threads run at the same time, each with
+shared between threads).  Here six threads run at the same time, each with
 its own handles and its own seeded read sets: binned and direct builds from
 host buffers, a captured binned build from device buffers, a merged direct
-build, and batched builds (whose per-device launch state is shared by every
-thread).  Every graph must equal the oracle's bit for bit.
+build, batched builds (whose per-device launch state is shared by every
+thread), and captured binned builds whose graph comes out of the same call.
+Every graph must equal the oracle's bit for bit.
 """
 
 import threading
@@ -67,6 +68,20 @@ def device_build(flags):
     return run
 
 
+def fused_build(rs):
+    d_reads = torch.from_numpy(rs.reads).cuda()
+    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
+    cap = 400_000
+    keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+    counts = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
+    with dbg.Graph(flags=dbg.F_BINNED | dbg.F_GRAPH) as g:
+        n = g.build_extract_device(d_reads, d_off, rs.k, keys, counts)
+    k = keys.cpu().numpy().view(np.uint64)[:n]
+    c = counts.cpu().numpy().view(np.uint32)[:n]
+    order = np.argsort(k, kind="stable")
+    return [(k[order], c[order])]
+
+
 def batch_build(sets):
     graphs = [dbg.Graph(flags=dbg.F_BINNED) for _ in sets]
     try:
@@ -84,6 +99,7 @@ WORKERS = [
     ("binned, captured, device input", device_build(dbg.F_BINNED | dbg.F_GRAPH), 1),
     ("direct with wave merge, device input", device_build(dbg.F_MERGE), 1),
     ("batched, three graphs", batch_build, 3),
+    ("binned build with the vertices written by its reduce", fused_build, 1),
 ]
 
 
