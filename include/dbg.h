@@ -155,10 +155,10 @@ int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
  * vertex of the resulting graph to d_keys / d_counts (as dbg_extract_device:
  * cap entries, d_counts 16-byte aligned, unspecified order) and set
  * *n_vertices.  The graph is the paper's makeGraph result (Algorithms 2-4)
- * over all builds of the handle so far.  For a binned graph with k <= 31 the
- * output is written by the build's last kernel, while each table segment is
- * still on chip, instead of by a second pass over the table; otherwise the
- * call builds and then extracts.  Synchronous (it waits for the build's
+ * over all builds of the handle so far.  For a binned graph (k <= 31 or
+ * 33 <= k <= 63) the output is written by the build's last kernel, while
+ * each table segment is still on chip, instead of by a second pass over the
+ * table; otherwise the call builds and then extracts.  Synchronous (it waits for the build's
  * status).  With d_keys == NULL only *n_vertices is set.  Errors: those of
  * dbg_build_device (reported here, not by dbg_sync) and DBG_E_SPACE when cap
  * is smaller than the vertex count: the graph is built, *n_vertices is set,

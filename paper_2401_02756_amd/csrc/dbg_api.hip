@@ -201,8 +201,8 @@ int dbg_build_extract_device(dbg_graph *g, const uint8_t *d_reads, uint64_t read
         rc = ensure_table(g, reads_len);
         if (rc == DBG_OK) rc = settle_mode(g, k);
         if (rc != DBG_OK) return rc;
-        // fused: binned, one-word records (the mode settle_mode chose for k)
-        const bool fuse = d_keys && g->binned && k <= 31;
+        // fused: a binned build (the mode settle_mode chose for k)
+        const bool fuse = d_keys && g->binned;
         rc = enqueue_single(g, d_reads, reads_len, d_offsets, n_reads, k, s, fuse ? d_keys : nullptr,
                             fuse ? d_counts : nullptr, fuse ? cap : 0);
         if (rc != DBG_OK) return rc;

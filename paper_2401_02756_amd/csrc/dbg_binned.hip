@@ -868,8 +868,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     static_assert(RW == 1 || EW == 4, "long keys take 32-byte entries");
     const uint32_t m = args->m;
     const uint64_t parts_total = args->parts_total;
-    // fused extraction (one instance, one-word keys): see the write-back
-    uint64_t *__restrict__ xkeys = RW == 1 ? args->xkeys : nullptr;
+    // fused extraction (one instance): see the write-back
+    uint64_t *__restrict__ xkeys = args->xkeys;
     uint4 *__restrict__ xcounts = reinterpret_cast<uint4 *>(args->xcounts);
     const uint64_t xcap = args->xcap;
     static_assert(kSegSlots % kReduceBlock == 0 && kReduceBlock % 64 == 0, "slot ranges per wavefront");
@@ -1034,7 +1034,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
                 if (tagv) {
                     const uint64_t o = xb + out + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
                     if (o < xcap) {
-                        xkeys[o] = key_of_image(tagv & ~kOccupied);
+                        if constexpr (RW == 1) {
+                            xkeys[o] = key_of_image(tagv & ~kOccupied);
+                        } else {  // two key words per record: K >> 64, K mod 2^64
+                            uint64_t kh, kl;
+                            wide_key(tagv & ~(kOccupied | kReady), s_key[kSegSlots + s], kh, kl);
+                            xkeys[2 * o] = kh;
+                            xkeys[2 * o + 1] = kl;
+                        }
                         xcounts[o] = reinterpret_cast<const uint4 *>(s_cnt)[s];
                     }
                     s_key[s] = 0;

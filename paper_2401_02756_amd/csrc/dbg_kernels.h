@@ -78,9 +78,9 @@ struct PassArgs {
     uint64_t max_windows;   // more windows than this flags every instance invalid
     uint64_t tile_cap;      // direct build: tile map entries
     uint64_t parts_total;   // binned build: segments over all instances
-    uint64_t *xkeys;        // binned build of one instance with one-word keys: when set, the
-    uint32_t *xcounts;      // reduce also writes every vertex of the graph to these arrays
-    uint64_t xcap;          // (keys, four counters each; entries past xcap are dropped)
+    uint64_t *xkeys;        // binned build of one instance: when set, the reduce also writes
+    uint32_t *xcounts;      // every vertex of the graph to these arrays (keys of one or two
+    uint64_t xcap;          // words, four counters each; entries past xcap are dropped)
     uint32_t m;             // instances
     uint32_t check_ends;    // require off[n] - off[0] == reads_len
     uint32_t tile;          // direct build: windows per tile

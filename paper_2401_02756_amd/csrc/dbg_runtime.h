@@ -361,7 +361,7 @@ struct Pass {
     // Reads are device-resident: read i is d_reads[off[i] - off[0] ..
     // off[i+1] - off[0]).
     // xkeys / xcounts / xcap: the fused extraction of a one-instance binned
-    // pass with one-word keys (PassArgs); null otherwise.
+    // pass (PassArgs); null otherwise.
     hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
                        uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
                        bool time_it, hipStream_t s, uint64_t *xkeys = nullptr, uint32_t *xcounts = nullptr,
@@ -417,7 +417,7 @@ struct Pass {
         a.m = mm;
         a.check_ends = check_ends ? 1 : 0;
         a.tile = (uint32_t)T;
-        if (binned && mm == 1 && k.rw == 1 && xkeys) {
+        if (binned && mm == 1 && xkeys) {
             a.xkeys = xkeys;
             a.xcounts = xcounts;
             a.xcap = xcap;

@@ -1,10 +1,12 @@
 """dbg_build_extract_device: a build whose graph comes out in the same call.
 
-For a binned graph with k <= 31 the vertices are written by the build's
-reduce kernel, one reserved range per table segment; otherwise the call
-builds and then extracts.  Either way the records, sorted, must equal the
+For a binned graph (k <= 31, or 33 <= k <= 63 with two-word keys) the
+vertices are written by the build's reduce kernel, one reserved range per
+table segment; otherwise the call builds and then extracts.  Either way the records, sorted, must equal the
 oracle's graph over every build of the handle, bit for bit.
 """
+
+import dataclasses
 
 import numpy as np
 import pytest
@@ -112,11 +114,22 @@ def test_fused_accumulates_and_reports_space():
         assert g.build_extract_device(e_reads, e_off, rs.k, None, None) == V
 
 
+@pytest.mark.parametrize("k", [33, 45, 63])
+def test_fused_long_k_matches_oracle(k):
+    rs = readsim.make_config(1)
+    say("fused binned build of two-word keys, k = %d" % k)
+    hi, lo, wc = oracle.build_graph_wide(rs.reads, rs.offsets, k)
+    with dbg.Graph(load_factor=0.5, flags=dbg.F_BINNED) as g:
+        got, n = fused(g, dataclasses.replace(rs, k=k), hi.shape[0] + 5, kw=2)
+        assert g.stats()["binned"] == 1 and n == hi.shape[0]
+    assert_same(got, (np.stack([hi, lo], axis=1), wc), "fused output, k = %d" % k)
+
+
 @pytest.mark.parametrize("flags,k", [(0, 21), (dbg.F_MERGE, 31), (dbg.F_BINNED, 32), (dbg.F_BINNED, 45),
                                      (0, 51)])
-def test_unfused_modes_build_then_extract(flags, k):
+def test_other_modes_equal_extract(flags, k):
     rs = readsim.make_config(1)
-    say("build + extract path: flags %d, k = %d" % (flags, k))
+    say("build_extract_device vs dbg_extract: flags %d, k = %d" % (flags, k))
     kw = 2 if k > 32 else 1
     with dbg.Graph(load_factor=0.5, flags=flags) as g:
         d_reads, d_off = dev(rs)
