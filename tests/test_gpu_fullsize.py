@@ -1,8 +1,10 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times (binned build with captured passes, load factor 0.5; the
-served runs through the server's defaults).
+benchmark times (binned build with captured passes: the bacterial step's
+dbg_build_extract_device at the tuned load factor 0.4, the large build at
+0.5; the served runs through the server's defaults).
 
-  * bacterial scale (5 Mbp, 120M k-mers): every vertex against the oracle;
+  * bacterial scale (5 Mbp, 120M k-mers): every vertex against the oracle,
+    both as the step writes them and as dbg_extract reads the table;
   * large (100 Mbp, 1.6G k-mers): totals for the whole graph, and every
     vertex of two of 256 key-space partitions against the oracle (the
     oracle restricted to a partition is exact for it);
@@ -58,14 +60,21 @@ def test_bacterial_full_exact():
     say("bacterial scale: %d reads, k=%d" % (rs.n_reads, rs.k))
     d_reads = torch.from_numpy(rs.reads).cuda()
     d_off = torch.from_numpy(rs.offsets.astype(np.int64)).cuda()
-    with dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.5,
+    with dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.4,
                    flags=dbg.F_BINNED | dbg.F_GRAPH) as g:
+        cap = int(g.stats()["capacity"])
+        d_keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+        d_counts = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
         for _ in range(2):  # the second build replays the captured pass
             g.reset()
-            g.build_device(d_reads, d_off, rs.k)
-            g.sync()
-        got = g.extract_sorted()
-    same(got, oracle.build_graph_parallel(rs.reads, rs.offsets, rs.k, threads=THREADS), "bacterial")
+            n = g.build_extract_device(d_reads, d_off, rs.k, d_keys, d_counts)
+        keys = d_keys[:n].cpu().numpy().view(np.uint64)
+        counts = d_counts[:n].cpu().numpy().view(np.uint32)
+        order = np.argsort(keys, kind="stable")
+        from_table = g.extract_sorted()
+    want = oracle.build_graph_parallel(rs.reads, rs.offsets, rs.k, threads=THREADS)
+    same((keys[order], counts[order]), want, "bacterial, the step's output")
+    same(from_table, want, "bacterial, dbg_extract")
 
 
 @pytest.mark.timeout(600)
