@@ -606,7 +606,9 @@ def main() -> int:
                    "load_factor": args.load_factor, "entry_bytes": st["entry_bytes"],
                    "block": st["block_size"], "windows_per_thread": st["windows_per_thread"],
                    "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode,
-                   "hip_graphs": not args.no_graph},
+                   "hip_graphs": not args.no_graph,
+                   "step": "reset + dbg_build_extract_device (build, every vertex written to device "
+                           "buffers, status read back)"},
         "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
         "extract_separate_ms": round(r["extract_ms"], 4),  # dbg_extract_device on the built graph
         "autotune": tuning,
