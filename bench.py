@@ -2,8 +2,9 @@
 
 One step is one pass of the whole plain-build path over the bacterial-scale
 workload (5 Mbp genome with 50 copies of a 1 kbp repeat, 150 bp reads at 30x =
-1,000,000 reads, 1 % substitutions, k = 31, table load factor 0.5), with the
-ASCII reads and offsets already resident in HBM:
+1,000,000 reads, 1 % substitutions, k = 31; binned table at the autotuned
+load factor, 0.4 in practice), with the ASCII reads and offsets already
+resident in HBM:
 
     table reset -> pack -> window scan -> build (find-or-claim + count)
     -> every vertex written to device buffers -> status readback
@@ -15,11 +16,14 @@ and the metric is k-mer inserts per second, inserts = sum over reads of
 max(0, L - k + 1) = 120,000,000 per step.
 
 Besides the driver's JSON fields the line carries:
-  * roofline       -- the build kernel (the dominant one) against HBM peak,
-                      with the algorithmic bytes per launch;
-  * atomic_roofline-- the same kernel against the measured rate of random
-                      64-bit compare-and-swap (and of the other random
-                      access kinds) at the table's footprint and op count;
+  * roofline       -- the longest kernel (binned: the segment reduce;
+                      direct: the build) against HBM peak, with the
+                      algorithmic bytes per launch and, from the committed
+                      counter profile, the HBM traffic;
+  * atomic_roofline-- the build pass and the step against the measured rate
+                      of random 64-bit compare-and-swap (and of the other
+                      random access kinds) at the table's footprint and op
+                      count;
   * cpu_baseline   -- the CPU oracle on a bounded sample of the same reads.
 """
 
