@@ -331,11 +331,12 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 
 // ---------------------------------------------------------------- pass 1
 
-// Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max],
-// s_rec[kBinTile] and, for one-word records, s_bin[kBinTile] when scattering).
+// Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max]
+// and s_rec[kBinTile] when scattering; the write-out recomputes each
+// record's bucket rather than keep it in LDS beside the record).
 __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + 8 * rw * kBinTile + (rw == 1 ? 2 * kBinTile : 0);
+    if (scatter) b += align16(8 * d1_max) + 8 * rw * kBinTile;
     return b;
 }
 
@@ -364,7 +365,6 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (d1_max + 1)));
     R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (d1_max + 1)) + align16(8 * d1_max));  // 16-byte aligned
-    uint16_t *s_bin = reinterpret_cast<uint16_t *>(s_rec + kBinTile);  // RW = 1 only
     R *rec1 = reinterpret_cast<R *>(rec1w);
     const uint32_t tid = threadIdx.x;
     const uint32_t m = args->m;
@@ -457,12 +457,11 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
             if (bk == d1) continue;  // past the tile's end
             const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
             s_rec[pos] = rec[q];
-            if (RW == 1) s_bin[pos] = (uint16_t)bk;
         }
         __syncthreads();
         for (uint32_t j = tid; j < n_in; j += blockDim.x) {
             const R r = s_rec[j];
-            const uint32_t bk = RW == 1 ? s_bin[j] : bucket_of(image_top(RecOf<RW>::head(r) >> 3), d1);
+            const uint32_t bk = bucket_of(image_top(RecOf<RW>::head(r) >> 3), d1);
             rec1[s_gbase[bk] + j] = r;
         }
         __syncthreads();
