@@ -104,6 +104,8 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_get_stats(None, None) == dbg.E_INVAL
     n = ctypes.c_uint64()
     assert L.dbg_extract(None, None, None, 0, ctypes.byref(n)) == dbg.E_INVAL
+    assert L.dbg_build_extract_device(None, None, 0, None, 1, 21, None, None, 0, ctypes.byref(n),
+                                      None) == dbg.E_INVAL
     L.dbg_destroy(None)
     assert L.dbg_build_batch(None, None, 0, None, None) == dbg.OK
     assert L.dbg_build_batch(None, None, 2, None, None) == dbg.E_INVAL
