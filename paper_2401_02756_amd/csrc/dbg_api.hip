@@ -374,6 +374,7 @@ int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t 
     std::vector<uint32_t> ks(m);
     std::vector<int32_t> pre(m, DBG_OK);
     uint64_t total_bytes = 0, total_reads = 0;
+    std::vector<uint64_t> bound(m, 0);  // each instance's windows: the size of an unsized graph
     for (uint32_t i = 0; i < m; ++i) {
         const dbg_input &in = inputs[i];
         ks[i] = in.k;
@@ -387,6 +388,7 @@ int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t 
             rc = DBG_E_INVAL;
         if (rc == DBG_OK && graphs[i]->inserts + km > kCounterLimit) rc = DBG_E_RANGE;
         pre[i] = rc;
+        bound[i] = w;
         if (rc == DBG_OK && in.n_reads) {
             total_reads += in.n_reads;
             total_bytes += in.offsets[in.n_reads] - in.offsets[0];
@@ -424,13 +426,14 @@ int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t 
     std::vector<uint64_t> rb(read_begin);
     std::vector<dbg_graph *> run_g;
     std::vector<uint32_t> run_k;
-    std::vector<uint64_t> run_rb;
+    std::vector<uint64_t> run_rb, run_bound;
     std::vector<uint32_t> where;
     for (uint32_t i = 0; i < m; ++i) {
         if (pre[i] != DBG_OK) continue;
         run_g.push_back(gs[i]);
         run_k.push_back(kk[i]);
         run_rb.push_back(rb[i]);
+        run_bound.push_back(bound[i]);
         where.push_back(i);
     }
     for (uint32_t i = 0; i < m; ++i) statuses[i] = pre[i];
@@ -439,8 +442,8 @@ int dbg_build_batch(dbg_graph *const *graphs, const dbg_input *inputs, uint32_t 
     std::vector<int32_t> st(run_g.size(), DBG_OK);
     if (total_reads == 0) return first_error(statuses, m);
     batch_device_impl(run_g.data(), (uint32_t)run_g.size(), run_rb.data(), run_k.data(),
-                      ctx->reads.as<uint8_t>(), byte_at, ctx->offsets.as<uint64_t>(), st.data(), s,
-                      ctx, true);
+                      ctx->reads.as<uint8_t>(), byte_at, ctx->offsets.as<uint64_t>(), run_bound.data(), st.data(),
+                      s, ctx, true);
     for (size_t j = 0; j < where.size(); ++j) statuses[where[j]] = st[j];
     return first_error(statuses, m);
 }
@@ -470,7 +473,7 @@ int dbg_build_batch_device(dbg_graph *const *graphs, uint32_t m, const uint64_t 
         for (uint32_t i = 0; i < m; ++i) statuses[i] = check_common(graphs[i], ks[i]);
         return first_error(statuses, m);
     }
-    batch_device_impl(graphs, m, read_begin, ks, d_reads, reads_len, d_offsets, statuses, s, ctx, true);
+    batch_device_impl(graphs, m, read_begin, ks, d_reads, reads_len, d_offsets, nullptr, statuses, s, ctx, true);
     return first_error(statuses, m);
 }
 

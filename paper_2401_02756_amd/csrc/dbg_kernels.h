@@ -200,6 +200,8 @@ inline uint64_t max_tiles(uint64_t bytes, uint64_t tile) { return bytes / tile +
 hipError_t launch_prepare(const PassArgs *args, Instance *inst, InstStatus *st, CallState *cs,
                           uint32_t m_cap, hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *words, uint64_t n_words, hipStream_t s);
+// out[i] = src[idx[i]] for i < n (device arrays).
+hipError_t launch_gather_u64(const uint64_t *src, const uint64_t *idx, uint64_t n, uint64_t *out, hipStream_t s);
 hipError_t launch_pack(const PassArgs *args, uint64_t *packed, const Instance *inst, InstStatus *st,
                        uint64_t len_cap, hipStream_t s);
 // tile_read may be null (no tile map).

@@ -63,6 +63,12 @@ __global__ void k_fill_zero(uint64_t *__restrict__ words, uint64_t n_words) {
     if ((n_words & 1) && blockIdx.x == 0 && threadIdx.x == 0) words[n_words - 1] = 0;
 }
 
+__global__ void k_gather_u64(const uint64_t *__restrict__ src, const uint64_t *__restrict__ idx, uint64_t n,
+                             uint64_t *__restrict__ out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = src[idx[i]];
+}
+
 // ---------------------------------------------------------------- pack
 
 // One thread per output word: 32 bases, letter code (c >> 1) & 3, first base
@@ -874,6 +880,12 @@ hipError_t launch_prepare(const PassArgs *args, Instance *inst, InstStatus *st, 
     const uint32_t threads = 256;
     const uint32_t blocks = (m_cap + threads - 1) / threads;
     hipLaunchKernelGGL(k_prepare, dim3(blocks ? blocks : 1), dim3(threads), 0, s, args, inst, st, cs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u64(const uint64_t *src, const uint64_t *idx, uint64_t n, uint64_t *out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_u64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, src, idx, n, out);
     return hipGetLastError();
 }
 

@@ -136,7 +136,8 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
     return (x + g - 1) / g * g;
 }
 
-// What a captured pass depends on besides its buffers.
+// What a captured pass depends on besides its buffers.  Every buffer of a
+// pass is sized from these capacities (pass_key, bin_caps, PassSizes).
 struct PassKey {
     int binned = 0;
     int single = 0;
@@ -154,6 +155,111 @@ struct PassKey {
                shape.wpt == o.shape.wpt && shape.grid == o.shape.grid && shape.merge == o.shape.merge;
     }
 };
+
+// Capacities of a pass over mm instances (host instances hi filled), n reads
+// and len bytes.
+inline PassKey pass_key(uint32_t mm, uint64_t n, uint64_t len, dbgk::BuildShape shape, bool binned,
+                        const Instance *hi) {
+    PassKey k;
+    k.binned = binned ? 1 : 0;
+    k.single = mm == 1 ? 1 : 0;
+    k.shape = shape;
+    k.wide = (mm == 1 && !binned && hi[0].k > 32) ? 1 : 0;
+    k.rw = (mm == 1 && binned && hi[0].k > 32) ? 2 : 1;  // long keys: one graph at a time
+    k.m_cap = (uint32_t)size_class(mm, 1);
+    k.n_cap = size_class(n, 1024);
+    k.len_cap = size_class(len, 4096);
+    uint64_t P = 0, G1 = 0;
+    uint32_t d1max = 1, fanmax = 1;
+    for (uint32_t i = 0; i < mm; ++i) {
+        P += hi[i].parts;
+        G1 += hi[i].d1;
+        d1max = std::max(d1max, hi[i].d1);
+        fanmax = std::max(fanmax, hi[i].fan);
+        if (hi[i].parts) k.ew = hi[i].entry_words;
+    }
+    if (binned) {
+        k.parts_cap = size_class(P, 64);
+        k.buckets_cap = size_class(G1, 64);
+        k.d1_cap = (uint32_t)std::min<uint64_t>(size_class(d1max, 16), dbgk::kMaxD1);
+        k.fan_cap = (uint32_t)std::min<uint64_t>(size_class(fanmax, 16), dbgk::kMaxFan);
+    }
+    return k;
+}
+
+// Capacities (not pointers) of the binned scratch of a key.
+inline void bin_caps(const PassKey &k, dbgk::BinBuffers &bb) {
+    bb.tiles1_cap = k.len_cap / dbgk::kBinTile + k.m_cap + 1;
+    bb.hist1_cap = (uint64_t)k.d1_cap * bb.tiles1_cap;
+    bb.tiles2_cap = k.len_cap / dbgk::kRefTile + k.buckets_cap + 1;
+    bb.hist2_cap = (uint64_t)k.fan_cap * bb.tiles2_cap;
+    const uint64_t chunk = 1024;
+    bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
+    bb.buckets_cap = k.buckets_cap;
+    bb.parts_cap = k.parts_cap;
+    bb.d1_max = k.d1_cap;
+    bb.fan_max = k.fan_cap;
+    bb.entry_words = k.ew;
+    bb.rec_words = k.rw;
+}
+
+// Byte sizes of every device buffer of a pass with key k (bb: bin_caps(k)).
+struct PassSizes {
+    // common: packed reads, window prefix, scan partials, arguments, status, tile map
+    uint64_t packed, ws, partials, args, status, tiles;
+    // binned
+    uint64_t plan, buckets, totals, hist1, scan1, hist2, scan2, bpartials, rec1, rec2, pstart, tread1, tile2;
+    uint64_t tile_cap;  // direct build: tile map entries
+    PassSizes(const PassKey &k, const dbgk::BinBuffers &bb) {
+        const uint64_t T = (uint64_t)k.shape.block * k.shape.wpt;
+        tile_cap = dbgk::max_tiles(k.len_cap, T);
+        packed = dbgk::packed_words(k.len_cap) * 8;
+        ws = (k.n_cap + 1) * 8;
+        partials = std::max<uint64_t>(1, dbgk::scan_blocks(k.n_cap)) * 16 + 8;
+        args = dbgk::kArgsBytes + sizeof(Instance) * k.m_cap;
+        status = sizeof(InstStatus) * k.m_cap + sizeof(CallState);
+        tiles = k.binned ? 0 : tile_cap * 8;
+        const bool b = k.binned != 0;
+        plan = b ? sizeof(dbgk::BinPlan) * k.m_cap : 0;
+        buckets = b ? sizeof(dbgk::Bucket) * std::max<uint64_t>(k.buckets_cap, 1) : 0;
+        totals = b ? sizeof(dbgk::BinTotals) : 0;
+        hist1 = b ? 4 * bb.hist1_cap : 0;
+        scan1 = b ? 8 * (bb.hist1_cap + 1) : 0;
+        hist2 = b ? 4 * bb.hist2_cap : 0;
+        scan2 = b ? 8 * (bb.hist2_cap + 1) : 0;
+        bpartials = b ? 8 * bb.partials_cap : 0;
+        rec1 = b ? 8 * k.rw * k.len_cap : 0;
+        rec2 = rec1;
+        pstart = b ? 8 * (k.parts_cap + 1) : 0;
+        tread1 = b ? 8 * bb.tiles1_cap : 0;
+        tile2 = b ? sizeof(dbgk::RefTile) * bb.tiles2_cap : 0;
+    }
+};
+
+// The argument block of a pass (PassArgs) for key k.
+inline void fill_args(dbgk::PassArgs &a, const PassKey &k, const PassSizes &z, uint32_t mm, const Instance *hi,
+                      const uint8_t *d_reads, uint64_t len, const uint64_t *d_off, uint64_t n, bool check_ends,
+                      uint64_t *xkeys, uint32_t *xcounts, uint64_t xcap) {
+    const uint64_t T = (uint64_t)k.shape.block * k.shape.wpt;
+    uint64_t P = 0;
+    for (uint32_t i = 0; i < mm; ++i) P += hi[i].parts;
+    std::memset(&a, 0, sizeof a);
+    a.reads = d_reads;
+    a.off = d_off;
+    a.n_reads = n;
+    a.reads_len = len;
+    a.max_windows = k.binned ? len : (z.tile_cap - 1) * T;
+    a.tile_cap = z.tile_cap;
+    a.parts_total = P;
+    a.m = mm;
+    a.check_ends = check_ends ? 1 : 0;
+    a.tile = (uint32_t)T;
+    if (k.binned && mm == 1 && xkeys) {
+        a.xkeys = xkeys;
+        a.xcounts = xcounts;
+        a.xcap = xcap;
+    }
+}
 
 // Buffers and launch sequence of one build pass over m instances.  With
 // graphs enabled the pass is captured as two HIP graphs (setup: arguments,
@@ -241,32 +347,16 @@ struct Pass {
 
     // Reserve the binned-mode scratch for the key's capacities.
     hipError_t reserve_binned(const PassKey &k, dbgk::BinBuffers &bb) {
-        bb.tiles1_cap = k.len_cap / dbgk::kBinTile + k.m_cap + 1;
-        bb.hist1_cap = (uint64_t)k.d1_cap * bb.tiles1_cap;
-        bb.tiles2_cap = k.len_cap / dbgk::kRefTile + k.buckets_cap + 1;
-        bb.hist2_cap = (uint64_t)k.fan_cap * bb.tiles2_cap;
-        const uint64_t chunk = 1024;
-        bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
-        bb.buckets_cap = k.buckets_cap;
-        bb.parts_cap = k.parts_cap;
-        bb.d1_max = k.d1_cap;
-        bb.fan_max = k.fan_cap;
-        bb.entry_words = k.ew;
-        bb.rec_words = k.rw;
+        bin_caps(k, bb);
+        const PassSizes z(k, bb);
         hipError_t e;
-        if ((e = grow(bplan, sizeof(dbgk::BinPlan) * k.m_cap)) != hipSuccess ||
-            (e = grow(bbuckets, sizeof(dbgk::Bucket) * std::max<uint64_t>(k.buckets_cap, 1))) != hipSuccess ||
-            (e = grow(btotals, sizeof(dbgk::BinTotals))) != hipSuccess ||
-            (e = grow(hist1, 4 * bb.hist1_cap)) != hipSuccess ||
-            (e = grow(scan1, 8 * (bb.hist1_cap + 1))) != hipSuccess ||
-            (e = grow(hist2, 4 * bb.hist2_cap)) != hipSuccess ||
-            (e = grow(scan2, 8 * (bb.hist2_cap + 1))) != hipSuccess ||
-            (e = grow(bpartials, 8 * bb.partials_cap)) != hipSuccess ||
-            (e = grow(rec1, 8 * k.rw * k.len_cap)) != hipSuccess ||
-            (e = grow(rec2, 8 * k.rw * k.len_cap)) != hipSuccess ||
-            (e = grow(pstart, 8 * (k.parts_cap + 1))) != hipSuccess ||
-            (e = grow(tread1, 8 * bb.tiles1_cap)) != hipSuccess ||
-            (e = grow(tbucket2, sizeof(dbgk::RefTile) * bb.tiles2_cap)) != hipSuccess)
+        if ((e = grow(bplan, z.plan)) != hipSuccess || (e = grow(bbuckets, z.buckets)) != hipSuccess ||
+            (e = grow(btotals, z.totals)) != hipSuccess || (e = grow(hist1, z.hist1)) != hipSuccess ||
+            (e = grow(scan1, z.scan1)) != hipSuccess || (e = grow(hist2, z.hist2)) != hipSuccess ||
+            (e = grow(scan2, z.scan2)) != hipSuccess || (e = grow(bpartials, z.bpartials)) != hipSuccess ||
+            (e = grow(rec1, z.rec1)) != hipSuccess || (e = grow(rec2, z.rec2)) != hipSuccess ||
+            (e = grow(pstart, z.pstart)) != hipSuccess || (e = grow(tread1, z.tread1)) != hipSuccess ||
+            (e = grow(tbucket2, z.tile2)) != hipSuccess)
             return e;
         bb.plan = bplan.as<dbgk::BinPlan>();
         bb.buckets = bbuckets.as<dbgk::Bucket>();
@@ -366,62 +456,19 @@ struct Pass {
                        uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
                        bool time_it, hipStream_t s, uint64_t *xkeys = nullptr, uint32_t *xcounts = nullptr,
                        uint64_t xcap = 0) {
-        PassKey k;
-        k.binned = binned ? 1 : 0;
-        k.single = mm == 1 ? 1 : 0;
-        k.shape = shape;
-        k.wide = (mm == 1 && !binned && host_instances()[0].k > 32) ? 1 : 0;
-        k.rw = (mm == 1 && binned && host_instances()[0].k > 32) ? 2 : 1;  // long keys: one graph at a time
-        k.m_cap = (uint32_t)size_class(mm, 1);
-        k.n_cap = size_class(n, 1024);
-        k.len_cap = size_class(len, 4096);
         const Instance *hi = host_instances();
-        uint64_t P = 0, G1 = 0;
-        uint32_t d1max = 1, fanmax = 1;
-        for (uint32_t i = 0; i < mm; ++i) {
-            P += hi[i].parts;
-            G1 += hi[i].d1;
-            d1max = std::max(d1max, hi[i].d1);
-            fanmax = std::max(fanmax, hi[i].fan);
-            if (hi[i].parts) k.ew = hi[i].entry_words;
-        }
-        if (binned) {
-            k.parts_cap = size_class(P, 64);
-            k.buckets_cap = size_class(G1, 64);
-            k.d1_cap = (uint32_t)std::min<uint64_t>(size_class(d1max, 16), dbgk::kMaxD1);
-            k.fan_cap = (uint32_t)std::min<uint64_t>(size_class(fanmax, 16), dbgk::kMaxFan);
-        }
-        const uint64_t T = (uint64_t)shape.block * shape.wpt;
-        const uint64_t tile_cap = dbgk::max_tiles(k.len_cap, T);
+        const PassKey k = pass_key(mm, n, len, shape, binned, hi);
         dbgk::BinBuffers bb{};
+        if (binned) bin_caps(k, bb);
+        const PassSizes z(k, bb);
         hipError_t e;
-        if ((e = grow(packed, dbgk::packed_words(k.len_cap) * 8)) != hipSuccess ||
-            (e = grow(ws, (k.n_cap + 1) * 8)) != hipSuccess ||
-            (e = grow(partials, std::max<uint64_t>(1, dbgk::scan_blocks(k.n_cap)) * 16 + 8)) != hipSuccess ||
-            (e = grow(dargs, dbgk::kArgsBytes + sizeof(Instance) * k.m_cap)) != hipSuccess ||
-            (e = grow(dstatus, sizeof(InstStatus) * k.m_cap + sizeof(CallState))) != hipSuccess ||
-            (!binned && (e = grow(tiles, tile_cap * 8)) != hipSuccess) ||
+        if ((e = grow(packed, z.packed)) != hipSuccess || (e = grow(ws, z.ws)) != hipSuccess ||
+            (e = grow(partials, z.partials)) != hipSuccess || (e = grow(dargs, z.args)) != hipSuccess ||
+            (e = grow(dstatus, z.status)) != hipSuccess || (!binned && (e = grow(tiles, z.tiles)) != hipSuccess) ||
             (binned && (e = reserve_binned(k, bb)) != hipSuccess))
             return e;
         if (binned) binned_grids(k, device, bb);
-
-        dbgk::PassArgs &a = *host_args();
-        std::memset(&a, 0, sizeof a);
-        a.reads = d_reads;
-        a.off = d_off;
-        a.n_reads = n;
-        a.reads_len = len;
-        a.max_windows = binned ? len : (tile_cap - 1) * T;
-        a.tile_cap = tile_cap;
-        a.parts_total = P;
-        a.m = mm;
-        a.check_ends = check_ends ? 1 : 0;
-        a.tile = (uint32_t)T;
-        if (binned && mm == 1 && xkeys) {
-            a.xkeys = xkeys;
-            a.xcounts = xcounts;
-            a.xcap = xcap;
-        }
+        fill_args(*host_args(), k, z, mm, hi, d_reads, len, d_off, n, check_ends, xkeys, xcounts, xcap);
 
         Cached *c = nullptr;
         if (use_graphs) {
@@ -722,6 +769,7 @@ struct BatchCtx {
     hipStream_t stream = nullptr;
     Pass pass;
     DevBuf reads, offsets;
+    DevBuf sizing;  // instance boundaries of a batch whose graphs are sized from their inputs
     std::vector<uint64_t> hoff;
     bool ready = false;
 };
@@ -755,10 +803,12 @@ struct BatchRun {
 // graph that fails a host-side check stays in the launch as a skipped
 // instance, so its reads are attributed to it and never touched; its status
 // is final here.  The others get their status from batch_finish.
+// bounds[i] bounds instance i's windows (its byte count will do); a graph
+// never sized is sized from its own bound, as dbg_build sizes it.
 inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
                           const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
-                          const uint64_t *d_offsets, int32_t *statuses, hipStream_t stream, Pass &pass,
-                          bool check_ends, BatchRun &br) {
+                          const uint64_t *d_offsets, const uint64_t *bounds, int32_t *statuses,
+                          hipStream_t stream, Pass &pass, bool check_ends, BatchRun &br) {
     br = BatchRun();
     br.graphs.assign(graphs, graphs + m);
     br.ks.assign(ks, ks + m);
@@ -775,8 +825,7 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
             if (graphs[j] == g) rc = DBG_E_INVAL;  // one graph per instance
         if (rc == DBG_OK && g->pass.pending) rc = harvest(g);
         if (rc == DBG_OK && read_begin[i + 1] > read_begin[i]) {
-            // a graph never sized takes the whole input's byte count as bound
-            rc = ensure_table(g, std::max<uint64_t>(reads_len, 1));
+            rc = ensure_table(g, std::max<uint64_t>(bounds[i], 1));
             if (rc == DBG_OK) rc = settle_mode(g, ks[i]);
             const int gm = g->binned ? (int)g->ew : 0;  // binned launches share one entry width
             if (rc == DBG_OK && mode < 0) mode = gm;
@@ -848,13 +897,41 @@ inline void batch_finish(BatchRun &br, Pass &pass, int32_t *statuses) {
     br.launched = false;
 }
 
-// Both halves, synchronously.
+// Both halves, synchronously.  bounds as for batch_enqueue; NULL: each
+// instance's byte count, read from the device offsets when some graph of the
+// batch still has to be sized.
 inline void batch_device_impl(dbg_graph *const *graphs, uint32_t m, const uint64_t *read_begin,
                               const uint32_t *ks, const uint8_t *d_reads, uint64_t reads_len,
-                              const uint64_t *d_offsets, int32_t *statuses, hipStream_t stream,
-                              BatchCtx *ctx, bool check_ends) {
+                              const uint64_t *d_offsets, const uint64_t *bounds, int32_t *statuses,
+                              hipStream_t stream, BatchCtx *ctx, bool check_ends) {
+    std::vector<uint64_t> own;
+    if (!bounds) {
+        own.assign(m, 0);
+        bool unsized = false;
+        for (uint32_t i = 0; i < m; ++i) unsized |= graphs[i] && !graphs[i]->cap;
+        if (unsized) {
+            // offsets at every instance boundary: a gather on the device, one copy back
+            hipError_t e = ctx->sizing.reserve(16 * (uint64_t)(m + 1));
+            uint64_t *d_idx = ctx->sizing.as<uint64_t>(), *d_at = d_idx + (m + 1);
+            std::vector<uint64_t> at(m + 1, 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_idx, read_begin, 8 * (uint64_t)(m + 1), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = dbgk::launch_gather_u64(d_offsets, d_idx, m + 1, d_at, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(at.data(), d_at, 8 * (uint64_t)(m + 1), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                for (uint32_t i = 0; i < m; ++i) statuses[i] = hip_code(e);
+                return;
+            }
+            // bytes of instance i (clamped: inconsistent offsets are the device checks' to report)
+            for (uint32_t i = 0; i < m; ++i)
+                own[i] = at[i + 1] >= at[i] ? std::min(at[i + 1] - at[i], reads_len) : reads_len;
+        }
+        bounds = own.data();
+    }
     BatchRun br;
-    batch_enqueue(graphs, m, read_begin, ks, d_reads, reads_len, d_offsets, statuses, stream, ctx->pass,
+    batch_enqueue(graphs, m, read_begin, ks, d_reads, reads_len, d_offsets, bounds, statuses, stream, ctx->pass,
                   check_ends, br);
     batch_finish(br, ctx->pass, statuses);
 }

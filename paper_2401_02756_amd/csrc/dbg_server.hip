@@ -358,8 +358,10 @@ bool dbg_server::launch(Slot &s) {
         return true;
     }
     if (n) {
+        std::vector<uint64_t> bounds(m);  // request graphs are sized at admission; this only bounds windows
+        for (uint32_t i = 0; i < m; ++i) bounds[i] = s.reqs[i]->reads_len;
         batch_enqueue(s.graphs.data(), m, s.read_begin.data(), s.ks.data(), dr, byte_at, s.offsets.as<uint64_t>(),
-                      s.statuses.data(), s.stream, s.pass, true, s.br);
+                      bounds.data(), s.statuses.data(), s.stream, s.pass, true, s.br);
     } else {
         s.br = BatchRun();
     }

@@ -413,6 +413,55 @@ def test_batch_device_matches_plain_device(mode):
             g.close()
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_batch_unsized_graphs_sized_from_own_input(mode):
+    """A graph created without a size is sized, in a batch as in dbg_build,
+    from its own input (ceil(bound / load factor) slots, bound = its windows
+    from host input, its bytes from device input), not from the whole
+    concatenation."""
+    say("batched build of unsized graphs: each table sized from its own input, mode %d" % mode)
+    sets = [readsim.make_instance(4, j) for j in range(8)]
+    sets = [s for s in sets if s.total_bases < 40_000_000][:5]
+    lf = 0.5
+
+    def windows(s):
+        L = s.lengths()
+        return int(np.where(L >= s.k, L - s.k + 2, 0).sum())
+
+    def check(graphs, bounds, what):
+        for i, (s, g, b) in enumerate(zip(sets, graphs, bounds)):
+            own = max(64, 2 * b)  # ceil(b / 0.5)
+            cap = g.stats()["capacity"]
+            if mode == dbg.F_BINNED:  # whole segments, a few more than asked for
+                assert own <= cap <= own + 64 * 2048 + own // 8, (what, i, cap, own)
+            else:
+                assert cap == own, (what, i, cap, own)
+            assert_same(g.extract_sorted(), oracle_of(s), "%s instance %d" % (what, i))
+
+    graphs = [dbg.Graph(load_factor=lf, flags=mode) for _ in sets]
+    try:
+        assert dbg.build_batch(graphs, [(s.reads, s.offsets, s.k) for s in sets]) == [0] * len(sets)
+        check(graphs, [windows(s) for s in sets], "host input")
+    finally:
+        for g in graphs:
+            g.close()
+    reads = np.concatenate([s.reads for s in sets])
+    lens = np.concatenate([s.lengths() for s in sets])
+    offs = np.zeros(lens.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    rb = np.zeros(len(sets) + 1, np.uint64)
+    np.cumsum([s.n_reads for s in sets], out=rb[1:])
+    graphs = [dbg.Graph(load_factor=lf, flags=mode) for _ in sets]
+    try:
+        st = dbg.build_batch_device(graphs, rb, [s.k for s in sets], torch.from_numpy(reads).cuda(),
+                                    torch.from_numpy(offs).cuda())
+        assert st == [0] * len(sets)
+        check(graphs, [int(s.total_bases) for s in sets], "device input")
+    finally:
+        for g in graphs:
+            g.close()
+
+
 # ---------------------------------------------------------------- graph capture and replay
 
 @pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
