@@ -1,30 +1,43 @@
 """Benchmark of the A-Bruijn graph build on one MI355X.
 
-One step is one pass of the whole plain-build path over the bacterial-scale
-workload (5 Mbp genome with 50 copies of a 1 kbp repeat, 150 bp reads at 30x =
-1,000,000 reads, 1 % substitutions, k = 31; binned table at the autotuned
-load factor, 0.4 in practice), with the ASCII reads and offsets already
-resident in HBM:
+One step is one pass of the whole plain-build path over the large workload
+(100 Mbp genome with 2 % of its length in repeat copies of 300-5000 bp units,
+150 bp reads at 20x = 13,333,333 reads, 1 % substitutions, k = 31; binned
+table at load factor 0.5: 1.04 G slots, 25 GB), with the ASCII reads and
+offsets already resident in HBM:
 
-    table reset -> pack -> window scan -> build (find-or-claim + count)
-    -> every vertex written to device buffers -> status readback
+    table reset -> pack -> window scan -> build (records partitioned by table
+    segment, find-or-claim + count in LDS) -> every vertex written to device
+    buffers -> status readback
 
 (one dbg_build_extract_device call: in binned mode the build's reduce kernel
-writes the vertices while each table segment is on chip; in direct mode a
-separate extraction pass follows the build)
-and the metric is k-mer inserts per second, inserts = sum over reads of
-max(0, L - k + 1) = 120,000,000 per step.
+writes the vertices while each table segment is on chip), and the metric is
+k-mer inserts per second, inserts = sum over reads of max(0, L - k + 1) =
+1,599,999,960 per step.
 
 Besides the driver's JSON fields the line carries:
-  * roofline       -- the longest kernel (binned: the segment reduce;
-                      direct: the build) against HBM peak, with the
-                      algorithmic bytes per launch and, from the committed
-                      counter profile, the HBM traffic;
-  * atomic_roofline-- the build pass and the step against the measured rate
-                      of random 64-bit compare-and-swap (and of the other
-                      random access kinds) at the table's footprint and op
-                      count;
-  * cpu_baseline   -- the CPU oracle on a bounded sample of the same reads.
+  * phases         -- device time and algorithmic bytes of every kernel group
+                      of the step, from an uncaptured timed pass with HIP
+                      events between the kernels;
+  * roofline       -- the longest kernel against HBM peak (its algorithmic
+                      bytes per launch over its event time), its HBM traffic
+                      from the committed counter profile, and under "step"
+                      the whole step against HBM peak with the byte model of
+                      the hot-path scope table (per k-mer an 8-byte key probe,
+                      a 4-byte counter add and the packed read; per table slot
+                      24 bytes initialised and 24 read by the extraction; per
+                      vertex 24 bytes written);
+  * atomic_roofline-- measured random-access rates (64-bit compare-and-swap,
+                      32-bit add, ...) at the table's footprint and op count,
+                      the bound of the direct design, with the step against
+                      them;
+  * bacterial      -- the bacterial-scale workload (5 Mbp + 50 copies of a
+                      1 kbp repeat, 1,000,000 reads, k = 31) at the
+                      autotuner's configuration, with its own phases and
+                      roofline, the direct-mode step, long k, contigs and
+                      host input;
+  * batched, served-- 256 read sets in one pass; a Poisson request stream;
+  * cpu_baseline   -- the CPU oracle on a bounded sample of the step's reads.
 """
 
 from __future__ import annotations
@@ -83,19 +96,31 @@ def committed_traffic(profile: str, workload: dict) -> int | None:
     return int(fields["traffic_bytes_per_launch"])
 
 
-def binned_phase_bytes(n_reads: int, total_bases: int, windows: int, vertices: int) -> dict:
-    """Algorithmic bytes of each phase of a binned build into an empty table
-    (8-byte window records, 24-byte vertex entries):
-      setup       ASCII in, packed reads out, offsets in, window prefix out;
-      partition1  packed reads read by the count and the scatter kernel,
-                  records written;
-      partition2  records read by the count and the scatter kernel, written;
-      reduce      records read, packed vertex entries written, and every
-                  vertex's key and counters written to the output arrays."""
-    return {"setup": total_bases + total_bases // 4 + 24 * n_reads,
-            "partition1": 2 * (total_bases // 4) + 8 * windows,
-            "partition2": 3 * 8 * windows,
-            "reduce": 8 * windows + 2 * 24 * vertices}
+def binned_kernel_bytes(n_reads: int, total_bases: int, windows: int, vertices: int, fused: bool) -> dict:
+    """Algorithmic bytes of each kernel group of a binned build of one-word
+    records into an empty table (8-byte window records, 24-byte vertex
+    entries); None where the work is bookkeeping of a size the host does not
+    know (plans, histogram scans, segment starts):
+      setup     ASCII in, packed reads out, offsets in, window prefix out;
+      count1    packed reads and each read's offset and window start read;
+      scatter1  the same, and every window's record written;
+      count2    records read;
+      scatter2  records read and written;
+      reduce    records read, packed vertex entries written and, with the
+                fused extraction, every vertex's key and counters written."""
+    packed = total_bases // 4 + 16 * n_reads
+    return {"setup": total_bases + total_bases // 4 + 24 * n_reads, "plan": None, "count1": packed,
+            "scan1": None, "scatter1": packed + 8 * windows, "plan2": None, "count2": 8 * windows,
+            "scan2": None, "scatter2": 16 * windows, "starts": None,
+            "reduce": 8 * windows + 24 * vertices * (2 if fused else 1)}
+
+
+def scope_step_bytes(inserts: int, total_bases: int, capacity: int, vertices: int) -> int:
+    """Bytes of one step under the hot-path scope table's model of the build:
+    per k-mer an 8-byte key probe and a 4-byte counter add, the packed reads
+    (2 bits a base), 24 bytes per table slot initialised and 24 read by the
+    extraction, 24 bytes per vertex written."""
+    return 12 * inserts + total_bases // 4 + 48 * capacity + 24 * vertices
 
 
 def batched_bench(dbg, torch, dev, n_inst: int, reps: int, graphs_on: bool) -> dict:
@@ -195,8 +220,10 @@ def served_bench(dbg, torch, dev, n_payloads: int, n_requests: int, loads, ref_g
     rng = np.random.default_rng(0x5E4E)
     choice = rng.integers(0, n_payloads, n_requests)
     ins = np.array([pay[c]["inserts"] for c in choice], dtype=np.float64)
-    out = {"workload": "served: %d requests over a pool of %d read sets, %.1f M k-mer inserts per request "
-                       "(mean), %.0f GB table budget" % (n_requests, n_payloads, ins.mean() / 1e6, budget / 1e9),
+    out = {"workload": "served: %d requests, each carrying one of a pool of %d read sets drawn as the served "
+                       "workload states (a fresh read set per request would take about 100 GB of reads), "
+                       "%.1f M k-mer inserts per request (mean), %.0f GB table budget"
+                       % (n_requests, n_payloads, ins.mean() / 1e6, budget / 1e9),
            "generation_s": round(gen_s, 1), "reference_ginserts_s": round(ref_gips, 3), "runs": []}
 
     srv = dbg.Server(hbm_budget=budget, flags=dbg.F_BINNED)
@@ -259,55 +286,6 @@ def served_bench(dbg, torch, dev, n_payloads: int, n_requests: int, loads, ref_g
     return out
 
 
-def large_bench(dbg, torch, dev, steps: int, graphs_on: bool) -> dict:
-    """The large plain build (100 Mbp genome with 2 % in repeats, 150 bp reads
-    at 20x, 1 % substitutions, k=31): binned mode at load factor 0.5, steps
-    of reset + build + sync, without an output (extraction timed apart)."""
-    import readsim
-
-    t0 = time.perf_counter()
-    rs = readsim.make_config(3)
-    gen_s = time.perf_counter() - t0
-    d_reads = torch.from_numpy(rs.reads).to(dev)
-    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
-    inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
-    g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=0.5, device=0,
-                  flags=dbg.F_BINNED | dbg.F_TIMING | (dbg.F_GRAPH if graphs_on else 0))
-
-    def step():
-        g.reset()
-        g.build_device(d_reads, d_off, rs.k)
-        g.sync()
-
-    step()
-    torch.cuda.synchronize()
-    ms, kern = [], []
-    for _ in range(steps):
-        t1 = time.perf_counter()
-        step()
-        ms.append((time.perf_counter() - t1) * 1e3)
-        kern.append(g.stats()["last_build_ms"])
-    st = g.stats()
-    cap = int(st["capacity"])
-    d_keys = torch.empty(st["vertices"], dtype=torch.int64, device=dev)
-    d_counts = torch.empty((st["vertices"], 4), dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    V = g.extract_device(d_keys, d_counts)
-    torch.cuda.synchronize()
-    x_ms = (time.perf_counter() - t1) * 1e3
-    assert st["inserts"] == inserts
-    g.close()
-    del d_keys, d_counts, d_reads, d_off
-    torch.cuda.empty_cache()
-    step_ms = float(np.median(ms))
-    return {"workload": "plain build, large: " + rs.meta["name"], "reads": rs.n_reads, "k": rs.k,
-            "inserts_per_step": inserts, "vertices": V, "capacity": cap,
-            "table_bytes": int(st["table_bytes"]), "generation_s": round(gen_s, 1),
-            "ms_per_step": round(step_ms, 3), "ginserts_s": round(inserts / step_ms / 1e6, 4),
-            "build_ms": round(float(np.median(kern)), 3), "extract_ms": round(x_ms, 3)}
-
-
 def host_cpu() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -366,36 +344,118 @@ def cpu_lfdbg_scaling(rs, sample_reads: int) -> dict:
     return out
 
 
+def measure_step(dbg, torch, dev, rs, inserts: int, mode: str, lf: float, steps: int, warmup: int,
+                 graphs: bool, block: int = 0, wpt: int = 0, merge: bool = False) -> dict:
+    """Steps of reset + dbg_build_extract_device (the whole path, every vertex
+    written to device buffers, status read back) on device-resident reads;
+    host wall time over the timed steps."""
+    flags = dbg.F_TIMING | (dbg.F_MERGE if merge else 0) | (dbg.F_BINNED if mode == "binned" else 0)
+    if graphs:
+        flags |= dbg.F_GRAPH
+    d_reads, d_off = rs.d_reads, rs.d_off
+    g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=lf, device=0, flags=flags,
+                  block_size=block, windows_per_thread=wpt)
+    cap_out = int(g.stats()["capacity"])
+    d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
+    d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
+
+    def step():
+        g.reset()
+        return g.build_extract_device(d_reads, d_off, rs.k, d_keys, d_counts)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    build_ms, phases = [], []
+    V = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        V = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s = g.stats()
+    build_ms = s["last_build_ms"]
+    phases = g.phase_times()
+    tx = []
+    for _ in range(3):  # extraction alone, host-timed around the synchronous call
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.extract_device(d_keys, d_counts)
+        tx.append((time.perf_counter() - t1) * 1000.0)
+    st = g.stats()
+    assert st["inserts"] == inserts, (st["inserts"], inserts)
+    g.close()
+    del d_keys, d_counts
+    torch.cuda.empty_cache()
+    return dict(V=V, cap=cap_out, st=st, ms_step=dt * 1000.0 / steps, value=inserts / (dt / steps) / 1e9,
+                kern_ms=build_ms, phases=phases, extract_ms=float(np.median(tx)))
+
+
+def kernel_roofline(dbg, rs, windows: int, inserts: int, V: int, cap: int, ms_step: float, phases: list,
+                    mode: str, lf: float, entry_bytes: int, workload: str, profile: str) -> tuple:
+    """Per-kernel phase table, and the roofline of the longest kernel group
+    (plus the whole step under the scope table's byte model)."""
+    table = []
+    if mode == "binned":
+        kb = binned_kernel_bytes(rs.n_reads, rs.total_bases, windows, V, True)
+        for name, ms in zip(dbg.BINNED_PHASES, phases):
+            b = kb[name]
+            table.append({"phase": name, "ms": round(ms, 4), "algorithmic_bytes": b,
+                          "gbs": round(b / (ms * 1e-3) / 1e9, 1) if b and ms > 0 else None})
+        cand = [p for p in table if p["algorithmic_bytes"] and p["phase"] != "setup"]
+        dom = max(cand, key=lambda p: p["ms"])
+        kernels = {"count1": "k_bin<false> (pass-1 count)", "scatter1": "k_bin<true> (pass-1 scatter)",
+                   "count2": "k_refine<false> (pass-2 count)", "scatter2": "k_refine<true> (pass-2 scatter)",
+                   "reduce": "k_reduce (segment reduce with the fused extraction)"}
+        kname, k_ms, bytes_alg = kernels[dom["phase"]], dom["ms"], dom["algorithmic_bytes"]
+        short = {"count1": "k_bin_count", "scatter1": "k_bin_scatter", "count2": "k_refine_count",
+                 "scatter2": "k_refine_scatter", "reduce": "k_reduce"}[dom["phase"]]
+    else:
+        bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
+        k_ms = phases[-1] if phases else 0.0
+        kname, short = "k_build (direct find-or-claim + count)", "k_build"
+    traffic = committed_traffic(profile.format(kernel=short),
+                                {"workload": workload, "kernel": short, "load_factor": lf, "mode": mode,
+                                 "entry_bytes": entry_bytes})
+    achieved = bytes_alg / (k_ms * 1e-3) / 1e9
+    step_bytes = scope_step_bytes(inserts, rs.total_bases, cap, V)
+    step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+            "kernel_ms": round(k_ms, 4), "algorithmic_bytes": bytes_alg,
+            "step": {"algorithmic_bytes": step_bytes, "ms": round(ms_step, 4), "achieved": round(step_gbs, 1),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "model": "12 B per k-mer + packed reads + 48 B per table slot + 24 B per vertex"}}
+    return table, roof
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
-    ap.add_argument("--load-factor", type=float, default=0.5)
-    ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--wpt", type=int, default=0)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3],
+                    help="workload of the headline step (3: large, the default)")
+    ap.add_argument("--load-factor", type=float, default=0.5, help="headline table load factor")
     ap.add_argument("--mode", choices=["direct", "binned"], default="binned")
+    ap.add_argument("--tune", action="store_true", help="autotune the headline workload too")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels without HIP graphs")
     ap.add_argument("--no-compare", action="store_true", help="skip the direct-mode comparison")
-    ap.add_argument("--merge", action="store_true")
-    ap.add_argument("--entry32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=250_000)
+    ap.add_argument("--no-bacterial", action="store_true", help="skip the bacterial-scale leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batched-sets", type=int, default=256)
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true", help="skip the serving benchmark")
-    ap.add_argument("--no-large", action="store_true", help="skip the large (100 Mbp) plain build")
-    ap.add_argument("--no-long-k", action="store_true", help="skip the k = 51 build of the same reads")
+    ap.add_argument("--no-long-k", action="store_true", help="skip the k = 51 build of the bacterial reads")
     ap.add_argument("--long-k", type=int, default=51)
-    ap.add_argument("--no-tune", action="store_true",
-                    help="use --mode/--load-factor/--block/--wpt/--merge instead of the autotuner's choice")
+    ap.add_argument("--no-tune", action="store_true", help="bacterial leg: binned at load factor 0.5, no autotuner")
     ap.add_argument("--served-payloads", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--calibrate", action="store_true",
-                    help="also run a 1 GiB read (sum) and a 1 GiB write (zero fill) of known size, "
+                    help="also run a streaming copy of known size (1 GiB read, 1 GiB written), "
                          "to scale hardware traffic counters")
     args = ap.parse_args()
 
@@ -413,74 +473,52 @@ def main() -> int:
         return 2
     dev = torch.device("cuda:0")
     dbg.lib()
+    graphs_on = not args.no_graph
 
-    t0 = time.perf_counter()
-    rs = readsim.make_config(args.config)
-    log("generated config %d: %d reads, %d bases in %.1f s" % (args.config, rs.n_reads,
-                                                              rs.total_bases, time.perf_counter() - t0))
-    d_reads = torch.from_numpy(rs.reads).to(dev)
-    d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
-    inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
-    windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
-    tuning = None
-    if not args.no_tune:
+    def load(cfg: int):
+        t0 = time.perf_counter()
+        rs = readsim.make_config(cfg)
+        log("generated config %d: %d reads, %d bases in %.1f s" % (cfg, rs.n_reads, rs.total_bases,
+                                                                  time.perf_counter() - t0))
+        rs.d_reads = torch.from_numpy(rs.reads).to(dev)
+        rs.d_off = torch.from_numpy(rs.offsets.astype(np.int64)).to(dev)
+        rs.inserts = int(np.maximum(rs.lengths() - rs.k + 1, 0).sum())
+        rs.windows = int(np.where(rs.lengths() >= rs.k, rs.lengths() - rs.k + 2, 0).sum())
+        return rs
+
+    def tuned(rs) -> tuple:
         t1 = time.perf_counter()
-        t = dbg.autotune([0, rs.n_reads], [rs.k], d_reads, d_off, [rs.meta["expected_vertices"]],
-                         keep_flags=0 if args.no_graph else dbg.F_GRAPH, force=True)
-        tuning = dict(t.as_dict(), seconds=round(time.perf_counter() - t1, 2))
-        args.mode = "binned" if t.flags & dbg.F_BINNED else "direct"
-        args.load_factor, args.block, args.wpt = t.load_factor, t.block_size, t.windows_per_thread
-        args.merge = bool(t.flags & dbg.F_MERGE)
-        log("autotune: %s" % json.dumps(tuning))
+        t = dbg.autotune([0, rs.n_reads], [rs.k], rs.d_reads, rs.d_off, [rs.meta["expected_vertices"]],
+                         keep_flags=dbg.F_GRAPH if graphs_on else 0, force=True)
+        info = dict(t.as_dict(), seconds=round(time.perf_counter() - t1, 2))
+        log("autotune: %s" % json.dumps(info))
+        mode = "binned" if t.flags & dbg.F_BINNED else "direct"
+        return info, mode, t.load_factor, t.block_size, t.windows_per_thread, bool(t.flags & dbg.F_MERGE)
 
-    def host_input_rate(reps: int = 3) -> dict:
-        """dbg_build from host memory: the ASCII reads and offsets cross PCIe
-        inside each timed build (pageable numpy buffers)."""
-        flags = dbg.F_BINNED if args.mode == "binned" else 0
-        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
-                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
-        g.build(rs.reads, rs.offsets, rs.k)  # warm-up
-        t = []
-        for _ in range(reps):
-            g.reset()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g.build(rs.reads, rs.offsets, rs.k)
-            t.append(time.perf_counter() - t0)
-        g.close()
-        ms = float(np.median(t)) * 1e3
-        return {"ms": round(ms, 3), "ginserts_s": round(inserts / ms / 1e6, 4),
-                "bytes_over_pcie": int(rs.total_bases + 8 * (rs.n_reads + 1))}
+    names = {1: "tiny", 2: "bacterial_c2", 3: "large_c3"}
+    profile = "{kernel}_traffic_%s.md"
 
-    def contig_rate(reps: int = 3) -> dict:
-        """Contigs (findContigs, Algorithm 5) of the built graph, on the
-        device: extraction, walk table, starts, walks, layout, spelling."""
-        flags = dbg.F_BINNED if args.mode == "binned" else 0
-        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
-                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
-        t = []
-        n = ln = 0
-        for _ in range(reps + 1):
-            g.reset()
-            g.build_device(d_reads, d_off, rs.k)
-            g.sync()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            n, ln = g.contig_sizes()
-            t.append(time.perf_counter() - t0)
-        g.close()
-        ms = float(np.median(t[1:])) * 1e3
-        return {"ms": round(ms, 3), "contigs": n, "bases": ln, "vertices_per_s": round(V / ms * 1e3, 1)}
+    def leg(rs, cfg: int, mode: str, lf: float, block: int, wpt: int, merge: bool, steps: int, warmup: int) -> dict:
+        r = measure_step(dbg, torch, dev, rs, rs.inserts, mode, lf, steps, warmup, graphs_on, block, wpt, merge)
+        log("%s %s: step %.3f ms (%.2f G/s), V=%d, cap=%d" % (names[cfg], mode, r["ms_step"], r["value"],
+                                                              r["V"], r["cap"]))
+        # phase times: an uncaptured timed pass with events between the kernels
+        pr = r if not graphs_on else measure_step(dbg, torch, dev, rs, rs.inserts, mode, lf, 2, 1, False, block,
+                                                  wpt, merge)
+        table, roof = kernel_roofline(dbg, rs, rs.windows, rs.inserts, r["V"], r["cap"], r["ms_step"],
+                                      pr["phases"], mode, lf, r["st"]["entry_bytes"], names[cfg],
+                                      profile % names[cfg])
+        return dict(r=r, phases=table, roofline=roof)
 
-    def long_k_rate(k: int, binned: bool, steps: int = 5) -> dict:
+    def long_k_rate(rs, k: int, binned: bool, lf: float, steps: int = 5) -> dict:
         """The same reads at long k (two-word keys, 32-byte entries), binned
         or direct: whole step (reset, build, extraction) and build pass."""
         kins = int(np.maximum(rs.lengths() - k + 1, 0).sum())
         ev = readsim.expected_vertices(int(rs.meta["genome_len"]), int(rs.meta["read_len"]), rs.n_reads,
                                        float(rs.meta["err"]), k)
-        flags = dbg.F_TIMING | (0 if args.no_graph else dbg.F_GRAPH) | (dbg.F_BINNED if binned else 0)
-        g = dbg.Graph(expected_vertices=ev, load_factor=args.load_factor if binned else 0.5, device=0, flags=flags)
-        g.build_device(d_reads, d_off, k)
+        flags = dbg.F_TIMING | (dbg.F_GRAPH if graphs_on else 0) | (dbg.F_BINNED if binned else 0)
+        g = dbg.Graph(expected_vertices=ev, load_factor=lf if binned else 0.5, device=0, flags=flags)
+        g.build_device(rs.d_reads, rs.d_off, k)
         g.sync()
         cap = int(g.stats()["capacity"])
         d_keys = torch.empty(2 * cap, dtype=torch.int64, device=dev)
@@ -488,7 +526,7 @@ def main() -> int:
 
         def step():
             g.reset()
-            return g.build_extract_device(d_reads, d_off, k, d_keys, d_counts)
+            return g.build_extract_device(rs.d_reads, rs.d_off, k, d_keys, d_counts)
 
         step()
         torch.cuda.synchronize()
@@ -505,56 +543,48 @@ def main() -> int:
         del d_keys, d_counts
         km = float(np.mean(kern))
         return {"k": k, "mode": "binned" if st["binned"] else "direct", "inserts_per_step": kins,
-                "vertices": nv, "capacity": cap, "load_factor": args.load_factor if binned else 0.5,
+                "vertices": nv, "capacity": cap, "load_factor": lf if binned else 0.5,
                 "entry_bytes": st["entry_bytes"], "ms_per_step": round(dt * 1e3, 3),
                 "value": round(kins / dt / 1e9, 4), "build_ms": round(km, 4),
                 "build_ginserts_s": round(kins / (km * 1e-3) / 1e9, 4)}
 
-    def run(mode: str, steps: int, warmup: int, graphs: bool = not args.no_graph):
-        flags = dbg.F_TIMING | (dbg.F_MERGE if args.merge else 0) | (dbg.F_ENTRY32 if args.entry32 else 0)
-        if mode == "binned":
-            flags |= dbg.F_BINNED
-        if graphs:
-            flags |= dbg.F_GRAPH
-        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=args.load_factor,
-                      device=0, flags=flags, block_size=args.block, windows_per_thread=args.wpt)
-        cap_out = int(g.stats()["capacity"])
-        d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
-        d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
-
-        def step():
+    def host_input_rate(rs, mode: str, lf: float, reps: int = 3) -> dict:
+        """dbg_build from host memory: the ASCII reads and offsets cross PCIe
+        inside each timed build (pageable numpy buffers)."""
+        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=lf, device=0,
+                      flags=dbg.F_BINNED if mode == "binned" else 0)
+        g.build(rs.reads, rs.offsets, rs.k)  # warm-up
+        t = []
+        for _ in range(reps):
             g.reset()
-            return g.build_extract_device(d_reads, d_off, rs.k, d_keys, d_counts)
-
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        build_ms, total_ms, phases = [], [], []
-        V = 0
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            V = step()
-            s = g.stats()
-            build_ms.append(s["last_build_ms"])
-            total_ms.append(s["last_total_ms"])
-            phases.append(g.phase_times())
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        tx = []
-        for _ in range(3):  # extraction alone, host-timed around the synchronous call
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            g.extract_device(d_keys, d_counts)
-            tx.append((time.perf_counter() - t1) * 1000.0)
-        st = g.stats()
-        assert st["inserts"] == inserts, (st["inserts"], inserts)
+            t0 = time.perf_counter()
+            g.build(rs.reads, rs.offsets, rs.k)
+            t.append(time.perf_counter() - t0)
         g.close()
-        del d_keys, d_counts
-        return dict(V=V, cap=cap_out, st=st, ms_step=dt * 1000.0 / steps,
-                    value=inserts / (dt / steps) / 1e9, kern_ms=float(np.mean(build_ms)),
-                    pass_ms=float(np.mean(total_ms)),
-                    phases=[float(x) for x in np.mean(np.array(phases), axis=0)] if phases else [],
-                    extract_ms=float(np.median(tx)))
+        ms = float(np.median(t)) * 1e3
+        return {"ms": round(ms, 3), "ginserts_s": round(rs.inserts / ms / 1e6, 4),
+                "bytes_over_pcie": int(rs.total_bases + 8 * (rs.n_reads + 1))}
+
+    def contig_rate(rs, mode: str, lf: float, reps: int = 3) -> dict:
+        """Contigs (findContigs, Algorithm 5) of the built graph, on the
+        device: walk table, starts, walks, layout, spelling."""
+        g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=lf, device=0,
+                      flags=dbg.F_BINNED if mode == "binned" else 0)
+        t = []
+        n = ln = V = 0
+        for _ in range(reps + 1):
+            g.reset()
+            g.build_device(rs.d_reads, rs.d_off, rs.k)
+            g.sync()
+            V = g.vertex_count()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n, ln = g.contig_sizes()
+            t.append(time.perf_counter() - t0)
+        g.close()
+        ms = float(np.median(t[1:])) * 1e3
+        return {"ms": round(ms, 3), "contigs": n, "bases": ln, "vertices_per_s": round(V / ms * 1e3, 1)}
 
     if args.calibrate:
         # k_stream_copy: reads 1 GiB and writes 1 GiB with 16-byte accesses
@@ -562,116 +592,105 @@ def main() -> int:
         dbg.atomic_roofline(dbg.ROOF_COPY, 2 << 30, 0, 256, 1)
         log("calibration: streaming copy of 1 GiB")
 
-    r = run(args.mode, args.steps, args.warmup)
-    V, cap_out, st, ms_step, value, kern_ms = r["V"], r["cap"], r["st"], r["ms_step"], r["value"], r["kern_ms"]
-    log("%s: step %.3f ms, build %.3f ms (pass %.3f ms), V=%d, cap=%d, graph captures %d replays %d" %
-        (args.mode, ms_step, kern_ms, r["pass_ms"], V, cap_out, st["graph_captures"], st["graph_replays"]))
-
-    phase_table = None
-    if args.mode == "binned":
-        # phase times from an uncaptured timed run (events between the phases)
-        pr = r if args.no_graph else run("binned", 5, 1, graphs=False)
-        names = ["setup", "partition1", "partition2", "reduce"]
-        pb = binned_phase_bytes(rs.n_reads, rs.total_bases, windows, V)
-        phase_table = []
-        for name, ms in zip(names, pr["phases"]):
-            phase_table.append({"phase": name, "ms": round(ms, 4), "algorithmic_bytes": pb[name],
-                                "gbs": round(pb[name] / (ms * 1e-3) / 1e9, 1)})
-        red = phase_table[3]
-        bytes_alg, k_ms, kname = red["algorithmic_bytes"], red["ms"], "k_reduce (binned segment reduce)"
-        traffic = (committed_traffic("k_reduce_traffic_bacterial_c2.md",
-                                     {"load_factor": args.load_factor, "mode": args.mode, "entry_bytes": st["entry_bytes"]})
-                   if args.config == 2 else None)
-    else:
-        bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
-        k_ms, kname = kern_ms, "k_build (direct find-or-claim + count)"
-        traffic = None
-    achieved = bytes_alg / (k_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-            "kernel_ms": round(k_ms, 4), "algorithmic_bytes": bytes_alg}
-
+    # ---------------------------------------------------------------- headline
+    rs = load(args.config)
+    tuning = None
+    mode, lf, block, wpt, merge = args.mode, args.load_factor, 0, 0, False
+    if args.tune:
+        tuning, mode, lf, block, wpt, merge = tuned(rs)
+    h = leg(rs, args.config, mode, lf, block, wpt, merge, args.steps, args.warmup)
+    r = h["r"]
+    st = r["st"]
     line = {
         "metric": "k-mer inserts/sec (G/s)",
-        "value": round(value, 4),
+        "value": round(r["value"], 4),
         "unit": "G k-mer inserts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(r["ms_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain build, bacterial scale: " + rs.meta["name"],
+        "config": {"workload": "plain build, %s" % rs.meta["name"],
                    "reads": rs.n_reads, "read_len": int(rs.meta["read_len"]), "k": rs.k,
-                   "inserts_per_step": inserts, "vertices": V, "capacity": cap_out,
-                   "load_factor": args.load_factor, "entry_bytes": st["entry_bytes"],
-                   "block": st["block_size"], "windows_per_thread": st["windows_per_thread"],
-                   "grid": st["grid_size"], "merge": bool(args.merge), "mode": args.mode,
-                   "hip_graphs": not args.no_graph,
+                   "inserts_per_step": rs.inserts, "vertices": r["V"], "capacity": r["cap"],
+                   "table_bytes": int(st["table_bytes"]), "load_factor": lf, "entry_bytes": st["entry_bytes"],
+                   "mode": mode, "hip_graphs": graphs_on,
                    "step": "reset + dbg_build_extract_device (build, every vertex written to device "
                            "buffers, status read back)"},
-        "build_kernel_ginserts_s": round(inserts / (kern_ms * 1e-3) / 1e9, 4),
+        "build_kernel_ginserts_s": round(rs.inserts / (r["kern_ms"] * 1e-3) / 1e9, 4),
         "extract_separate_ms": round(r["extract_ms"], 4),  # dbg_extract_device on the built graph
         "autotune": tuning,
-        "roofline": roof,
+        "roofline": h["roofline"],
+        "phases": h["phases"],
     }
-    if phase_table:
-        line["phases"] = phase_table
-
+    log("roofline %s" % json.dumps(h["roofline"]))
     if not args.no_compare:
-        other = "direct" if args.mode == "binned" else "binned"
-        o = run(other, max(3, args.steps // 2), 1)
+        other = "direct" if mode == "binned" else "binned"
+        o = measure_step(dbg, torch, dev, rs, rs.inserts, other, lf, 3, 1, graphs_on)
         line["compare_" + other] = {"value": round(o["value"], 4), "ms_per_step": round(o["ms_step"], 4),
-                                   "build_ginserts_s": round(inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
+                                   "build_ginserts_s": round(rs.inserts / (o["kern_ms"] * 1e-3) / 1e9, 4),
                                    "build_ms": round(o["kern_ms"], 4)}
-        log("%s: step %.3f ms, build %.3f ms" % (other, o["ms_step"], o["kern_ms"]))
-
-    if not args.no_long_k:
-        line["long_k"] = long_k_rate(args.long_k, True)
-        log("long k %s" % json.dumps(line["long_k"]))
-        line["long_k"]["compare_direct"] = long_k_rate(args.long_k, False)
-        log("long k direct %s" % json.dumps(line["long_k"]["compare_direct"]))
-
-    line["contigs"] = contig_rate()
-    log("contigs %s" % json.dumps(line["contigs"]))
-
-    line["host_input"] = host_input_rate()
-    log("host input %s" % json.dumps(line["host_input"]))
-
-    if not args.no_batched:
-        line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps,
-                                        not args.no_graph)
-        log("batched %s" % json.dumps(line["batched"]))
-
-    if not args.no_large:
-        line["large"] = large_bench(dbg, torch, dev, 5, not args.no_graph)
-        log("large %s" % json.dumps(line["large"]))
-
-    if not args.no_served:
-        ref = line["batched"]["batched"]["ginserts_s"] if "batched" in line else value
-        line["served"] = served_bench(dbg, torch, dev, args.served_payloads, args.served_requests,
-                                      (0.7, 0.5, 0.9), ref)
-
+        log("%s: %s" % (other, json.dumps(line["compare_" + other])))
     if not args.no_roofline:
         foot = int(st["table_bytes"])
-        ar = {"footprint_bytes": foot, "ops": inserts}
+        ar = {"footprint_bytes": foot, "ops": rs.inserts}
         for name, kind in (("cas64", dbg.ROOF_CAS64), ("add32", dbg.ROOF_ADD32),
                            ("load64", dbg.ROOF_LOAD64), ("load_add", dbg.ROOF_LOAD_ADD)):
-            best = min(dbg.atomic_roofline(kind, foot, inserts, b, 5) for b in (256, 1024))
-            ar[name + "_gops"] = round(inserts / (best * 1e-3) / 1e9, 4)
-        ar["frac_of_cas64"] = round(line["build_kernel_ginserts_s"] / ar["cas64_gops"], 4)
-        ar["step_frac_of_cas64"] = round(value / ar["cas64_gops"], 4)
+            best = min(dbg.atomic_roofline(kind, foot, rs.inserts, b, 3) for b in (256, 1024))
+            ar[name + "_gops"] = round(rs.inserts / (best * 1e-3) / 1e9, 4)
+        ar["build_frac_of_cas64"] = round(line["build_kernel_ginserts_s"] / ar["cas64_gops"], 4)
+        ar["step_frac_of_cas64"] = round(r["value"] / ar["cas64_gops"], 4)
         line["atomic_roofline"] = ar
         log("atomic roofline %s" % json.dumps(ar))
-
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_reads)
         log("cpu baseline %s" % json.dumps(line["cpu_baseline"]))
         line["cpu_lfdbg"] = cpu_lfdbg_scaling(rs, args.cpu_sample_reads)
         log("cpu lfdbg %s" % json.dumps(line["cpu_lfdbg"]))
+    del rs.d_reads, rs.d_off
+    del rs
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- bacterial scale
+    if not args.no_bacterial and args.config != 2:
+        b = load(2)
+        if args.no_tune:
+            btune, bmode, blf, bblock, bwpt, bmerge = None, "binned", 0.5, 0, 0, False
+        else:
+            btune, bmode, blf, bblock, bwpt, bmerge = tuned(b)
+        bl = leg(b, 2, bmode, blf, bblock, bwpt, bmerge, max(args.steps, 10), args.warmup)
+        br = bl["r"]
+        bac = {"workload": "plain build, %s" % b.meta["name"], "inserts_per_step": b.inserts,
+               "vertices": br["V"], "capacity": br["cap"], "load_factor": blf, "mode": bmode,
+               "value": round(br["value"], 4), "ms_per_step": round(br["ms_step"], 4),
+               "build_kernel_ginserts_s": round(b.inserts / (br["kern_ms"] * 1e-3) / 1e9, 4),
+               "autotune": btune, "roofline": bl["roofline"], "phases": bl["phases"]}
+        if not args.no_compare:
+            o = measure_step(dbg, torch, dev, b, b.inserts, "direct", 0.5, 5, 1, graphs_on)
+            bac["compare_direct"] = {"value": round(o["value"], 4), "ms_per_step": round(o["ms_step"], 4),
+                                     "build_ginserts_s": round(b.inserts / (o["kern_ms"] * 1e-3) / 1e9, 4)}
+        if not args.no_long_k:
+            bac["long_k"] = long_k_rate(b, args.long_k, True, blf)
+            bac["long_k"]["compare_direct"] = long_k_rate(b, args.long_k, False, blf)
+        bac["contigs"] = contig_rate(b, bmode, blf)
+        bac["host_input"] = host_input_rate(b, bmode, blf)
+        line["bacterial"] = bac
+        log("bacterial %s" % json.dumps(bac))
+        del b.d_reads, b.d_off
+        torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        line["batched"] = batched_bench(dbg, torch, dev, args.batched_sets, args.batched_reps, graphs_on)
+        log("batched %s" % json.dumps(line["batched"]))
+
+    if not args.no_served:
+        ref = line["batched"]["batched"]["ginserts_s"] if "batched" in line else line["value"]
+        line["served"] = served_bench(dbg, torch, dev, args.served_payloads, args.served_requests,
+                                      (0.7, 0.5, 0.9), ref)
 
     print(json.dumps(line), flush=True)
     return 0

@@ -197,9 +197,11 @@ int dbg_get_stats(dbg_graph *g, dbg_stats *out);
 
 /* Device time of each phase of the handle's last timed build (DBG_F_TIMING),
  * in ms, in this order: setup (argument copy, prepare, pack, window scan),
- * then, for a binned build launched without a graph, partition pass 1,
- * partition pass 2 and segment reduce, else the whole build.  Writes
- * min(cap, *n_phases) values; *n_phases is 0 before any timed build. */
+ * then, for a binned build launched without a graph, ten phases -- plan,
+ * pass-1 count, pass-1 scan, pass-1 scatter, pass-2 plan, pass-2 count,
+ * pass-2 scan, pass-2 scatter, segment starts, segment reduce -- else the
+ * whole build.  Writes min(cap, *n_phases) values; *n_phases is 0 before any
+ * timed build. */
 int dbg_get_phase_times(dbg_graph *g, double *ms, uint32_t cap, uint32_t *n_phases);
 
 /* Release all device memory of the handle.  NULL is ignored. */

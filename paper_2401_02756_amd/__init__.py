@@ -39,6 +39,9 @@ EXPORTS = (
     "dbg_build_extract_device",
 )
 NORM_U8 = 0x1
+# phases of a timed binned build launched without graphs (dbg_get_phase_times)
+BINNED_PHASES = ("setup", "plan", "count1", "scan1", "scatter1", "plan2", "count2", "scan2", "scatter2",
+                 "starts", "reduce")
 TUNE_FORCE = 0x1
 
 
@@ -383,11 +386,12 @@ class Graph:
         return int(n.value), int(ln.value)
 
     def phase_times(self) -> list[float]:
-        """Per-phase device ms of the last timed build (see dbg_get_phase_times)."""
-        buf = (ctypes.c_double * 8)()
+        """Per-phase device ms of the last timed build (see dbg_get_phase_times;
+        binned builds launched without graphs: BINNED_PHASES)."""
+        buf = (ctypes.c_double * 16)()
         n = ctypes.c_uint32(0)
-        _check(lib().dbg_get_phase_times(self.handle, buf, 8, ctypes.byref(n)), "dbg_get_phase_times")
-        return [float(buf[i]) for i in range(min(8, n.value))]
+        _check(lib().dbg_get_phase_times(self.handle, buf, 16, ctypes.byref(n)), "dbg_get_phase_times")
+        return [float(buf[i]) for i in range(min(16, n.value))]
 
     def reset(self) -> None:
         _check(lib().dbg_reset(self.handle), "dbg_reset")

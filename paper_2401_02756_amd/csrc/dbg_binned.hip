@@ -1118,16 +1118,18 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
                        bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks) (void)hipEventRecord(marks[1], s);
     const uint64_t nb1 = std::max<uint64_t>((bb.hist1_cap + kFlatChunk - 1) / kFlatChunk, 1);
     const uint64_t *len1 = &bb.totals->hist1_len;
     hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, bb.hist1, len1, bb.scan1,
                        bb.partials);
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
+    if (marks) (void)hipEventRecord(marks[2], s);
     hipLaunchKernelGGL((k_bin<true, RW>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
                        bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (marks) (void)hipEventRecord(marks[0], s);
+    if (marks) (void)hipEventRecord(marks[3], s);
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
@@ -1137,27 +1139,31 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
         hipLaunchKernelGGL(k_tile_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.tile2,
                            bb.tiles2_cap);
     }
+    if (marks) (void)hipEventRecord(marks[4], s);
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW), lr1 = ref_lds_bytes(bb.fan_max, true, RW);
     const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
     hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.tile2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks) (void)hipEventRecord(marks[5], s);
     const uint64_t nb2 = std::max<uint64_t>((bb.hist2_cap + kFlatChunk - 1) / kFlatChunk, 1);
     const uint64_t *len2 = &bb.totals->hist2_len;
     hipLaunchKernelGGL(k_flat_local, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, bb.hist2, len2, bb.scan2,
                        bb.partials);
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
+    if (marks) (void)hipEventRecord(marks[6], s);
     hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.tile2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks) (void)hipEventRecord(marks[7], s);
 
     // segment starts and the reduction
     const uint64_t P = bb.parts_cap;
     const uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((P + 255) / 256, 4096));
     hipLaunchKernelGGL(k_part_starts, dim3(gs), dim3(256), 0, s, args, inst, bb.plan, bb.buckets, bb.scan2,
                        bb.totals, bb.pstart);
-    if (marks) (void)hipEventRecord(marks[1], s);
+    if (marks) (void)hipEventRecord(marks[8], s);
     // every instance of a binned launch has the same entry width
     const uint32_t gr = bb.grid_reduce;
     if (RW == 2)
@@ -1184,6 +1190,7 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
         hipLaunchKernelGGL(k_tile_reads, dim3(g), dim3(256), 0, s, args, inst, ws, bb.plan, bb.tile_read1,
                            bb.tiles1_cap);
     }
+    if (marks) (void)hipEventRecord(marks[0], s);
 
     if (bb.rec_words == 2) return launch_passes<2>(args, inst, packed, ws, st, bb, s, marks);
     return launch_passes<1>(args, inst, packed, ws, st, bb, s, marks);

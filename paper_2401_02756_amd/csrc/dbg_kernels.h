@@ -232,8 +232,12 @@ hipError_t launch_count(const uint64_t *table, uint32_t entry_words, uint64_t ca
 hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32_t kind,
                            uint64_t seed, uint32_t block, uint64_t *sink, hipStream_t s);
 
-// marks, when not null, are two events recorded after the first partition
-// pass and before the segment reduce (phase timing; never under capture).
+// marks, when not null, are kBinMarks events recorded between the kernels of
+// the binned build, which times its phases (never under capture): after the
+// plan, the pass-1 count, its scan, the pass-1 scatter, the pass-2 plan, the
+// pass-2 count, its scan, the pass-2 scatter and the segment starts; the
+// segment reduce follows the last.
+constexpr uint32_t kBinMarks = 9;
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                          const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
                          int device, hipStream_t s, hipEvent_t *marks);

@@ -274,7 +274,7 @@ struct Pass {
     DevBuf tread1, tbucket2;
     HostBuf hargs, hstatus;  // pinned: PassArgs + Instance[m_cap]; InstStatus[m_cap] + CallState
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
-    hipEvent_t marks[2] = {nullptr, nullptr};  // binned phase boundaries (timed, uncaptured)
+    hipEvent_t marks[dbgk::kBinMarks] = {};  // binned phase boundaries (timed, uncaptured)
     bool marked = false;
     hipStream_t cap_stream = nullptr;
     uint32_t m = 0;
@@ -296,8 +296,8 @@ struct Pass {
         if (e == hipSuccess) e = hipEventCreate(&ev_b);
         if (e == hipSuccess) e = hipEventCreate(&ev_c);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreate(&marks[0]);
-        if (e == hipSuccess) e = hipEventCreate(&marks[1]);
+        for (hipEvent_t &x : marks)
+            if (e == hipSuccess) e = hipEventCreate(&x);
         return e;
     }
     void drop_graphs() {
@@ -504,8 +504,9 @@ struct Pass {
     }
 
     // Phase times of the last timed pass, in ms: setup, then (binned,
-    // uncaptured) partition 1, partition 2, reduce, or (otherwise) build.
-    double phase_ms[4] = {0, 0, 0, 0};
+    // uncaptured) the kBinMarks + 1 phases between the marks and the end of
+    // the pass, or (otherwise) the whole build.
+    double phase_ms[dbgk::kBinMarks + 2] = {};
     uint32_t n_phases = 0;
 
     // Wait for the enqueued pass; times in ms when it was timed.
@@ -520,9 +521,12 @@ struct Pass {
             n_phases = 0;
             if (hipEventElapsedTime(&x, ev_a, ev_b) == hipSuccess) phase_ms[n_phases++] = x;
             if (marked) {
-                if (hipEventElapsedTime(&x, ev_b, marks[0]) == hipSuccess) phase_ms[n_phases++] = x;
-                if (hipEventElapsedTime(&x, marks[0], marks[1]) == hipSuccess) phase_ms[n_phases++] = x;
-                if (hipEventElapsedTime(&x, marks[1], ev_c) == hipSuccess) phase_ms[n_phases++] = x;
+                hipEvent_t prev = ev_b;
+                for (hipEvent_t m : marks) {
+                    phase_ms[n_phases++] = hipEventElapsedTime(&x, prev, m) == hipSuccess ? x : 0.0;
+                    prev = m;
+                }
+                phase_ms[n_phases++] = hipEventElapsedTime(&x, prev, ev_c) == hipSuccess ? x : 0.0;
             } else {
                 phase_ms[n_phases++] = a;
             }
