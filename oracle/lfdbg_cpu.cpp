@@ -92,7 +92,7 @@ struct Table {
         for (;;) {
             mine->next = seen;
             Node *expected = seen;
-            if (head.compare_exchange_weak(expected, mine, std::memory_order_release, std::memory_order_acquire))
+            if (head.compare_exchange_weak(expected, mine, std::memory_order_acq_rel, std::memory_order_acquire))
                 return mine;
             // other nodes were pushed in front of `seen`: ours may be one of them
             if (Node *n = scan(expected, seen, key)) {
