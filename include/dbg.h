@@ -59,6 +59,7 @@ extern "C" {
 #define DBG_E_DEVICE (-7) /* HIP runtime error */
 #define DBG_E_RANGE (-8)  /* cumulative k-mers on the handle would exceed 2^32-1 */
 #define DBG_E_STATE (-9)  /* handle poisoned by an earlier DBG_E_FULL */
+#define DBG_E_SCRATCH (-10) /* input needs more than the static scratch of dbg_build_device_static */
 
 /* ---- configuration flags ------------------------------------------- */
 #define DBG_F_MERGE 0x1u   /* merge equal vertices within a wavefront first */
@@ -149,6 +150,24 @@ int dbg_build(dbg_graph *g, const char *reads, const uint64_t *offsets, uint64_t
  * dbg_sync.  As with dbg_build, a rejected input modifies nothing. */
 int dbg_build_device(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len,
                      const uint64_t *d_offsets, uint64_t n_reads, uint32_t k, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * build as dbg_build_device (arguments, layout and result alike) with every
+ * scratch buffer of the pass taken from a static device array of 256 MiB
+ * that each device holds from its first call until the process ends, and no
+ * allocation of any kind (device, pinned or library).  Limits: 2 <= k <= 32;
+ * the graph's table must already exist (created with capacity or
+ * expected_vertices, or sized by an earlier build), else DBG_E_INVAL; an
+ * input whose pass needs more scratch than the array holds is refused with
+ * DBG_E_SCRATCH before any device work (direct graphs take about 0.3 bytes
+ * per read base, binned graphs about 16.3, so roughly 800 MB and 15 MB of
+ * reads).  Synchronous: it returns after the build and its status readback,
+ * with the codes of dbg_build.  Calls on one device share its array: the
+ * library serialises them with a lock, so they never overlap on it; the array
+ * keeps the last call's contents, and the pass rewrites all it reads. */
+int dbg_build_device_static(dbg_graph *g, const uint8_t *d_reads, uint64_t reads_len, const uint64_t *d_offsets,
+                            uint64_t n_reads, uint32_t k, void *stream);
 
 /* dbg_build_device followed by dbg_extract_device, as one call: build from
  * device-resident input (arguments as dbg_build_device), then write every

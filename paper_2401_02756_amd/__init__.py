@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
 
 OK = 0
 PENDING = 1
-E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE = range(-1, -10, -1)
+E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE, E_SCRATCH = range(-1, -11, -1)
 F_MERGE, F_TIMING, F_ENTRY32, F_BINNED, F_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
 # every symbol include/dbg.h declares
@@ -36,7 +36,7 @@ EXPORTS = (
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
     "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
     "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device", "dbg_extract_normalized",
-    "dbg_build_extract_device",
+    "dbg_build_extract_device", "dbg_build_device_static",
 )
 NORM_U8 = 0x1
 # phases of a timed binned build launched without graphs (dbg_get_phase_times)
@@ -152,6 +152,7 @@ def lib() -> ctypes.CDLL:
             "dbg_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(vp)]),
             "dbg_build": (ctypes.c_int, [vp, vp, vp, u64, u32]),
             "dbg_build_device": (ctypes.c_int, [vp, vp, u64, vp, u64, u32, vp]),
+            "dbg_build_device_static": (ctypes.c_int, [vp, vp, u64, vp, u64, u32, vp]),
             "dbg_sync": (ctypes.c_int, [vp]),
             "dbg_extract": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
             "dbg_extract_device": (ctypes.c_int, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
@@ -288,6 +289,16 @@ class Graph:
         rc = lib().dbg_build_device(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
                                     _stream(stream))
         _check(rc, "dbg_build_device")
+
+    def build_device_static(self, d_reads, d_offsets, k: int, n_reads: int | None = None,
+                            reads_len: int | None = None, stream=None) -> None:
+        """``dbg_build_device_static``: the device build with its scratch in
+        the library's static device array (no allocation; synchronous)."""
+        n = int(d_offsets.numel() - 1) if n_reads is None else int(n_reads)
+        ln = int(d_reads.numel()) if reads_len is None else int(reads_len)
+        rc = lib().dbg_build_device_static(self.handle, _ptr(d_reads), ln, _ptr(d_offsets), n, int(k),
+                                           _stream(stream))
+        _check(rc, "dbg_build_device_static")
 
     def build_extract_device(self, d_reads, d_offsets, k: int, d_keys, d_counts, n_reads: int | None = None,
                              reads_len: int | None = None, stream=None) -> int:

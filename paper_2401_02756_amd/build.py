@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/dbg_kernels.hip", "csrc/dbg_binned.hip", "csrc/dbg_api.hip", "csrc/dbg_server.hip", "csrc/dbg_tune.hip", "csrc/dbg_contigs.hip"]
+SOURCES = ["csrc/dbg_kernels.hip", "csrc/dbg_binned.hip", "csrc/dbg_api.hip", "csrc/dbg_server.hip", "csrc/dbg_tune.hip", "csrc/dbg_contigs.hip", "csrc/dbg_static.hip"]
 OUT = os.path.join(HERE, "_lib", "libdbg.so")
 
 HIPCC_FLAGS = [

@@ -345,6 +345,7 @@ const char *dbg_strerror(int code) {
     case DBG_E_DEVICE: return "HIP runtime error";
     case DBG_E_RANGE: return "cumulative k-mers would exceed 2^32-1";
     case DBG_E_STATE: return "graph poisoned by an earlier capacity overflow";
+    case DBG_E_SCRATCH: return "input needs more than the static scratch buffer of dbg_build_device_static";
     default: return "unknown error";
     }
 }

@@ -40,7 +40,7 @@ def test_binding_codes_match_header():
     assert codes["E_BASE"] == dbg.E_BASE and codes["E_NOMEM"] == dbg.E_NOMEM
     assert codes["E_FULL"] == dbg.E_FULL and codes["E_SPACE"] == dbg.E_SPACE
     assert codes["E_DEVICE"] == dbg.E_DEVICE and codes["E_RANGE"] == dbg.E_RANGE
-    assert codes["E_STATE"] == dbg.E_STATE
+    assert codes["E_STATE"] == dbg.E_STATE and codes["E_SCRATCH"] == dbg.E_SCRATCH
     text = open(os.path.join(ROOT, "include", "dbg.h")).read()
     assert int(re.search(r"#define DBG_PENDING (\d+)", text).group(1)) == dbg.PENDING
 
@@ -76,7 +76,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_strerror_and_config_init():
     L = dbg.lib()
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         assert L.dbg_strerror(code)
     assert L.dbg_strerror(-99) == b"unknown error"
     cfg = dbg.Config()
@@ -99,6 +99,7 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
     assert L.dbg_build(None, None, None, 1, 21) == dbg.E_INVAL
     assert L.dbg_build_device(None, None, 0, None, 1, 21, None) == dbg.E_INVAL
+    assert L.dbg_build_device_static(None, None, 0, None, 1, 21, None) == dbg.E_INVAL
     assert L.dbg_sync(None) == dbg.E_INVAL
     assert L.dbg_reset(None) == dbg.E_INVAL
     assert L.dbg_get_stats(None, None) == dbg.E_INVAL
