@@ -70,11 +70,12 @@ def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int
     return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
 
 
-def committed_traffic(profile: str, workload: dict) -> int | None:
-    """HBM bytes per launch recorded by the counter runs in `profile`, or
-    None when any of the kernel sources changed since they were taken or the
-    run's workload parameters (`workload`, e.g. load factor and mode) differ
-    from the ones recorded there."""
+def committed_traffic(profile: str, workload: dict, kernel: str) -> int | None:
+    """HBM bytes per launch of `kernel` recorded by the counter runs in
+    `profile` (a line "traffic_bytes_per_launch[<kernel>]: N"), or None when
+    the profile does not exist, any of its kernel sources changed since the
+    counters were taken, or the run's workload parameters (`workload`, e.g.
+    load factor and mode) differ from the ones recorded there."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", profile)
@@ -93,7 +94,8 @@ def committed_traffic(profile: str, workload: dict) -> int | None:
     for k, v in workload.items():
         if fields.get(k) != str(v):
             return None
-    return int(fields["traffic_bytes_per_launch"])
+    v = fields.get("traffic_bytes_per_launch[%s]" % kernel)
+    return int(v) if v else None
 
 
 def binned_kernel_bytes(n_reads: int, total_bases: int, windows: int, vertices: int, fused: bool) -> dict:
@@ -345,7 +347,7 @@ def cpu_lfdbg_scaling(rs, sample_reads: int) -> dict:
 
 
 def measure_step(dbg, torch, dev, rs, inserts: int, mode: str, lf: float, steps: int, warmup: int,
-                 graphs: bool, block: int = 0, wpt: int = 0, merge: bool = False) -> dict:
+                 graphs: bool, block: int = 0, wpt: int = 0, merge: bool = False, shape: dict | None = None) -> dict:
     """Steps of reset + dbg_build_extract_device (the whole path, every vertex
     written to device buffers, status read back) on device-resident reads;
     host wall time over the timed steps."""
@@ -354,7 +356,7 @@ def measure_step(dbg, torch, dev, rs, inserts: int, mode: str, lf: float, steps:
         flags |= dbg.F_GRAPH
     d_reads, d_off = rs.d_reads, rs.d_off
     g = dbg.Graph(expected_vertices=rs.meta["expected_vertices"], load_factor=lf, device=0, flags=flags,
-                  block_size=block, windows_per_thread=wpt)
+                  block_size=block, windows_per_thread=wpt, **(shape or {}))
     cap_out = int(g.stats()["capacity"])
     d_keys = torch.empty(cap_out, dtype=torch.int64, device=dev)
     d_counts = torch.empty((cap_out, 4), dtype=torch.int32, device=dev)
@@ -414,9 +416,8 @@ def kernel_roofline(dbg, rs, windows: int, inserts: int, V: int, cap: int, ms_st
         bytes_alg = algorithmic_bytes(rs.n_reads, rs.total_bases, windows, inserts, V)
         k_ms = phases[-1] if phases else 0.0
         kname, short = "k_build (direct find-or-claim + count)", "k_build"
-    traffic = committed_traffic(profile.format(kernel=short),
-                                {"workload": workload, "kernel": short, "load_factor": lf, "mode": mode,
-                                 "entry_bytes": entry_bytes})
+    traffic = committed_traffic(profile, {"workload": workload, "load_factor": lf, "mode": mode,
+                                          "entry_bytes": entry_bytes}, short)
     achieved = bytes_alg / (k_ms * 1e-3) / 1e9
     step_bytes = scope_step_bytes(inserts, rs.total_bases, cap, V)
     step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
@@ -439,6 +440,8 @@ def main() -> int:
     ap.add_argument("--load-factor", type=float, default=0.5, help="headline table load factor")
     ap.add_argument("--mode", choices=["direct", "binned"], default="binned")
     ap.add_argument("--tune", action="store_true", help="autotune the headline workload too")
+    ap.add_argument("--bin-chunks", type=int, default=0, help="headline binned launch shape: chunks per workgroup")
+    ap.add_argument("--bin-div", type=int, default=0, help="headline binned launch shape: pass-2 scatter grid divisor")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels without HIP graphs")
     ap.add_argument("--no-compare", action="store_true", help="skip the direct-mode comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -493,18 +496,21 @@ def main() -> int:
         info = dict(t.as_dict(), seconds=round(time.perf_counter() - t1, 2))
         log("autotune: %s" % json.dumps(info))
         mode = "binned" if t.flags & dbg.F_BINNED else "direct"
-        return info, mode, t.load_factor, t.block_size, t.windows_per_thread, bool(t.flags & dbg.F_MERGE)
+        return (info, mode, t.load_factor, t.block_size, t.windows_per_thread, bool(t.flags & dbg.F_MERGE),
+                dict(bin_chunks=t.bin_chunks, bin_scatter_div=t.bin_scatter_div))
 
     names = {1: "tiny", 2: "bacterial_c2", 3: "large_c3"}
-    profile = "{kernel}_traffic_%s.md"
+    profile = "hbm_traffic_%s.md"
 
-    def leg(rs, cfg: int, mode: str, lf: float, block: int, wpt: int, merge: bool, steps: int, warmup: int) -> dict:
-        r = measure_step(dbg, torch, dev, rs, rs.inserts, mode, lf, steps, warmup, graphs_on, block, wpt, merge)
+    def leg(rs, cfg: int, mode: str, lf: float, block: int, wpt: int, merge: bool, steps: int, warmup: int,
+            shape: dict) -> dict:
+        r = measure_step(dbg, torch, dev, rs, rs.inserts, mode, lf, steps, warmup, graphs_on, block, wpt, merge,
+                         shape)
         log("%s %s: step %.3f ms (%.2f G/s), V=%d, cap=%d" % (names[cfg], mode, r["ms_step"], r["value"],
                                                               r["V"], r["cap"]))
         # phase times: an uncaptured timed pass with events between the kernels
         pr = r if not graphs_on else measure_step(dbg, torch, dev, rs, rs.inserts, mode, lf, 2, 1, False, block,
-                                                  wpt, merge)
+                                                  wpt, merge, shape)
         table, roof = kernel_roofline(dbg, rs, rs.windows, rs.inserts, r["V"], r["cap"], r["ms_step"],
                                       pr["phases"], mode, lf, r["st"]["entry_bytes"], names[cfg],
                                       profile % names[cfg])
@@ -596,9 +602,10 @@ def main() -> int:
     rs = load(args.config)
     tuning = None
     mode, lf, block, wpt, merge = args.mode, args.load_factor, 0, 0, False
+    shape = dict(bin_chunks=args.bin_chunks, bin_scatter_div=args.bin_div)
     if args.tune:
-        tuning, mode, lf, block, wpt, merge = tuned(rs)
-    h = leg(rs, args.config, mode, lf, block, wpt, merge, args.steps, args.warmup)
+        tuning, mode, lf, block, wpt, merge, shape = tuned(rs)
+    h = leg(rs, args.config, mode, lf, block, wpt, merge, args.steps, args.warmup, shape)
     r = h["r"]
     st = r["st"]
     line = {
@@ -618,7 +625,8 @@ def main() -> int:
                    "reads": rs.n_reads, "read_len": int(rs.meta["read_len"]), "k": rs.k,
                    "inserts_per_step": rs.inserts, "vertices": r["V"], "capacity": r["cap"],
                    "table_bytes": int(st["table_bytes"]), "load_factor": lf, "entry_bytes": st["entry_bytes"],
-                   "mode": mode, "hip_graphs": graphs_on,
+                   "mode": mode, "hip_graphs": graphs_on, "bin_chunks": shape["bin_chunks"],
+                   "bin_scatter_div": shape["bin_scatter_div"],
                    "step": "reset + dbg_build_extract_device (build, every vertex written to device "
                            "buffers, status read back)"},
         "build_kernel_ginserts_s": round(rs.inserts / (r["kern_ms"] * 1e-3) / 1e9, 4),
@@ -659,10 +667,10 @@ def main() -> int:
     if not args.no_bacterial and args.config != 2:
         b = load(2)
         if args.no_tune:
-            btune, bmode, blf, bblock, bwpt, bmerge = None, "binned", 0.5, 0, 0, False
+            btune, bmode, blf, bblock, bwpt, bmerge, bshape = None, "binned", 0.5, 0, 0, False, {}
         else:
-            btune, bmode, blf, bblock, bwpt, bmerge = tuned(b)
-        bl = leg(b, 2, bmode, blf, bblock, bwpt, bmerge, max(args.steps, 10), args.warmup)
+            btune, bmode, blf, bblock, bwpt, bmerge, bshape = tuned(b)
+        bl = leg(b, 2, bmode, blf, bblock, bwpt, bmerge, max(args.steps, 10), args.warmup, bshape)
         br = bl["r"]
         bac = {"workload": "plain build, %s" % b.meta["name"], "inserts_per_step": b.inserts,
                "vertices": br["V"], "capacity": br["cap"], "load_factor": blf, "mode": bmode,

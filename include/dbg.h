@@ -71,6 +71,18 @@ extern "C" {
                               k = 32 or k = 64 falls back to the direct build) */
 #define DBG_F_GRAPH 0x10u  /* capture each build pass as HIP graphs on first use of
                               its size class and replay them afterwards */
+#define DBG_F_STATS 0x20u  /* count probes and compare-and-swap races of every build
+                              of the graph (dbg_get_probe_stats); its builds run the
+                              counting kernels, which are slower; batched builds and
+                              dbg_build_device_static do not count */
+#define DBG_F_TEST_HASH 0x40u /* tests only: every key's home slot is the low 3 bits
+                              of its key (of its image in a binned segment), so all
+                              keys of a table (of a segment) share one probe chain
+                              and race for its slots; results are unchanged, builds
+                              are far slower, and a direct table whose chain passes
+                              the probe limit of 65,536 slots reports DBG_E_FULL.
+                              A batched launch takes graphs of one setting only
+                              (DBG_E_INVAL otherwise). */
 
 typedef struct dbg_graph dbg_graph;
 
@@ -80,9 +92,21 @@ typedef struct dbg_graph dbg_graph;
  * exact number of slots; otherwise capacity = ceil(expected_vertices /
  * load_factor).  With both zero the table is sized at the first build as
  * ceil(windows / load_factor): the number of windows bounds the number of
- * distinct vertices, so that build cannot run out of slots (if that first
- * input is rejected, the next build sizes the table instead).
+ * distinct vertices, so a direct table cannot run out of slots in that build
+ * (if that first input is rejected, the next build sizes the table instead).
+ *
+ * A binned table (DBG_F_BINNED) is cut into segments of 2048 slots, and a key
+ * can only take a slot of its own segment, so DBG_E_FULL comes when one
+ * segment receives more than 2048 distinct vertices, not when the table is
+ * full.  Keys reach segments through a bijective mix, so a segment's vertex
+ * count is close to Poisson with mean 2048 x (vertices / capacity); the
+ * chance that a given segment overflows is below 1e-22 at a load of 0.8 and
+ * 3.6e-13 at 0.85 (so below 1e-6 for a table of a million segments, 49 GB),
+ * but 1.3e-6 at 0.9 (one in two for a 25 GB table).  dbg_create therefore
+ * refuses load_factor > 0.85 for binned graphs; a caller who passes capacity
+ * or expected_vertices sets the load itself and should keep it there.
  */
+#define DBG_BINNED_MAX_LOAD 0.85
 typedef struct {
     uint64_t expected_vertices;  /* estimate of distinct (k-1)-mers; 0 = from input */
     uint64_t capacity;           /* exact slot count; 0 = derive as above */
@@ -92,6 +116,13 @@ typedef struct {
     uint32_t block_size;         /* build kernel threads per block; 0 = 256 */
     uint32_t windows_per_thread; /* windows per thread per tile; 0 = 4 */
     void *stream;                /* hipStream_t for all work; NULL = own stream */
+    /* binned build launch shape: the partition passes work on chunks of
+     * consecutive tiles, about bin_chunks per resident scatter workgroup
+     * (0 = 16; at most 16384 chunks a pass); bin_scatter_div divides the
+     * resident grid of the second partition scatter (0 = automatic: 2 when
+     * a level-1 bucket spans more than 384 table segments, else 1) */
+    uint32_t bin_chunks;
+    uint32_t bin_scatter_div;
 } dbg_config;
 
 typedef struct {
@@ -113,7 +144,27 @@ typedef struct {
     uint64_t graph_replays;   /* build passes replayed from a captured graph */
     uint32_t binned;          /* 1 if the graph uses the binned build */
     uint32_t pad;
+    uint32_t bin_chunks;      /* binned launch shape in use (0 = defaults) */
+    uint32_t bin_scatter_div;
 } dbg_stats;
+
+/* Probe statistics of a graph created with DBG_F_STATS, summed over its
+ * builds since creation or the last dbg_reset.  A lookup is the search for
+ * one vertex's slot: in the global table for a direct graph (one per window,
+ * or per merged group of windows with DBG_F_MERGE), in the LDS copy of a
+ * table segment for a binned graph (one per window).  It examines slots one
+ * after another (linear probing) until it finds its key or claims an empty
+ * slot with a compare-and-swap; a compare-and-swap is lost when another
+ * thread wrote the slot first (the paper's retry case of Algorithms 1 and 3).
+ * For a build into an empty table, cas_attempts - cas_lost is the number of
+ * vertices. */
+typedef struct {
+    uint64_t lookups;
+    uint64_t probes;        /* slots examined by the lookups */
+    uint64_t cas_attempts;  /* compare-and-swaps issued to claim a slot */
+    uint64_t cas_lost;      /* of those, the ones another thread won first */
+    uint64_t probe_hist[8]; /* lookups by slots examined: 1, 2, 3-4, 5-8, 9-16, 17-32, 33-64, more */
+} dbg_probe_stats;
 
 /* Fill *cfg with the defaults (all zero, device -1). */
 void dbg_config_init(dbg_config *cfg);
@@ -121,8 +172,8 @@ void dbg_config_init(dbg_config *cfg);
 /* Create a graph handle.  The table is allocated here when its size is known
  * (capacity or expected_vertices given), else at the first build.  On success
  * *out owns all device memory of the graph until dbg_destroy.
- * Errors: DBG_E_INVAL (NULL, load_factor outside (0,1)), DBG_E_NOMEM,
- * DBG_E_DEVICE. */
+ * Errors: DBG_E_INVAL (NULL, load_factor outside (0,1), or above
+ * DBG_BINNED_MAX_LOAD with DBG_F_BINNED), DBG_E_NOMEM, DBG_E_DEVICE. */
 int dbg_create(const dbg_config *cfg, dbg_graph **out);
 
 /* Add the k-mers of host-resident reads (makeGraph over all reads).  The
@@ -222,6 +273,10 @@ int dbg_get_stats(dbg_graph *g, dbg_stats *out);
  * whole build.  Writes min(cap, *n_phases) values; *n_phases is 0 before any
  * timed build. */
 int dbg_get_phase_times(dbg_graph *g, double *ms, uint32_t cap, uint32_t *n_phases);
+
+/* Probe statistics of the handle's builds (synchronises first).  All zero for
+ * a graph created without DBG_F_STATS.  Errors: DBG_E_INVAL, DBG_E_DEVICE. */
+int dbg_get_probe_stats(dbg_graph *g, dbg_probe_stats *out);
 
 /* Release all device memory of the handle.  NULL is ignored. */
 void dbg_destroy(dbg_graph *g);
@@ -382,31 +437,43 @@ void dbg_server_destroy(dbg_server *s);
 /* ---- autotuning -------------------------------------------------------
  * Picks the build configuration of a workload by timing complete builds of a
  * calibration input (the workload itself, or a slice of it that the caller
- * passes): the table mode (binned or direct), the load factor and, for the
- * direct build, block size, windows per thread and wavefront merging.  Every
- * candidate must produce the same vertex and k-mer totals; one that does not,
- * or that fails (a table overflow at a high load factor), is discarded.  The
- * graph itself never depends on the choice: only the speed does. */
+ * passes): the table mode (binned or direct) and the load factor; for the
+ * binned build, the chunks per workgroup of its partition passes and the
+ * grid divisor of its second scatter; for the direct build, block size,
+ * windows per thread and wavefront merging.  The search goes one axis at a
+ * time from the defaults.  Every candidate must produce the same vertex and
+ * k-mer totals; one that does not, or that fails (a table overflow at a high
+ * load factor), is discarded.  The graph itself never depends on the
+ * choice: only the speed does (the GPU tests build the oracle's graph under
+ * every configuration of dbg_autotune_space). */
 typedef struct {
     double load_factor;
     uint32_t flags;              /* chosen DBG_F_BINNED / DBG_F_MERGE bits (others 0) */
     uint32_t block_size;         /* direct build launch shape (0 for binned) */
     uint32_t windows_per_thread;
-    uint32_t candidates;         /* configurations timed (0 when served from the cache) */
+    uint32_t candidates;         /* configurations timed (0 when served from a cache) */
     double best_ms;              /* median build time of the choice */
     double default_ms;           /* median build time of binned mode at load factor 0.5 */
-    uint32_t from_cache;         /* 1 when the result came from the cache */
+    uint32_t from_cache;         /* 0: timed now; 1: this process's cache; 2: the cache file */
+    uint32_t bin_chunks;         /* binned launch shape (dbg_config), 0 = default */
+    uint32_t bin_scatter_div;
     uint32_t pad;
 } dbg_tuning;
 
-#define DBG_TUNE_FORCE 0x1u /* ignore the cache (and refresh it) */
+#define DBG_TUNE_FORCE 0x1u /* ignore the caches (and refresh them) */
 
 /* Tune for m instances given as in dbg_build_batch_device (m = 1: a plain
  * build).  expected_vertices[i] sizes instance i's table as dbg_config does
  * (NULL or 0 = bound from the input).  keep_flags are DBG_F_* bits every
  * candidate keeps (DBG_F_GRAPH, DBG_F_ENTRY32, DBG_F_TIMING).  repeats timed
- * builds per candidate (0 = 3) after one warm-up.  Results are cached per
- * process by device, instance count, k values, input size class and flags.
+ * builds per candidate (0 = 3) after one warm-up.  Results are cached by
+ * device model (architecture, compute units, memory), instance count, k
+ * values, half-octave size classes of the input and flags: in the process,
+ * and in a cache file that later processes read -- the path in the
+ * environment variable DBG_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/libdbg/autotune.tsv or $HOME/.cache/libdbg/autotune.tsv
+ * (DBG_TUNE_CACHE set but empty: no file).  Lines are appended, the last
+ * line of a key wins.
  * k may exceed 32 (up to 64) only for m = 1; such a graph is tuned over the
  * direct build's launch shape and load factor.
  * Errors: DBG_E_INVAL, or the error of the default configuration's build. */
@@ -415,7 +482,14 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
                  const uint64_t *d_offsets, uint32_t keep_flags, uint32_t repeats, uint32_t tune_flags,
                  dbg_tuning *out);
 
-/* Copy a tuning into a configuration (load factor, launch shape, mode and
+/* Every configuration the tuner's search may time, for the binned (binned
+ * != 0) or the direct build: the cross product of its axes (load factor,
+ * and binned chunks and scatter divisor, or direct block size, windows per
+ * thread and merging).  Writes min(cap, *n) entries (only the configuration
+ * fields are set); *n is the size of the space. */
+int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t *n);
+
+/* Copy a tuning into a configuration (load factor, launch shapes, mode and
  * merge bits; the configuration's other fields are left as they are). */
 void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t);
 

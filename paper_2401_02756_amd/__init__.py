@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libdbg.so")
 OK = 0
 PENDING = 1
 E_INVAL, E_K, E_BASE, E_NOMEM, E_FULL, E_SPACE, E_DEVICE, E_RANGE, E_STATE, E_SCRATCH = range(-1, -11, -1)
-F_MERGE, F_TIMING, F_ENTRY32, F_BINNED, F_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
+F_MERGE, F_TIMING, F_ENTRY32, F_BINNED, F_GRAPH, F_STATS, F_TEST_HASH = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
 
 # every symbol include/dbg.h declares
 EXPORTS = (
@@ -36,9 +36,10 @@ EXPORTS = (
     "dbg_server_poll", "dbg_server_wait", "dbg_server_graph", "dbg_server_times",
     "dbg_server_release", "dbg_server_get_stats", "dbg_server_destroy", "dbg_autotune",
     "dbg_config_apply_tuning", "dbg_contigs", "dbg_contigs_device", "dbg_extract_normalized",
-    "dbg_build_extract_device", "dbg_build_device_static",
+    "dbg_build_extract_device", "dbg_build_device_static", "dbg_get_probe_stats", "dbg_autotune_space",
 )
 NORM_U8 = 0x1
+BINNED_MAX_LOAD = 0.85  # DBG_BINNED_MAX_LOAD: the largest load factor dbg_create takes for a binned graph
 # phases of a timed binned build launched without graphs (dbg_get_phase_times)
 BINNED_PHASES = ("setup", "plan", "count1", "scan1", "scatter1", "plan2", "count2", "scan2", "scatter2",
                  "starts", "reduce")
@@ -55,6 +56,8 @@ class Config(ctypes.Structure):
         ("block_size", ctypes.c_uint32),
         ("windows_per_thread", ctypes.c_uint32),
         ("stream", ctypes.c_void_p),
+        ("bin_chunks", ctypes.c_uint32),
+        ("bin_scatter_div", ctypes.c_uint32),
     ]
 
 
@@ -78,10 +81,22 @@ class Stats(ctypes.Structure):
         ("graph_replays", ctypes.c_uint64),
         ("binned", ctypes.c_uint32),
         ("pad", ctypes.c_uint32),
+        ("bin_chunks", ctypes.c_uint32),
+        ("bin_scatter_div", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ProbeStats(ctypes.Structure):
+    _fields_ = [("lookups", ctypes.c_uint64), ("probes", ctypes.c_uint64), ("cas_attempts", ctypes.c_uint64),
+                ("cas_lost", ctypes.c_uint64), ("probe_hist", ctypes.c_uint64 * 8)]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "probe_hist"}
+        d["probe_hist"] = [int(x) for x in self.probe_hist]
+        return d
 
 
 class Input(ctypes.Structure):
@@ -124,6 +139,8 @@ class Tuning(ctypes.Structure):
         ("best_ms", ctypes.c_double),
         ("default_ms", ctypes.c_double),
         ("from_cache", ctypes.c_uint32),
+        ("bin_chunks", ctypes.c_uint32),
+        ("bin_scatter_div", ctypes.c_uint32),
         ("pad", ctypes.c_uint32),
     ]
 
@@ -133,7 +150,8 @@ class Tuning(ctypes.Structure):
     def graph_kwargs(self) -> dict:
         """Keyword arguments of ``Graph`` that apply this tuning."""
         return dict(load_factor=self.load_factor, block_size=self.block_size,
-                    windows_per_thread=self.windows_per_thread, flags=self.flags)
+                    windows_per_thread=self.windows_per_thread, flags=self.flags,
+                    bin_chunks=self.bin_chunks, bin_scatter_div=self.bin_scatter_div)
 
 
 _lib = None
@@ -160,6 +178,7 @@ def lib() -> ctypes.CDLL:
                                                         ctypes.POINTER(u64), vp]),
             "dbg_reset": (ctypes.c_int, [vp]),
             "dbg_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(Stats)]),
+            "dbg_get_probe_stats": (ctypes.c_int, [vp, ctypes.POINTER(ProbeStats)]),
             "dbg_destroy": (None, [vp]),
             "dbg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "dbg_build_batch": (ctypes.c_int, [vp, vp, u32, vp, vp]),
@@ -184,6 +203,7 @@ def lib() -> ctypes.CDLL:
             "dbg_autotune": (ctypes.c_int, [i32, u32, vp, vp, vp, vp, u64, vp, u32, u32, u32,
                                             ctypes.POINTER(Tuning)]),
             "dbg_config_apply_tuning": (None, [ctypes.POINTER(Config), ctypes.POINTER(Tuning)]),
+            "dbg_autotune_space": (ctypes.c_int, [u32, ctypes.POINTER(Tuning), u32, ctypes.POINTER(u32)]),
             "dbg_extract_normalized": (ctypes.c_int, [vp, u64, u32, vp, vp, u64, ctypes.POINTER(u64)]),
             "dbg_contigs": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
             "dbg_contigs_device": (ctypes.c_int, [vp, vp, u64, vp, u64, ctypes.POINTER(u64),
@@ -235,7 +255,8 @@ class Graph:
 
     def __init__(self, expected_vertices: int = 0, capacity: int = 0, load_factor: float = 0.0,
                  device: int = -1, flags: int = 0, block_size: int = 0,
-                 windows_per_thread: int = 0, stream=None, _borrowed=None):
+                 windows_per_thread: int = 0, stream=None, bin_chunks: int = 0, bin_scatter_div: int = 0,
+                 _borrowed=None):
         self._owned = _borrowed is None
         if not self._owned:
             self._h = ctypes.c_void_p(_borrowed)
@@ -250,6 +271,8 @@ class Graph:
         cfg.block_size = int(block_size)
         cfg.windows_per_thread = int(windows_per_thread)
         cfg.stream = _stream(stream)
+        cfg.bin_chunks = int(bin_chunks)
+        cfg.bin_scatter_div = int(bin_scatter_div)
         h = ctypes.c_void_p()
         _check(lib().dbg_create(ctypes.byref(cfg), ctypes.byref(h)), "dbg_create")
         self._h = h
@@ -412,6 +435,13 @@ class Graph:
         _check(lib().dbg_get_stats(self.handle, ctypes.byref(s)), "dbg_get_stats")
         return s.as_dict()
 
+    def probe_stats(self) -> dict:
+        """``dbg_get_probe_stats``: lookups, probes, compare-and-swaps and lost
+        races of the graph's builds (zeros without F_STATS)."""
+        s = ProbeStats()
+        _check(lib().dbg_get_probe_stats(self.handle, ctypes.byref(s)), "dbg_get_probe_stats")
+        return s.as_dict()
+
 
 def build_batch(graphs: list[Graph], inputs: list[tuple], stream=None) -> list[int]:
     """``dbg_build_batch``: inputs[i] = (reads, offsets, k) for graphs[i].
@@ -465,6 +495,16 @@ def autotune(read_begin, ks, d_reads, d_offsets, expected_vertices=None, keep_fl
                             int(keep_flags), int(repeats), TUNE_FORCE if force else 0, ctypes.byref(t))
     _check(rc, "dbg_autotune")
     return t
+
+
+def autotune_space(binned: bool) -> list[Tuning]:
+    """``dbg_autotune_space``: every configuration the tuner may time for the
+    binned or the direct build."""
+    n = ctypes.c_uint32(0)
+    _check(lib().dbg_autotune_space(1 if binned else 0, None, 0, ctypes.byref(n)), "dbg_autotune_space")
+    arr = (Tuning * max(n.value, 1))()
+    _check(lib().dbg_autotune_space(1 if binned else 0, arr, n.value, ctypes.byref(n)), "dbg_autotune_space")
+    return [arr[i] for i in range(n.value)]
 
 
 ROOF_LOAD64, ROOF_ADD32, ROOF_CAS64, ROOF_LOAD_ADD, ROOF_COPY = 0, 1, 2, 3, 4

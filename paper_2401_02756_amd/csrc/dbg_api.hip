@@ -27,10 +27,12 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     if (cfg_in) cfg = *cfg_in;
     const double lf = cfg.load_factor == 0 ? 0.5 : cfg.load_factor;
     if (!(lf > 0 && lf < 1)) return DBG_E_INVAL;
+    if ((cfg.flags & DBG_F_BINNED) && lf > DBG_BINNED_MAX_LOAD) return DBG_E_INVAL;  // segment overflow odds
     const uint32_t block = cfg.block_size ? cfg.block_size : 256;
     if (block % 64 || block > 1024) return DBG_E_INVAL;
     const uint32_t wpt = cfg.windows_per_thread ? cfg.windows_per_thread : 4;
     if (wpt > 64) return DBG_E_INVAL;
+    if (cfg.bin_chunks > dbgk::kMaxChunkTarget || cfg.bin_scatter_div > 64) return DBG_E_INVAL;
 
     int device = cfg.device;
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
@@ -50,6 +52,8 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     g->shape.wpt = wpt;
     g->shape.merge = (cfg.flags & DBG_F_MERGE) ? 1 : 0;
     g->shape.grid = dbgk::build_grid(device, block);
+    g->bin_chunks = cfg.bin_chunks;
+    g->bin_div = cfg.bin_scatter_div;
     g->grid_wide = dbgk::build_grid_wide(device, block);
 
     int rc = DBG_OK;
@@ -63,6 +67,11 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     if (rc == DBG_OK && g->pass.init() != hipSuccess) rc = DBG_E_DEVICE;
     if (rc == DBG_OK && hipEventCreateWithFlags(&g->zero_ev, hipEventDisableTiming) != hipSuccess)
         rc = DBG_E_DEVICE;
+    if (rc == DBG_OK && (g->flags & DBG_F_STATS)) {
+        hipError_t e = g->pstats.reserve(8 * dbgk::kStatWords);
+        if (e == hipSuccess) e = zero_stats(g);
+        if (e != hipSuccess) rc = hip_code(e);
+    }
     if (rc == DBG_OK && (g->cap_req || g->expected)) rc = ensure_table(g, 0);
     if (rc != DBG_OK) {
         dbg_destroy(g);
@@ -271,6 +280,7 @@ int dbg_reset(dbg_graph *g) {
     g->vertices = g->inserts = g->windows = g->builds = 0;
     ++g->epoch;
     g->fresh = true;
+    if ((g->flags & DBG_F_STATS) && zero_stats(g) != hipSuccess) return DBG_E_DEVICE;
     // A binned build rewrites every slot of a fresh table, so its reset only
     // marks the table empty; the direct build needs the zeros.
     if (!g->cap || g->binned) return DBG_OK;
@@ -302,6 +312,8 @@ int dbg_get_stats(dbg_graph *g, dbg_stats *out) {
     out->graph_captures = g->pass.captures;
     out->graph_replays = g->pass.replays;
     out->binned = g->binned ? 1u : 0u;
+    out->bin_chunks = g->bin_chunks;
+    out->bin_scatter_div = g->bin_div;
     return DBG_OK;
 }
 
@@ -312,13 +324,34 @@ void dbg_destroy(dbg_graph *g) {
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     DevBuf *bufs[] = {&g->table, &g->reads,     &g->offsets, &g->xkeys,        &g->xcnt,    &g->xn,
                       &g->nkeys, &g->ncnt,      &g->n8,      &g->seg_count,    &g->seg_off, &g->seg_partials,
-                      &g->seg_len};
+                      &g->seg_len, &g->pstats};
     for (DevBuf *b : bufs) b->release();
     g->pass.release();
     dbg_contigs_free(g->contigs);
     if (g->zero_ev) (void)hipEventDestroy(g->zero_ev);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+int dbg_get_probe_stats(dbg_graph *g, dbg_probe_stats *out) {
+    if (!g || !out) return DBG_E_INVAL;
+    DeviceGuard guard(g->device);
+    if (g->pass.pending) {
+        const int rc = harvest(g);
+        if (rc != DBG_OK) g->unreported = rc;
+    }
+    std::memset(out, 0, sizeof *out);
+    if (!(g->flags & DBG_F_STATS)) return DBG_OK;
+    uint64_t w[dbgk::kStatWords] = {};
+    hipError_t e = hipMemcpyAsync(w, g->pstats.p, sizeof w, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return DBG_E_DEVICE;
+    out->lookups = w[dbgk::kStatLookups];
+    out->probes = w[dbgk::kStatProbes];
+    out->cas_attempts = w[dbgk::kStatCas];
+    out->cas_lost = w[dbgk::kStatCasLost];
+    for (int i = 0; i < 8; ++i) out->probe_hist[i] = w[dbgk::kStatHist + i];
+    return DBG_OK;
 }
 
 int dbg_get_phase_times(dbg_graph *g, double *ms, uint32_t cap, uint32_t *n_phases) {

@@ -13,11 +13,13 @@
 //           instance, each covering `fan` consecutive segments)
 //   pass 2  records of each bucket -> records grouped by segment
 //
-// Every pass is count -> flat exclusive scan -> scatter.  The count kernel
-// writes one histogram per tile, laid out bucket-major and tile-minor, so one
-// exclusive scan over the whole histogram array gives each (tile, bucket) its
-// output offset directly; the scatter kernel sorts its tile by bucket in LDS
-// and writes each bucket's run contiguously.
+// Every pass is count -> flat exclusive scan -> scatter, over chunks of
+// consecutive tiles.  The count kernel writes one histogram per chunk, laid
+// out bucket-major and chunk-minor, so one exclusive scan over the whole
+// histogram array gives each (chunk, bucket) its output offset directly; the
+// scatter kernel sorts each tile of its chunk by bucket in LDS and appends
+// each bucket's run to the chunk's run of that bucket, so a chunk writes one
+// contiguous run per bucket however many tiles it spans.
 //
 // Finally one workgroup owns each segment: it stages the segment in LDS,
 // finds or claims each record's vertex with a 64-bit LDS compare-and-swap
@@ -245,42 +247,20 @@ __device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, G 
     }
 }
 
-// The same, with the global bases already loaded: g[q] holds the base of
-// bucket threadIdx.x * per + q, per = ceil(n / blockDim.x) <= N.
-template <uint32_t N>
-__device__ void bucket_starts_pre(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, const uint64_t (&g)[N]) {
-    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t j0 = threadIdx.x * per;
-    uint64_t sum = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < N; ++q)
-        if (q < per && j0 + q < n) sum += s_cnt[j0 + q] - ((j0 + q) << 12);
-    uint64_t total;
-    uint64_t pre = block_exclusive_scan(sum, &total);
-#pragma unroll
-    for (uint32_t q = 0; q < N; ++q) {
-        const uint32_t j = j0 + q;
-        if (q < per && j < n) {
-            const uint32_t c = s_cnt[j] - (j << 12);
-            s_cnt[j] = (uint32_t)pre;
-            s_gbase[j] = g[q] - pre;
-            pre += c;
-        }
-    }
-}
-
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // ---------------------------------------------------------------- plan
 
-// Per instance: its window range, pass-1 tiles, histogram and bucket bases.
-// An instance that failed validation (or whose k-mer total would overflow a
-// counter) gets no tiles, so it produces no records.
+// Per instance: its window range, pass-1 tiles and chunks, histogram and
+// bucket bases.  The chunk length (tiles) is max(1, floor(tiles / target))
+// over the whole launch; chunks never span instances.  An instance that
+// failed validation (or whose k-mer total would overflow a counter) gets no
+// tiles, so it produces no records.
 __global__ void k_bin_plan(const PassArgs *__restrict__ args, const Instance *inst, const uint64_t *ws,
-                           InstStatus *st, BinPlan *plan, BinTotals *tot) {
+                           InstStatus *st, BinPlan *plan, BinTotals *tot, uint32_t target) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t m = args->m;
-    uint64_t tiles = 0, hist = 0, buckets = 0;
+    uint64_t all_tiles = 0;
     for (uint32_t i = 0; i < m; ++i) {
         const Instance &in = inst[i];
         uint32_t e = st[i].err;
@@ -288,23 +268,37 @@ __global__ void k_bin_plan(const PassArgs *__restrict__ args, const Instance *in
             atomic_or_u32(&st[i].err, kErrRange);
             e |= kErrRange;
         }
+        const uint64_t wb = ws[in.read_begin], we = ws[in.read_end];
+        if (!(e & kSkipMask) && we > wb) all_tiles += (we - wb + kBinTile - 1) / kBinTile;
+    }
+    const uint64_t chunk = max<uint64_t>(1, all_tiles / max(target, 1u));
+    uint64_t tiles = 0, chunks = 0, hist = 0, buckets = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const Instance &in = inst[i];
+        const uint32_t e = st[i].err;
         BinPlan pl;
         pl.w_begin = ws[in.read_begin];
         pl.w_end = ws[in.read_end];
         const bool run = !(e & kSkipMask) && pl.w_end > pl.w_begin;
         pl.tiles = run ? (pl.w_end - pl.w_begin + kBinTile - 1) / kBinTile : 0;
+        pl.chunks = (pl.tiles + chunk - 1) / chunk;
         pl.tile_base = tiles;
+        pl.chunk_base = chunks;
         pl.hist_base = hist;
         pl.bucket_base = buckets;
         tiles += pl.tiles;
-        hist += (uint64_t)in.d1 * pl.tiles;
+        chunks += pl.chunks;
+        hist += (uint64_t)in.d1 * pl.chunks;
         buckets += in.d1;
         plan[i] = pl;
     }
     tot->tiles1 = tiles;
+    tot->chunk1 = chunk;
+    tot->chunks1 = chunks;
     tot->hist1_len = hist;
     tot->buckets = buckets;
-    tot->tiles2 = 0;
+    tot->chunk2 = 1;
+    tot->chunks2 = 0;
     tot->hist2_len = 0;
     tot->records = 0;
 }
@@ -340,13 +334,20 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
     return b;
 }
 
-// Pass 1.  A thread takes kBinPerThread consecutive windows of the tile: it
-// finds their read once, loads three packed words, and slides through them,
-// so a window costs a few shifts instead of a search and two loads.  The
-// next read's bases follow the current read's in the packed array, so a
-// window that starts another read (k - 2 bases further on) is found in the
-// staged reads and mostly stays inside the three words.  Long keys (RW = 2)
-// take each window's 128 bits from the packed array directly.
+// Pass 1, per chunk of tiles.  A thread takes kBinPerThread consecutive
+// windows of a tile: it finds their read once, loads three packed words, and
+// slides through them, so a window costs a few shifts instead of a search
+// and two loads.  The next read's bases follow the current read's in the
+// packed array, so a window that starts another read (k - 2 bases further
+// on) is found in the staged reads and mostly stays inside the three words.
+// Long keys (RW = 2) take each window's 128 bits from the packed array
+// directly.
+//
+// Counting, a chunk's histogram accumulates in LDS over its tiles and is
+// written once.  Scattering, s_gbase[j] holds the global position where the
+// chunk's run of bucket j continues: each tile sorts its records by bucket
+// in LDS, writes bucket j's records at s_gbase[j] on, and advances s_gbase[j]
+// by their number.
 template <bool SCATTER, uint32_t RW>
 __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
@@ -369,102 +370,131 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
     const uint32_t tid = threadIdx.x;
     const uint32_t m = args->m;
     const uint64_t *__restrict__ off = args->off;
-    const uint64_t tiles = tot->tiles1;
+    const uint64_t chunks = tot->chunks1, chunk = tot->chunk1;
     const uint64_t off0 = off[0];
-    for (XcdTiles it(tiles); it.valid(); it.advance()) {
-        const uint64_t t = it.next;
-        const uint32_t i = (uint32_t)last_le(m, t, [&](uint64_t j) { return plan[j].tile_base; });
+    // One flat loop over the tiles of this workgroup's chunks: only the chunk
+    // cursor and the tile index t carry from one tile to the next (a nested
+    // chunk/tile loop keeps the chunk's values live across the decode, which
+    // then spills).  Each tile looks its chunk up again.
+    XcdTiles it(chunks);
+    for (uint32_t t = 0; it.valid();) {
+        const uint64_t gc = it.next;
+        const uint32_t i = (uint32_t)last_le(m, gc, [&](uint64_t j) { return plan[j].chunk_base; });
         const Instance &in = inst[i];
-        const BinPlan pl = plan[i];
-        const uint64_t tl = t - pl.tile_base;
-        const uint64_t w0 = pl.w_begin + tl * kBinTile;
-        const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, pl.w_end) - w0);
         const uint32_t d1 = in.d1;
         const uint32_t kshift = 64 - 2 * (in.k - 1), lshift = 62 - 2 * (in.k - 1);
-        for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = SCATTER ? j << 12 : 0u;
-        stage_reads(S, ws, off, off0, tile_read1[t], in.read_end);
-
-        R rec[kBinPerThread];
-        uint32_t tag[kBinPerThread];  // scatter: bucket << 12 | rank (bucket d1: past the end)
-        const uint32_t j0 = tid * kBinPerThread;
-#pragma unroll
-        for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = d1 << 12;
-        if (j0 < n_in) {
-            uint64_t w = w0 + j0;
-            ReadCursor rp = first_read(S, ws, off, off0, in.read_end, w);
-            uint64_t p = w + rp.delta;
-            uint64_t wbase = p >> 5;
-            uint64_t a = 0, b = 0, c = 0;
-            if (RW == 1) {
-                a = packed[wbase];
-                b = packed[wbase + 1];
-                c = packed[wbase + 2];
+        const uint64_t read_end = in.read_end;
+        const uint64_t c = gc - plan[i].chunk_base;
+        const uint64_t tbeg = c * chunk;
+        const uint32_t nt = (uint32_t)(min(tbeg + chunk, plan[i].tiles) - tbeg);
+        if (t == 0) {  // the chunk starts
+            if (!SCATTER) {
+                for (uint32_t j = tid; j < d1; j += blockDim.x) s_cnt[j] = 0u;
+            } else {
+                const uint64_t *col = scan1 + plan[i].hist_base + c;
+                const uint64_t stride = plan[i].chunks;
+                for (uint32_t j = tid; j < d1; j += blockDim.x) s_gbase[j] = col[(uint64_t)j * stride];
             }
+        }
+        {
+            const uint64_t w0 = plan[i].w_begin + (tbeg + t) * kBinTile;
+            const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, plan[i].w_end) - w0);
+            if (SCATTER)
+                for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = j << 12;
+            stage_reads(S, ws, off, off0, tile_read1[plan[i].tile_base + tbeg + t], read_end);
+
+            R rec[kBinPerThread];
+            uint32_t tag[kBinPerThread];  // scatter: bucket << 12 | rank (bucket d1: past the end)
+            const uint32_t j0 = tid * kBinPerThread;
+#pragma unroll
+            for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = d1 << 12;
+            if (j0 < n_in) {
+                uint64_t w = w0 + j0;
+                ReadCursor rp = first_read(S, ws, off, off0, read_end, w);
+                uint64_t p = w + rp.delta;
+                uint64_t wbase = p >> 5;
+                uint64_t a = 0, b = 0, cc = 0;
+                if (RW == 1) {
+                    a = packed[wbase];
+                    b = packed[wbase + 1];
+                    cc = packed[wbase + 2];
+                }
+#pragma unroll
+                for (uint32_t q = 0; q < kBinPerThread; ++q) {
+                    if (j0 + q >= n_in) break;
+                    if (w >= rp.wr1) {  // the next window starts another read
+                        next_read(rp, S, ws, off, off0, read_end, w);
+                        p = w + rp.delta;
+                        // the words must hold this and the remaining windows' first
+                        // bases at offsets below 64 (without a crossing a thread's
+                        // offsets stay below 32 + kBinPerThread)
+                        if (RW == 1 && p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
+                            wbase = p >> 5;
+                            a = packed[wbase];
+                            b = packed[wbase + 1];
+                            cc = packed[wbase + 2];
+                        }
+                    }
+                    const uint64_t sink = w + 1 == rp.wr1 ? 4u : 0u;
+                    uint64_t head;
+                    if constexpr (RW == 1) {
+                        const uint64_t v = funnel3(a, b, cc, (uint32_t)(p - 32 * wbase) * 2);
+                        head = (key_image(v >> kshift) << 3) | sink | ((uint32_t)(v >> lshift) & 3u);
+                        rec[q] = head;
+                    } else {
+                        uint64_t x0, x1, kh, kl, ih, il;
+                        uint32_t letter;
+                        bases128_at(packed, p, x0, x1);
+                        wide_window(x0, x1, in.k - 1, kh, kl, letter);
+                        wide_image(kh, kl, ih, il);
+                        head = (ih << 3) | sink | letter;
+                        rec[q] = make_ulonglong2(head, il);
+                    }
+                    const uint32_t bk = bucket_of(image_top(head >> 3), d1);
+                    if (SCATTER) {
+                        tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
+                    } else {
+                        __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    ++w;
+                    ++p;
+                }
+            }
+            __syncthreads();  // the next tile's staging waits on this barrier
+            if (SCATTER) {
+            // s_gbase[j] becomes the global position of the tile's first record
+            // of bucket j minus its position in the sorted tile
+            bucket_starts(s_cnt, s_gbase, d1, [&](uint32_t j) { return s_gbase[j]; });
+            __syncthreads();
 #pragma unroll
             for (uint32_t q = 0; q < kBinPerThread; ++q) {
-                if (j0 + q >= n_in) break;
-                if (w >= rp.wr1) {  // the next window starts another read
-                    next_read(rp, S, ws, off, off0, in.read_end, w);
-                    p = w + rp.delta;
-                    // the words must hold this and the remaining windows' first
-                    // bases at offsets below 64 (without a crossing a thread's
-                    // offsets stay below 32 + kBinPerThread)
-                    if (RW == 1 && p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
-                        wbase = p >> 5;
-                        a = packed[wbase];
-                        b = packed[wbase + 1];
-                        c = packed[wbase + 2];
-                    }
-                }
-                const uint64_t sink = w + 1 == rp.wr1 ? 4u : 0u;
-                uint64_t head;
-                if constexpr (RW == 1) {
-                    const uint64_t v = funnel3(a, b, c, (uint32_t)(p - 32 * wbase) * 2);
-                    head = (key_image(v >> kshift) << 3) | sink | ((uint32_t)(v >> lshift) & 3u);
-                    rec[q] = head;
-                } else {
-                    uint64_t x0, x1, kh, kl, ih, il;
-                    uint32_t letter;
-                    bases128_at(packed, p, x0, x1);
-                    wide_window(x0, x1, in.k - 1, kh, kl, letter);
-                    wide_image(kh, kl, ih, il);
-                    head = (ih << 3) | sink | letter;
-                    rec[q] = make_ulonglong2(head, il);
-                }
-                const uint32_t bk = bucket_of(image_top(head >> 3), d1);
-                if (SCATTER) {
-                    tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
-                } else {
-                    __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                ++w;
-                ++p;
+                const uint32_t bk = tag[q] >> 12;
+                if (bk == d1) continue;  // past the tile's end
+                const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
+                s_rec[pos] = rec[q];
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < n_in; j += blockDim.x) {
+                const R r = s_rec[j];
+                const uint32_t bk = bucket_of(image_top(RecOf<RW>::head(r) >> 3), d1);
+                rec1[s_gbase[bk] + j] = r;
+            }
+            __syncthreads();
+            // the runs continue after this tile's records: start of bucket j + 1
+            for (uint32_t j = tid; j < d1; j += blockDim.x) s_gbase[j] += j + 1 < d1 ? s_cnt[j + 1] : n_in;
+            __syncthreads();
             }
         }
-        __syncthreads();
+        if (++t < nt) continue;
+        // the chunk ends
         if (!SCATTER) {
-            for (uint32_t j = tid; j < d1; j += blockDim.x)
-                hist1[pl.hist_base + (uint64_t)j * pl.tiles + tl] = s_cnt[j];
+            uint32_t *col = hist1 + plan[i].hist_base + c;
+            const uint64_t stride = plan[i].chunks;
+            for (uint32_t j = tid; j < d1; j += blockDim.x) col[(uint64_t)j * stride] = s_cnt[j];
             __syncthreads();
-            continue;
         }
-        bucket_starts(s_cnt, s_gbase, d1,
-                      [&](uint32_t j) { return scan1[pl.hist_base + (uint64_t)j * pl.tiles + tl]; });
-        __syncthreads();
-#pragma unroll
-        for (uint32_t q = 0; q < kBinPerThread; ++q) {
-            const uint32_t bk = tag[q] >> 12;
-            if (bk == d1) continue;  // past the tile's end
-            const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
-            s_rec[pos] = rec[q];
-        }
-        __syncthreads();
-        for (uint32_t j = tid; j < n_in; j += blockDim.x) {
-            const R r = s_rec[j];
-            const uint32_t bk = bucket_of(image_top(RecOf<RW>::head(r) >> 3), d1);
-            rec1[s_gbase[bk] + j] = r;
-        }
-        __syncthreads();
+        t = 0;
+        it.advance();
     }
 }
 
@@ -529,46 +559,64 @@ __global__ __launch_bounds__(kFlatBlock) void k_flat_add(const uint64_t *len_ptr
 
 // ---------------------------------------------------------------- pass 2
 
-// Per level-1 bucket: its record range, pass-2 tiles and histogram base.
+// Per level-1 bucket: its record range, pass-2 chunks and histogram base.
+// The chunk length (tiles of kRefTile records) is max(1, floor(tiles /
+// target)) over the launch; chunks never span buckets.
+__device__ __forceinline__ Bucket bucket_range(const PassArgs *__restrict__ args, const Instance *__restrict__ inst,
+                                               const BinPlan *__restrict__ plan, const uint64_t *__restrict__ scan1,
+                                               uint64_t g) {
+    const uint32_t i = (uint32_t)last_le(args->m, g, [&](uint64_t j) { return plan[j].bucket_base; });
+    const Instance &in = inst[i];
+    const BinPlan pl = plan[i];
+    const uint32_t b = (uint32_t)(g - pl.bucket_base);
+    Bucket B{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    B.start = scan1[pl.hist_base + (uint64_t)b * pl.chunks];
+    B.size = scan1[pl.hist_base + (uint64_t)(b + 1) * pl.chunks] - B.start;
+    B.inst = i;
+    B.b = b;
+    B.fan = min(in.fan, in.parts - b * in.fan);
+    return B;
+}
+
 __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict__ args,
                                                      const Instance *__restrict__ inst,
                                                      const BinPlan *__restrict__ plan,
                                                      const uint64_t *__restrict__ scan1,
-                                                     BinTotals *tot, Bucket *__restrict__ buckets) {
-    const uint32_t m = args->m;
+                                                     BinTotals *tot, Bucket *__restrict__ buckets, uint32_t target) {
     const uint64_t G = tot->buckets;
-    uint64_t carry_t = 0, carry_h = 0;
+    // tiles over all buckets, for the chunk length
+    uint64_t my_tiles = 0;
+    for (uint64_t g = threadIdx.x; g < G; g += blockDim.x)
+        my_tiles += (bucket_range(args, inst, plan, scan1, g).size + kRefTile - 1) / kRefTile;
+    uint64_t all_tiles;
+    (void)block_exclusive_scan(my_tiles, &all_tiles);
+    const uint64_t chunk = max<uint64_t>(1, all_tiles / max(target, 1u));
+    uint64_t carry_c = 0, carry_h = 0;
     for (uint64_t base = 0; base < G; base += blockDim.x) {
         const uint64_t g = base + threadIdx.x;
         Bucket B{0, 0, 0, 0, 0, 0, 0, 0, 0};
-        uint64_t nt = 0, nh = 0;
+        uint64_t nc = 0, nh = 0;
         if (g < G) {
-            const uint32_t i = (uint32_t)last_le(m, g, [&](uint64_t j) { return plan[j].bucket_base; });
-            const Instance &in = inst[i];
-            const BinPlan pl = plan[i];
-            const uint32_t b = (uint32_t)(g - pl.bucket_base);
-            B.start = scan1[pl.hist_base + (uint64_t)b * pl.tiles];
-            B.size = scan1[pl.hist_base + (uint64_t)(b + 1) * pl.tiles] - B.start;
-            B.inst = i;
-            B.b = b;
-            B.fan = min(in.fan, in.parts - b * in.fan);
-            nt = (B.size + kRefTile - 1) / kRefTile;
-            nh = nt * B.fan;
+            B = bucket_range(args, inst, plan, scan1, g);
+            const uint64_t nt = (B.size + kRefTile - 1) / kRefTile;
+            nc = (nt + chunk - 1) / chunk;
+            nh = nc * B.fan;
         }
-        uint64_t tt, th;
-        const uint64_t pt = block_exclusive_scan(nt, &tt);
+        uint64_t tc, th;
+        const uint64_t pc = block_exclusive_scan(nc, &tc);
         const uint64_t ph = block_exclusive_scan(nh, &th);
         if (g < G) {
-            B.tiles = nt;
-            B.tile_base = carry_t + pt;
+            B.chunks = nc;
+            B.chunk_base = carry_c + pc;
             B.hist_base = carry_h + ph;
             buckets[g] = B;
         }
-        carry_t += tt;
+        carry_c += tc;
         carry_h += th;
     }
     if (threadIdx.x == 0) {
-        tot->tiles2 = carry_t;
+        tot->chunk2 = chunk;
+        tot->chunks2 = carry_c;
         tot->hist2_len = carry_h;
         tot->records = scan1[tot->hist1_len];
     }
@@ -583,23 +631,23 @@ __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter
     return b;
 }
 
-constexpr uint32_t kRefMaxPer = (kMaxFan + kRefBlock - 1) / kRefBlock;  // segments per thread in a scan
 
-// Load a pass-2 tile's records (the tile's order of records over threads is
-// free: counts and ranks only need each record once).  One-word records go
-// two per load.
+// Load the records of one pass-2 tile: [r0, r0 + n) with n <= kRefTile (the
+// order of records over threads is free: counts and ranks only need each
+// record once).  One-word records go two per load.
 template <typename R>
-__device__ __forceinline__ void refine_load(const RefTile &T, const R *__restrict__ rec1, R (&rec)[kRefPerThread]) {
+__device__ __forceinline__ void refine_load(uint64_t r0, uint32_t n, const R *__restrict__ rec1,
+                                            R (&rec)[kRefPerThread]) {
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
         for (uint32_t it = 0; it < kRefPerThread / 2; ++it) {
             const uint32_t j = 2 * (it * blockDim.x + threadIdx.x);
-            if (j + 1 < T.n) {
-                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(rec1 + T.r0 + j);
+            if (j + 1 < n) {
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(rec1 + r0 + j);
                 rec[2 * it] = v.x;
                 rec[2 * it + 1] = v.y;
             } else {
-                rec[2 * it] = j < T.n ? rec1[T.r0 + j] : R{};
+                rec[2 * it] = j < n ? rec1[r0 + j] : R{};
                 rec[2 * it + 1] = R{};
             }
         }
@@ -607,29 +655,29 @@ __device__ __forceinline__ void refine_load(const RefTile &T, const R *__restric
 #pragma unroll
         for (uint32_t it = 0; it < kRefPerThread; ++it) {
             const uint32_t j = it * blockDim.x + threadIdx.x;
-            rec[it] = j < T.n ? rec1[T.r0 + j] : R{};
+            rec[it] = j < n ? rec1[r0 + j] : R{};
         }
     }
 }
 
 // Whether slot it of a thread's records holds one (matches refine_load).
 template <typename R>
-__device__ __forceinline__ bool refine_has(const RefTile &T, uint32_t it) {
+__device__ __forceinline__ bool refine_has(uint32_t n, uint32_t it) {
     if constexpr (sizeof(R) == 8)
-        return 2 * ((it / 2) * blockDim.x + threadIdx.x) + (it & 1) < T.n;
+        return 2 * ((it / 2) * blockDim.x + threadIdx.x) + (it & 1) < n;
     else
-        return it * blockDim.x + threadIdx.x < T.n;
+        return it * blockDim.x + threadIdx.x < n;
 }
 
-// Pass 2, per tile of records of one level-1 bucket: count (or, with
-// SCATTER, place) each record by its segment inside the bucket.  The next
-// tile's descriptor is read while this one is counted and its records are
-// loaded while this one is written; a scatter tile's global bases load while
-// its records are counted.  So a tile's global loads never wait on the
-// previous tile.
+// Pass 2, per chunk of tiles of one level-1 bucket's records: count (or,
+// with SCATTER, place) each record by its segment inside the bucket.  The
+// next tile's records (in this chunk or the next one) are loaded while this
+// tile is written.  Counting, a chunk's histogram accumulates in LDS over its
+// tiles; scattering, s_gbase[j] holds where the chunk's run of segment j
+// continues, as in pass 1.
 template <bool SCATTER, uint32_t RW>
 __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
-                                                     const RefTile *__restrict__ tile2,
+                                                     const RefChunk *__restrict__ chunk2,
                                                      const uint64_t *__restrict__ rec1w,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
@@ -643,46 +691,48 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
     const R *rec1 = reinterpret_cast<const R *>(rec1w);
     R *rec2 = reinterpret_cast<R *>(rec2w);
     const uint32_t tid = threadIdx.x;
-    XcdTiles xt(tot->tiles2);
+    XcdTiles xt(tot->chunks2);
     if (!xt.valid()) return;
-    RefTile T = tile2[xt.next];
+    RefChunk C = chunk2[xt.next];
     R rec[kRefPerThread];
-    refine_load(T, rec1, rec);
+    refine_load(C.r0, (uint32_t)min<uint64_t>(C.n, kRefTile), rec1, rec);
     for (;;) {
         xt.advance();
         const bool more = xt.valid();
-        RefTile N{};
-        if (more) N = tile2[xt.next];
-        const uint32_t fan = T.fan, d1 = T.d1;
-        // scatter: this tile's segment bases (thread t: segments t * per ..
-        // t * per + per - 1), first used after the count
-        uint64_t gb[kRefMaxPer];
-        if (SCATTER) {
-            const uint32_t per = (fan + blockDim.x - 1) / blockDim.x;
-#pragma unroll
-            for (uint32_t q = 0; q < kRefMaxPer; ++q) {
-                const uint32_t j = tid * per + q;
-                gb[q] = (q < per && j < fan) ? scan2[T.hcol + (uint64_t)j * T.stride] : 0;
-            }
-        }
-        for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = SCATTER ? j << 12 : 0u;
-        __syncthreads();
-        uint32_t tag[kRefPerThread];  // scatter: segment << 12 | rank (segment fan: past the end)
-#pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread; ++it) {
-            const uint32_t c = refine_has<R>(T, it) ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
-            if (SCATTER)
-                tag[it] = lds_add32(&s_cnt[c], 1u);
-            else
-                __hip_atomic_fetch_add(&s_cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        __syncthreads();
+        RefChunk N{};
+        if (more) N = chunk2[xt.next];
+        const uint32_t fan = C.fan, d1 = C.d1;
         if (!SCATTER) {
-            for (uint32_t j = tid; j < fan; j += blockDim.x) hist2[T.hcol + (uint64_t)j * T.stride] = s_cnt[j];
-            if (more) refine_load(N, rec1, rec);
-            __syncthreads();
+            for (uint32_t j = tid; j < fan; j += blockDim.x) s_cnt[j] = 0u;
         } else {
-            bucket_starts_pre(s_cnt, s_gbase, fan, gb);
+            for (uint32_t j = tid; j < fan; j += blockDim.x) s_gbase[j] = scan2[C.hcol + (uint64_t)j * C.stride];
+        }
+        for (uint64_t t0 = 0; t0 < C.n; t0 += kRefTile) {
+            const uint32_t n = (uint32_t)min<uint64_t>(kRefTile, C.n - t0);
+            // the tile after this one: in this chunk, else the next chunk's first
+            const bool next_here = t0 + kRefTile < C.n;
+            const uint64_t nr0 = next_here ? C.r0 + t0 + kRefTile : N.r0;
+            const uint32_t nn = next_here ? (uint32_t)min<uint64_t>(kRefTile, C.n - t0 - kRefTile)
+                                          : (more ? (uint32_t)min<uint64_t>(kRefTile, N.n) : 0u);
+            if (SCATTER)
+                for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = j << 12;
+            __syncthreads();
+            uint32_t tag[kRefPerThread];  // scatter: segment << 12 | rank (segment fan: past the end)
+#pragma unroll
+            for (uint32_t it = 0; it < kRefPerThread; ++it) {
+                const uint32_t c =
+                    refine_has<R>(n, it) ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
+                if (SCATTER)
+                    tag[it] = lds_add32(&s_cnt[c], 1u);
+                else
+                    __hip_atomic_fetch_add(&s_cnt[c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (!SCATTER) {
+                if (nn) refine_load(nr0, nn, rec1, rec);
+                continue;  // the next tile's adds go to the same counters
+            }
+            __syncthreads();
+            bucket_starts(s_cnt, s_gbase, fan, [&](uint32_t j) { return s_gbase[j]; });
             __syncthreads();
 #pragma unroll
             for (uint32_t it = 0; it < kRefPerThread; ++it) {
@@ -692,38 +742,45 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
                 s_rec[pos] = rec[it];
                 if (RW == 1) s_child[pos] = (uint16_t)c;
             }
-            if (more) refine_load(N, rec1, rec);
+            if (nn) refine_load(nr0, nn, rec1, rec);
             __syncthreads();
-            for (uint32_t j = tid; j < T.n; j += blockDim.x) {
+            for (uint32_t j = tid; j < n; j += blockDim.x) {
                 const R r = s_rec[j];
                 const uint32_t c = RW == 1 ? s_child[j] : child_of(image_top(RecOf<RW>::head(r) >> 3), d1, fan);
                 rec2[s_gbase[c] + j] = r;
             }
             __syncthreads();
+            for (uint32_t j = tid; j < fan; j += blockDim.x) s_gbase[j] += j + 1 < fan ? s_cnt[j + 1] : n;
+            __syncthreads();  // before the next tile resets the counters
+        }
+        __syncthreads();
+        if (!SCATTER) {
+            for (uint32_t j = tid; j < fan; j += blockDim.x) hist2[C.hcol + (uint64_t)j * C.stride] = s_cnt[j];
+            __syncthreads();
         }
         if (!more) break;
-        T = N;
+        C = N;
     }
 }
 
-// Descriptor of every pass-2 tile: a block per level-1 bucket, a thread per tile.
-__global__ void k_tile_descs(const Instance *__restrict__ inst, const Bucket *__restrict__ buckets,
-                             const BinTotals *__restrict__ tot, RefTile *__restrict__ tile2,
-                             uint64_t tiles_cap) {
+// Descriptor of every pass-2 chunk: a block per level-1 bucket, a thread per chunk.
+__global__ void k_chunk_descs(const Instance *__restrict__ inst, const Bucket *__restrict__ buckets,
+                              const BinTotals *__restrict__ tot, RefChunk *__restrict__ chunk2,
+                              uint64_t chunks_cap) {
     const uint64_t G = tot->buckets;
+    const uint64_t span = tot->chunk2 * (uint64_t)kRefTile;  // records per chunk
     for (uint64_t g = blockIdx.x; g < G; g += gridDim.x) {
         const Bucket B = buckets[g];
         const uint32_t d1 = inst[B.inst].d1;
-        for (uint64_t tl = threadIdx.x; tl < B.tiles && B.tile_base + tl < tiles_cap; tl += blockDim.x) {
-            RefTile T;
-            T.r0 = B.start + tl * kRefTile;
-            T.hcol = B.hist_base + tl;
-            T.stride = B.tiles;
-            T.n = (uint32_t)min<uint64_t>(kRefTile, B.size - tl * kRefTile);
-            T.fan = B.fan;
-            T.d1 = d1;
-            T.pad = 0;
-            tile2[B.tile_base + tl] = T;
+        for (uint64_t c = threadIdx.x; c < B.chunks && B.chunk_base + c < chunks_cap; c += blockDim.x) {
+            RefChunk C;
+            C.r0 = B.start + c * span;
+            C.n = min<uint64_t>(span, B.size - c * span);
+            C.hcol = B.hist_base + c;
+            C.stride = B.chunks;
+            C.fan = B.fan;
+            C.d1 = d1;
+            chunk2[B.chunk_base + c] = C;
         }
     }
 }
@@ -742,7 +799,7 @@ __global__ void k_part_starts(const PassArgs *__restrict__ args, const Instance 
         const uint32_t p = (uint32_t)(gp - in.part_base);
         const uint32_t b = p / in.fan, c = p - b * in.fan;
         const Bucket &B = buckets[plan[i].bucket_base + b];
-        pstart[gp] = scan2[B.hist_base + (uint64_t)c * B.tiles];
+        pstart[gp] = scan2[B.hist_base + (uint64_t)c * B.chunks];
         if (gp + 1 == parts_total) pstart[parts_total] = scan2[tot->hist2_len];
     }
 }
@@ -766,19 +823,27 @@ constexpr uint64_t kNoRecord = ~0ull;     // no record: a record's first word st
 
 // Find-or-claim one record's vertex in the LDS segment and count its letter.
 // Returns false when the segment has no free slot for it.
+// home_mask: kSegSlots - 1, or 7 with the test hash (every key of a segment
+// then starts at one of its first eight slots).
+template <bool STATS>
 __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uint32_t *s_cnt,
-                                              uint64_t &claims) {
+                                              uint64_t &claims, uint32_t home_mask, ProbeStats &ps) {
     const uint64_t img = rec >> 3;
     const uint64_t tagv = img | kOccupied;
-    uint32_t s = seg_home(img);
+    uint32_t s = seg_home(img) & home_mask;
     uint64_t cur = lds_load64(&s_key[s]);
     // probe until the slot holds this key (found, or claimed here); the count
     // is added once, after the loop
-    for (uint32_t q = 0;;) {
+    uint32_t q = 0;
+    for (;;) {
         if (cur == 0) {
             uint64_t expected = 0;
             __hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (STATS) {
+                ++ps.cas;
+                ps.lost += expected != 0 ? 1u : 0u;
+            }
             if (expected == 0) {
                 ++claims;
                 break;
@@ -790,6 +855,7 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
         s = (s + 1) & (kSegSlots - 1);
         cur = lds_load64(&s_key[s]);
     }
+    if (STATS) ps.lookup(q + 1);
     if (!(rec & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec & 3)], 1u);
     return true;
 }
@@ -803,19 +869,25 @@ __device__ __forceinline__ bool reduce_record(uint64_t rec, uint64_t *s_key, uin
 constexpr uint64_t kReady = 1ull << 62;
 constexpr uint32_t kMaxInFlightReads = 1u << 20;
 
+template <bool STATS>
 __device__ __forceinline__ uint32_t wide_slot(uint64_t tag, uint64_t lo, uint64_t *s_hi, uint64_t *s_lo,
-                                              bool &claimed) {
-    uint32_t s = seg_home(lo), waits = 0;
+                                              bool &claimed, uint32_t home_mask, ProbeStats &ps) {
+    uint32_t s = seg_home(lo) & home_mask, waits = 0;
     for (uint32_t q = 0;;) {
         uint64_t cur = __hip_atomic_load(&s_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == 0) {
             uint64_t expected = 0;
             __hip_atomic_compare_exchange_strong(&s_hi[s], &expected, tag, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (STATS) {
+                ++ps.cas;
+                ps.lost += expected != 0 ? 1u : 0u;
+            }
             if (expected == 0) {
                 __hip_atomic_store(&s_lo[s], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __hip_atomic_store(&s_hi[s], tag | kReady, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 claimed = true;
+                if (STATS) ps.lookup(q + 1);
                 return s;
             }
             cur = expected;
@@ -825,16 +897,22 @@ __device__ __forceinline__ uint32_t wide_slot(uint64_t tag, uint64_t lo, uint64_
                 if (++waits > kMaxInFlightReads) return kSegSlots;
                 continue;
             }
-            if (lds_load64(&s_lo[s]) == lo) return s;
+            if (lds_load64(&s_lo[s]) == lo) {
+                if (STATS) ps.lookup(q + 1);
+                return s;
+            }
         }
         if (++q == kSegSlots) return kSegSlots;
         s = (s + 1) & (kSegSlots - 1);
     }
 }
 
-__device__ __forceinline__ bool reduce_record(ulonglong2 rec, uint64_t *s_key, uint32_t *s_cnt, uint64_t &claims) {
+template <bool STATS>
+__device__ __forceinline__ bool reduce_record(ulonglong2 rec, uint64_t *s_key, uint32_t *s_cnt, uint64_t &claims,
+                                              uint32_t home_mask, ProbeStats &ps) {
     bool claimed = false;
-    const uint32_t s = wide_slot((rec.x >> 3) | kOccupied, rec.y, s_key, s_key + kSegSlots, claimed);
+    const uint32_t s =
+        wide_slot<STATS>((rec.x >> 3) | kOccupied, rec.y, s_key, s_key + kSegSlots, claimed, home_mask, ps);
     if (s == kSegSlots) return false;
     claims += claimed ? 1u : 0u;
     if (!(rec.x & 4)) lds_add32(&s_cnt[4 * s + (uint32_t)(rec.x & 3)], 1u);
@@ -856,7 +934,7 @@ __device__ __forceinline__ bool reduce_record(ulonglong2 rec, uint64_t *s_key, u
 // segment's first records are loaded while this one is written back.
 constexpr uint32_t kStartsChunk = 256;  // segment starts staged per LDS refill
 
-template <uint32_t EW, uint32_t RW>
+template <uint32_t EW, uint32_t RW, bool STATS>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restrict__ args,
                                                         const Instance *__restrict__ inst,
                                                         const uint64_t *__restrict__ pstart,
@@ -880,6 +958,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
     __shared__ uint32_t s_wave_n[kWaves];
     __shared__ uint64_t s_sum, s_xbase;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t home_mask = args->test_hash ? 7u : kSegSlots - 1;
+    ProbeStats ps, ps_old;  // ps_old: re-inserted vertices of earlier builds, not counted
     const uint64_t per_block = (parts_total + gridDim.x - 1) / gridDim.x;
     const uint64_t gp0 = min((uint64_t)blockIdx.x * per_block, parts_total);
     const uint64_t gp1 = min(gp0 + per_block, parts_total);
@@ -940,11 +1020,12 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
             const uint4 cv = seg_counts<RW>(seg)[e];
             if constexpr (RW == 2) {
                 bool claimed = false;
-                const uint32_t s = wide_slot(tagv, seg[kSegSlots + e], s_key, s_key + kSegSlots, claimed);
+                const uint32_t s =
+                    wide_slot<false>(tagv, seg[kSegSlots + e], s_key, s_key + kSegSlots, claimed, home_mask, ps_old);
                 if (s < kSegSlots) reinterpret_cast<uint4 *>(s_cnt)[s] = cv;
                 continue;
             }
-            uint32_t s = seg_home(tagv);
+            uint32_t s = seg_home(tagv) & home_mask;
             for (uint32_t q = 0; q < kSegSlots; ++q) {
                 uint64_t expected = 0;
                 if (__hip_atomic_compare_exchange_strong(&s_key[s], &expected, tagv, __ATOMIC_RELAXED,
@@ -960,7 +1041,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         for (uint64_t base = a;;) {
 #pragma unroll
             for (uint32_t c = 0; c < kReducePrefetch; ++c)
-                if (RecOf<RW>::head(rv[c]) != kNoRecord && !reduce_record(rv[c], s_key, s_cnt, my_claims))
+                if (RecOf<RW>::head(rv[c]) != kNoRecord &&
+                    !reduce_record<STATS>(rv[c], s_key, s_cnt, my_claims, home_mask, ps))
                     full = true;
             base += (uint64_t)blockDim.x * kReducePrefetch;
             if (base >= z) break;
@@ -1053,6 +1135,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const PassArgs *__restr
         __syncthreads();
     }
     flush_block_sum(my_claims, &st[cur_inst].claimed, &s_sum);
+    if (STATS) ps.flush(args->stats);
 }
 
 // ---------------------------------------------------------------- extract
@@ -1110,7 +1193,7 @@ uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint
 // The binned pass for records of RW words (enqueue only).
 template <uint32_t RW>
 hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint64_t *packed, const uint64_t *ws,
-                         InstStatus *st, const BinBuffers &bb, hipStream_t s, hipEvent_t *marks) {
+                         InstStatus *st, const BinBuffers &bb, bool stats, hipStream_t s, hipEvent_t *marks) {
     hipError_t e;
     // pass 1
     const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW), lb1 = bin_lds_bytes(bb.d1_max, true, RW);
@@ -1133,16 +1216,16 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
-                       bb.buckets);
+                       bb.buckets, bb.target2);
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
-        hipLaunchKernelGGL(k_tile_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.tile2,
-                           bb.tiles2_cap);
+        hipLaunchKernelGGL(k_chunk_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.chunk2,
+                           bb.chunks2_cap);
     }
     if (marks) (void)hipEventRecord(marks[4], s);
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW), lr1 = ref_lds_bytes(bb.fan_max, true, RW);
     const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
-    hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.tile2, bb.rec1,
+    hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.chunk2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[5], s);
@@ -1153,7 +1236,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
     if (marks) (void)hipEventRecord(marks[6], s);
-    hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.tile2, bb.rec1,
+    hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.chunk2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[7], s);
@@ -1166,12 +1249,16 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     if (marks) (void)hipEventRecord(marks[8], s);
     // every instance of a binned launch has the same entry width
     const uint32_t gr = bb.grid_reduce;
-    if (RW == 2)
-        hipLaunchKernelGGL((k_reduce<4, 2>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
-    else if (bb.entry_words == 4)
-        hipLaunchKernelGGL((k_reduce<4, 1>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
-    else
-        hipLaunchKernelGGL((k_reduce<3, 1>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st);
+#define DBG_LAUNCH_REDUCE(EW, R2, STATS) \
+    hipLaunchKernelGGL((k_reduce<EW, R2, STATS>), dim3(gr), dim3(kReduceBlock), 0, s, args, inst, bb.pstart, bb.rec2, st)
+    if (RW == 2) {
+        if (stats) DBG_LAUNCH_REDUCE(4, 2, true); else DBG_LAUNCH_REDUCE(4, 2, false);
+    } else if (bb.entry_words == 4) {
+        if (stats) DBG_LAUNCH_REDUCE(4, 1, true); else DBG_LAUNCH_REDUCE(4, 1, false);
+    } else {
+        if (stats) DBG_LAUNCH_REDUCE(3, 1, true); else DBG_LAUNCH_REDUCE(3, 1, false);
+    }
+#undef DBG_LAUNCH_REDUCE
     return hipGetLastError();
 }
 
@@ -1180,10 +1267,10 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
 
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                          const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
-                         int device, hipStream_t s, hipEvent_t *marks) {
+                         int device, bool stats, hipStream_t s, hipEvent_t *marks) {
     (void)device;
     hipError_t e;
-    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals);
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
@@ -1192,34 +1279,36 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     }
     if (marks) (void)hipEventRecord(marks[0], s);
 
-    if (bb.rec_words == 2) return launch_passes<2>(args, inst, packed, ws, st, bb, s, marks);
-    return launch_passes<1>(args, inst, packed, ws, st, bb, s, marks);
+    if (bb.rec_words == 2) return launch_passes<2>(args, inst, packed, ws, st, bb, stats, s, marks);
+    return launch_passes<1>(args, inst, packed, ws, st, bb, stats, s, marks);
 }
 
 namespace {
-constexpr uint32_t kScatterWide = 384;  // segments per bucket beyond which pass 2 takes half the grid
+constexpr uint32_t kScatterWide = 384;  // segments per bucket beyond which pass 2 scatters on half the grid
 
 template <uint32_t RW>
 void grids_for(int device, BinBuffers &bb) {
     bb.grid_bin_count =
-        occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, false, RW));
-    // A scatter tile writes one run per segment, and the runs of the tiles in
-    // flight on an XCD meet in its L2 (they are adjacent in the output).  With
-    // many segments per bucket those partial lines overflow the L2 before
-    // they fill, so pass 2 writes faster on half the resident grid above
-    // kScatterWide digits.  (Pass 1, which also decodes windows, measured
-    // slower that way.)
-    const uint32_t ref_div = bb.fan_max > kScatterWide ? 2 : 1;
+        occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
     bb.grid_bin_scatter =
-        occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.tiles1_cap, bin_lds_bytes(bb.d1_max, true, RW));
+        occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, true, RW));
     bb.grid_ref_count =
-        occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, false, RW));
+        occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
+    // A scatter tile writes one short run per segment when a bucket has many
+    // segments; the partial lines of the workgroups in flight on an XCD then
+    // outgrow its L2 before the next tiles complete them, and the pass-2
+    // scatter writes faster on part of its resident grid.
+    const uint32_t div = bb.scatter_div ? bb.scatter_div : (bb.fan_max > kScatterWide ? 2u : 1u);
     bb.grid_ref_scatter = std::max<uint32_t>(
-        8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.tiles2_cap, ref_lds_bytes(bb.fan_max, true, RW)) /
-               ref_div);
-    bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2>, device, kReduceBlock, bb.parts_cap, 0)
-                   : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1>, device, kReduceBlock, bb.parts_cap, 0)
-                                         : occupancy_grid(k_reduce<3, 1>, device, kReduceBlock, bb.parts_cap, 0);
+        8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, true, RW)) /
+               div);
+    bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2, false>, device, kReduceBlock, bb.parts_cap, 0)
+                   : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1, false>, device, kReduceBlock, bb.parts_cap, 0)
+                                         : occupancy_grid(k_reduce<3, 1, false>, device, kReduceBlock, bb.parts_cap, 0);
+    // about kChunksPerGroup chunks per resident scatter workgroup
+    const uint32_t per = bb.chunks_per_group ? bb.chunks_per_group : kChunksPerGroup;
+    bb.target1 = (uint32_t)std::min<uint64_t>(kMaxChunkTarget, (uint64_t)per * bb.grid_bin_scatter);
+    bb.target2 = (uint32_t)std::min<uint64_t>(kMaxChunkTarget, (uint64_t)per * bb.grid_ref_scatter);
 }
 }  // namespace
 

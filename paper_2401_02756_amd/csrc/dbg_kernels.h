@@ -81,10 +81,11 @@ struct PassArgs {
     uint64_t *xkeys;        // binned build of one instance: when set, the reduce also writes
     uint32_t *xcounts;      // every vertex of the graph to these arrays (keys of one or two
     uint64_t xcap;          // words, four counters each; entries past xcap are dropped)
+    uint64_t *stats;        // probe statistics of this pass (kStat* words), accumulated; null: not kept
     uint32_t m;             // instances
     uint32_t check_ends;    // require off[n] - off[0] == reads_len
     uint32_t tile;          // direct build: windows per tile
-    uint32_t pad;
+    uint32_t test_hash;     // nonzero: every key's home slot is its low 3 bits (tests only)
 };
 constexpr uint32_t kArgsBytes = 128;
 static_assert(sizeof(PassArgs) <= kArgsBytes, "PassArgs grew");
@@ -96,6 +97,39 @@ struct InstStatus {
     uint64_t inserts;   // k-mers of this call
     uint64_t windows;   // windows of this call
     uint64_t emitted;   // vertices the reduce wrote to the PassArgs output arrays
+};
+
+// Probe statistics (kernels built with STATS): words of PassArgs::stats.
+enum : uint32_t {
+    kStatLookups = 0,   // vertex lookups that reached the table
+    kStatProbes = 1,    // slots they examined
+    kStatCas = 2,       // compare-and-swaps issued to claim a slot
+    kStatCasLost = 3,   // of those, the ones another thread won first
+    kStatHist = 4,      // 8 words: lookups by slots examined, 1, 2, 3-4, 5-8, 9-16, 17-32, 33-64, more
+    kStatWords = 12,
+};
+
+// One thread's probe statistics, flushed once per wavefront.
+struct ProbeStats {
+    uint32_t lookups = 0, cas = 0, lost = 0;
+    uint64_t probes = 0;
+    uint32_t hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ void lookup(uint32_t n_probes) {
+        ++lookups;
+        probes += n_probes;
+        const uint32_t bin = n_probes <= 1 ? 0u : min(7u, 32u - (uint32_t)__clz(n_probes - 1));
+        ++hist[bin];
+    }
+    // Wavefront sums, added to stats[] by lane 0 (whole wavefront).
+    __device__ void flush(uint64_t *stats) {
+        uint64_t v[kStatWords] = {lookups, probes, cas, lost};
+        for (int i = 0; i < 8; ++i) v[kStatHist + i] = hist[i];
+        for (int i = 0; i < (int)kStatWords; ++i) {
+            for (int d = 32; d >= 1; d >>= 1) v[i] += __shfl_xor(v[i], d, 64);
+            if ((threadIdx.x & 63) == 0 && v[i])
+                __hip_atomic_fetch_add(stats + i, v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 };
 
 struct CallState {
@@ -116,6 +150,13 @@ struct BuildShape {
 // are partitioned by segment in two levels (d1 buckets, each split into at
 // most `fan` segments), and one workgroup then owns each segment: it stages
 // the segment in LDS, claims and counts there, and writes it back.
+//
+// Each partition pass works on chunks of consecutive tiles (a tile is what a
+// workgroup sorts in LDS at once).  A chunk has one histogram, so a chunk's
+// records of one bucket (or segment) form one contiguous output run that its
+// workgroup extends tile after tile: runs stay long when there are many
+// buckets, and the histograms stay small.  The chunk length is chosen on the
+// device so that a pass has about `target` chunks.
 constexpr uint32_t kSegSlots = 2048;
 constexpr uint32_t kMaxD1 = 1024;     // level-1 buckets per instance, at most
 constexpr uint32_t kMaxFan = 2048;    // segments per level-1 bucket, at most
@@ -126,38 +167,41 @@ constexpr uint32_t kRefBlock = 512;
 constexpr uint32_t kRefPerThread = 8;
 constexpr uint32_t kRefTile = kRefBlock * kRefPerThread;  // records per pass-2 tile
 constexpr uint32_t kReduceBlock = 512;
+constexpr uint32_t kMaxChunkTarget = 16384;  // chunks a pass aims for, at most
+constexpr uint32_t kChunksPerGroup = 16;     // default target: chunks per resident workgroup
 
 struct BinPlan {        // per instance
     uint64_t w_begin, w_end;  // its windows
     uint64_t tiles;           // pass-1 tiles
     uint64_t tile_base;       // first pass-1 tile
-    uint64_t hist_base;       // first pass-1 histogram entry
+    uint64_t chunks;          // pass-1 chunks (of BinTotals::chunk1 tiles; the last may have fewer)
+    uint64_t chunk_base;      // first pass-1 chunk
+    uint64_t hist_base;       // first pass-1 histogram entry (d1 x chunks, bucket-major)
     uint64_t bucket_base;     // first level-1 bucket
 };
 
 struct Bucket {         // per level-1 bucket
     uint64_t start, size;     // record range in the level-1 output
-    uint64_t tiles;           // pass-2 tiles
-    uint64_t tile_base;       // first pass-2 tile
-    uint64_t hist_base;       // first pass-2 histogram entry
+    uint64_t chunks;          // pass-2 chunks (of BinTotals::chunk2 tiles; the last may have fewer)
+    uint64_t chunk_base;      // first pass-2 chunk
+    uint64_t hist_base;       // first pass-2 histogram entry (fan x chunks, segment-major)
     uint32_t inst;            // owning instance
     uint32_t b;               // bucket index within the instance
     uint32_t fan;             // segments in this bucket
     uint32_t pad;
 };
 
-struct RefTile {        // per pass-2 tile: everything its kernels need, in one load
+struct RefChunk {       // per pass-2 chunk: everything its kernels need, in one load
     uint64_t r0;              // first record (level-1 output)
-    uint64_t hcol;            // histogram entry of the bucket's first segment for this tile
-    uint64_t stride;          // histogram entries from one segment to the next (the bucket's tiles)
-    uint32_t n;               // records
+    uint64_t n;               // records
+    uint64_t hcol;            // histogram entry of the bucket's first segment for this chunk
+    uint64_t stride;          // histogram entries from one segment to the next (the bucket's chunks)
     uint32_t fan;             // segments in the bucket
     uint32_t d1;              // level-1 buckets of the instance (first digit's radix)
-    uint32_t pad;
 };
 
 struct BinTotals {
-    uint64_t tiles1, hist1_len, buckets, tiles2, hist2_len, records;
+    uint64_t tiles1, chunk1, chunks1, hist1_len, buckets, chunk2, chunks2, hist2_len, records;
 };
 
 struct BinBuffers {     // device scratch of one binned pass
@@ -172,15 +216,20 @@ struct BinBuffers {     // device scratch of one binned pass
     uint64_t *rec1, *rec2;    // records (rec_words words each), windows_cap each
     uint64_t *pstart;         // parts_total + 1
     uint64_t *tile_read1;     // first read of each pass-1 tile (tiles1_cap)
-    RefTile *tile2;           // pass-2 tiles (tiles2_cap)
+    RefChunk *chunk2;         // pass-2 chunks (chunks2_cap)
     uint64_t hist1_cap, hist2_cap, partials_cap;
-    uint64_t tiles1_cap, tiles2_cap, buckets_cap, parts_cap;
+    uint64_t tiles1_cap, chunks1_cap, tiles2_cap, chunks2_cap, buckets_cap, parts_cap;
     uint32_t d1_max, fan_max;  // largest d1 and fan over the launch (LDS sizing)
     uint32_t entry_words;      // of every instance in the launch
     uint32_t rec_words;        // record words: 1, or 2 for long keys (33 <= k <= 63)
     // persistent grids (binned_grids fills them; no query happens while a
     // launch is being captured)
     uint32_t grid_bin_count, grid_bin_scatter, grid_ref_count, grid_ref_scatter, grid_reduce;
+    uint32_t target1, target2;  // chunks each partition pass aims for (<= kMaxChunkTarget)
+    // launch shape (set before binned_grids): chunks per resident scatter
+    // workgroup (0: kChunksPerGroup), and the divisor of the pass-2 scatter's
+    // resident grid (0: automatic, 2 when a bucket has more than 384 segments)
+    uint32_t chunks_per_group, scatter_div;
 };
 
 // Fill the grid sizes of bb from occupancy and its capacities.
@@ -208,13 +257,14 @@ hipError_t launch_pack(const PassArgs *args, uint64_t *packed, const Instance *i
 hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *st, uint64_t *ws,
                        uint64_t *partials, uint64_t *tile_read, CallState *cs, uint64_t n_cap,
                        hipStream_t s);
+// stats: launch the kernels that keep probe statistics (PassArgs::stats set).
 hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                         const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
-                        BuildShape shape, bool single, hipStream_t s);
+                        BuildShape shape, bool single, bool stats, hipStream_t s);
 // Plain build for 32 < k <= 64 (one instance, direct table of 32-byte entries).
 hipError_t launch_build_wide(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                              const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
-                             BuildShape shape, hipStream_t s);
+                             BuildShape shape, bool stats, hipStream_t s);
 // Records of a long-k table: two key words per record, (K >> 64, K mod 2^64).
 hipError_t launch_extract_wide(const uint64_t *table, uint64_t cap, uint64_t *out_keys, uint32_t *out_counts,
                                uint64_t out_cap, uint64_t *out_n, hipStream_t s);
@@ -240,7 +290,7 @@ hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32
 constexpr uint32_t kBinMarks = 9;
 hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                          const uint64_t *ws, InstStatus *st, const BinBuffers &bb, uint64_t n_cap,
-                         int device, hipStream_t s, hipEvent_t *marks);
+                         int device, bool stats, hipStream_t s, hipEvent_t *marks);
 
 // Extraction of a binned table: seg_count (parts entries) is scanned into
 // seg_off (parts + 1 entries, using `partials` of ceil(parts / 1024) + 1

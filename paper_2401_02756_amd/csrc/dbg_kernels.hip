@@ -294,24 +294,40 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(
 // than kMaxProbe, so this only fires on a table that is full in practice.
 constexpr uint64_t kMaxProbe = 1ull << 16;
 
+// Home slot of a key in the direct table: the mixed key's range reduction,
+// or, with the test hash, the key's low 3 bits (cap >= 64), which sends
+// every key of the table down the same probe chain.
+__device__ __forceinline__ uint64_t direct_home(uint64_t key_bits, uint64_t h, uint64_t cap, uint32_t test_hash) {
+    return test_hash ? (key_bits & 7u) : home_slot(h, cap);
+}
+
+template <bool STATS>
 __device__ __forceinline__ uint64_t find_or_claim(uint64_t *table, uint32_t ew, uint64_t cap,
                                                   uint64_t key, uint64_t h, bool &claimed,
-                                                  uint32_t *err) {
+                                                  uint32_t *err, uint32_t test_hash, ProbeStats &ps) {
     const uint64_t tag = key | kOccupied;
     const uint64_t limit = cap < kMaxProbe ? cap : kMaxProbe;
-    uint64_t s = home_slot(h, cap);
+    uint64_t s = direct_home(key, h, cap, test_hash);
     for (uint64_t probe = 0; probe < limit; ++probe) {
         uint64_t *kp = table + s * ew;
         const uint64_t cur = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == tag) return s;
+        if (cur == tag) {
+            if (STATS) ps.lookup((uint32_t)min<uint64_t>(probe + 1, 0xffffffffu));
+            return s;
+        }
         if (cur == 0) {
             uint64_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(kp, &expected, tag, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                claimed = true;
+            const bool won = __hip_atomic_compare_exchange_strong(kp, &expected, tag, __ATOMIC_RELAXED,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (STATS) {
+                ++ps.cas;
+                ps.lost += won ? 0u : 1u;
+            }
+            if (won || expected == tag) {
+                claimed = won;
+                if (STATS) ps.lookup((uint32_t)min<uint64_t>(probe + 1, 0xffffffffu));
                 return s;
             }
-            if (expected == tag) return s;
         }
         s = (s + 1 == cap) ? 0 : s + 1;
         if ((probe & 255) == 255 &&
@@ -353,7 +369,7 @@ __device__ __forceinline__ uint32_t instance_state(const Instance *inst, uint32_
     return (e & (kErrBase | kErrInval | kErrRange | kErrFull | kErrSkip)) ? (t | 0x80000000u) : t;
 }
 
-template <bool SINGLE, bool MERGE>
+template <bool SINGLE, bool MERGE, bool STATS>
 __global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ args,
                                                const Instance *__restrict__ inst,
                                                const uint64_t *__restrict__ packed,
@@ -399,6 +415,8 @@ __global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ arg
 
     uint64_t my_claims = 0;  // SINGLE: flushed once at the end
     if (tid == 0) s_claims = 0;
+    const uint32_t test_hash = args->test_hash;
+    ProbeStats ps;
 
     for (;;) {
         if (tid == 0) {
@@ -524,7 +542,8 @@ __global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ arg
 
             if (leader) {
                 bool claimed = false;
-                const uint64_t s = find_or_claim(tab, ew, cap, win.key, h, claimed, &st[win.inst].err);
+                const uint64_t s =
+                    find_or_claim<STATS>(tab, ew, cap, win.key, h, claimed, &st[win.inst].err, test_hash, ps);
                 if (s == kAllOnes) {
                     atomic_or_u32(&st[win.inst].err, kErrFull);
                 } else {
@@ -564,6 +583,7 @@ __global__ __launch_bounds__(1024) void k_build(const PassArgs *__restrict__ arg
         }
         __syncthreads();
     }
+    if (STATS) ps.flush(args->stats);
     if (SINGLE) {
         for (int d = 32; d >= 1; d >>= 1) my_claims += __shfl_xor(my_claims, d, 64);
         if (lane == 0 && my_claims)
@@ -589,11 +609,12 @@ constexpr uint64_t kWritten = 1ull << 63;
 constexpr uint64_t kLow63 = kWritten - 1;
 constexpr uint32_t kMaxInFlight = 1u << 20;  // re-reads of one claim in flight
 
+template <bool STATS>
 __device__ __forceinline__ uint64_t find_or_claim_wide(uint64_t *table, uint64_t cap, uint64_t tag0,
                                                        uint64_t tag1, uint64_t h, bool &claimed,
-                                                       uint32_t *err) {
+                                                       uint32_t *err, uint32_t test_hash, ProbeStats &ps) {
     const uint64_t limit = cap < kMaxProbe ? cap : kMaxProbe;
-    uint64_t s = home_slot(h, cap);
+    uint64_t s = direct_home(tag1, h, cap, test_hash);
     uint64_t probes = 0;
     uint32_t waits = 0;
     for (;;) {
@@ -601,17 +622,26 @@ __device__ __forceinline__ uint64_t find_or_claim_wide(uint64_t *table, uint64_t
         uint64_t cur = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == 0) {
             uint64_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(e, &expected, tag0, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            const bool won = __hip_atomic_compare_exchange_strong(e, &expected, tag0, __ATOMIC_RELAXED,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (STATS) {
+                ++ps.cas;
+                ps.lost += won ? 0u : 1u;
+            }
+            if (won) {
                 __hip_atomic_store(e + 1, tag1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 claimed = true;
+                if (STATS) ps.lookup((uint32_t)min<uint64_t>(probes + 1, 0xffffffffu));
                 return s;
             }
             cur = expected;
         }
         if (cur == tag0) {
             const uint64_t w1 = __hip_atomic_load(e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (w1 == tag1) return s;
+            if (w1 == tag1) {
+                if (STATS) ps.lookup((uint32_t)min<uint64_t>(probes + 1, 0xffffffffu));
+                return s;
+            }
             if (w1 == 0) {  // a claim in flight: read this slot again
                 if (++waits > kMaxInFlight) return kAllOnes;
                 __builtin_amdgcn_s_sleep(1);
@@ -628,6 +658,7 @@ __device__ __forceinline__ uint64_t find_or_claim_wide(uint64_t *table, uint64_t
 
 // Plain (one-graph) build for 32 < k <= 64; same tiles and window map as
 // k_build, one window per thread per step, no merging.
+template <bool STATS>
 __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict__ args,
                                                     const Instance *__restrict__ inst,
                                                     const uint64_t *__restrict__ packed,
@@ -659,6 +690,8 @@ __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict_
 
     uint64_t my_claims = 0;
     if (tid == 0) s_claims = 0;
+    const uint32_t test_hash = args->test_hash;
+    ProbeStats ps;
     for (;;) {
         if (tid == 0) {
             s_tile = __hip_atomic_fetch_add(&cs->cursor, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -710,7 +743,7 @@ __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict_
             const uint64_t tag0 = a | kOccupied, tag1 = (klo & kLow63) | kWritten;
             const uint64_t h = mix64(tag1 ^ mix64(a));
             bool claimed = false;
-            const uint64_t s = find_or_claim_wide(tab, cap, tag0, tag1, h, claimed, &st[0].err);
+            const uint64_t s = find_or_claim_wide<STATS>(tab, cap, tag0, tag1, h, claimed, &st[0].err, test_hash, ps);
             if (s == kAllOnes) {
                 atomic_or_u32(&st[0].err, kErrFull);
                 continue;
@@ -722,6 +755,7 @@ __global__ __launch_bounds__(1024) void k_build_wide(const PassArgs *__restrict_
         }
         __syncthreads();
     }
+    if (STATS) ps.flush(args->stats);
     for (int d = 32; d >= 1; d >>= 1) my_claims += __shfl_xor(my_claims, d, 64);
     if (lane == 0 && my_claims)
         __hip_atomic_fetch_add(&s_claims, my_claims, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -926,31 +960,37 @@ hipError_t launch_scan(const PassArgs *args, const Instance *inst, InstStatus *s
 
 hipError_t launch_build(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                         const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
-                        BuildShape shape, bool single, hipStream_t s) {
+                        BuildShape shape, bool single, bool stats, hipStream_t s) {
     const dim3 g(shape.grid), b(shape.block);
-    if (single) {
-        if (shape.merge)
-            hipLaunchKernelGGL((k_build<true, true>), g, b, 0, s, args, inst, packed, ws, tile_read, st, cs,
-                               shape.wpt);
-        else
-            hipLaunchKernelGGL((k_build<true, false>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
-                               cs, shape.wpt);
+#define DBG_LAUNCH_BUILD(SINGLE, MERGE, STATS)                                                                    \
+    hipLaunchKernelGGL((k_build<SINGLE, MERGE, STATS>), g, b, 0, s, args, inst, packed, ws, tile_read, st, cs, \
+                       shape.wpt)
+    if (stats) {
+        if (single) {
+            if (shape.merge) DBG_LAUNCH_BUILD(true, true, true); else DBG_LAUNCH_BUILD(true, false, true);
+        } else {
+            if (shape.merge) DBG_LAUNCH_BUILD(false, true, true); else DBG_LAUNCH_BUILD(false, false, true);
+        }
     } else {
-        if (shape.merge)
-            hipLaunchKernelGGL((k_build<false, true>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
-                               cs, shape.wpt);
-        else
-            hipLaunchKernelGGL((k_build<false, false>), g, b, 0, s, args, inst, packed, ws, tile_read, st,
-                               cs, shape.wpt);
+        if (single) {
+            if (shape.merge) DBG_LAUNCH_BUILD(true, true, false); else DBG_LAUNCH_BUILD(true, false, false);
+        } else {
+            if (shape.merge) DBG_LAUNCH_BUILD(false, true, false); else DBG_LAUNCH_BUILD(false, false, false);
+        }
     }
+#undef DBG_LAUNCH_BUILD
     return hipGetLastError();
 }
 
 hipError_t launch_build_wide(const PassArgs *args, const Instance *inst, const uint64_t *packed,
                              const uint64_t *ws, const uint64_t *tile_read, InstStatus *st, CallState *cs,
-                             BuildShape shape, hipStream_t s) {
-    hipLaunchKernelGGL(k_build_wide, dim3(shape.grid), dim3(shape.block), 0, s, args, inst, packed, ws, tile_read,
-                       st, cs, shape.wpt);
+                             BuildShape shape, bool stats, hipStream_t s) {
+    if (stats)
+        hipLaunchKernelGGL(k_build_wide<true>, dim3(shape.grid), dim3(shape.block), 0, s, args, inst, packed, ws,
+                           tile_read, st, cs, shape.wpt);
+    else
+        hipLaunchKernelGGL(k_build_wide<false>, dim3(shape.grid), dim3(shape.block), 0, s, args, inst, packed, ws,
+                           tile_read, st, cs, shape.wpt);
     return hipGetLastError();
 }
 
@@ -1043,12 +1083,14 @@ hipError_t launch_roofline(uint64_t *mem, uint64_t words, uint64_t n_ops, uint32
     return hipGetLastError();
 }
 
-uint32_t build_grid_wide(int device, uint32_t block) { return grid_for(k_build_wide, device, block); }
+uint32_t build_grid_wide(int device, uint32_t block) { return grid_for(k_build_wide<false>, device, block); }
 
 uint32_t build_grid(int device, uint32_t block) {
-    // all four instantiations share the same resource shape up to LDS; the
-    // merging one uses the most LDS and registers, so size from it
-    return grid_for(k_build<false, true>, device, block);
+    // the instantiations share the same resource shape up to LDS; the
+    // merging one uses the most LDS and registers, so size from it (the
+    // statistics kernels may fit fewer workgroups: tiles come from a cursor,
+    // so extra workgroups simply start later)
+    return grid_for(k_build<false, true, false>, device, block);
 }
 
 }  // namespace dbgk

@@ -140,6 +140,8 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
 // pass is sized from these capacities (pass_key, bin_caps, PassSizes).
 struct PassKey {
     int binned = 0;
+    int stats = 0;  // kernels that keep probe statistics
+    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (dbg_config)
     int single = 0;
     int wide = 0;  // one instance with 32 < k <= 64, direct build
     uint32_t rw = 1;  // binned record words (2: long keys)
@@ -148,7 +150,8 @@ struct PassKey {
     uint64_t n_cap = 0, len_cap = 0, parts_cap = 0, buckets_cap = 0;
     dbgk::BuildShape shape{};
     bool operator==(const PassKey &o) const {
-        return binned == o.binned && single == o.single && wide == o.wide && rw == o.rw && ew == o.ew &&
+        return binned == o.binned && stats == o.stats && bin_chunks == o.bin_chunks && bin_div == o.bin_div &&
+               single == o.single && wide == o.wide && rw == o.rw && ew == o.ew &&
                m_cap == o.m_cap &&
                d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
                parts_cap == o.parts_cap && buckets_cap == o.buckets_cap && shape.block == o.shape.block &&
@@ -189,10 +192,15 @@ inline PassKey pass_key(uint32_t mm, uint64_t n, uint64_t len, dbgk::BuildShape 
 
 // Capacities (not pointers) of the binned scratch of a key.
 inline void bin_caps(const PassKey &k, dbgk::BinBuffers &bb) {
+    // A pass with T tiles takes chunks of max(1, floor(T / target)) tiles
+    // (target <= kMaxChunkTarget), so it has at most min(T, 2 target + one
+    // partial chunk per instance or bucket) chunks.
     bb.tiles1_cap = k.len_cap / dbgk::kBinTile + k.m_cap + 1;
-    bb.hist1_cap = (uint64_t)k.d1_cap * bb.tiles1_cap;
+    bb.chunks1_cap = std::min<uint64_t>(bb.tiles1_cap, 2ull * dbgk::kMaxChunkTarget + k.m_cap) + 1;
+    bb.hist1_cap = (uint64_t)k.d1_cap * bb.chunks1_cap;
     bb.tiles2_cap = k.len_cap / dbgk::kRefTile + k.buckets_cap + 1;
-    bb.hist2_cap = (uint64_t)k.fan_cap * bb.tiles2_cap;
+    bb.chunks2_cap = std::min<uint64_t>(bb.tiles2_cap, 2ull * dbgk::kMaxChunkTarget + k.buckets_cap) + 1;
+    bb.hist2_cap = (uint64_t)k.fan_cap * bb.chunks2_cap;
     const uint64_t chunk = 1024;
     bb.partials_cap = std::max((bb.hist1_cap + chunk - 1) / chunk, (bb.hist2_cap + chunk - 1) / chunk) + 1;
     bb.buckets_cap = k.buckets_cap;
@@ -232,14 +240,24 @@ struct PassSizes {
         rec2 = rec1;
         pstart = b ? 8 * (k.parts_cap + 1) : 0;
         tread1 = b ? 8 * bb.tiles1_cap : 0;
-        tile2 = b ? sizeof(dbgk::RefTile) * bb.tiles2_cap : 0;
+        tile2 = b ? sizeof(dbgk::RefChunk) * bb.chunks2_cap : 0;
     }
 };
+
+// Options of a pass besides its input: where its probe statistics go
+// (DBG_F_STATS; null: none kept) and whether keys take the test hash.
+struct PassOpts {
+    uint64_t *stats = nullptr;
+    uint32_t test_hash = 0;
+    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (0: defaults)
+};
+
+inline PassOpts opts_of(const dbg_graph *g);
 
 // The argument block of a pass (PassArgs) for key k.
 inline void fill_args(dbgk::PassArgs &a, const PassKey &k, const PassSizes &z, uint32_t mm, const Instance *hi,
                       const uint8_t *d_reads, uint64_t len, const uint64_t *d_off, uint64_t n, bool check_ends,
-                      uint64_t *xkeys, uint32_t *xcounts, uint64_t xcap) {
+                      uint64_t *xkeys, uint32_t *xcounts, uint64_t xcap, const PassOpts &o) {
     const uint64_t T = (uint64_t)k.shape.block * k.shape.wpt;
     uint64_t P = 0;
     for (uint32_t i = 0; i < mm; ++i) P += hi[i].parts;
@@ -254,6 +272,8 @@ inline void fill_args(dbgk::PassArgs &a, const PassKey &k, const PassSizes &z, u
     a.m = mm;
     a.check_ends = check_ends ? 1 : 0;
     a.tile = (uint32_t)T;
+    a.stats = o.stats;
+    a.test_hash = o.test_hash;
     if (k.binned && mm == 1 && xkeys) {
         a.xkeys = xkeys;
         a.xcounts = xcounts;
@@ -370,7 +390,7 @@ struct Pass {
         bb.rec2 = rec2.as<uint64_t>();
         bb.pstart = pstart.as<uint64_t>();
         bb.tile_read1 = tread1.as<uint64_t>();
-        bb.tile2 = tbucket2.as<dbgk::RefTile>();
+        bb.chunk2 = tbucket2.as<dbgk::RefChunk>();
         return hipSuccess;
     }
     // Grid sizes per binned key (queried once, outside any capture).
@@ -383,8 +403,12 @@ struct Pass {
                 bb.grid_ref_count = g.second.grid_ref_count;
                 bb.grid_ref_scatter = g.second.grid_ref_scatter;
                 bb.grid_reduce = g.second.grid_reduce;
+                bb.target1 = g.second.target1;
+                bb.target2 = g.second.target2;
                 return;
             }
+        bb.chunks_per_group = k.bin_chunks;
+        bb.scatter_div = k.bin_div;
         dbgk::binned_grids(device, bb);
         if (grid_memo.size() > 16) grid_memo.clear();
         grid_memo.emplace_back(k, bb);
@@ -414,13 +438,14 @@ struct Pass {
         hipError_t e;
         if (k.wide)
             e = dbgk::launch_build_wide(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
-                                        cs, k.shape, s);
+                                        cs, k.shape, k.stats != 0, s);
         else if (k.binned)
-            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device, s,
+            e = dbgk::launch_binned(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), dst, bb, k.n_cap, device,
+                                    k.stats != 0, s,
                                     mark ? marks : nullptr);
         else
             e = dbgk::launch_build(da, di, packed.as<uint64_t>(), ws.as<uint64_t>(), tiles.as<uint64_t>(), dst,
-                                   cs, k.shape, k.single != 0, s);
+                                   cs, k.shape, k.single != 0, k.stats != 0, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hstatus.p, dstatus.p, sizeof(InstStatus) * k.m_cap + sizeof(CallState),
                                hipMemcpyDeviceToHost, s);
@@ -454,10 +479,13 @@ struct Pass {
     // pass (PassArgs); null otherwise.
     hipError_t enqueue(uint32_t mm, const uint8_t *d_reads, uint64_t len, const uint64_t *d_off,
                        uint64_t n, dbgk::BuildShape shape, bool binned, int device, bool check_ends,
-                       bool time_it, hipStream_t s, uint64_t *xkeys = nullptr, uint32_t *xcounts = nullptr,
-                       uint64_t xcap = 0) {
+                       bool time_it, hipStream_t s, const PassOpts &o, uint64_t *xkeys = nullptr,
+                       uint32_t *xcounts = nullptr, uint64_t xcap = 0) {
         const Instance *hi = host_instances();
-        const PassKey k = pass_key(mm, n, len, shape, binned, hi);
+        PassKey k = pass_key(mm, n, len, shape, binned, hi);
+        k.stats = o.stats != nullptr;
+        k.bin_chunks = o.bin_chunks;
+        k.bin_div = o.bin_div;
         dbgk::BinBuffers bb{};
         if (binned) bin_caps(k, bb);
         const PassSizes z(k, bb);
@@ -468,7 +496,7 @@ struct Pass {
             (binned && (e = reserve_binned(k, bb)) != hipSuccess))
             return e;
         if (binned) binned_grids(k, device, bb);
-        fill_args(*host_args(), k, z, mm, hi, d_reads, len, d_off, n, check_ends, xkeys, xcounts, xcap);
+        fill_args(*host_args(), k, z, mm, hi, d_reads, len, d_off, n, check_ends, xkeys, xcounts, xcap, o);
 
         Cached *c = nullptr;
         if (use_graphs) {
@@ -551,6 +579,7 @@ struct dbg_graph {
     uint64_t expected = 0, cap_req = 0;
     dbgk::BuildShape shape{256, 4, 0, 0};
     uint32_t grid_wide = 0;  // persistent grid of the long-k build
+    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (dbg_config)
 
     uint64_t cap = 0;
     uint32_t ew = 3;
@@ -573,6 +602,7 @@ struct dbg_graph {
     uint32_t pending_k = 0;
     dbgrt::DevBuf reads, offsets;   // staging of host input
     dbgrt::DevBuf xkeys, xcnt, xn;  // extraction staging
+    dbgrt::DevBuf pstats;           // probe statistics (DBG_F_STATS): dbgk::kStatWords words
     dbgrt::DevBuf nkeys, ncnt, n8;  // normalized extraction staging
 
     uint64_t vertices = 0, inserts = 0, windows = 0, builds = 0;
@@ -585,6 +615,15 @@ struct dbg_graph {
 };
 
 namespace dbgrt {
+
+inline PassOpts opts_of(const dbg_graph *g) {
+    PassOpts o;
+    o.stats = (g->flags & DBG_F_STATS) ? g->pstats.as<uint64_t>() : nullptr;
+    o.test_hash = (g->flags & DBG_F_TEST_HASH) ? 1u : 0u;
+    o.bin_chunks = g->bin_chunks;
+    o.bin_div = g->bin_div;
+    return o;
+}
 
 // Segment geometry of a binned table of at least `cap` slots: d1 level-1
 // buckets of `fan` segments each (about the square root, so both partition
@@ -607,6 +646,15 @@ inline bool binned_geometry(uint64_t cap, uint32_t *d1, uint32_t *fan, uint64_t 
 // ordered after it by order_after_zero.
 inline hipError_t zero_table(dbg_graph *g) {
     hipError_t e = dbgk::launch_fill_zero(g->table.as<uint64_t>(), g->table_words(), g->stream);
+    if (e == hipSuccess && g->zero_ev) e = hipEventRecord(g->zero_ev, g->stream);
+    if (e == hipSuccess) g->zero_wait = g->zero_ev != nullptr;
+    return e;
+}
+
+// Zero the probe statistics (DBG_F_STATS) on the graph's stream, ordered
+// before later builds on other streams like a table fill.
+inline hipError_t zero_stats(dbg_graph *g) {
+    hipError_t e = dbgk::launch_fill_zero(g->pstats.as<uint64_t>(), dbgk::kStatWords, g->stream);
     if (e == hipSuccess && g->zero_ev) e = hipEventRecord(g->zero_ev, g->stream);
     if (e == hipSuccess) g->zero_wait = g->zero_ev != nullptr;
     return e;
@@ -758,7 +806,7 @@ inline int enqueue_single(dbg_graph *g, const uint8_t *d_reads, uint64_t len, co
         shape.merge = 0;
     }
     e = g->pass.enqueue(1, d_reads, len, d_off, n, shape, g->binned, g->device, true,
-                        (g->flags & DBG_F_TIMING) != 0, s, xkeys, xcounts, xcap);
+                        (g->flags & DBG_F_TIMING) != 0, s, opts_of(g), xkeys, xcounts, xcap);
     if (e != hipSuccess) return hip_code(e);
     g->pending_k = k;
     return DBG_OK;
@@ -831,7 +879,8 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
         if (rc == DBG_OK && read_begin[i + 1] > read_begin[i]) {
             rc = ensure_table(g, std::max<uint64_t>(bounds[i], 1));
             if (rc == DBG_OK) rc = settle_mode(g, ks[i]);
-            const int gm = g->binned ? (int)g->ew : 0;  // binned launches share one entry width
+            // binned launches share one entry width, and a launch one home-slot function
+            const int gm = (g->binned ? (int)g->ew : 0) | ((g->flags & DBG_F_TEST_HASH) ? 16 : 0);
             if (rc == DBG_OK && mode < 0) mode = gm;
             if (rc == DBG_OK && gm != mode) rc = DBG_E_INVAL;  // one mode per launch
             if (rc == DBG_OK) {
@@ -855,7 +904,7 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
     for (uint32_t i = 0; i < m; ++i) {
         fill_instance(hi[i], graphs[i], read_begin[i], read_begin[i + 1], br.run[i] ? ks[i] : 31u);
         hi[i].skip = br.run[i] ? 0u : 1u;
-        if (mode == 0 || !br.run[i]) {
+        if ((mode & 15) == 0 || !br.run[i]) {
             // segments only for the graphs a binned launch builds
             hi[i].parts = hi[i].d1 = hi[i].fan = 0;
             hi[i].fresh = 0;
@@ -874,8 +923,11 @@ inline void batch_enqueue(dbg_graph *const *graphs, uint32_t m, const uint64_t *
     br.timing = (g0->flags & DBG_F_TIMING) != 0;
     pass.use_graphs = (g0->flags & DBG_F_GRAPH) != 0;
     const uint64_t n = read_begin[m];
-    br.error = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, mode != 0, device, check_ends,
-                            br.timing, stream);
+    PassOpts o = opts_of(g0);  // the first graph's launch shape; batched passes keep no probe statistics
+    o.stats = nullptr;
+    o.test_hash = (mode & 16) ? 1u : 0u;
+    br.error = pass.enqueue(m, d_reads, reads_len, d_offsets, n, g0->shape, (mode & 15) != 0, device, check_ends,
+                            br.timing, stream, o);
     br.launched = br.error == hipSuccess;
 }
 

@@ -537,6 +537,7 @@ int dbg_server_create(const dbg_server_config *cfg_in, dbg_server **out) {
     if (c.load_factor == 0) c.load_factor = 0.5;
     if (!c.slots) c.slots = 2;
     if (!(c.load_factor > 0 && c.load_factor < 1) || c.slots > 8 || c.max_batch > 4096) return DBG_E_INVAL;
+    if ((c.flags & DBG_F_BINNED) && c.load_factor > DBG_BINNED_MAX_LOAD) return DBG_E_INVAL;
     int device = c.device;
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
     DeviceGuard guard(device);

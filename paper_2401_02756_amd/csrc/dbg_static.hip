@@ -141,11 +141,15 @@ extern "C" int dbg_build_device_static(dbg_graph *g, const uint8_t *d_reads, uin
         bb.rec2 = reinterpret_cast<uint64_t *>(base + o_rec2);
         bb.pstart = reinterpret_cast<uint64_t *>(base + o_pstart);
         bb.tile_read1 = reinterpret_cast<uint64_t *>(base + o_tread1);
-        bb.tile2 = reinterpret_cast<dbgk::RefTile *>(base + o_tile2);
+        bb.chunk2 = reinterpret_cast<dbgk::RefChunk *>(base + o_tile2);
+        bb.chunks_per_group = g->bin_chunks;
+        bb.scatter_div = g->bin_div;
         dbgk::binned_grids(g->device, bb);
     }
     dbgk::PassArgs a;
-    fill_args(a, key, z, 1, hi, d_reads, reads_len, d_offsets, n_reads, true, nullptr, nullptr, 0);
+    PassOpts o = opts_of(g);
+    o.stats = nullptr;  // the statistics kernels are not part of this entry point
+    fill_args(a, key, z, 1, hi, d_reads, reads_len, d_offsets, n_reads, true, nullptr, nullptr, 0, o);
 
     hipLaunchKernelGGL(k_put_args, dim3(1), dim3(64), 0, s, a, hi[0], dargs);
     hipError_t e = hipGetLastError();
@@ -156,10 +160,10 @@ extern "C" int dbg_build_device_static(dbg_graph *g, const uint8_t *d_reads, uin
                               binned ? nullptr : reinterpret_cast<uint64_t *>(base + o_tiles), cs, key.n_cap, s);
     if (e == hipSuccess) {
         if (binned)
-            e = dbgk::launch_binned(da, di, packed, ws, dst, bb, key.n_cap, g->device, s, nullptr);
+            e = dbgk::launch_binned(da, di, packed, ws, dst, bb, key.n_cap, g->device, false, s, nullptr);
         else
             e = dbgk::launch_build(da, di, packed, ws, reinterpret_cast<uint64_t *>(base + o_tiles), dst, cs,
-                                   key.shape, true, s);
+                                   key.shape, true, false, s);
     }
     InstStatus st{};
     if (e == hipSuccess) e = hipMemcpyAsync(&st, dst, sizeof st, hipMemcpyDeviceToHost, s);

@@ -1,10 +1,15 @@
 // Autotuner: times complete builds of a calibration input under candidate
 // configurations and keeps the fastest.  The search is coordinate-wise:
-// binned mode over load factors, then (unless binned mode is already far
-// ahead) the direct build over launch shapes, wavefront merging and load
-// factors.  Choices are cached per process.
+// binned mode over load factors, then over its partition launch shape
+// (chunks per workgroup, then the second scatter's grid divisor); then
+// (unless binned mode is already far ahead) the direct build over launch
+// shapes, wavefront merging and load factors.  Choices are cached in the
+// process and in a cache file keyed by device model.
 #include "dbg_runtime.h"
 
+#include <sys/stat.h>
+
+#include <cerrno>
 #include <chrono>
 #include <cstdio>
 #include <string>
@@ -18,7 +23,15 @@ struct Cand {
     double lf;
     uint32_t block, wpt;
     bool merge;
+    uint32_t bin_chunks = 0, bin_div = 0;
 };
+
+// The axes of the search.
+constexpr double kLoadFactors[] = {0.5, 0.4, 0.6, 0.7};
+constexpr uint32_t kBinChunks[] = {0, 4, 8, 32, 64};  // 0: the default, 16
+constexpr uint32_t kBinDivs[] = {0, 1, 2, 4};         // 0: automatic
+constexpr uint32_t kBlocks[] = {256, 512, 1024};
+constexpr uint32_t kWpts[] = {2, 4, 8};
 
 struct Workload {
     int device;
@@ -58,6 +71,8 @@ Outcome time_candidate(const Workload &w, const Cand &c) {
         cfg.flags = cand_flags(c, w.keep_flags);
         cfg.block_size = c.block;
         cfg.windows_per_thread = c.wpt;
+        cfg.bin_chunks = c.bin_chunks;
+        cfg.bin_scatter_div = c.bin_div;
         o.rc = dbg_create(&cfg, &gs[i]);
     }
     std::vector<int32_t> st(w.m, DBG_OK);
@@ -93,7 +108,77 @@ Outcome time_candidate(const Workload &w, const Cand &c) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, dbg_tuning> g_tune_cache;
+std::map<std::string, dbg_tuning> g_tune_cache;  // key -> tuning; from_cache says where it came from
+bool g_file_loaded = false;
+
+// The cache file's path ("" when there is none).
+std::string cache_path() {
+    if (const char *p = std::getenv("DBG_TUNE_CACHE")) return p;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) return std::string(x) + "/libdbg/autotune.tsv";
+    if (const char *h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/libdbg/autotune.tsv";
+    return "";
+}
+
+// Read the cache file into the process cache (under g_tune_mu).  Lines are
+// "key<TAB>lf flags block wpt bin_chunks bin_div best_ms default_ms"; later
+// lines of a key override earlier ones; malformed lines are skipped.
+void load_cache_file() {
+    g_file_loaded = true;
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        dbg_tuning t{};
+        unsigned flags = 0, block = 0, wpt = 0, chunks = 0, div = 0;
+        if (std::sscanf(tab + 1, "%lf %u %u %u %u %u %lf %lf", &t.load_factor, &flags, &block, &wpt, &chunks, &div,
+                        &t.best_ms, &t.default_ms) != 8)
+            continue;
+        if (!(t.load_factor > 0 && t.load_factor < 1) || (flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)))
+            continue;
+        t.flags = flags;
+        t.block_size = block;
+        t.windows_per_thread = wpt;
+        t.bin_chunks = chunks;
+        t.bin_scatter_div = div;
+        t.from_cache = 2;
+        g_tune_cache[line] = t;
+    }
+    std::fclose(f);
+}
+
+// Append a tuning to the cache file, creating its directory (best effort:
+// a cache that cannot be written only costs a later process the search).
+void save_cache_line(const std::string &key, const dbg_tuning &t) {
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    for (size_t i = 1; i < path.size(); ++i)
+        if (path[i] == '/') {
+            const std::string dir = path.substr(0, i);
+            if (mkdir(dir.c_str(), 0755) != 0 && errno != EEXIST) return;
+        }
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%.6g %u %u %u %u %u %.6f %.6f\n", key.c_str(), t.load_factor, t.flags, t.block_size,
+                 t.windows_per_thread, t.bin_chunks, t.bin_scatter_div, t.best_ms, t.default_ms);
+    std::fclose(f);
+}
+
+// The device model: what a tuning depends on besides the workload.
+std::string device_model(int device) {
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s:%dcu:%zumb", p.gcnArchName, p.multiProcessorCount,
+                  (size_t)(p.totalGlobalMem >> 20));
+    for (char *c = buf; *c; ++c)
+        if (*c == '\t' || *c == ' ' || *c == '\n') *c = '_';
+    return buf;
+}
 
 int size_bucket(uint64_t x) {  // half-octaves
     if (!x) return -1;
@@ -108,9 +193,9 @@ std::string cache_key(const Workload &w) {
         ev += w.expected ? w.expected[i] : 0;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%d/%u/%llx/%d/%d/%d/%x", w.device, w.m, (unsigned long long)kmask,
+    std::snprintf(buf, sizeof buf, "v1/%u/%llx/%d/%d/%d/%x", w.m, (unsigned long long)kmask,
                   size_bucket(w.reads_len), size_bucket(w.read_begin[w.m]), size_bucket(ev), w.keep_flags);
-    return buf;
+    return device_model(w.device) + "/" + buf;
 }
 
 }  // namespace
@@ -122,6 +207,8 @@ void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t) {
     cfg->load_factor = t->load_factor;
     cfg->block_size = t->block_size;
     cfg->windows_per_thread = t->windows_per_thread;
+    cfg->bin_chunks = t->bin_chunks;
+    cfg->bin_scatter_div = t->bin_scatter_div;
     cfg->flags = (cfg->flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)) | (t->flags & (DBG_F_BINNED | DBG_F_MERGE));
 }
 
@@ -147,11 +234,12 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
     const std::string key = cache_key(w);
     if (!(tune_flags & DBG_TUNE_FORCE)) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_file_loaded) load_cache_file();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             *out = it->second;
             out->candidates = 0;
-            out->from_cache = 1;
+            it->second.from_cache = 1;  // served from this process from now on
             return DBG_OK;
         }
     }
@@ -180,16 +268,35 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             best.flags = (c.binned ? DBG_F_BINNED : 0u) | (c.merge ? DBG_F_MERGE : 0u);
             best.block_size = c.binned ? 0 : c.block;
             best.windows_per_thread = c.binned ? 0 : c.wpt;
+            best.bin_chunks = c.binned ? c.bin_chunks : 0;
+            best.bin_scatter_div = c.binned ? c.bin_div : 0;
         }
         return o.ms;
     };
 
     double binned_best = 1e300;
     if (all_binnable) {
-        for (double lf : {0.5, 0.4, 0.6, 0.7}) {
-            const double ms = consider(Cand{true, lf, 256, 4, false});
+        // load factor at the default launch shape, then the launch shape at the best load factor
+        Cand bc{true, 0.5, 256, 4, false};
+        for (double lf : kLoadFactors) {
+            const Cand c{true, lf, 256, 4, false};
+            const double ms = consider(c);
             if (lf == 0.5) best.default_ms = ms;
-            binned_best = std::min(binned_best, ms);
+            if (ms < binned_best) binned_best = ms, bc = c;
+        }
+        for (uint32_t ch : kBinChunks) {
+            if (ch == 0) continue;
+            Cand c = bc;
+            c.bin_chunks = ch;
+            const double ms = consider(c);
+            if (ms < binned_best) binned_best = ms, bc = c;
+        }
+        for (uint32_t dv : kBinDivs) {
+            if (dv == 0) continue;
+            Cand c = bc;
+            c.bin_div = dv;
+            const double ms = consider(c);
+            if (ms < binned_best) binned_best = ms, bc = c;
         }
     }
     // direct build: launch shape, then merging, then load factor
@@ -197,8 +304,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
     double dbest = consider(dc);
     if (!all_binnable) best.default_ms = dbest;
     if (dbest < 1.5 * binned_best) {
-        for (uint32_t block : {256u, 512u, 1024u})
-            for (uint32_t wpt : {2u, 4u, 8u}) {
+        for (uint32_t block : kBlocks)
+            for (uint32_t wpt : kWpts) {
                 if (block == 256 && wpt == 4) continue;
                 const Cand c{false, 0.5, block, wpt, false};
                 const double ms = consider(c);
@@ -210,7 +317,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             const double mms = consider(mc);
             if (mms < dbest) dbest = mms, dc = mc;
         }
-        for (double lf : {0.4, 0.6, 0.7}) {
+        for (double lf : kLoadFactors) {
+            if (lf == 0.5) continue;
             Cand c = dc;
             c.lf = lf;
             const double ms = consider(c);
@@ -223,9 +331,42 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
     best.from_cache = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_file_loaded) load_cache_file();
         g_tune_cache[key] = best;
+        g_tune_cache[key].from_cache = 1;
+        save_cache_line(key, best);
     }
     *out = best;
+    return DBG_OK;
+}
+
+int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t *n) {
+    if (!n || (cap && !out)) return DBG_E_INVAL;
+    uint32_t k = 0;
+    auto put = [&](double lf, uint32_t flags, uint32_t block, uint32_t wpt, uint32_t ch, uint32_t dv) {
+        if (k < cap) {
+            dbg_tuning t{};
+            t.load_factor = lf;
+            t.flags = flags;
+            t.block_size = block;
+            t.windows_per_thread = wpt;
+            t.bin_chunks = ch;
+            t.bin_scatter_div = dv;
+            out[k] = t;
+        }
+        ++k;
+    };
+    for (double lf : kLoadFactors) {
+        if (binned) {
+            for (uint32_t ch : kBinChunks)
+                for (uint32_t dv : kBinDivs) put(lf, DBG_F_BINNED, 0, 0, ch, dv);
+        } else {
+            for (uint32_t block : kBlocks)
+                for (uint32_t wpt : kWpts)
+                    for (uint32_t merge : {0u, (uint32_t)DBG_F_MERGE}) put(lf, merge, block, wpt, 0, 0);
+        }
+    }
+    *n = k;
     return DBG_OK;
 }
 

@@ -11,6 +11,10 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def pytest_configure(config):
+    # the autotuner's cache file: one per test session, never the user's
+    if "DBG_TUNE_CACHE" not in os.environ:
+        import tempfile
+        os.environ["DBG_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="dbg_tune_"), "autotune.tsv")
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C ABI on the device)")
     config.addinivalue_line("markers", "slow: large inputs; minutes of CPU")
 

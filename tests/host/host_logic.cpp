@@ -93,6 +93,64 @@ static void check_host_counts(std::mt19937_64 &rng) {
     }
 }
 
+// Chunk counts of the two partition passes stay within the capacities the
+// runtime reserves (bin_caps): for random instance and bucket sizes, the
+// chunk length max(1, floor(tiles / target)) that the plan kernels use gives
+// at most chunks1_cap - 1 (pass 1) and chunks2_cap - 1 (pass 2) chunks, and
+// the histograms fit.
+static uint64_t chunks_of(const std::vector<uint64_t> &tiles, uint64_t target) {
+    uint64_t all = 0;
+    for (uint64_t t : tiles) all += t;
+    const uint64_t chunk = std::max<uint64_t>(1, all / std::max<uint64_t>(target, 1));
+    uint64_t n = 0;
+    for (uint64_t t : tiles) n += (t + chunk - 1) / chunk;
+    return n;
+}
+
+static void check_chunks(std::mt19937_64 &rng) {
+    for (int round = 0; round < 3000; ++round) {
+        const uint32_t m = 1 + (uint32_t)(rng() % (round % 3 ? 8 : 300));
+        const uint64_t len = 4096 + rng() % (round % 5 ? (1ull << 24) : (1ull << 33));
+        const uint32_t target = 1 + (uint32_t)(rng() % dbgk::kMaxChunkTarget);
+        // windows of each instance: a random split of at most len
+        std::vector<uint64_t> w(m), tiles(m);
+        uint64_t left = len;
+        for (uint32_t i = 0; i < m; ++i) {
+            w[i] = i + 1 == m ? left : (left ? rng() % (left + 1) : 0);
+            left -= w[i];
+            tiles[i] = (w[i] + dbgk::kBinTile - 1) / dbgk::kBinTile;
+        }
+        dbgrt::PassKey k;
+        k.binned = 1;
+        k.m_cap = (uint32_t)dbgrt::size_class(m, 1);
+        k.len_cap = dbgrt::size_class(len, 4096);
+        const uint32_t d1 = 1 + (uint32_t)(rng() % dbgk::kMaxD1), fan = 1 + (uint32_t)(rng() % dbgk::kMaxFan);
+        const uint64_t G = (uint64_t)m * d1;  // buckets over the launch
+        k.buckets_cap = dbgrt::size_class(G, 64);
+        k.d1_cap = (uint32_t)std::min<uint64_t>(dbgrt::size_class(d1, 16), dbgk::kMaxD1);
+        k.fan_cap = (uint32_t)std::min<uint64_t>(dbgrt::size_class(fan, 16), dbgk::kMaxFan);
+        dbgk::BinBuffers bb{};
+        dbgrt::bin_caps(k, bb);
+        const uint64_t c1 = chunks_of(tiles, target);
+        CHECK(c1 + 1 <= bb.chunks1_cap, "pass 1: %llu chunks, cap %llu", (unsigned long long)c1,
+              (unsigned long long)bb.chunks1_cap);
+        CHECK((uint64_t)d1 * c1 <= bb.hist1_cap, "pass 1 histogram");
+        // records (one per window) split over the G buckets
+        std::vector<uint64_t> bt(G);
+        uint64_t rec_left = len;
+        for (uint64_t g = 0; g < G; ++g) {
+            const uint64_t sz = g + 1 == G ? rec_left : (rec_left ? rng() % (2 * rec_left / (G - g) + 1) : 0);
+            const uint64_t take = std::min(sz, rec_left);
+            rec_left -= take;
+            bt[g] = (take + dbgk::kRefTile - 1) / dbgk::kRefTile;
+        }
+        const uint64_t c2 = chunks_of(bt, target);
+        CHECK(c2 + 1 <= bb.chunks2_cap, "pass 2: %llu chunks, cap %llu", (unsigned long long)c2,
+              (unsigned long long)bb.chunks2_cap);
+        CHECK((uint64_t)fan * c2 <= bb.hist2_cap, "pass 2 histogram");
+    }
+}
+
 int main() {
     for (uint64_t cap = 0; cap < 200000; cap += 7) check_geometry(cap);
     for (uint64_t cap = 1; cap < (1ull << 45); cap = cap * 9 / 8 + 1) check_geometry(cap);
@@ -105,6 +163,7 @@ int main() {
     check_size_class();
     std::mt19937_64 rng(20240105);
     check_host_counts(rng);
+    check_chunks(rng);
     if (failures) std::printf("%d failures\n", failures);
     else std::printf("ok\n");
     return failures > 100 ? 100 : failures;

@@ -66,7 +66,7 @@ def _c_layout(tmp_path, structs):
 def test_struct_layouts_match_header(tmp_path):
     structs = [("dbg_config", dbg.Config), ("dbg_stats", dbg.Stats), ("dbg_input", dbg.Input),
                ("dbg_server_config", dbg.ServerConfig), ("dbg_server_stats", dbg.ServerStats),
-               ("dbg_tuning", dbg.Tuning)]
+               ("dbg_tuning", dbg.Tuning), ("dbg_probe_stats", dbg.ProbeStats)]
     got = _c_layout(tmp_path, structs)
     for cname, py in structs:
         assert got[cname] == ctypes.sizeof(py), cname
@@ -94,6 +94,13 @@ def test_host_side_argument_errors_need_no_device():
     for lf in (-0.5, 1.0, 2.0):
         cfg.load_factor = lf
         assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    cfg.flags = dbg.F_BINNED  # a binned table's segments overflow above the bound
+    for lf in (0.86, 0.9):
+        cfg.load_factor = lf
+        assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    text = open(os.path.join(ROOT, "include", "dbg.h")).read()
+    assert float(re.search(r"#define DBG_BINNED_MAX_LOAD ([0-9.]+)", text).group(1)) == dbg.BINNED_MAX_LOAD
+    cfg.flags = 0
     cfg.load_factor = 0.5
     cfg.block_size = 100  # not a multiple of 64
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
@@ -103,6 +110,7 @@ def test_host_side_argument_errors_need_no_device():
     assert L.dbg_sync(None) == dbg.E_INVAL
     assert L.dbg_reset(None) == dbg.E_INVAL
     assert L.dbg_get_stats(None, None) == dbg.E_INVAL
+    assert L.dbg_get_probe_stats(None, None) == dbg.E_INVAL
     n = ctypes.c_uint64()
     assert L.dbg_extract(None, None, None, 0, ctypes.byref(n)) == dbg.E_INVAL
     assert L.dbg_build_extract_device(None, None, 0, None, 1, 21, None, None, 0, ctypes.byref(n),
@@ -121,6 +129,8 @@ def test_host_side_argument_errors_need_no_device():
         sc.load_factor = lf
         assert L.dbg_server_create(ctypes.byref(sc), ctypes.byref(h)) == dbg.E_INVAL
     sc.load_factor, sc.slots = 0.5, 9
+    assert L.dbg_server_create(ctypes.byref(sc), ctypes.byref(h)) == dbg.E_INVAL
+    sc.load_factor, sc.slots = 0.9, 0  # binned by default: above the bound
     assert L.dbg_server_create(ctypes.byref(sc), ctypes.byref(h)) == dbg.E_INVAL
     rid = ctypes.c_uint64()
     st = ctypes.c_int32()
@@ -147,8 +157,17 @@ def test_host_side_argument_errors_need_no_device():
     L.dbg_config_init(ctypes.byref(cfg))
     cfg.flags = dbg.F_GRAPH | dbg.F_MERGE
     t.load_factor, t.flags, t.block_size, t.windows_per_thread = 0.6, dbg.F_BINNED, 0, 0
+    t.bin_chunks, t.bin_scatter_div = 32, 2
     L.dbg_config_apply_tuning(ctypes.byref(cfg), ctypes.byref(t))
     assert cfg.flags == dbg.F_GRAPH | dbg.F_BINNED and cfg.load_factor == 0.6
+    assert cfg.bin_chunks == 32 and cfg.bin_scatter_div == 2
+    cfg.bin_chunks = 1 << 20  # more chunks per workgroup than a pass has
+    assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    # the search space: binned load factors x chunks x divisors, direct load factors x shapes x merging
+    nb = len(dbg.autotune_space(True))
+    nd = len(dbg.autotune_space(False))
+    assert nb == 4 * 5 * 4 and nd == 4 * 3 * 3 * 2
+    assert all(c.flags == dbg.F_BINNED and 0 < c.load_factor < dbg.BINNED_MAX_LOAD for c in dbg.autotune_space(True))
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

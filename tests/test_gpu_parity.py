@@ -109,14 +109,16 @@ def test_config1_device_build(config1, mode):
     assert_same(gpu_build_device(rs, flags=mode), want, "config1 device")
 
 
-@pytest.mark.parametrize("lf", [0.3, 0.7, 0.95])
+@pytest.mark.parametrize("lf", [0.3, 0.7, 0.85, 0.95])
 def test_config1_load_factors(config1, lf):
     rs, want = config1
     say("config1 load factor %.2f" % lf)
     V = want[0].shape[0]
     assert_same(gpu_build(rs, capacity=int(V / lf) + 1), want, "lf %.2f" % lf)
-    if lf <= 0.7:  # a binned table fails when one 2048-slot segment overflows
+    if lf <= dbg.BINNED_MAX_LOAD:  # a binned table fails when one 2048-slot segment overflows
         assert_same(gpu_build(rs, capacity=int(V / lf) + 1, flags=dbg.F_BINNED), want, "binned lf %.2f" % lf)
+        assert_same(gpu_build(rs, expected_vertices=V, load_factor=lf, flags=dbg.F_BINNED), want,
+                    "binned, load factor %.2f" % lf)
 
 
 def test_config1_stats_and_timing(config1):

@@ -97,7 +97,7 @@ def test_shared_prefixes_on_a_crowded_table():
     exp = want(rs, k)
     for mode in MODES:
         say("long k shared prefixes, mode %d" % mode)
-        with dbg.Graph(flags=mode, expected_vertices=90_000, load_factor=0.9) as g:
+        with dbg.Graph(flags=mode, expected_vertices=90_000, load_factor=0.85) as g:
             g.build(rs.reads, rs.offsets, k)
             check(g.extract_sorted(), exp)
 
