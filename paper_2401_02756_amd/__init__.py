@@ -58,6 +58,8 @@ class Config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
+        ("bin_stage", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -83,6 +85,8 @@ class Stats(ctypes.Structure):
         ("pad", ctypes.c_uint32),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
+        ("bin_stage", ctypes.c_uint32),
+        ("bin_staged", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -141,17 +145,17 @@ class Tuning(ctypes.Structure):
         ("from_cache", ctypes.c_uint32),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
-        ("pad", ctypes.c_uint32),
+        ("bin_stage", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
     def graph_kwargs(self) -> dict:
         """Keyword arguments of ``Graph`` that apply this tuning."""
         return dict(load_factor=self.load_factor, block_size=self.block_size,
                     windows_per_thread=self.windows_per_thread, flags=self.flags,
-                    bin_chunks=self.bin_chunks, bin_scatter_div=self.bin_scatter_div)
+                    bin_chunks=self.bin_chunks, bin_scatter_div=self.bin_scatter_div, bin_stage=self.bin_stage)
 
 
 _lib = None
@@ -256,7 +260,7 @@ class Graph:
     def __init__(self, expected_vertices: int = 0, capacity: int = 0, load_factor: float = 0.0,
                  device: int = -1, flags: int = 0, block_size: int = 0,
                  windows_per_thread: int = 0, stream=None, bin_chunks: int = 0, bin_scatter_div: int = 0,
-                 _borrowed=None):
+                 bin_stage: int = 0, _borrowed=None):
         self._owned = _borrowed is None
         if not self._owned:
             self._h = ctypes.c_void_p(_borrowed)
@@ -273,6 +277,7 @@ class Graph:
         cfg.stream = _stream(stream)
         cfg.bin_chunks = int(bin_chunks)
         cfg.bin_scatter_div = int(bin_scatter_div)
+        cfg.bin_stage = int(bin_stage)
         h = ctypes.c_void_p()
         _check(lib().dbg_create(ctypes.byref(cfg), ctypes.byref(h)), "dbg_create")
         self._h = h

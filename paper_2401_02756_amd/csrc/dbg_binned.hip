@@ -249,6 +249,141 @@ __device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, G 
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
+// ---------------------------------------------------------------- line-staged scatters
+//
+// A scatter chunk writes each of its runs (one per bucket or segment) in
+// order, a tile at a time, and a tile adds only a few records to each run
+// when there are many runs (about 6 per run for 713 runs and 4096 records).
+// Stored as they come, those pieces cover parts of 128-byte lines, and HBM
+// takes pieces of lines far more slowly than whole ones: appending 6-record
+// pieces to 713 runs moves 12.8 GB in 12 ms where whole aligned lines (or a
+// plain copy) take 5.5 ms, and 64-byte pieces 7.2 ms.  A staged scatter
+// keeps each run's records that do not yet fill their line in LDS (s_stg,
+// one line per run) and stores only whole lines, each by one group of
+// consecutive lanes in one instruction; the chunk's end stores what is left.
+// Only the first and last line of a chunk's run can then be partial.
+//
+// Per run j between tiles: s_front[j] is the global position of the run's
+// next record, f, and s_cc[j] the number of records waiting in s_stg, at
+// global [f - cc, f), all inside the line holding f; a waiting record sits
+// at s_stg[j * L + (position mod L)].
+constexpr uint32_t kLineBytes = 128;
+constexpr uint32_t kStageBlock = 1024;  // threads of a staged scatter workgroup (one per CU when staging 713 runs)
+
+template <typename R>
+struct Lines {
+    static constexpr uint32_t L = kLineBytes / (uint32_t)sizeof(R);  // records per line
+    static constexpr uint32_t kShift = L == 16 ? 4 : 3;
+    static_assert((1u << kShift) == L, "records per line");
+};
+
+// Dynamic LDS of a staged scatter with n runs and tiles of `tile` records:
+// s_cnt[n + 1], s_front[n], s_rec[tile], s_stg[n lines], s_pack[n], s_cc[n]
+// and the line-to-run table s_lrun (the lines a tile completes: at most
+// tile / L + n, one per run beyond the tile's own records).
+struct StageLayout {
+    uint32_t front, rec, stg, pack, cc, lrun, bytes;
+};
+
+template <typename R>
+__host__ __device__ inline StageLayout stage_layout(uint32_t n, uint32_t tile) {
+    StageLayout o;
+    o.front = align16(4 * (n + 1));
+    o.rec = o.front + align16(8 * n);
+    o.stg = o.rec + (uint32_t)sizeof(R) * tile;
+    o.pack = o.stg + kLineBytes * n;
+    o.cc = o.pack + align16(4 * n);
+    o.lrun = o.cc + align16(n);
+    o.bytes = o.lrun + align16(2 * (tile / Lines<R>::L + n + 1));
+    return o;
+}
+
+// After a tile's tagged counts: s_cnt[j] becomes run j's start in the sorted
+// tile; the lines the tile completes are numbered run by run (run j's from
+// lp on: its line holding f, if the tile fills it, and every whole line
+// after), s_lrun maps a line number to its run, and s_pack[j] packs start |
+// lp << 13 | cc << 24.  *s_nlines receives the tile's line count.  Whole block.
+template <typename R>
+__device__ void stage_starts(uint32_t *s_cnt, const uint64_t *s_front, const uint8_t *s_cc, uint32_t *s_pack,
+                             uint16_t *s_lrun, uint32_t *s_nlines, uint32_t n) {
+    constexpr uint32_t S = Lines<R>::kShift;
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t j0 = threadIdx.x * per;
+    uint64_t sum = 0;  // records in the low half, lines in the high half
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t j = j0 + q;
+        if (j < n) {
+            const uint32_t c = s_cnt[j] - (j << 12);
+            const uint64_t f = s_front[j];
+            sum += c | ((((f + c) >> S) - (f >> S)) << 32);
+        }
+    }
+    uint64_t total;
+    uint64_t pre = block_exclusive_scan(sum, &total);
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t j = j0 + q;
+        if (j >= n) break;
+        const uint32_t c = s_cnt[j] - (j << 12);
+        const uint64_t f = s_front[j];
+        const uint32_t nl = (uint32_t)(((f + c) >> S) - (f >> S));
+        const uint32_t start = (uint32_t)pre, lp = (uint32_t)(pre >> 32);
+        s_cnt[j] = start;
+        s_pack[j] = start | lp << 13 | (uint32_t)s_cc[j] << 24;
+        for (uint32_t i = 0; i < nl; ++i) s_lrun[lp + i] = (uint16_t)j;
+        pre += c | (uint64_t)nl << 32;
+    }
+    if (threadIdx.x == 0) *s_nlines = (uint32_t)(total >> 32);
+}
+
+// Store the tile's completed lines: L consecutive lanes per line, each
+// record from the waiting ones (below f) or the sorted tile.  Positions of
+// the run's first line below its start (another chunk's) are skipped.
+template <typename R>
+__device__ void stage_write(const uint16_t *s_lrun, const uint32_t *s_pack, const uint64_t *s_front, const R *s_stg,
+                            const R *s_rec, uint32_t nlines, R *__restrict__ out) {
+    constexpr uint32_t L = Lines<R>::L, S = Lines<R>::kShift;
+    for (uint32_t idx = threadIdx.x; idx < nlines * L; idx += blockDim.x) {
+        const uint32_t k = idx >> S, e = idx & (L - 1);
+        const uint32_t j = s_lrun[k];
+        const uint32_t pk = s_pack[j];
+        const uint32_t start = pk & 0x1fffu, lp = (pk >> 13) & 0x7ffu, cc = pk >> 24;
+        const uint64_t f = s_front[j];
+        const uint64_t pos = (((f >> S) + (k - lp)) << S) | e;
+        if (pos + cc >= f) out[pos] = pos < f ? s_stg[j * L + e] : s_rec[start + (uint32_t)(pos - f)];
+    }
+}
+
+// After the lines are stored: the tile's records past its last whole line
+// wait in s_stg, and each run's frontier moves to its end.  tile_n is the
+// tile's record count.  Whole block, no barrier.
+template <typename R>
+__device__ void stage_tail(const uint32_t *s_cnt, uint64_t *s_front, uint8_t *s_cc, R *s_stg, const R *s_rec,
+                           uint32_t n, uint32_t tile_n) {
+    constexpr uint32_t L = Lines<R>::L;
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const uint32_t start = s_cnt[j], c = (j + 1 < n ? s_cnt[j + 1] : tile_n) - start;
+        const uint64_t f = s_front[j], F = f + c, line = F & ~(uint64_t)(L - 1);
+        for (uint64_t pos = line > f ? line : f; pos < F; ++pos)
+            s_stg[j * L + (uint32_t)(pos & (L - 1))] = s_rec[start + (uint32_t)(pos - f)];
+        const uint64_t first = f - s_cc[j];  // the first waiting record before the tile
+        s_cc[j] = (uint8_t)(F - (line > first ? line : first));
+        s_front[j] = F;
+    }
+}
+
+// The chunk's end: every run's waiting records are stored (the run's last
+// line, partial), L lanes per run.  Whole block, no barrier.
+template <typename R>
+__device__ void stage_flush(const uint64_t *s_front, const uint8_t *s_cc, const R *s_stg, uint32_t n,
+                            R *__restrict__ out) {
+    constexpr uint32_t L = Lines<R>::L, S = Lines<R>::kShift;
+    for (uint32_t idx = threadIdx.x; idx < n * L; idx += blockDim.x) {
+        const uint32_t j = idx >> S, e = idx & (L - 1);
+        const uint64_t f = s_front[j], pos = (f & ~(uint64_t)(L - 1)) | e;
+        if (pos < f && pos + s_cc[j] >= f) out[pos] = s_stg[j * L + e];
+    }
+}
+
 // ---------------------------------------------------------------- plan
 
 // Per instance: its window range, pass-1 tiles and chunks, histogram and
@@ -334,8 +469,8 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
     return b;
 }
 
-// Pass 1, per chunk of tiles.  A thread takes kBinPerThread consecutive
-// windows of a tile: it finds their read once, loads three packed words, and
+// Pass 1, per chunk of tiles.  A thread takes WPT consecutive windows of a
+// tile (kBinPerThread; 4 in the staged scatter's 1024-thread workgroups): it finds their read once, loads three packed words, and
 // slides through them, so a window costs a few shifts instead of a search
 // and two loads.  The next read's bases follow the current read's in the
 // packed array, so a window that starts another read (k - 2 bases further
@@ -347,9 +482,10 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
 // written once.  Scattering, s_gbase[j] holds the global position where the
 // chunk's run of bucket j continues: each tile sorts its records by bucket
 // in LDS, writes bucket j's records at s_gbase[j] on, and advances s_gbase[j]
-// by their number.
-template <bool SCATTER, uint32_t RW>
-__global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
+// by their number; STAGED, it stores whole lines only (line-staged scatters
+// above) and s_gbase[j] is the run's frontier throughout.
+template <bool SCATTER, uint32_t RW, bool STAGED = false>
+__global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((amdgpu_waves_per_eu(STAGED ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -361,11 +497,19 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
                                                   const uint64_t *__restrict__ tile_read1,
                                                   uint32_t d1_max) {
     using R = typename RecOf<RW>::T;
+    constexpr uint32_t WPT = STAGED ? kBinTile / kStageBlock : kBinPerThread;
+    static_assert(WPT * (STAGED ? kStageBlock : kBinBlock) == kBinTile, "a tile is one window per thread slot");
     __shared__ ReadStage S;
+    __shared__ uint32_t s_nlines;
     extern __shared__ __align__(16) unsigned char s_dyn[];
+    const StageLayout lay = stage_layout<R>(d1_max, kBinTile);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (d1_max + 1)));
     R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (d1_max + 1)) + align16(8 * d1_max));  // 16-byte aligned
+    R *s_stg = reinterpret_cast<R *>(s_dyn + lay.stg);  // STAGED only, from here on
+    uint32_t *s_pack = reinterpret_cast<uint32_t *>(s_dyn + lay.pack);
+    uint8_t *s_cc = reinterpret_cast<uint8_t *>(s_dyn + lay.cc);
+    uint16_t *s_lrun = reinterpret_cast<uint16_t *>(s_dyn + lay.lrun);
     R *rec1 = reinterpret_cast<R *>(rec1w);
     const uint32_t tid = threadIdx.x;
     const uint32_t m = args->m;
@@ -393,7 +537,10 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
             } else {
                 const uint64_t *col = scan1 + plan[i].hist_base + c;
                 const uint64_t stride = plan[i].chunks;
-                for (uint32_t j = tid; j < d1; j += blockDim.x) s_gbase[j] = col[(uint64_t)j * stride];
+                for (uint32_t j = tid; j < d1; j += blockDim.x) {
+                    s_gbase[j] = col[(uint64_t)j * stride];
+                    if (STAGED) s_cc[j] = 0;
+                }
             }
         }
         {
@@ -403,11 +550,11 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
                 for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = j << 12;
             stage_reads(S, ws, off, off0, tile_read1[plan[i].tile_base + tbeg + t], read_end);
 
-            R rec[kBinPerThread];
-            uint32_t tag[kBinPerThread];  // scatter: bucket << 12 | rank (bucket d1: past the end)
-            const uint32_t j0 = tid * kBinPerThread;
+            R rec[WPT];
+            uint32_t tag[WPT];  // scatter: bucket << 12 | rank (bucket d1: past the end)
+            const uint32_t j0 = tid * WPT;
 #pragma unroll
-            for (uint32_t q = 0; q < kBinPerThread; ++q) tag[q] = d1 << 12;
+            for (uint32_t q = 0; q < WPT; ++q) tag[q] = d1 << 12;
             if (j0 < n_in) {
                 uint64_t w = w0 + j0;
                 ReadCursor rp = first_read(S, ws, off, off0, read_end, w);
@@ -420,15 +567,15 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
                     cc = packed[wbase + 2];
                 }
 #pragma unroll
-                for (uint32_t q = 0; q < kBinPerThread; ++q) {
+                for (uint32_t q = 0; q < WPT; ++q) {
                     if (j0 + q >= n_in) break;
                     if (w >= rp.wr1) {  // the next window starts another read
                         next_read(rp, S, ws, off, off0, read_end, w);
                         p = w + rp.delta;
                         // the words must hold this and the remaining windows' first
                         // bases at offsets below 64 (without a crossing a thread's
-                        // offsets stay below 32 + kBinPerThread)
-                        if (RW == 1 && p - 32 * wbase + (kBinPerThread - 1 - q) > 63) {
+                        // offsets stay below 32 + WPT)
+                        if (RW == 1 && p - 32 * wbase + (WPT - 1 - q) > 63) {
                             wbase = p >> 5;
                             a = packed[wbase];
                             b = packed[wbase + 1];
@@ -461,13 +608,27 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
                 }
             }
             __syncthreads();  // the next tile's staging waits on this barrier
-            if (SCATTER) {
+            if (SCATTER && STAGED) {
+                stage_starts<R>(s_cnt, s_gbase, s_cc, s_pack, s_lrun, &s_nlines, d1);
+                __syncthreads();
+#pragma unroll
+                for (uint32_t q = 0; q < WPT; ++q) {
+                    const uint32_t bk = tag[q] >> 12;
+                    if (bk == d1) continue;  // past the tile's end
+                    s_rec[s_cnt[bk] + (tag[q] & 0xfffu)] = rec[q];
+                }
+                __syncthreads();
+                stage_write<R>(s_lrun, s_pack, s_gbase, s_stg, s_rec, s_nlines, rec1);
+                __syncthreads();
+                stage_tail<R>(s_cnt, s_gbase, s_cc, s_stg, s_rec, d1, n_in);
+                __syncthreads();
+            } else if (SCATTER) {
             // s_gbase[j] becomes the global position of the tile's first record
             // of bucket j minus its position in the sorted tile
             bucket_starts(s_cnt, s_gbase, d1, [&](uint32_t j) { return s_gbase[j]; });
             __syncthreads();
 #pragma unroll
-            for (uint32_t q = 0; q < kBinPerThread; ++q) {
+            for (uint32_t q = 0; q < WPT; ++q) {
                 const uint32_t bk = tag[q] >> 12;
                 if (bk == d1) continue;  // past the tile's end
                 const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
@@ -491,6 +652,9 @@ __global__ __launch_bounds__(kBinBlock) __attribute__((amdgpu_waves_per_eu(RW ==
             uint32_t *col = hist1 + plan[i].hist_base + c;
             const uint64_t stride = plan[i].chunks;
             for (uint32_t j = tid; j < d1; j += blockDim.x) col[(uint64_t)j * stride] = s_cnt[j];
+            __syncthreads();
+        } else if (STAGED) {
+            stage_flush<R>(s_gbase, s_cc, s_stg, d1, rec1);
             __syncthreads();
         }
         t = 0;
@@ -632,15 +796,14 @@ __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter
 }
 
 
-// Load the records of one pass-2 tile: [r0, r0 + n) with n <= kRefTile (the
-// order of records over threads is free: counts and ranks only need each
-// record once).  One-word records go two per load.
-template <typename R>
-__device__ __forceinline__ void refine_load(uint64_t r0, uint32_t n, const R *__restrict__ rec1,
-                                            R (&rec)[kRefPerThread]) {
+// Load the records of one pass-2 tile: [r0, r0 + n) with n <= kRefTile, PT
+// per thread (the order of records over threads is free: counts and ranks
+// only need each record once).  One-word records go two per load.
+template <typename R, uint32_t PT>
+__device__ __forceinline__ void refine_load(uint64_t r0, uint32_t n, const R *__restrict__ rec1, R (&rec)[PT]) {
     if constexpr (sizeof(R) == 8) {
 #pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread / 2; ++it) {
+        for (uint32_t it = 0; it < PT / 2; ++it) {
             const uint32_t j = 2 * (it * blockDim.x + threadIdx.x);
             if (j + 1 < n) {
                 const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(rec1 + r0 + j);
@@ -653,7 +816,7 @@ __device__ __forceinline__ void refine_load(uint64_t r0, uint32_t n, const R *__
         }
     } else {
 #pragma unroll
-        for (uint32_t it = 0; it < kRefPerThread; ++it) {
+        for (uint32_t it = 0; it < PT; ++it) {
             const uint32_t j = it * blockDim.x + threadIdx.x;
             rec[it] = j < n ? rec1[r0 + j] : R{};
         }
@@ -674,27 +837,35 @@ __device__ __forceinline__ bool refine_has(uint32_t n, uint32_t it) {
 // next tile's records (in this chunk or the next one) are loaded while this
 // tile is written.  Counting, a chunk's histogram accumulates in LDS over its
 // tiles; scattering, s_gbase[j] holds where the chunk's run of segment j
-// continues, as in pass 1.
-template <bool SCATTER, uint32_t RW>
-__global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
+// continues, as in pass 1 (STAGED: whole lines only, 1024 threads).
+template <bool SCATTER, uint32_t RW, bool STAGED = false>
+__global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
                                                      const RefChunk *__restrict__ chunk2,
                                                      const uint64_t *__restrict__ rec1w,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
                                                      uint64_t *__restrict__ rec2w, uint32_t fan_max) {
     using R = typename RecOf<RW>::T;
+    constexpr uint32_t PT = STAGED ? kRefTile / kStageBlock : kRefPerThread;
+    static_assert(PT * (STAGED ? kStageBlock : kRefBlock) == kRefTile && PT % 2 == 0, "tile shape");
+    __shared__ uint32_t s_nlines;
     extern __shared__ __align__(16) unsigned char s_dyn[];
+    const StageLayout lay = stage_layout<R>(fan_max, kRefTile);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (fan_max + 1)));
     R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (fan_max + 1)) + align16(8 * fan_max));  // 16-byte aligned
-    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);  // RW = 1 only
+    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);  // RW = 1, not STAGED
+    R *s_stg = reinterpret_cast<R *>(s_dyn + lay.stg);  // STAGED only, from here on
+    uint32_t *s_pack = reinterpret_cast<uint32_t *>(s_dyn + lay.pack);
+    uint8_t *s_cc = reinterpret_cast<uint8_t *>(s_dyn + lay.cc);
+    uint16_t *s_lrun = reinterpret_cast<uint16_t *>(s_dyn + lay.lrun);
     const R *rec1 = reinterpret_cast<const R *>(rec1w);
     R *rec2 = reinterpret_cast<R *>(rec2w);
     const uint32_t tid = threadIdx.x;
     XcdTiles xt(tot->chunks2);
     if (!xt.valid()) return;
     RefChunk C = chunk2[xt.next];
-    R rec[kRefPerThread];
+    R rec[PT];
     refine_load(C.r0, (uint32_t)min<uint64_t>(C.n, kRefTile), rec1, rec);
     for (;;) {
         xt.advance();
@@ -705,7 +876,10 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
         if (!SCATTER) {
             for (uint32_t j = tid; j < fan; j += blockDim.x) s_cnt[j] = 0u;
         } else {
-            for (uint32_t j = tid; j < fan; j += blockDim.x) s_gbase[j] = scan2[C.hcol + (uint64_t)j * C.stride];
+            for (uint32_t j = tid; j < fan; j += blockDim.x) {
+                s_gbase[j] = scan2[C.hcol + (uint64_t)j * C.stride];
+                if (STAGED) s_cc[j] = 0;
+            }
         }
         for (uint64_t t0 = 0; t0 < C.n; t0 += kRefTile) {
             const uint32_t n = (uint32_t)min<uint64_t>(kRefTile, C.n - t0);
@@ -717,9 +891,9 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
             if (SCATTER)
                 for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = j << 12;
             __syncthreads();
-            uint32_t tag[kRefPerThread];  // scatter: segment << 12 | rank (segment fan: past the end)
+            uint32_t tag[PT];  // scatter: segment << 12 | rank (segment fan: past the end)
 #pragma unroll
-            for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            for (uint32_t it = 0; it < PT; ++it) {
                 const uint32_t c =
                     refine_has<R>(n, it) ? child_of(image_top(RecOf<RW>::head(rec[it]) >> 3), d1, fan) : fan;
                 if (SCATTER)
@@ -732,10 +906,27 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
                 continue;  // the next tile's adds go to the same counters
             }
             __syncthreads();
+            if (STAGED) {
+                stage_starts<R>(s_cnt, s_gbase, s_cc, s_pack, s_lrun, &s_nlines, fan);
+                __syncthreads();
+#pragma unroll
+                for (uint32_t it = 0; it < PT; ++it) {
+                    const uint32_t c = tag[it] >> 12;
+                    if (c == fan) continue;  // past the tile's end
+                    s_rec[s_cnt[c] + (tag[it] & 0xfffu)] = rec[it];
+                }
+                if (nn) refine_load(nr0, nn, rec1, rec);
+                __syncthreads();
+                stage_write<R>(s_lrun, s_pack, s_gbase, s_stg, s_rec, s_nlines, rec2);
+                __syncthreads();
+                stage_tail<R>(s_cnt, s_gbase, s_cc, s_stg, s_rec, fan, n);
+                __syncthreads();  // before the next tile resets the counters
+                continue;
+            }
             bucket_starts(s_cnt, s_gbase, fan, [&](uint32_t j) { return s_gbase[j]; });
             __syncthreads();
 #pragma unroll
-            for (uint32_t it = 0; it < kRefPerThread; ++it) {
+            for (uint32_t it = 0; it < PT; ++it) {
                 const uint32_t c = tag[it] >> 12;
                 if (c == fan) continue;  // past the tile's end
                 const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
@@ -756,6 +947,9 @@ __global__ __launch_bounds__(kRefBlock) void k_refine(const BinTotals *__restric
         __syncthreads();
         if (!SCATTER) {
             for (uint32_t j = tid; j < fan; j += blockDim.x) hist2[C.hcol + (uint64_t)j * C.stride] = s_cnt[j];
+            __syncthreads();
+        } else if (STAGED) {
+            stage_flush<R>(s_gbase, s_cc, s_stg, fan, rec2);
             __syncthreads();
         }
         if (!more) break;
@@ -1196,7 +1390,9 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
                          InstStatus *st, const BinBuffers &bb, bool stats, hipStream_t s, hipEvent_t *marks) {
     hipError_t e;
     // pass 1
-    const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW), lb1 = bin_lds_bytes(bb.d1_max, true, RW);
+    using R = typename RecOf<RW>::T;
+    const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW);
+    const uint32_t lb1 = bb.staged1 ? stage_layout<R>(bb.d1_max, kBinTile).bytes : bin_lds_bytes(bb.d1_max, true, RW);
     const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
     hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
                        bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
@@ -1209,8 +1405,12 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
     if (marks) (void)hipEventRecord(marks[2], s);
-    hipLaunchKernelGGL((k_bin<true, RW>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
-                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    if (bb.staged1)
+        hipLaunchKernelGGL((k_bin<true, RW, true>), dim3(g1s), dim3(kStageBlock), lb1, s, args, inst, packed, ws,
+                           bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    else
+        hipLaunchKernelGGL((k_bin<true, RW>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
+                           bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[3], s);
 
@@ -1223,7 +1423,9 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
                            bb.chunks2_cap);
     }
     if (marks) (void)hipEventRecord(marks[4], s);
-    const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW), lr1 = ref_lds_bytes(bb.fan_max, true, RW);
+    const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW);
+    const uint32_t lr1 =
+        bb.staged2 ? stage_layout<R>(bb.fan_max, kRefTile).bytes : ref_lds_bytes(bb.fan_max, true, RW);
     const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
     hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.chunk2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
@@ -1236,8 +1438,12 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
     if (marks) (void)hipEventRecord(marks[6], s);
-    hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.chunk2, bb.rec1,
-                       bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    if (bb.staged2)
+        hipLaunchKernelGGL((k_refine<true, RW, true>), dim3(g2s), dim3(kStageBlock), lr1, s, bb.totals, bb.chunk2,
+                           bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+    else
+        hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.chunk2, bb.rec1,
+                           bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[7], s);
 
@@ -1286,22 +1492,55 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
 namespace {
 constexpr uint32_t kScatterWide = 384;  // segments per bucket beyond which pass 2 scatters on half the grid
 
+// Whether a staged scatter kernel with `dyn` bytes of dynamic LDS fits one
+// workgroup (its static LDS included), with dynamic LDS allowed up to that.
+template <typename K>
+bool stage_fits(K kernel, int device, uint32_t dyn) {
+    int max_lds = 0;
+    hipFuncAttributes fa{};
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)) != hipSuccess)
+        return false;
+    if ((uint64_t)dyn + fa.sharedSizeBytes > (uint64_t)max_lds) return false;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dyn) == hipSuccess;
+}
+
 template <uint32_t RW>
 void grids_for(int device, BinBuffers &bb) {
+    using R = typename RecOf<RW>::T;
+    // Staging holds one LDS line per run, so with many runs a staged scatter
+    // runs one 1024-thread workgroup per CU, and its waves stall together at
+    // every barrier.  It pays where runs are shortest: the second scatter
+    // when a bucket spans more than kScatterWide segments (713 at 508 k
+    // segments: 12.8 -> 9.2 ms); the first scatter, which also decodes
+    // windows, and scatters of fewer runs measured slower staged (bacterial
+    // scale, 212 runs: 0.51 -> 1.0 ms and 0.53 -> 0.69 ms).  The line
+    // numbers of a tile must fit s_pack's 11 bits.
+    const StageLayout st1 = stage_layout<R>(bb.d1_max, kBinTile), st2 = stage_layout<R>(bb.fan_max, kRefTile);
+    // stage_mode 2 stages every scatter whose staging fits.
+    bb.staged1 = bb.stage_mode == 2 && kBinTile / Lines<R>::L + bb.d1_max < 2048 &&
+                 stage_fits(k_bin<true, RW, true>, device, st1.bytes);
+    bb.staged2 = bb.stage_mode != 1 && (bb.stage_mode == 2 || bb.fan_max > kScatterWide) &&
+                 kRefTile / Lines<R>::L + bb.fan_max < 2048 && stage_fits(k_refine<true, RW, true>, device, st2.bytes);
     bb.grid_bin_count =
         occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
     bb.grid_bin_scatter =
-        occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, true, RW));
+        bb.staged1 ? occupancy_grid(k_bin<true, RW, true>, device, kStageBlock, bb.chunks1_cap, st1.bytes)
+                   : occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, true, RW));
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
-    // A scatter tile writes one short run per segment when a bucket has many
-    // segments; the partial lines of the workgroups in flight on an XCD then
-    // outgrow its L2 before the next tiles complete them, and the pass-2
-    // scatter writes faster on part of its resident grid.
+    // Unstaged, a scatter tile writes one short run per segment when a bucket
+    // has many segments; the partial lines of the workgroups in flight on an
+    // XCD then outgrow its L2 before the next tiles complete them, and the
+    // pass-2 scatter writes faster on part of its resident grid.
     const uint32_t div = bb.scatter_div ? bb.scatter_div : (bb.fan_max > kScatterWide ? 2u : 1u);
-    bb.grid_ref_scatter = std::max<uint32_t>(
-        8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, true, RW)) /
-               div);
+    bb.grid_ref_scatter =
+        bb.staged2
+            ? occupancy_grid(k_refine<true, RW, true>, device, kStageBlock, bb.chunks2_cap, st2.bytes)
+            : std::max<uint32_t>(8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap,
+                                                   ref_lds_bytes(bb.fan_max, true, RW)) /
+                                        div);
     bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2, false>, device, kReduceBlock, bb.parts_cap, 0)
                    : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1, false>, device, kReduceBlock, bb.parts_cap, 0)
                                          : occupancy_grid(k_reduce<3, 1, false>, device, kReduceBlock, bb.parts_cap, 0);

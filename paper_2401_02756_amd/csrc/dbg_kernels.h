@@ -227,9 +227,14 @@ struct BinBuffers {     // device scratch of one binned pass
     uint32_t grid_bin_count, grid_bin_scatter, grid_ref_count, grid_ref_scatter, grid_reduce;
     uint32_t target1, target2;  // chunks each partition pass aims for (<= kMaxChunkTarget)
     // launch shape (set before binned_grids): chunks per resident scatter
-    // workgroup (0: kChunksPerGroup), and the divisor of the pass-2 scatter's
-    // resident grid (0: automatic, 2 when a bucket has more than 384 segments)
-    uint32_t chunks_per_group, scatter_div;
+    // workgroup (0: kChunksPerGroup), the divisor of the pass-2 scatter's
+    // resident grid when it stores runs as they come (0: automatic, 2 when a
+    // bucket has more than 384 segments), and the staging of scatter lines
+    // in LDS (dbg_config bin_stage: 0 automatic, 1 never, 2 wherever it fits)
+    uint32_t chunks_per_group, scatter_div, stage_mode;
+    // whether each scatter stages whole lines in LDS (binned_grids decides:
+    // when its staging fits in a workgroup's LDS)
+    uint32_t staged1, staged2;
 };
 
 // Fill the grid sizes of bb from occupancy and its capacities.

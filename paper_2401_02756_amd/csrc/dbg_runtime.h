@@ -141,7 +141,7 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
 struct PassKey {
     int binned = 0;
     int stats = 0;  // kernels that keep probe statistics
-    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (dbg_config)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (dbg_config)
     int single = 0;
     int wide = 0;  // one instance with 32 < k <= 64, direct build
     uint32_t rw = 1;  // binned record words (2: long keys)
@@ -151,6 +151,7 @@ struct PassKey {
     dbgk::BuildShape shape{};
     bool operator==(const PassKey &o) const {
         return binned == o.binned && stats == o.stats && bin_chunks == o.bin_chunks && bin_div == o.bin_div &&
+               bin_stage == o.bin_stage &&
                single == o.single && wide == o.wide && rw == o.rw && ew == o.ew &&
                m_cap == o.m_cap &&
                d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
@@ -249,7 +250,7 @@ struct PassSizes {
 struct PassOpts {
     uint64_t *stats = nullptr;
     uint32_t test_hash = 0;
-    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (0: defaults)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (0: defaults)
 };
 
 inline PassOpts opts_of(const dbg_graph *g);
@@ -310,6 +311,7 @@ struct Pass {
     };
     std::vector<Cached> graphs;
     uint64_t captures = 0, replays = 0;
+    uint32_t staged = 0;  // the last binned pass's staged scatters: bit 0 pass 1, bit 1 pass 2
 
     hipError_t init() {
         hipError_t e = hipEventCreate(&ev_a);
@@ -405,10 +407,13 @@ struct Pass {
                 bb.grid_reduce = g.second.grid_reduce;
                 bb.target1 = g.second.target1;
                 bb.target2 = g.second.target2;
+                bb.staged1 = g.second.staged1;
+                bb.staged2 = g.second.staged2;
                 return;
             }
         bb.chunks_per_group = k.bin_chunks;
         bb.scatter_div = k.bin_div;
+        bb.stage_mode = k.bin_stage;
         dbgk::binned_grids(device, bb);
         if (grid_memo.size() > 16) grid_memo.clear();
         grid_memo.emplace_back(k, bb);
@@ -486,6 +491,7 @@ struct Pass {
         k.stats = o.stats != nullptr;
         k.bin_chunks = o.bin_chunks;
         k.bin_div = o.bin_div;
+        k.bin_stage = o.bin_stage;
         dbgk::BinBuffers bb{};
         if (binned) bin_caps(k, bb);
         const PassSizes z(k, bb);
@@ -495,7 +501,10 @@ struct Pass {
             (e = grow(dstatus, z.status)) != hipSuccess || (!binned && (e = grow(tiles, z.tiles)) != hipSuccess) ||
             (binned && (e = reserve_binned(k, bb)) != hipSuccess))
             return e;
-        if (binned) binned_grids(k, device, bb);
+        if (binned) {
+            binned_grids(k, device, bb);
+            staged = bb.staged1 | bb.staged2 << 1;
+        }
         fill_args(*host_args(), k, z, mm, hi, d_reads, len, d_off, n, check_ends, xkeys, xcounts, xcap, o);
 
         Cached *c = nullptr;
@@ -579,7 +588,7 @@ struct dbg_graph {
     uint64_t expected = 0, cap_req = 0;
     dbgk::BuildShape shape{256, 4, 0, 0};
     uint32_t grid_wide = 0;  // persistent grid of the long-k build
-    uint32_t bin_chunks = 0, bin_div = 0;  // binned launch shape (dbg_config)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (dbg_config)
 
     uint64_t cap = 0;
     uint32_t ew = 3;
@@ -622,6 +631,7 @@ inline PassOpts opts_of(const dbg_graph *g) {
     o.test_hash = (g->flags & DBG_F_TEST_HASH) ? 1u : 0u;
     o.bin_chunks = g->bin_chunks;
     o.bin_div = g->bin_div;
+    o.bin_stage = g->bin_stage;
     return o;
 }
 

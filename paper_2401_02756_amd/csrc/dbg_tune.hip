@@ -1,7 +1,8 @@
 // Autotuner: times complete builds of a calibration input under candidate
 // configurations and keeps the fastest.  The search is coordinate-wise:
 // binned mode over load factors, then over its partition launch shape
-// (chunks per workgroup, then the second scatter's grid divisor); then
+// (chunks per workgroup, line staging on or off, then the second scatter's
+// grid divisor); then
 // (unless binned mode is already far ahead) the direct build over launch
 // shapes, wavefront merging and load factors.  Choices are cached in the
 // process and in a cache file keyed by device model.
@@ -23,13 +24,14 @@ struct Cand {
     double lf;
     uint32_t block, wpt;
     bool merge;
-    uint32_t bin_chunks = 0, bin_div = 0;
+    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;
 };
 
 // The axes of the search.
 constexpr double kLoadFactors[] = {0.5, 0.4, 0.6, 0.7};
 constexpr uint32_t kBinChunks[] = {0, 4, 8, 32, 64};  // 0: the default, 16
 constexpr uint32_t kBinDivs[] = {0, 1, 2, 4};         // 0: automatic
+constexpr uint32_t kBinStages[] = {0, 1, 2};          // line staging: 0 automatic, 1 never, 2 wherever it fits
 constexpr uint32_t kBlocks[] = {256, 512, 1024};
 constexpr uint32_t kWpts[] = {2, 4, 8};
 
@@ -73,6 +75,7 @@ Outcome time_candidate(const Workload &w, const Cand &c) {
         cfg.windows_per_thread = c.wpt;
         cfg.bin_chunks = c.bin_chunks;
         cfg.bin_scatter_div = c.bin_div;
+        cfg.bin_stage = c.bin_stage;
         o.rc = dbg_create(&cfg, &gs[i]);
     }
     std::vector<int32_t> st(w.m, DBG_OK);
@@ -120,7 +123,7 @@ std::string cache_path() {
 }
 
 // Read the cache file into the process cache (under g_tune_mu).  Lines are
-// "key<TAB>lf flags block wpt bin_chunks bin_div best_ms default_ms"; later
+// "key<TAB>lf flags block wpt bin_chunks bin_div bin_stage best_ms default_ms"; later
 // lines of a key override earlier ones; malformed lines are skipped.
 void load_cache_file() {
     g_file_loaded = true;
@@ -134,9 +137,10 @@ void load_cache_file() {
         if (!tab) continue;
         *tab = 0;
         dbg_tuning t{};
-        unsigned flags = 0, block = 0, wpt = 0, chunks = 0, div = 0;
-        if (std::sscanf(tab + 1, "%lf %u %u %u %u %u %lf %lf", &t.load_factor, &flags, &block, &wpt, &chunks, &div,
-                        &t.best_ms, &t.default_ms) != 8)
+        unsigned flags = 0, block = 0, wpt = 0, chunks = 0, div = 0, stage = 0;
+        if (std::sscanf(tab + 1, "%lf %u %u %u %u %u %u %lf %lf", &t.load_factor, &flags, &block, &wpt, &chunks,
+                        &div, &stage, &t.best_ms, &t.default_ms) != 9 ||
+            stage > 2)
             continue;
         if (!(t.load_factor > 0 && t.load_factor < 1) || (flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)))
             continue;
@@ -145,6 +149,7 @@ void load_cache_file() {
         t.windows_per_thread = wpt;
         t.bin_chunks = chunks;
         t.bin_scatter_div = div;
+        t.bin_stage = stage;
         t.from_cache = 2;
         g_tune_cache[line] = t;
     }
@@ -163,8 +168,8 @@ void save_cache_line(const std::string &key, const dbg_tuning &t) {
         }
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%.6g %u %u %u %u %u %.6f %.6f\n", key.c_str(), t.load_factor, t.flags, t.block_size,
-                 t.windows_per_thread, t.bin_chunks, t.bin_scatter_div, t.best_ms, t.default_ms);
+    std::fprintf(f, "%s\t%.6g %u %u %u %u %u %u %.6f %.6f\n", key.c_str(), t.load_factor, t.flags, t.block_size,
+                 t.windows_per_thread, t.bin_chunks, t.bin_scatter_div, t.bin_stage, t.best_ms, t.default_ms);
     std::fclose(f);
 }
 
@@ -193,7 +198,7 @@ std::string cache_key(const Workload &w) {
         ev += w.expected ? w.expected[i] : 0;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "v1/%u/%llx/%d/%d/%d/%x", w.m, (unsigned long long)kmask,
+    std::snprintf(buf, sizeof buf, "v2/%u/%llx/%d/%d/%d/%x", w.m, (unsigned long long)kmask,
                   size_bucket(w.reads_len), size_bucket(w.read_begin[w.m]), size_bucket(ev), w.keep_flags);
     return device_model(w.device) + "/" + buf;
 }
@@ -209,6 +214,7 @@ void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t) {
     cfg->windows_per_thread = t->windows_per_thread;
     cfg->bin_chunks = t->bin_chunks;
     cfg->bin_scatter_div = t->bin_scatter_div;
+    cfg->bin_stage = t->bin_stage;
     cfg->flags = (cfg->flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)) | (t->flags & (DBG_F_BINNED | DBG_F_MERGE));
 }
 
@@ -270,6 +276,7 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             best.windows_per_thread = c.binned ? 0 : c.wpt;
             best.bin_chunks = c.binned ? c.bin_chunks : 0;
             best.bin_scatter_div = c.binned ? c.bin_div : 0;
+            best.bin_stage = c.binned ? c.bin_stage : 0;
         }
         return o.ms;
     };
@@ -288,6 +295,13 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             if (ch == 0) continue;
             Cand c = bc;
             c.bin_chunks = ch;
+            const double ms = consider(c);
+            if (ms < binned_best) binned_best = ms, bc = c;
+        }
+        for (uint32_t sg : kBinStages) {
+            if (sg == 0) continue;
+            Cand c = bc;
+            c.bin_stage = sg;
             const double ms = consider(c);
             if (ms < binned_best) binned_best = ms, bc = c;
         }
@@ -343,7 +357,7 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
 int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t *n) {
     if (!n || (cap && !out)) return DBG_E_INVAL;
     uint32_t k = 0;
-    auto put = [&](double lf, uint32_t flags, uint32_t block, uint32_t wpt, uint32_t ch, uint32_t dv) {
+    auto put = [&](double lf, uint32_t flags, uint32_t block, uint32_t wpt, uint32_t ch, uint32_t dv, uint32_t sg) {
         if (k < cap) {
             dbg_tuning t{};
             t.load_factor = lf;
@@ -352,6 +366,7 @@ int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t 
             t.windows_per_thread = wpt;
             t.bin_chunks = ch;
             t.bin_scatter_div = dv;
+            t.bin_stage = sg;
             out[k] = t;
         }
         ++k;
@@ -359,11 +374,12 @@ int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t 
     for (double lf : kLoadFactors) {
         if (binned) {
             for (uint32_t ch : kBinChunks)
-                for (uint32_t dv : kBinDivs) put(lf, DBG_F_BINNED, 0, 0, ch, dv);
+                for (uint32_t sg : kBinStages)
+                    for (uint32_t dv : kBinDivs) put(lf, DBG_F_BINNED, 0, 0, ch, dv, sg);
         } else {
             for (uint32_t block : kBlocks)
                 for (uint32_t wpt : kWpts)
-                    for (uint32_t merge : {0u, (uint32_t)DBG_F_MERGE}) put(lf, merge, block, wpt, 0, 0);
+                    for (uint32_t merge : {0u, (uint32_t)DBG_F_MERGE}) put(lf, merge, block, wpt, 0, 0, 0);
         }
     }
     *n = k;
