@@ -118,20 +118,23 @@ typedef struct {
     void *stream;                /* hipStream_t for all work; NULL = own stream */
     /* binned build launch shape: the partition passes work on chunks of
      * consecutive tiles, about bin_chunks per resident scatter workgroup
-     * (0 = 16; at most 16384 chunks a pass).  A staged partition scatter
-     * keeps each run's records in LDS until they fill a 128-byte line and
-     * stores whole lines only; unstaged, it stores records as each tile
-     * sorts them, in runs of a few records when there are many runs.
-     * bin_stage 0 stages the second scatter when a level-1 bucket spans
-     * more than 384 table segments; 1 never stages; 2 stages every scatter
-     * whose staging (one line per run) fits in a workgroup's LDS.
-     * bin_scatter_div divides the resident grid of an unstaged second
-     * scatter (0 = automatic: 2 when a level-1 bucket spans more than 384
-     * table segments, else 1). */
+     * (0 = 32; at most 16384 chunks a pass).  bin_shape1 and bin_shape2
+     * set the shape of the first and second partition scatter: 1 = plain
+     * tiles of 4096 records, stored as each tile sorts them (in runs of a
+     * few records when there are many runs); 2 = staged: each run's
+     * records wait in LDS until they fill a 128-byte line, and only whole
+     * lines are stored; 3 = big tiles of 16384 records, runs four times
+     * longer; 0 = automatic (big tiles for the second scatter, and for the
+     * first beyond 384 runs, else plain tiles).
+     * A shape
+     * whose LDS does not fit one workgroup falls back to plain tiles.
+     * bin_scatter_div divides the resident grid of a second scatter of
+     * plain tiles (0 = automatic: 2 when a level-1 bucket spans more than
+     * 384 table segments, else 1). */
     uint32_t bin_chunks;
     uint32_t bin_scatter_div;
-    uint32_t bin_stage;
-    uint32_t reserved;           /* 0 */
+    uint32_t bin_shape1;
+    uint32_t bin_shape2;
 } dbg_config;
 
 typedef struct {
@@ -155,8 +158,8 @@ typedef struct {
     uint32_t pad;
     uint32_t bin_chunks;      /* binned launch shape in use (0 = defaults) */
     uint32_t bin_scatter_div;
-    uint32_t bin_stage;
-    uint32_t bin_staged;      /* scatters of the last binned pass that staged lines: bit 0 the first, bit 1 the second */
+    uint32_t bin_shape1;      /* scatter shapes of the last binned pass (as dbg_config; 0 before one) */
+    uint32_t bin_shape2;
 } dbg_stats;
 
 /* Probe statistics of a graph created with DBG_F_STATS, summed over its
@@ -449,9 +452,9 @@ void dbg_server_destroy(dbg_server *s);
  * Picks the build configuration of a workload by timing complete builds of a
  * calibration input (the workload itself, or a slice of it that the caller
  * passes): the table mode (binned or direct) and the load factor; for the
- * binned build, the chunks per workgroup of its partition passes, line
- * staging on or off, and the grid divisor of its second scatter; for the
- * direct build, block size,
+ * binned build, the chunks per workgroup of its partition passes, the
+ * shapes of its scatters, and the grid divisor of its second scatter; for
+ * the direct build, block size,
  * windows per thread and wavefront merging.  The search goes one axis at a
  * time from the defaults.  Every candidate must produce the same vertex and
  * k-mer totals; one that does not, or that fails (a table overflow at a high
@@ -469,7 +472,9 @@ typedef struct {
     uint32_t from_cache;         /* 0: timed now; 1: this process's cache; 2: the cache file */
     uint32_t bin_chunks;         /* binned launch shape (dbg_config), 0 = default */
     uint32_t bin_scatter_div;
-    uint32_t bin_stage;
+    uint32_t bin_shape1;
+    uint32_t bin_shape2;
+    uint32_t pad;
 } dbg_tuning;
 
 #define DBG_TUNE_FORCE 0x1u /* ignore the caches (and refresh them) */
@@ -496,8 +501,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
 
 /* Every configuration the tuner's search may time, for the binned (binned
  * != 0) or the direct build: the cross product of its axes (load factor,
- * and binned chunks, line staging and scatter divisor, or direct block
- * size, windows per thread and merging).  Writes min(cap, *n) entries (only the configuration
+ * and binned chunks, scatter shapes (five pairs) and scatter divisor, or
+ * direct block size, windows per thread and merging).  Writes min(cap, *n) entries (only the configuration
  * fields are set); *n is the size of the space. */
 int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t *n);
 

@@ -44,6 +44,8 @@ BINNED_MAX_LOAD = 0.85  # DBG_BINNED_MAX_LOAD: the largest load factor dbg_creat
 BINNED_PHASES = ("setup", "plan", "count1", "scan1", "scatter1", "plan2", "count2", "scan2", "scatter2",
                  "starts", "reduce")
 TUNE_FORCE = 0x1
+# partition scatter shapes (dbg_config bin_shape1 / bin_shape2)
+SHAPE_AUTO, SHAPE_TILES, SHAPE_STAGED, SHAPE_BIG = 0, 1, 2, 3
 
 
 class Config(ctypes.Structure):
@@ -58,8 +60,8 @@ class Config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
-        ("bin_stage", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("bin_shape1", ctypes.c_uint32),
+        ("bin_shape2", ctypes.c_uint32),
     ]
 
 
@@ -85,8 +87,8 @@ class Stats(ctypes.Structure):
         ("pad", ctypes.c_uint32),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
-        ("bin_stage", ctypes.c_uint32),
-        ("bin_staged", ctypes.c_uint32),
+        ("bin_shape1", ctypes.c_uint32),
+        ("bin_shape2", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -145,17 +147,20 @@ class Tuning(ctypes.Structure):
         ("from_cache", ctypes.c_uint32),
         ("bin_chunks", ctypes.c_uint32),
         ("bin_scatter_div", ctypes.c_uint32),
-        ("bin_stage", ctypes.c_uint32),
+        ("bin_shape1", ctypes.c_uint32),
+        ("bin_shape2", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
     def graph_kwargs(self) -> dict:
         """Keyword arguments of ``Graph`` that apply this tuning."""
         return dict(load_factor=self.load_factor, block_size=self.block_size,
                     windows_per_thread=self.windows_per_thread, flags=self.flags,
-                    bin_chunks=self.bin_chunks, bin_scatter_div=self.bin_scatter_div, bin_stage=self.bin_stage)
+                    bin_chunks=self.bin_chunks, bin_scatter_div=self.bin_scatter_div,
+                    bin_shape1=self.bin_shape1, bin_shape2=self.bin_shape2)
 
 
 _lib = None
@@ -260,7 +265,7 @@ class Graph:
     def __init__(self, expected_vertices: int = 0, capacity: int = 0, load_factor: float = 0.0,
                  device: int = -1, flags: int = 0, block_size: int = 0,
                  windows_per_thread: int = 0, stream=None, bin_chunks: int = 0, bin_scatter_div: int = 0,
-                 bin_stage: int = 0, _borrowed=None):
+                 bin_shape1: int = 0, bin_shape2: int = 0, _borrowed=None):
         self._owned = _borrowed is None
         if not self._owned:
             self._h = ctypes.c_void_p(_borrowed)
@@ -277,7 +282,8 @@ class Graph:
         cfg.stream = _stream(stream)
         cfg.bin_chunks = int(bin_chunks)
         cfg.bin_scatter_div = int(bin_scatter_div)
-        cfg.bin_stage = int(bin_stage)
+        cfg.bin_shape1 = int(bin_shape1)
+        cfg.bin_shape2 = int(bin_shape2)
         h = ctypes.c_void_p()
         _check(lib().dbg_create(ctypes.byref(cfg), ctypes.byref(h)), "dbg_create")
         self._h = h

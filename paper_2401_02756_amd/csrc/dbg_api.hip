@@ -32,7 +32,9 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     if (block % 64 || block > 1024) return DBG_E_INVAL;
     const uint32_t wpt = cfg.windows_per_thread ? cfg.windows_per_thread : 4;
     if (wpt > 64) return DBG_E_INVAL;
-    if (cfg.bin_chunks > dbgk::kMaxChunkTarget || cfg.bin_scatter_div > 64 || cfg.bin_stage > 2) return DBG_E_INVAL;
+    if (cfg.bin_chunks > dbgk::kMaxChunkTarget || cfg.bin_scatter_div > 64 || cfg.bin_shape1 > 3 ||
+        cfg.bin_shape2 > 3)
+        return DBG_E_INVAL;
 
     int device = cfg.device;
     if (device < 0 && hipGetDevice(&device) != hipSuccess) return DBG_E_DEVICE;
@@ -54,7 +56,8 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     g->shape.grid = dbgk::build_grid(device, block);
     g->bin_chunks = cfg.bin_chunks;
     g->bin_div = cfg.bin_scatter_div;
-    g->bin_stage = cfg.bin_stage;
+    g->bin_shape1 = cfg.bin_shape1;
+    g->bin_shape2 = cfg.bin_shape2;
     g->grid_wide = dbgk::build_grid_wide(device, block);
 
     int rc = DBG_OK;
@@ -315,8 +318,8 @@ int dbg_get_stats(dbg_graph *g, dbg_stats *out) {
     out->binned = g->binned ? 1u : 0u;
     out->bin_chunks = g->bin_chunks;
     out->bin_scatter_div = g->bin_div;
-    out->bin_stage = g->bin_stage;
-    out->bin_staged = g->pass.staged;
+    out->bin_shape1 = g->pass.shapes & 0xffu;
+    out->bin_shape2 = g->pass.shapes >> 8;
     return DBG_OK;
 }
 

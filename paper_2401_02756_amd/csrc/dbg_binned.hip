@@ -219,27 +219,27 @@ __device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, 
     return o ? (a << o) | (b >> (64 - o)) : a;
 }
 
-// Scatter tiles count with tagged counters: s_cnt[j] starts at j << 12, so
-// the value a record's fetch-add returns is its tag, bucket << 12 | rank, and
-// bucket j's count is s_cnt[j] - (j << 12) (at most the 4096 records of a
-// tile).  Records past the end of a tile add into one extra counter, so the
-// adds of a thread's records issue without branches.
+// Scatter tiles count with tagged counters: s_cnt[j] starts at j << rb, so
+// the value a record's fetch-add returns is its tag, bucket << rb | rank, and
+// bucket j's count is s_cnt[j] - (j << rb) (rb = 12 for tiles of 4096
+// records, 14 for 16384).  Records past the end of a tile add into one extra
+// counter, so the adds of a thread's records issue without branches.
 //
 // Exclusive prefix of the counts of s_cnt[0..n) in place (whole block): the
 // starts are left in s_cnt, and s_gbase[j] = gbase(j) - start.
 template <typename G>
-__device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, G gbase) {
+__device__ void bucket_starts(uint32_t *s_cnt, uint64_t *s_gbase, uint32_t n, uint32_t rb, G gbase) {
     const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
     const uint32_t j0 = threadIdx.x * per;
     uint64_t sum = 0;
     for (uint32_t q = 0; q < per; ++q)
-        if (j0 + q < n) sum += s_cnt[j0 + q] - ((j0 + q) << 12);
+        if (j0 + q < n) sum += s_cnt[j0 + q] - ((j0 + q) << rb);
     uint64_t total;
     uint64_t pre = block_exclusive_scan(sum, &total);
     for (uint32_t q = 0; q < per; ++q) {
         const uint32_t j = j0 + q;
         if (j < n) {
-            const uint32_t c = s_cnt[j] - (j << 12);
+            const uint32_t c = s_cnt[j] - (j << rb);
             s_cnt[j] = (uint32_t)pre;
             s_gbase[j] = gbase(j) - pre;
             pre += c;
@@ -268,7 +268,23 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 // global [f - cc, f), all inside the line holding f; a waiting record sits
 // at s_stg[j * L + (position mod L)].
 constexpr uint32_t kLineBytes = 128;
-constexpr uint32_t kStageBlock = 1024;  // threads of a staged scatter workgroup (one per CU when staging 713 runs)
+
+// Scatter shapes.  A plain scatter (512 threads, tiles of 4096 records)
+// stores each tile's runs as it sorts them; a staged one (1024 threads, one
+// workgroup per CU when it stages 713 runs) stores whole lines only; a big
+// one (1024 threads, tiles of 16384 records: four planning tiles, 128 KB of
+// LDS) stores runs as they come, four times longer than a plain tile's.
+enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2 };
+
+template <uint32_t SHAPE>
+struct ScatterShape {
+    static constexpr uint32_t block = SHAPE == kShapeTile ? 512u : 1024u;
+    static constexpr uint32_t tile = SHAPE == kShapeBig ? 16384u : 4096u;
+    static constexpr uint32_t per = tile / block;  // records per thread
+    static constexpr uint32_t rb = SHAPE == kShapeBig ? 14u : 12u;  // rank bits of a tag
+};
+constexpr uint32_t kStageBlock = ScatterShape<kShapeStaged>::block;
+constexpr uint32_t kBigTile = ScatterShape<kShapeBig>::tile;
 
 template <typename R>
 struct Lines {
@@ -313,7 +329,7 @@ __device__ void stage_starts(uint32_t *s_cnt, const uint64_t *s_front, const uin
     for (uint32_t q = 0; q < per; ++q) {
         const uint32_t j = j0 + q;
         if (j < n) {
-            const uint32_t c = s_cnt[j] - (j << 12);
+            const uint32_t c = s_cnt[j] - (j << 12);  // staged tiles: 4096 records
             const uint64_t f = s_front[j];
             sum += c | ((((f + c) >> S) - (f >> S)) << 32);
         }
@@ -387,12 +403,12 @@ __device__ void stage_flush(const uint64_t *s_front, const uint8_t *s_cc, const 
 // ---------------------------------------------------------------- plan
 
 // Per instance: its window range, pass-1 tiles and chunks, histogram and
-// bucket bases.  The chunk length (tiles) is max(1, floor(tiles / target))
+// bucket bases.  The chunk length (tiles) is max(min_chunk, floor(tiles / target))
 // over the whole launch; chunks never span instances.  An instance that
 // failed validation (or whose k-mer total would overflow a counter) gets no
 // tiles, so it produces no records.
 __global__ void k_bin_plan(const PassArgs *__restrict__ args, const Instance *inst, const uint64_t *ws,
-                           InstStatus *st, BinPlan *plan, BinTotals *tot, uint32_t target) {
+                           InstStatus *st, BinPlan *plan, BinTotals *tot, uint32_t target, uint32_t min_chunk) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t m = args->m;
     uint64_t all_tiles = 0;
@@ -406,7 +422,7 @@ __global__ void k_bin_plan(const PassArgs *__restrict__ args, const Instance *in
         const uint64_t wb = ws[in.read_begin], we = ws[in.read_end];
         if (!(e & kSkipMask) && we > wb) all_tiles += (we - wb + kBinTile - 1) / kBinTile;
     }
-    const uint64_t chunk = max<uint64_t>(1, all_tiles / max(target, 1u));
+    const uint64_t chunk = max<uint64_t>(min_chunk, all_tiles / max(target, 1u));
     uint64_t tiles = 0, chunks = 0, hist = 0, buckets = 0;
     for (uint32_t i = 0; i < m; ++i) {
         const Instance &in = inst[i];
@@ -463,9 +479,9 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 // Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max]
 // and s_rec[kBinTile] when scattering; the write-out recomputes each
 // record's bucket rather than keep it in LDS beside the record).
-__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1) {
+__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + 8 * rw * kBinTile;
+    if (scatter) b += align16(8 * d1_max) + 8 * rw * (big ? kBigTile : kBinTile);
     return b;
 }
 
@@ -482,10 +498,11 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
 // written once.  Scattering, s_gbase[j] holds the global position where the
 // chunk's run of bucket j continues: each tile sorts its records by bucket
 // in LDS, writes bucket j's records at s_gbase[j] on, and advances s_gbase[j]
-// by their number; STAGED, it stores whole lines only (line-staged scatters
-// above) and s_gbase[j] is the run's frontier throughout.
-template <bool SCATTER, uint32_t RW, bool STAGED = false>
-__global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((amdgpu_waves_per_eu(STAGED ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
+// by their number; staged, it stores whole lines only (line-staged scatters
+// above) and s_gbase[j] is the run's frontier throughout.  A big tile is
+// four consecutive planning tiles of the chunk (fewer at its end).
+template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile>
+__global__ __launch_bounds__(ScatterShape<SHAPE>::block) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -497,8 +514,11 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((am
                                                   const uint64_t *__restrict__ tile_read1,
                                                   uint32_t d1_max) {
     using R = typename RecOf<RW>::T;
-    constexpr uint32_t WPT = STAGED ? kBinTile / kStageBlock : kBinPerThread;
-    static_assert(WPT * (STAGED ? kStageBlock : kBinBlock) == kBinTile, "a tile is one window per thread slot");
+    using Sh = ScatterShape<SHAPE>;
+    constexpr bool STAGED = SHAPE == kShapeStaged;
+    constexpr uint32_t WPT = Sh::per, TILE = Sh::tile, RB = Sh::rb, TPS = TILE / kBinTile;
+    static_assert(WPT * Sh::block == TILE && TILE % kBinTile == 0, "a tile is one window per thread slot");
+    static_assert(SHAPE == kShapeTile || SCATTER, "counting uses plain tiles");
     __shared__ ReadStage S;
     __shared__ uint32_t s_nlines;
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -545,16 +565,17 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((am
         }
         {
             const uint64_t w0 = plan[i].w_begin + (tbeg + t) * kBinTile;
-            const uint32_t n_in = (uint32_t)(min(w0 + kBinTile, plan[i].w_end) - w0);
+            const uint64_t w_end = min(plan[i].w_begin + (tbeg + nt) * kBinTile, plan[i].w_end);  // the chunk's
+            const uint32_t n_in = (uint32_t)(min(w0 + TILE, w_end) - w0);
             if (SCATTER)
-                for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = j << 12;
+                for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = j << RB;
             stage_reads(S, ws, off, off0, tile_read1[plan[i].tile_base + tbeg + t], read_end);
 
             R rec[WPT];
-            uint32_t tag[WPT];  // scatter: bucket << 12 | rank (bucket d1: past the end)
+            uint32_t tag[WPT];  // scatter: bucket << RB | rank (bucket d1: past the end)
             const uint32_t j0 = tid * WPT;
 #pragma unroll
-            for (uint32_t q = 0; q < WPT; ++q) tag[q] = d1 << 12;
+            for (uint32_t q = 0; q < WPT; ++q) tag[q] = d1 << RB;
             if (j0 < n_in) {
                 uint64_t w = w0 + j0;
                 ReadCursor rp = first_read(S, ws, off, off0, read_end, w);
@@ -613,9 +634,9 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((am
                 __syncthreads();
 #pragma unroll
                 for (uint32_t q = 0; q < WPT; ++q) {
-                    const uint32_t bk = tag[q] >> 12;
+                    const uint32_t bk = tag[q] >> RB;
                     if (bk == d1) continue;  // past the tile's end
-                    s_rec[s_cnt[bk] + (tag[q] & 0xfffu)] = rec[q];
+                    s_rec[s_cnt[bk] + (tag[q] & ((1u << RB) - 1))] = rec[q];
                 }
                 __syncthreads();
                 stage_write<R>(s_lrun, s_pack, s_gbase, s_stg, s_rec, s_nlines, rec1);
@@ -625,13 +646,13 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((am
             } else if (SCATTER) {
             // s_gbase[j] becomes the global position of the tile's first record
             // of bucket j minus its position in the sorted tile
-            bucket_starts(s_cnt, s_gbase, d1, [&](uint32_t j) { return s_gbase[j]; });
+            bucket_starts(s_cnt, s_gbase, d1, RB, [&](uint32_t j) { return s_gbase[j]; });
             __syncthreads();
 #pragma unroll
             for (uint32_t q = 0; q < WPT; ++q) {
-                const uint32_t bk = tag[q] >> 12;
+                const uint32_t bk = tag[q] >> RB;
                 if (bk == d1) continue;  // past the tile's end
-                const uint32_t pos = s_cnt[bk] + (tag[q] & 0xfffu);
+                const uint32_t pos = s_cnt[bk] + (tag[q] & ((1u << RB) - 1));
                 s_rec[pos] = rec[q];
             }
             __syncthreads();
@@ -646,7 +667,8 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kBinBlock) __attribute__((am
             __syncthreads();
             }
         }
-        if (++t < nt) continue;
+        t += TPS;
+        if (t < nt) continue;
         // the chunk ends
         if (!SCATTER) {
             uint32_t *col = hist1 + plan[i].hist_base + c;
@@ -724,7 +746,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_flat_add(const uint64_t *len_ptr
 // ---------------------------------------------------------------- pass 2
 
 // Per level-1 bucket: its record range, pass-2 chunks and histogram base.
-// The chunk length (tiles of kRefTile records) is max(1, floor(tiles /
+// The chunk length (tiles of kRefTile records) is max(min_chunk, floor(tiles /
 // target)) over the launch; chunks never span buckets.
 __device__ __forceinline__ Bucket bucket_range(const PassArgs *__restrict__ args, const Instance *__restrict__ inst,
                                                const BinPlan *__restrict__ plan, const uint64_t *__restrict__ scan1,
@@ -746,7 +768,8 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
                                                      const Instance *__restrict__ inst,
                                                      const BinPlan *__restrict__ plan,
                                                      const uint64_t *__restrict__ scan1,
-                                                     BinTotals *tot, Bucket *__restrict__ buckets, uint32_t target) {
+                                                     BinTotals *tot, Bucket *__restrict__ buckets, uint32_t target,
+                                                     uint32_t min_chunk) {
     const uint64_t G = tot->buckets;
     // tiles over all buckets, for the chunk length
     uint64_t my_tiles = 0;
@@ -754,7 +777,7 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
         my_tiles += (bucket_range(args, inst, plan, scan1, g).size + kRefTile - 1) / kRefTile;
     uint64_t all_tiles;
     (void)block_exclusive_scan(my_tiles, &all_tiles);
-    const uint64_t chunk = max<uint64_t>(1, all_tiles / max(target, 1u));
+    const uint64_t chunk = max<uint64_t>(min_chunk, all_tiles / max(target, 1u));
     uint64_t carry_c = 0, carry_h = 0;
     for (uint64_t base = 0; base < G; base += blockDim.x) {
         const uint64_t g = base + threadIdx.x;
@@ -787,11 +810,11 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 }
 
 // Dynamic LDS of the pass-2 kernels: s_cnt[fan_max] (+ s_gbase[fan_max],
-// s_rec[kRefTile] and, for one-word records, s_child[kRefTile] when
-// scattering).
-__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1) {
+// s_rec[tile] and, for one-word records in plain tiles, s_child[kRefTile]
+// when scattering).
+__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (fan_max + 1));
-    if (scatter) b += align16(8 * fan_max) + 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0);
+    if (scatter) b += align16(8 * fan_max) + (big ? 8 * rw * kBigTile : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
     return b;
 }
 
@@ -837,24 +860,29 @@ __device__ __forceinline__ bool refine_has(uint32_t n, uint32_t it) {
 // next tile's records (in this chunk or the next one) are loaded while this
 // tile is written.  Counting, a chunk's histogram accumulates in LDS over its
 // tiles; scattering, s_gbase[j] holds where the chunk's run of segment j
-// continues, as in pass 1 (STAGED: whole lines only, 1024 threads).
-template <bool SCATTER, uint32_t RW, bool STAGED = false>
-__global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(const BinTotals *__restrict__ tot,
+// continues, as in pass 1 (staged: whole lines only; big: tiles of 16384
+// records).
+template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile>
+__global__ __launch_bounds__(ScatterShape<SHAPE>::block) void k_refine(const BinTotals *__restrict__ tot,
                                                      const RefChunk *__restrict__ chunk2,
                                                      const uint64_t *__restrict__ rec1w,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
                                                      uint64_t *__restrict__ rec2w, uint32_t fan_max) {
     using R = typename RecOf<RW>::T;
-    constexpr uint32_t PT = STAGED ? kRefTile / kStageBlock : kRefPerThread;
-    static_assert(PT * (STAGED ? kStageBlock : kRefBlock) == kRefTile && PT % 2 == 0, "tile shape");
+    using Sh = ScatterShape<SHAPE>;
+    constexpr bool STAGED = SHAPE == kShapeStaged;
+    constexpr bool CHILD = RW == 1 && SHAPE == kShapeTile;  // segments kept in s_child
+    constexpr uint32_t PT = Sh::per, TILE = Sh::tile, RB = Sh::rb;
+    static_assert(PT * Sh::block == TILE && PT % 2 == 0, "tile shape");
+    static_assert(SHAPE == kShapeTile || SCATTER, "counting uses plain tiles");
     __shared__ uint32_t s_nlines;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     const StageLayout lay = stage_layout<R>(fan_max, kRefTile);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
     uint64_t *s_gbase = reinterpret_cast<uint64_t *>(s_dyn + align16(4 * (fan_max + 1)));
     R *s_rec = reinterpret_cast<R *>(s_dyn + align16(4 * (fan_max + 1)) + align16(8 * fan_max));  // 16-byte aligned
-    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);  // RW = 1, not STAGED
+    uint16_t *s_child = reinterpret_cast<uint16_t *>(s_rec + kRefTile);  // CHILD only
     R *s_stg = reinterpret_cast<R *>(s_dyn + lay.stg);  // STAGED only, from here on
     uint32_t *s_pack = reinterpret_cast<uint32_t *>(s_dyn + lay.pack);
     uint8_t *s_cc = reinterpret_cast<uint8_t *>(s_dyn + lay.cc);
@@ -866,7 +894,7 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(con
     if (!xt.valid()) return;
     RefChunk C = chunk2[xt.next];
     R rec[PT];
-    refine_load(C.r0, (uint32_t)min<uint64_t>(C.n, kRefTile), rec1, rec);
+    refine_load(C.r0, (uint32_t)min<uint64_t>(C.n, TILE), rec1, rec);
     for (;;) {
         xt.advance();
         const bool more = xt.valid();
@@ -881,17 +909,17 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(con
                 if (STAGED) s_cc[j] = 0;
             }
         }
-        for (uint64_t t0 = 0; t0 < C.n; t0 += kRefTile) {
-            const uint32_t n = (uint32_t)min<uint64_t>(kRefTile, C.n - t0);
+        for (uint64_t t0 = 0; t0 < C.n; t0 += TILE) {
+            const uint32_t n = (uint32_t)min<uint64_t>(TILE, C.n - t0);
             // the tile after this one: in this chunk, else the next chunk's first
-            const bool next_here = t0 + kRefTile < C.n;
-            const uint64_t nr0 = next_here ? C.r0 + t0 + kRefTile : N.r0;
-            const uint32_t nn = next_here ? (uint32_t)min<uint64_t>(kRefTile, C.n - t0 - kRefTile)
-                                          : (more ? (uint32_t)min<uint64_t>(kRefTile, N.n) : 0u);
+            const bool next_here = t0 + TILE < C.n;
+            const uint64_t nr0 = next_here ? C.r0 + t0 + TILE : N.r0;
+            const uint32_t nn = next_here ? (uint32_t)min<uint64_t>(TILE, C.n - t0 - TILE)
+                                          : (more ? (uint32_t)min<uint64_t>(TILE, N.n) : 0u);
             if (SCATTER)
-                for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = j << 12;
+                for (uint32_t j = tid; j <= fan; j += blockDim.x) s_cnt[j] = j << RB;
             __syncthreads();
-            uint32_t tag[PT];  // scatter: segment << 12 | rank (segment fan: past the end)
+            uint32_t tag[PT];  // scatter: segment << RB | rank (segment fan: past the end)
 #pragma unroll
             for (uint32_t it = 0; it < PT; ++it) {
                 const uint32_t c =
@@ -911,9 +939,9 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(con
                 __syncthreads();
 #pragma unroll
                 for (uint32_t it = 0; it < PT; ++it) {
-                    const uint32_t c = tag[it] >> 12;
+                    const uint32_t c = tag[it] >> RB;
                     if (c == fan) continue;  // past the tile's end
-                    s_rec[s_cnt[c] + (tag[it] & 0xfffu)] = rec[it];
+                    s_rec[s_cnt[c] + (tag[it] & ((1u << RB) - 1))] = rec[it];
                 }
                 if (nn) refine_load(nr0, nn, rec1, rec);
                 __syncthreads();
@@ -923,21 +951,21 @@ __global__ __launch_bounds__(STAGED ? kStageBlock : kRefBlock) void k_refine(con
                 __syncthreads();  // before the next tile resets the counters
                 continue;
             }
-            bucket_starts(s_cnt, s_gbase, fan, [&](uint32_t j) { return s_gbase[j]; });
+            bucket_starts(s_cnt, s_gbase, fan, RB, [&](uint32_t j) { return s_gbase[j]; });
             __syncthreads();
 #pragma unroll
             for (uint32_t it = 0; it < PT; ++it) {
-                const uint32_t c = tag[it] >> 12;
+                const uint32_t c = tag[it] >> RB;
                 if (c == fan) continue;  // past the tile's end
-                const uint32_t pos = s_cnt[c] + (tag[it] & 0xfffu);
+                const uint32_t pos = s_cnt[c] + (tag[it] & ((1u << RB) - 1));
                 s_rec[pos] = rec[it];
-                if (RW == 1) s_child[pos] = (uint16_t)c;
+                if (CHILD) s_child[pos] = (uint16_t)c;
             }
             if (nn) refine_load(nr0, nn, rec1, rec);
             __syncthreads();
             for (uint32_t j = tid; j < n; j += blockDim.x) {
                 const R r = s_rec[j];
-                const uint32_t c = RW == 1 ? s_child[j] : child_of(image_top(RecOf<RW>::head(r) >> 3), d1, fan);
+                const uint32_t c = CHILD ? s_child[j] : child_of(image_top(RecOf<RW>::head(r) >> 3), d1, fan);
                 rec2[s_gbase[c] + j] = r;
             }
             __syncthreads();
@@ -1384,6 +1412,15 @@ uint32_t occupancy_grid(K kernel, int device, uint32_t block, uint64_t cap, uint
     return (uint32_t)std::max<uint64_t>(1, g);
 }
 
+// Dynamic LDS of a scatter of `shape` over n runs (pass 1: first, else pass 2).
+template <typename R>
+uint32_t scatter_lds_bytes(uint32_t shape, bool first, uint32_t n) {
+    constexpr uint32_t rw = sizeof(R) / 8;
+    if (shape == kShapeStaged) return stage_layout<R>(n, first ? kBinTile : kRefTile).bytes;
+    const bool big = shape == kShapeBig;
+    return first ? bin_lds_bytes(n, true, rw, big) : ref_lds_bytes(n, true, rw, big);
+}
+
 // The binned pass for records of RW words (enqueue only).
 template <uint32_t RW>
 hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint64_t *packed, const uint64_t *ws,
@@ -1392,7 +1429,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     // pass 1
     using R = typename RecOf<RW>::T;
     const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW);
-    const uint32_t lb1 = bb.staged1 ? stage_layout<R>(bb.d1_max, kBinTile).bytes : bin_lds_bytes(bb.d1_max, true, RW);
+    const uint32_t lb1 = scatter_lds_bytes<R>(bb.shape1, true, bb.d1_max);
     const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
     hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
                        bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
@@ -1405,18 +1442,28 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb1, len1, bb.scan1);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
     if (marks) (void)hipEventRecord(marks[2], s);
-    if (bb.staged1)
-        hipLaunchKernelGGL((k_bin<true, RW, true>), dim3(g1s), dim3(kStageBlock), lb1, s, args, inst, packed, ws,
-                           bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
-    else
-        hipLaunchKernelGGL((k_bin<true, RW>), dim3(g1s), dim3(kBinBlock), lb1, s, args, inst, packed, ws, bb.plan,
-                           bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+#define DBG_LAUNCH_BIN(SH)                                                                                      \
+    hipLaunchKernelGGL((k_bin<true, RW, SH>), dim3(g1s), dim3(ScatterShape<SH>::block), lb1, s, args, inst, packed, \
+                       ws, bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max)
+    bool launched = false;
+    if (bb.shape1 == kShapeStaged) {
+        DBG_LAUNCH_BIN(kShapeStaged);
+        launched = true;
+    }
+    if constexpr (RW == 1) {  // big tiles of 16-byte records do not fit a workgroup's LDS
+        if (bb.shape1 == kShapeBig) {
+            DBG_LAUNCH_BIN(kShapeBig);
+            launched = true;
+        }
+    }
+    if (!launched) DBG_LAUNCH_BIN(kShapeTile);
+#undef DBG_LAUNCH_BIN
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[3], s);
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
-                       bb.buckets, bb.target2);
+                       bb.buckets, bb.target2, bb.shape2 == kShapeBig ? kBigTile / kRefTile : 1u);
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
         hipLaunchKernelGGL(k_chunk_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.chunk2,
@@ -1424,8 +1471,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     }
     if (marks) (void)hipEventRecord(marks[4], s);
     const uint32_t lr0 = ref_lds_bytes(bb.fan_max, false, RW);
-    const uint32_t lr1 =
-        bb.staged2 ? stage_layout<R>(bb.fan_max, kRefTile).bytes : ref_lds_bytes(bb.fan_max, true, RW);
+    const uint32_t lr1 = scatter_lds_bytes<R>(bb.shape2, false, bb.fan_max);
     const uint32_t g2c = bb.grid_ref_count, g2s = bb.grid_ref_scatter;
     hipLaunchKernelGGL((k_refine<false, RW>), dim3(g2c), dim3(kRefBlock), lr0, s, bb.totals, bb.chunk2, bb.rec1,
                        bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
@@ -1438,12 +1484,22 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_partials, dim3(1), dim3(1024), 0, s, bb.partials, nb2, len2, bb.scan2);
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
     if (marks) (void)hipEventRecord(marks[6], s);
-    if (bb.staged2)
-        hipLaunchKernelGGL((k_refine<true, RW, true>), dim3(g2s), dim3(kStageBlock), lr1, s, bb.totals, bb.chunk2,
-                           bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
-    else
-        hipLaunchKernelGGL((k_refine<true, RW>), dim3(g2s), dim3(kRefBlock), lr1, s, bb.totals, bb.chunk2, bb.rec1,
-                           bb.hist2, bb.scan2, bb.rec2, bb.fan_max);
+#define DBG_LAUNCH_REF(SH)                                                                                   \
+    hipLaunchKernelGGL((k_refine<true, RW, SH>), dim3(g2s), dim3(ScatterShape<SH>::block), lr1, s, bb.totals, \
+                       bb.chunk2, bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max)
+    launched = false;
+    if (bb.shape2 == kShapeStaged) {
+        DBG_LAUNCH_REF(kShapeStaged);
+        launched = true;
+    }
+    if constexpr (RW == 1) {  // big tiles of 16-byte records do not fit a workgroup's LDS
+        if (bb.shape2 == kShapeBig) {
+            DBG_LAUNCH_REF(kShapeBig);
+            launched = true;
+        }
+    }
+    if (!launched) DBG_LAUNCH_REF(kShapeTile);
+#undef DBG_LAUNCH_REF
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[7], s);
 
@@ -1476,7 +1532,8 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
                          int device, bool stats, hipStream_t s, hipEvent_t *marks) {
     (void)device;
     hipError_t e;
-    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1);
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1,
+                       bb.shape1 == kShapeBig ? kBigTile / kBinTile : 1u);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
@@ -1509,38 +1566,67 @@ bool stage_fits(K kernel, int device, uint32_t dyn) {
 template <uint32_t RW>
 void grids_for(int device, BinBuffers &bb) {
     using R = typename RecOf<RW>::T;
-    // Staging holds one LDS line per run, so with many runs a staged scatter
-    // runs one 1024-thread workgroup per CU, and its waves stall together at
-    // every barrier.  It pays where runs are shortest: the second scatter
-    // when a bucket spans more than kScatterWide segments (713 at 508 k
-    // segments: 12.8 -> 9.2 ms); the first scatter, which also decodes
-    // windows, and scatters of fewer runs measured slower staged (bacterial
-    // scale, 212 runs: 0.51 -> 1.0 ms and 0.53 -> 0.69 ms).  The line
-    // numbers of a tile must fit s_pack's 11 bits.
-    const StageLayout st1 = stage_layout<R>(bb.d1_max, kBinTile), st2 = stage_layout<R>(bb.fan_max, kRefTile);
-    // stage_mode 2 stages every scatter whose staging fits.
-    bb.staged1 = bb.stage_mode == 2 && kBinTile / Lines<R>::L + bb.d1_max < 2048 &&
-                 stage_fits(k_bin<true, RW, true>, device, st1.bytes);
-    bb.staged2 = bb.stage_mode != 1 && (bb.stage_mode == 2 || bb.fan_max > kScatterWide) &&
-                 kRefTile / Lines<R>::L + bb.fan_max < 2048 && stage_fits(k_refine<true, RW, true>, device, st2.bytes);
+    // Scatter shapes (dbg_config bin_shape1/2: 0 automatic, 1 plain tiles,
+    // 2 staged, 3 big tiles; a shape whose LDS does not fit falls back to
+    // plain tiles).  Staging holds one LDS line per run, so with many runs
+    // a staged scatter runs one 1024-thread workgroup per CU, and it
+    // executes about twice the instructions of a plain one per record.  Big
+    // tiles make a tile's runs four times longer (about 23 records at 713
+    // runs), at one workgroup per CU as well.  Measured at 508 k segments
+    // (713 runs a scatter): plain 11.1 and 11.9 ms, staged 15.5 and 9.1 ms,
+    // big 9.5 and 8.1 ms for the first and second scatter; at 44.7 k
+    // segments (212 runs) plain 0.52 and 0.61 ms, big 0.62 and 0.51 ms (the
+    // first scatter also decodes windows, four planning tiles per thread
+    // group at once).  Automatic: the second scatter takes big tiles, the
+    // first beyond kScatterWide runs.  A big tile needs chunks of at least
+    // four planning tiles (the plan kernels' min_chunk).  The line numbers
+    // of a staged tile must fit s_pack's 11 bits.
+    const auto pick = [&](uint32_t req, bool first, uint32_t n) -> uint32_t {
+        uint32_t sh = req == 1 ? kShapeTile : req == 2 ? kShapeStaged : req == 3 ? kShapeBig
+                    : !first || n > kScatterWide ? kShapeBig : kShapeTile;
+        const uint32_t tile = first ? kBinTile : kRefTile;
+        if (sh == kShapeStaged && !(tile / Lines<R>::L + n < 2048 &&
+                                    (first ? stage_fits(k_bin<true, RW, kShapeStaged>, device,
+                                                        scatter_lds_bytes<R>(sh, first, n))
+                                           : stage_fits(k_refine<true, RW, kShapeStaged>, device,
+                                                        scatter_lds_bytes<R>(sh, first, n)))))
+            sh = kShapeTile;
+        if constexpr (RW == 1) {
+            if (sh == kShapeBig &&
+                !(first ? stage_fits(k_bin<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))
+                        : stage_fits(k_refine<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))))
+                sh = kShapeTile;
+        } else if (sh == kShapeBig) {
+            sh = kShapeTile;  // 16384 records of 16 bytes: more than a workgroup's LDS
+        }
+        return sh;
+    };
+    bb.shape1 = pick(bb.shape_req1, true, bb.d1_max);
+    bb.shape2 = pick(bb.shape_req2, false, bb.fan_max);
+    const uint32_t l1 = scatter_lds_bytes<R>(bb.shape1, true, bb.d1_max);
+    const uint32_t l2 = scatter_lds_bytes<R>(bb.shape2, false, bb.fan_max);
     bb.grid_bin_count =
         occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
-    bb.grid_bin_scatter =
-        bb.staged1 ? occupancy_grid(k_bin<true, RW, true>, device, kStageBlock, bb.chunks1_cap, st1.bytes)
-                   : occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, true, RW));
+    bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, l1);
+    if (bb.shape1 == kShapeStaged)
+        bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks1_cap, l1);
+    if constexpr (RW == 1)
+        if (bb.shape1 == kShapeBig)
+            bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeBig>, device, kStageBlock, bb.chunks1_cap, l1);
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
-    // Unstaged, a scatter tile writes one short run per segment when a bucket
-    // has many segments; the partial lines of the workgroups in flight on an
-    // XCD then outgrow its L2 before the next tiles complete them, and the
-    // pass-2 scatter writes faster on part of its resident grid.
+    // Plain tiles write one short run per segment when a bucket has many
+    // segments; the partial lines of the workgroups in flight on an XCD then
+    // outgrow its L2 before the next tiles complete them, and the pass-2
+    // scatter writes faster on part of its resident grid.
     const uint32_t div = bb.scatter_div ? bb.scatter_div : (bb.fan_max > kScatterWide ? 2u : 1u);
     bb.grid_ref_scatter =
-        bb.staged2
-            ? occupancy_grid(k_refine<true, RW, true>, device, kStageBlock, bb.chunks2_cap, st2.bytes)
-            : std::max<uint32_t>(8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap,
-                                                   ref_lds_bytes(bb.fan_max, true, RW)) /
-                                        div);
+        std::max<uint32_t>(8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap, l2) / div);
+    if (bb.shape2 == kShapeStaged)
+        bb.grid_ref_scatter = occupancy_grid(k_refine<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks2_cap, l2);
+    if constexpr (RW == 1)
+        if (bb.shape2 == kShapeBig)
+            bb.grid_ref_scatter = occupancy_grid(k_refine<true, RW, kShapeBig>, device, kStageBlock, bb.chunks2_cap, l2);
     bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2, false>, device, kReduceBlock, bb.parts_cap, 0)
                    : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1, false>, device, kReduceBlock, bb.parts_cap, 0)
                                          : occupancy_grid(k_reduce<3, 1, false>, device, kReduceBlock, bb.parts_cap, 0);

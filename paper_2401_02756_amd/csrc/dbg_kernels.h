@@ -168,7 +168,7 @@ constexpr uint32_t kRefPerThread = 8;
 constexpr uint32_t kRefTile = kRefBlock * kRefPerThread;  // records per pass-2 tile
 constexpr uint32_t kReduceBlock = 512;
 constexpr uint32_t kMaxChunkTarget = 16384;  // chunks a pass aims for, at most
-constexpr uint32_t kChunksPerGroup = 16;     // default target: chunks per resident workgroup
+constexpr uint32_t kChunksPerGroup = 32;     // default target: chunks per resident workgroup
 
 struct BinPlan {        // per instance
     uint64_t w_begin, w_end;  // its windows
@@ -229,12 +229,13 @@ struct BinBuffers {     // device scratch of one binned pass
     // launch shape (set before binned_grids): chunks per resident scatter
     // workgroup (0: kChunksPerGroup), the divisor of the pass-2 scatter's
     // resident grid when it stores runs as they come (0: automatic, 2 when a
-    // bucket has more than 384 segments), and the staging of scatter lines
-    // in LDS (dbg_config bin_stage: 0 automatic, 1 never, 2 wherever it fits)
-    uint32_t chunks_per_group, scatter_div, stage_mode;
-    // whether each scatter stages whole lines in LDS (binned_grids decides:
-    // when its staging fits in a workgroup's LDS)
-    uint32_t staged1, staged2;
+    // bucket has more than 384 segments), and the requested scatter shapes
+    // (dbg_config bin_shape1/2: 0 automatic, 1 plain tiles, 2 staged lines,
+    // 3 big tiles)
+    uint32_t chunks_per_group, scatter_div, shape_req1, shape_req2;
+    // the scatter shapes in use (binned_grids decides: kShape* of
+    // dbg_binned.hip, 0 plain tiles, 1 staged, 2 big tiles)
+    uint32_t shape1, shape2;
 };
 
 // Fill the grid sizes of bb from occupancy and its capacities.

@@ -141,7 +141,7 @@ inline uint64_t size_class(uint64_t x, uint64_t floor) {
 struct PassKey {
     int binned = 0;
     int stats = 0;  // kernels that keep probe statistics
-    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (dbg_config)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_shape1 = 0, bin_shape2 = 0;  // binned launch shape (dbg_config)
     int single = 0;
     int wide = 0;  // one instance with 32 < k <= 64, direct build
     uint32_t rw = 1;  // binned record words (2: long keys)
@@ -151,7 +151,7 @@ struct PassKey {
     dbgk::BuildShape shape{};
     bool operator==(const PassKey &o) const {
         return binned == o.binned && stats == o.stats && bin_chunks == o.bin_chunks && bin_div == o.bin_div &&
-               bin_stage == o.bin_stage &&
+               bin_shape1 == o.bin_shape1 && bin_shape2 == o.bin_shape2 &&
                single == o.single && wide == o.wide && rw == o.rw && ew == o.ew &&
                m_cap == o.m_cap &&
                d1_cap == o.d1_cap && fan_cap == o.fan_cap && n_cap == o.n_cap && len_cap == o.len_cap &&
@@ -250,7 +250,7 @@ struct PassSizes {
 struct PassOpts {
     uint64_t *stats = nullptr;
     uint32_t test_hash = 0;
-    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (0: defaults)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_shape1 = 0, bin_shape2 = 0;  // binned launch shape (0: defaults)
 };
 
 inline PassOpts opts_of(const dbg_graph *g);
@@ -311,7 +311,7 @@ struct Pass {
     };
     std::vector<Cached> graphs;
     uint64_t captures = 0, replays = 0;
-    uint32_t staged = 0;  // the last binned pass's staged scatters: bit 0 pass 1, bit 1 pass 2
+    uint32_t shapes = 0;  // scatter shapes of the last binned pass, as dbg_stats reports them (shape + 1)
 
     hipError_t init() {
         hipError_t e = hipEventCreate(&ev_a);
@@ -407,13 +407,14 @@ struct Pass {
                 bb.grid_reduce = g.second.grid_reduce;
                 bb.target1 = g.second.target1;
                 bb.target2 = g.second.target2;
-                bb.staged1 = g.second.staged1;
-                bb.staged2 = g.second.staged2;
+                bb.shape1 = g.second.shape1;
+                bb.shape2 = g.second.shape2;
                 return;
             }
         bb.chunks_per_group = k.bin_chunks;
         bb.scatter_div = k.bin_div;
-        bb.stage_mode = k.bin_stage;
+        bb.shape_req1 = k.bin_shape1;
+        bb.shape_req2 = k.bin_shape2;
         dbgk::binned_grids(device, bb);
         if (grid_memo.size() > 16) grid_memo.clear();
         grid_memo.emplace_back(k, bb);
@@ -491,7 +492,8 @@ struct Pass {
         k.stats = o.stats != nullptr;
         k.bin_chunks = o.bin_chunks;
         k.bin_div = o.bin_div;
-        k.bin_stage = o.bin_stage;
+        k.bin_shape1 = o.bin_shape1;
+        k.bin_shape2 = o.bin_shape2;
         dbgk::BinBuffers bb{};
         if (binned) bin_caps(k, bb);
         const PassSizes z(k, bb);
@@ -503,7 +505,7 @@ struct Pass {
             return e;
         if (binned) {
             binned_grids(k, device, bb);
-            staged = bb.staged1 | bb.staged2 << 1;
+            shapes = (bb.shape1 + 1) | (bb.shape2 + 1) << 8;
         }
         fill_args(*host_args(), k, z, mm, hi, d_reads, len, d_off, n, check_ends, xkeys, xcounts, xcap, o);
 
@@ -588,7 +590,7 @@ struct dbg_graph {
     uint64_t expected = 0, cap_req = 0;
     dbgk::BuildShape shape{256, 4, 0, 0};
     uint32_t grid_wide = 0;  // persistent grid of the long-k build
-    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;  // binned launch shape (dbg_config)
+    uint32_t bin_chunks = 0, bin_div = 0, bin_shape1 = 0, bin_shape2 = 0;  // binned launch shape (dbg_config)
 
     uint64_t cap = 0;
     uint32_t ew = 3;
@@ -631,7 +633,8 @@ inline PassOpts opts_of(const dbg_graph *g) {
     o.test_hash = (g->flags & DBG_F_TEST_HASH) ? 1u : 0u;
     o.bin_chunks = g->bin_chunks;
     o.bin_div = g->bin_div;
-    o.bin_stage = g->bin_stage;
+    o.bin_shape1 = g->bin_shape1;
+    o.bin_shape2 = g->bin_shape2;
     return o;
 }
 

@@ -144,7 +144,8 @@ extern "C" int dbg_build_device_static(dbg_graph *g, const uint8_t *d_reads, uin
         bb.chunk2 = reinterpret_cast<dbgk::RefChunk *>(base + o_tile2);
         bb.chunks_per_group = g->bin_chunks;
         bb.scatter_div = g->bin_div;
-        bb.stage_mode = g->bin_stage;
+        bb.shape_req1 = g->bin_shape1;
+        bb.shape_req2 = g->bin_shape2;
         dbgk::binned_grids(g->device, bb);
     }
     dbgk::PassArgs a;

@@ -1,8 +1,8 @@
 // Autotuner: times complete builds of a calibration input under candidate
 // configurations and keeps the fastest.  The search is coordinate-wise:
 // binned mode over load factors, then over its partition launch shape
-// (chunks per workgroup, line staging on or off, then the second scatter's
-// grid divisor); then
+// (chunks per workgroup, the scatter shapes, then the second scatter's grid
+// divisor); then
 // (unless binned mode is already far ahead) the direct build over launch
 // shapes, wavefront merging and load factors.  Choices are cached in the
 // process and in a cache file keyed by device model.
@@ -24,14 +24,16 @@ struct Cand {
     double lf;
     uint32_t block, wpt;
     bool merge;
-    uint32_t bin_chunks = 0, bin_div = 0, bin_stage = 0;
+    uint32_t bin_chunks = 0, bin_div = 0, bin_shape1 = 0, bin_shape2 = 0;
 };
 
 // The axes of the search.
 constexpr double kLoadFactors[] = {0.5, 0.4, 0.6, 0.7};
-constexpr uint32_t kBinChunks[] = {0, 4, 8, 32, 64};  // 0: the default, 16
+constexpr uint32_t kBinChunks[] = {0, 4, 8, 16, 64};  // 0: the default, 32
 constexpr uint32_t kBinDivs[] = {0, 1, 2, 4};         // 0: automatic
-constexpr uint32_t kBinStages[] = {0, 1, 2};          // line staging: 0 automatic, 1 never, 2 wherever it fits
+// scatter shapes, first and second (dbg_config bin_shape1/2): automatic,
+// plain tiles, staged lines, big tiles, big tiles then staged lines
+constexpr uint32_t kBinShapes[][2] = {{0, 0}, {1, 1}, {2, 2}, {3, 3}, {3, 2}};
 constexpr uint32_t kBlocks[] = {256, 512, 1024};
 constexpr uint32_t kWpts[] = {2, 4, 8};
 
@@ -75,7 +77,8 @@ Outcome time_candidate(const Workload &w, const Cand &c) {
         cfg.windows_per_thread = c.wpt;
         cfg.bin_chunks = c.bin_chunks;
         cfg.bin_scatter_div = c.bin_div;
-        cfg.bin_stage = c.bin_stage;
+        cfg.bin_shape1 = c.bin_shape1;
+        cfg.bin_shape2 = c.bin_shape2;
         o.rc = dbg_create(&cfg, &gs[i]);
     }
     std::vector<int32_t> st(w.m, DBG_OK);
@@ -123,7 +126,7 @@ std::string cache_path() {
 }
 
 // Read the cache file into the process cache (under g_tune_mu).  Lines are
-// "key<TAB>lf flags block wpt bin_chunks bin_div bin_stage best_ms default_ms"; later
+// "key<TAB>lf flags block wpt bin_chunks bin_div shape1 shape2 best_ms default_ms"; later
 // lines of a key override earlier ones; malformed lines are skipped.
 void load_cache_file() {
     g_file_loaded = true;
@@ -137,10 +140,10 @@ void load_cache_file() {
         if (!tab) continue;
         *tab = 0;
         dbg_tuning t{};
-        unsigned flags = 0, block = 0, wpt = 0, chunks = 0, div = 0, stage = 0;
-        if (std::sscanf(tab + 1, "%lf %u %u %u %u %u %u %lf %lf", &t.load_factor, &flags, &block, &wpt, &chunks,
-                        &div, &stage, &t.best_ms, &t.default_ms) != 9 ||
-            stage > 2)
+        unsigned flags = 0, block = 0, wpt = 0, chunks = 0, div = 0, sh1 = 0, sh2 = 0;
+        if (std::sscanf(tab + 1, "%lf %u %u %u %u %u %u %u %lf %lf", &t.load_factor, &flags, &block, &wpt, &chunks,
+                        &div, &sh1, &sh2, &t.best_ms, &t.default_ms) != 10 ||
+            sh1 > 3 || sh2 > 3)
             continue;
         if (!(t.load_factor > 0 && t.load_factor < 1) || (flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)))
             continue;
@@ -149,7 +152,8 @@ void load_cache_file() {
         t.windows_per_thread = wpt;
         t.bin_chunks = chunks;
         t.bin_scatter_div = div;
-        t.bin_stage = stage;
+        t.bin_shape1 = sh1;
+        t.bin_shape2 = sh2;
         t.from_cache = 2;
         g_tune_cache[line] = t;
     }
@@ -168,8 +172,9 @@ void save_cache_line(const std::string &key, const dbg_tuning &t) {
         }
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%.6g %u %u %u %u %u %u %.6f %.6f\n", key.c_str(), t.load_factor, t.flags, t.block_size,
-                 t.windows_per_thread, t.bin_chunks, t.bin_scatter_div, t.bin_stage, t.best_ms, t.default_ms);
+    std::fprintf(f, "%s\t%.6g %u %u %u %u %u %u %u %.6f %.6f\n", key.c_str(), t.load_factor, t.flags, t.block_size,
+                 t.windows_per_thread, t.bin_chunks, t.bin_scatter_div, t.bin_shape1, t.bin_shape2, t.best_ms,
+                 t.default_ms);
     std::fclose(f);
 }
 
@@ -198,7 +203,7 @@ std::string cache_key(const Workload &w) {
         ev += w.expected ? w.expected[i] : 0;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "v2/%u/%llx/%d/%d/%d/%x", w.m, (unsigned long long)kmask,
+    std::snprintf(buf, sizeof buf, "v3/%u/%llx/%d/%d/%d/%x", w.m, (unsigned long long)kmask,
                   size_bucket(w.reads_len), size_bucket(w.read_begin[w.m]), size_bucket(ev), w.keep_flags);
     return device_model(w.device) + "/" + buf;
 }
@@ -214,7 +219,8 @@ void dbg_config_apply_tuning(dbg_config *cfg, const dbg_tuning *t) {
     cfg->windows_per_thread = t->windows_per_thread;
     cfg->bin_chunks = t->bin_chunks;
     cfg->bin_scatter_div = t->bin_scatter_div;
-    cfg->bin_stage = t->bin_stage;
+    cfg->bin_shape1 = t->bin_shape1;
+    cfg->bin_shape2 = t->bin_shape2;
     cfg->flags = (cfg->flags & ~(uint32_t)(DBG_F_BINNED | DBG_F_MERGE)) | (t->flags & (DBG_F_BINNED | DBG_F_MERGE));
 }
 
@@ -276,7 +282,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             best.windows_per_thread = c.binned ? 0 : c.wpt;
             best.bin_chunks = c.binned ? c.bin_chunks : 0;
             best.bin_scatter_div = c.binned ? c.bin_div : 0;
-            best.bin_stage = c.binned ? c.bin_stage : 0;
+            best.bin_shape1 = c.binned ? c.bin_shape1 : 0;
+            best.bin_shape2 = c.binned ? c.bin_shape2 : 0;
         }
         return o.ms;
     };
@@ -298,10 +305,11 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
             const double ms = consider(c);
             if (ms < binned_best) binned_best = ms, bc = c;
         }
-        for (uint32_t sg : kBinStages) {
-            if (sg == 0) continue;
+        for (const auto &sh : kBinShapes) {
+            if (sh[0] == 0 && sh[1] == 0) continue;
             Cand c = bc;
-            c.bin_stage = sg;
+            c.bin_shape1 = sh[0];
+            c.bin_shape2 = sh[1];
             const double ms = consider(c);
             if (ms < binned_best) binned_best = ms, bc = c;
         }
@@ -357,7 +365,8 @@ int dbg_autotune(int32_t device, uint32_t m, const uint64_t *read_begin, const u
 int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t *n) {
     if (!n || (cap && !out)) return DBG_E_INVAL;
     uint32_t k = 0;
-    auto put = [&](double lf, uint32_t flags, uint32_t block, uint32_t wpt, uint32_t ch, uint32_t dv, uint32_t sg) {
+    auto put = [&](double lf, uint32_t flags, uint32_t block, uint32_t wpt, uint32_t ch, uint32_t dv, uint32_t s1,
+                   uint32_t s2) {
         if (k < cap) {
             dbg_tuning t{};
             t.load_factor = lf;
@@ -366,7 +375,8 @@ int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t 
             t.windows_per_thread = wpt;
             t.bin_chunks = ch;
             t.bin_scatter_div = dv;
-            t.bin_stage = sg;
+            t.bin_shape1 = s1;
+            t.bin_shape2 = s2;
             out[k] = t;
         }
         ++k;
@@ -374,12 +384,12 @@ int dbg_autotune_space(uint32_t binned, dbg_tuning *out, uint32_t cap, uint32_t 
     for (double lf : kLoadFactors) {
         if (binned) {
             for (uint32_t ch : kBinChunks)
-                for (uint32_t sg : kBinStages)
-                    for (uint32_t dv : kBinDivs) put(lf, DBG_F_BINNED, 0, 0, ch, dv, sg);
+                for (const auto &sh : kBinShapes)
+                    for (uint32_t dv : kBinDivs) put(lf, DBG_F_BINNED, 0, 0, ch, dv, sh[0], sh[1]);
         } else {
             for (uint32_t block : kBlocks)
                 for (uint32_t wpt : kWpts)
-                    for (uint32_t merge : {0u, (uint32_t)DBG_F_MERGE}) put(lf, merge, block, wpt, 0, 0, 0);
+                    for (uint32_t merge : {0u, (uint32_t)DBG_F_MERGE}) put(lf, merge, block, wpt, 0, 0, 0, 0);
         }
     }
     *n = k;

@@ -157,18 +157,22 @@ def test_host_side_argument_errors_need_no_device():
     L.dbg_config_init(ctypes.byref(cfg))
     cfg.flags = dbg.F_GRAPH | dbg.F_MERGE
     t.load_factor, t.flags, t.block_size, t.windows_per_thread = 0.6, dbg.F_BINNED, 0, 0
-    t.bin_chunks, t.bin_scatter_div, t.bin_stage = 32, 2, 1
+    t.bin_chunks, t.bin_scatter_div, t.bin_shape1, t.bin_shape2 = 32, 2, dbg.SHAPE_BIG, dbg.SHAPE_STAGED
     L.dbg_config_apply_tuning(ctypes.byref(cfg), ctypes.byref(t))
     assert cfg.flags == dbg.F_GRAPH | dbg.F_BINNED and cfg.load_factor == 0.6
-    assert cfg.bin_chunks == 32 and cfg.bin_scatter_div == 2 and cfg.bin_stage == 1
+    assert cfg.bin_chunks == 32 and cfg.bin_scatter_div == 2
+    assert (cfg.bin_shape1, cfg.bin_shape2) == (dbg.SHAPE_BIG, dbg.SHAPE_STAGED)
     cfg.bin_chunks = 1 << 20  # more chunks per workgroup than a pass has
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
-    cfg.bin_chunks, cfg.bin_stage = 0, 3  # staging is 0 (automatic), 1 (never) or 2 (wherever it fits)
+    cfg.bin_chunks, cfg.bin_shape1, cfg.bin_shape2 = 0, 4, 0  # shapes are 0 (automatic) to 3 (big tiles)
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
-    # the search space: binned load factors x chunks x staging x divisors, direct load factors x shapes x merging
+    cfg.bin_shape1, cfg.bin_shape2 = 0, 4
+    assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
+    # the search space: binned load factors x chunks x scatter shape pairs x divisors, direct load factors x
+    # shapes x merging
     nb = len(dbg.autotune_space(True))
     nd = len(dbg.autotune_space(False))
-    assert nb == 4 * 5 * 3 * 4 and nd == 4 * 3 * 3 * 2
+    assert nb == 4 * 5 * 5 * 4 and nd == 4 * 3 * 3 * 2
     assert all(c.flags == dbg.F_BINNED and 0 < c.load_factor < dbg.BINNED_MAX_LOAD for c in dbg.autotune_space(True))
 
 

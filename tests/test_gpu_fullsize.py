@@ -169,7 +169,8 @@ def test_large_full_exact():
     del d_reads, d_off
     torch.cuda.empty_cache()
     assert st["inserts"] == ins and st["vertices"] == n
-    assert st["bin_staged"] == 2, st  # a bucket spans ~713 segments: the second scatter stages lines
+    # ~713 buckets of ~713 segments: both scatters take big tiles
+    assert (st["bin_shape1"], st["bin_shape2"]) == (dbg.SHAPE_BIG, dbg.SHAPE_BIG), st
     assert int(step_counts.sum(dtype=np.uint64)) == ins
     job = Job("large", rs, 16, lambda: [("the step's output", step_keys, step_counts),
                                         ("dbg_extract", table_keys, table_counts)])

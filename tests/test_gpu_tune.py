@@ -50,10 +50,11 @@ def check_choice(t):
     assert t.flags & ~(dbg.F_BINNED | dbg.F_MERGE) == 0
     if t.flags & dbg.F_BINNED:
         assert t.block_size == 0 and t.windows_per_thread == 0 and not t.flags & dbg.F_MERGE
-        assert t.bin_chunks in (0, 4, 8, 32, 64) and t.bin_scatter_div in (0, 1, 2, 4) and t.bin_stage in (0, 1, 2)
+        assert t.bin_chunks in (0, 4, 8, 16, 64) and t.bin_scatter_div in (0, 1, 2, 4) and (t.bin_shape1, t.bin_shape2) in (
+            (0, 0), (1, 1), (2, 2), (3, 3), (3, 2))
     else:
         assert t.block_size in (256, 512, 1024) and t.windows_per_thread in (2, 4, 8)
-        assert t.bin_chunks == 0 and t.bin_scatter_div == 0 and t.bin_stage == 0
+        assert t.bin_chunks == 0 and t.bin_scatter_div == 0 and t.bin_shape1 == 0 and t.bin_shape2 == 0
     assert t.best_ms > 0
 
 
@@ -158,7 +159,7 @@ def test_tuning_persists_in_the_cache_file(tmp_path):
     assert first["from_cache"] == 0 and first["candidates"] >= 4
     assert second["from_cache"] == 2 and second["candidates"] == 0
     for key in ("load_factor", "flags", "block_size", "windows_per_thread", "bin_chunks", "bin_scatter_div",
-                "bin_stage"):
+                "bin_shape1", "bin_shape2"):
         assert first[key] == second[key], key
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and "\t" in lines[0] and "gfx" in lines[0]
