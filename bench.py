@@ -442,6 +442,9 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true", help="autotune the headline workload too")
     ap.add_argument("--bin-chunks", type=int, default=0, help="headline binned launch shape: chunks per workgroup")
     ap.add_argument("--bin-div", type=int, default=0, help="headline binned launch shape: pass-2 scatter grid divisor")
+    ap.add_argument("--bin-shape1", type=int, default=0, help="headline binned launch shape: first scatter shape "
+                    "(0 automatic, 1 plain tiles, 2 staged lines, 3 big tiles)")
+    ap.add_argument("--bin-shape2", type=int, default=0, help="headline binned launch shape: second scatter shape")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels without HIP graphs")
     ap.add_argument("--no-compare", action="store_true", help="skip the direct-mode comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -454,7 +457,8 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true", help="skip the serving benchmark")
     ap.add_argument("--no-long-k", action="store_true", help="skip the k = 51 build of the bacterial reads")
     ap.add_argument("--long-k", type=int, default=51)
-    ap.add_argument("--no-tune", action="store_true", help="bacterial leg: binned at load factor 0.5, no autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="bacterial leg: no autotuned run beside the one at the "
+                    "configuration's load factor 0.5")
     ap.add_argument("--served-payloads", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--calibrate", action="store_true",
@@ -497,7 +501,8 @@ def main() -> int:
         log("autotune: %s" % json.dumps(info))
         mode = "binned" if t.flags & dbg.F_BINNED else "direct"
         return (info, mode, t.load_factor, t.block_size, t.windows_per_thread, bool(t.flags & dbg.F_MERGE),
-                dict(bin_chunks=t.bin_chunks, bin_scatter_div=t.bin_scatter_div))
+                dict(bin_chunks=t.bin_chunks, bin_scatter_div=t.bin_scatter_div, bin_shape1=t.bin_shape1,
+                     bin_shape2=t.bin_shape2))
 
     names = {1: "tiny", 2: "bacterial_c2", 3: "large_c3"}
     profile = "hbm_traffic_%s.md"
@@ -602,7 +607,8 @@ def main() -> int:
     rs = load(args.config)
     tuning = None
     mode, lf, block, wpt, merge = args.mode, args.load_factor, 0, 0, False
-    shape = dict(bin_chunks=args.bin_chunks, bin_scatter_div=args.bin_div)
+    shape = dict(bin_chunks=args.bin_chunks, bin_scatter_div=args.bin_div, bin_shape1=args.bin_shape1,
+                 bin_shape2=args.bin_shape2)
     if args.tune:
         tuning, mode, lf, block, wpt, merge, shape = tuned(rs)
     h = leg(rs, args.config, mode, lf, block, wpt, merge, args.steps, args.warmup, shape)
@@ -627,6 +633,7 @@ def main() -> int:
                    "table_bytes": int(st["table_bytes"]), "load_factor": lf, "entry_bytes": st["entry_bytes"],
                    "mode": mode, "hip_graphs": graphs_on, "bin_chunks": shape["bin_chunks"],
                    "bin_scatter_div": shape["bin_scatter_div"],
+                   "bin_shapes": [int(st["bin_shape1"]), int(st["bin_shape2"])],
                    "step": "reset + dbg_build_extract_device (build, every vertex written to device "
                            "buffers, status read back)"},
         "build_kernel_ginserts_s": round(rs.inserts / (r["kern_ms"] * 1e-3) / 1e9, 4),
@@ -666,17 +673,24 @@ def main() -> int:
     # ---------------------------------------------------------------- bacterial scale
     if not args.no_bacterial and args.config != 2:
         b = load(2)
-        if args.no_tune:
-            btune, bmode, blf, bblock, bwpt, bmerge, bshape = None, "binned", 0.5, 0, 0, False, {}
-        else:
-            btune, bmode, blf, bblock, bwpt, bmerge, bshape = tuned(b)
-        bl = leg(b, 2, bmode, blf, bblock, bwpt, bmerge, max(args.steps, 10), args.warmup, bshape)
+        # the configuration's own table load factor (0.5), default launch shape
+        bmode, blf = "binned", 0.5
+        bl = leg(b, 2, bmode, blf, 0, 0, False, max(args.steps, 10), args.warmup, {})
         br = bl["r"]
         bac = {"workload": "plain build, %s" % b.meta["name"], "inserts_per_step": b.inserts,
                "vertices": br["V"], "capacity": br["cap"], "load_factor": blf, "mode": bmode,
+               "bin_shapes": [int(br["st"]["bin_shape1"]), int(br["st"]["bin_shape2"])],
                "value": round(br["value"], 4), "ms_per_step": round(br["ms_step"], 4),
                "build_kernel_ginserts_s": round(b.inserts / (br["kern_ms"] * 1e-3) / 1e9, 4),
-               "autotune": btune, "roofline": bl["roofline"], "phases": bl["phases"]}
+               "roofline": bl["roofline"], "phases": bl["phases"]}
+        if not args.no_tune:
+            # the autotuner's choice for the same reads, timed the same way
+            btune, tmode, tlf, tblock, twpt, tmerge, tshape = tuned(b)
+            tr = measure_step(dbg, torch, dev, b, b.inserts, tmode, tlf, max(args.steps, 10), args.warmup, graphs_on,
+                              tblock, twpt, tmerge, tshape)
+            bac["autotuned"] = {"tuning": btune, "value": round(tr["value"], 4), "ms_per_step": round(tr["ms_step"], 4),
+                                "vertices": tr["V"], "capacity": tr["cap"]}
+            log("bacterial autotuned: %s" % json.dumps(bac["autotuned"]))
         if not args.no_compare:
             o = measure_step(dbg, torch, dev, b, b.inserts, "direct", 0.5, 5, 1, graphs_on)
             bac["compare_direct"] = {"value": round(o["value"], 4), "ms_per_step": round(o["ms_step"], 4),
