@@ -272,19 +272,21 @@ constexpr uint32_t kLineBytes = 128;
 // Scatter shapes.  A plain scatter (512 threads, tiles of 4096 records)
 // stores each tile's runs as it sorts them; a staged one (1024 threads, one
 // workgroup per CU when it stages 713 runs) stores whole lines only; a big
-// one (1024 threads, tiles of 16384 records: four planning tiles, 128 KB of
-// LDS) stores runs as they come, four times longer than a plain tile's.
+// one (1024 threads, tiles of 128 KB of records: 16384 one-word or 8192
+// two-word records, four or two planning tiles) stores runs as they come,
+// four or two times longer than a plain tile's.
 enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2 };
+constexpr uint32_t kBigTileBytes = 128u * 1024u;
 
-template <uint32_t SHAPE>
+template <uint32_t SHAPE, uint32_t RW = 1>
 struct ScatterShape {
     static constexpr uint32_t block = SHAPE == kShapeTile ? 512u : 1024u;
-    static constexpr uint32_t tile = SHAPE == kShapeBig ? 16384u : 4096u;
+    static constexpr uint32_t tile = SHAPE == kShapeBig ? kBigTileBytes / (8u * RW) : 4096u;
     static constexpr uint32_t per = tile / block;  // records per thread
-    static constexpr uint32_t rb = SHAPE == kShapeBig ? 14u : 12u;  // rank bits of a tag
+    static constexpr uint32_t rb = SHAPE != kShapeBig ? 12u : RW == 1 ? 14u : 13u;  // rank bits of a tag
+    static_assert((1u << rb) == tile || (SHAPE != kShapeBig && tile == 4096u), "a tag's rank holds a tile");
 };
 constexpr uint32_t kStageBlock = ScatterShape<kShapeStaged>::block;
-constexpr uint32_t kBigTile = ScatterShape<kShapeBig>::tile;
 
 template <typename R>
 struct Lines {
@@ -481,7 +483,7 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 // record's bucket rather than keep it in LDS beside the record).
 __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + 8 * rw * (big ? kBigTile : kBinTile);
+    if (scatter) b += align16(8 * d1_max) + (big ? kBigTileBytes : 8 * rw * kBinTile);
     return b;
 }
 
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(ScatterShape<SHAPE>::block) __attribute__((amdgpu_w
                                                   const uint64_t *__restrict__ tile_read1,
                                                   uint32_t d1_max) {
     using R = typename RecOf<RW>::T;
-    using Sh = ScatterShape<SHAPE>;
+    using Sh = ScatterShape<SHAPE, RW>;
     constexpr bool STAGED = SHAPE == kShapeStaged;
     constexpr uint32_t WPT = Sh::per, TILE = Sh::tile, RB = Sh::rb, TPS = TILE / kBinTile;
     static_assert(WPT * Sh::block == TILE && TILE % kBinTile == 0, "a tile is one window per thread slot");
@@ -814,7 +816,7 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 // when scattering).
 __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (fan_max + 1));
-    if (scatter) b += align16(8 * fan_max) + (big ? 8 * rw * kBigTile : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
+    if (scatter) b += align16(8 * fan_max) + (big ? kBigTileBytes : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
     return b;
 }
 
@@ -870,7 +872,7 @@ __global__ __launch_bounds__(ScatterShape<SHAPE>::block) void k_refine(const Bin
                                                      const uint64_t *__restrict__ scan2,
                                                      uint64_t *__restrict__ rec2w, uint32_t fan_max) {
     using R = typename RecOf<RW>::T;
-    using Sh = ScatterShape<SHAPE>;
+    using Sh = ScatterShape<SHAPE, RW>;
     constexpr bool STAGED = SHAPE == kShapeStaged;
     constexpr bool CHILD = RW == 1 && SHAPE == kShapeTile;  // segments kept in s_child
     constexpr uint32_t PT = Sh::per, TILE = Sh::tile, RB = Sh::rb;
@@ -1450,11 +1452,9 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
         DBG_LAUNCH_BIN(kShapeStaged);
         launched = true;
     }
-    if constexpr (RW == 1) {  // big tiles of 16-byte records do not fit a workgroup's LDS
-        if (bb.shape1 == kShapeBig) {
-            DBG_LAUNCH_BIN(kShapeBig);
-            launched = true;
-        }
+    if (bb.shape1 == kShapeBig) {
+        DBG_LAUNCH_BIN(kShapeBig);
+        launched = true;
     }
     if (!launched) DBG_LAUNCH_BIN(kShapeTile);
 #undef DBG_LAUNCH_BIN
@@ -1463,7 +1463,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
-                       bb.buckets, bb.target2, bb.shape2 == kShapeBig ? kBigTile / kRefTile : 1u);
+                       bb.buckets, bb.target2, bb.shape2 == kShapeBig ? ScatterShape<kShapeBig, RW>::tile / kRefTile : 1u);
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
         hipLaunchKernelGGL(k_chunk_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.chunk2,
@@ -1492,11 +1492,9 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
         DBG_LAUNCH_REF(kShapeStaged);
         launched = true;
     }
-    if constexpr (RW == 1) {  // big tiles of 16-byte records do not fit a workgroup's LDS
-        if (bb.shape2 == kShapeBig) {
-            DBG_LAUNCH_REF(kShapeBig);
-            launched = true;
-        }
+    if (bb.shape2 == kShapeBig) {
+        DBG_LAUNCH_REF(kShapeBig);
+        launched = true;
     }
     if (!launched) DBG_LAUNCH_REF(kShapeTile);
 #undef DBG_LAUNCH_REF
@@ -1533,7 +1531,7 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     (void)device;
     hipError_t e;
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1,
-                       bb.shape1 == kShapeBig ? kBigTile / kBinTile : 1u);
+                       bb.shape1 == kShapeBig ? kBigTileBytes / (8u * bb.rec_words) / kBinTile : 1u);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
@@ -1591,14 +1589,10 @@ void grids_for(int device, BinBuffers &bb) {
                                            : stage_fits(k_refine<true, RW, kShapeStaged>, device,
                                                         scatter_lds_bytes<R>(sh, first, n)))))
             sh = kShapeTile;
-        if constexpr (RW == 1) {
-            if (sh == kShapeBig &&
-                !(first ? stage_fits(k_bin<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))
-                        : stage_fits(k_refine<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))))
-                sh = kShapeTile;
-        } else if (sh == kShapeBig) {
-            sh = kShapeTile;  // 16384 records of 16 bytes: more than a workgroup's LDS
-        }
+        if (sh == kShapeBig &&
+            !(first ? stage_fits(k_bin<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))
+                    : stage_fits(k_refine<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))))
+            sh = kShapeTile;
         return sh;
     };
     bb.shape1 = pick(bb.shape_req1, true, bb.d1_max);
@@ -1610,9 +1604,9 @@ void grids_for(int device, BinBuffers &bb) {
     bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, l1);
     if (bb.shape1 == kShapeStaged)
         bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks1_cap, l1);
-    if constexpr (RW == 1)
-        if (bb.shape1 == kShapeBig)
-            bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeBig>, device, kStageBlock, bb.chunks1_cap, l1);
+    if (bb.shape1 == kShapeBig)
+        bb.grid_bin_scatter =
+            occupancy_grid(k_bin<true, RW, kShapeBig>, device, ScatterShape<kShapeBig>::block, bb.chunks1_cap, l1);
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
     // Plain tiles write one short run per segment when a bucket has many
@@ -1624,9 +1618,9 @@ void grids_for(int device, BinBuffers &bb) {
         std::max<uint32_t>(8, occupancy_grid(k_refine<true, RW>, device, kRefBlock, bb.chunks2_cap, l2) / div);
     if (bb.shape2 == kShapeStaged)
         bb.grid_ref_scatter = occupancy_grid(k_refine<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks2_cap, l2);
-    if constexpr (RW == 1)
-        if (bb.shape2 == kShapeBig)
-            bb.grid_ref_scatter = occupancy_grid(k_refine<true, RW, kShapeBig>, device, kStageBlock, bb.chunks2_cap, l2);
+    if (bb.shape2 == kShapeBig)
+        bb.grid_ref_scatter =
+            occupancy_grid(k_refine<true, RW, kShapeBig>, device, ScatterShape<kShapeBig>::block, bb.chunks2_cap, l2);
     bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2, false>, device, kReduceBlock, bb.parts_cap, 0)
                    : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1, false>, device, kReduceBlock, bb.parts_cap, 0)
                                          : occupancy_grid(k_reduce<3, 1, false>, device, kReduceBlock, bb.parts_cap, 0);

@@ -63,14 +63,13 @@ def test_shapes_build_the_oracle_graph(req, used):
 
 def test_shapes_long_keys():
     """Two-word records (k = 45): 16-byte records, eight to a line; big
-    tiles of 16-byte records do not fit a workgroup's LDS and fall back to
-    plain tiles."""
+    tiles hold 8192 of them (the same 128 KB of LDS)."""
     rng = np.random.default_rng(11)
     k = 45
     reads = ["".join("ACGT"[x] for x in rng.integers(0, 4, int(rng.integers(40, 300)))) for _ in range(3000)]
     rs = readsim.reads_from_strings(reads, k)
     hi, lo, c = oracle.build_graph_wide(rs.reads, rs.offsets, k)
-    for req, used in (((T, T), (T, T)), ((S, S), (S, S)), ((B, B), (T, T))):
+    for req, used in (((T, T), (T, T)), ((S, S), (S, S)), ((B, B), (B, B)), ((0, 0), (T, B))):
         say("long k, shapes %s: %d vertices" % (req, hi.shape[0]))
         with dbg.Graph(expected_vertices=hi.shape[0], flags=dbg.F_BINNED, bin_shape1=req[0],
                        bin_shape2=req[1]) as g:
