@@ -272,21 +272,31 @@ constexpr uint32_t kLineBytes = 128;
 // Scatter shapes.  A plain scatter (512 threads, tiles of 4096 records)
 // stores each tile's runs as it sorts them; a staged one (1024 threads, one
 // workgroup per CU when it stages 713 runs) stores whole lines only; a big
-// one (1024 threads, tiles of 128 KB of records: 16384 one-word or 8192
-// two-word records, four or two planning tiles) stores runs as they come,
-// four or two times longer than a plain tile's.
+// one stores runs as they come from tiles two to four times larger.  Big
+// tiles hold 128 KB of records (16384 one-word or 8192 two-word records;
+// 1024 threads, one workgroup per CU), except in the first scatter of
+// one-word records: 64 KB there (8192 records, 512 threads, 16 windows
+// each, two workgroups per CU), whose window decode gains more from the
+// second workgroup's waves than from longer runs.
 enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2 };
-constexpr uint32_t kBigTileBytes = 128u * 1024u;
 
-template <uint32_t SHAPE, uint32_t RW = 1>
+__host__ __device__ constexpr uint32_t big_tile_bytes(bool first, uint32_t rw) {
+    return first && rw == 1 ? 64u * 1024u : 128u * 1024u;
+}
+
+__host__ __device__ constexpr uint32_t scatter_block(uint32_t shape, bool first, uint32_t rw) {
+    return shape == kShapeStaged || (shape == kShapeBig && big_tile_bytes(first, rw) == 128u * 1024u) ? 1024u : 512u;
+}
+
+template <uint32_t SHAPE, uint32_t RW, bool FIRST>
 struct ScatterShape {
-    static constexpr uint32_t block = SHAPE == kShapeTile ? 512u : 1024u;
-    static constexpr uint32_t tile = SHAPE == kShapeBig ? kBigTileBytes / (8u * RW) : 4096u;
+    static constexpr uint32_t block = scatter_block(SHAPE, FIRST, RW);
+    static constexpr uint32_t tile = SHAPE == kShapeBig ? big_tile_bytes(FIRST, RW) / (8u * RW) : 4096u;
     static constexpr uint32_t per = tile / block;  // records per thread
-    static constexpr uint32_t rb = SHAPE != kShapeBig ? 12u : RW == 1 ? 14u : 13u;  // rank bits of a tag
-    static_assert((1u << rb) == tile || (SHAPE != kShapeBig && tile == 4096u), "a tag's rank holds a tile");
+    static constexpr uint32_t rb = tile == 16384u ? 14u : tile == 8192u ? 13u : 12u;  // rank bits of a tag
+    static_assert((1u << rb) == tile, "a tag's rank holds a tile");
 };
-constexpr uint32_t kStageBlock = ScatterShape<kShapeStaged>::block;
+constexpr uint32_t kStageBlock = scatter_block(kShapeStaged, false, 1);
 
 template <typename R>
 struct Lines {
@@ -483,7 +493,7 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 // record's bucket rather than keep it in LDS beside the record).
 __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + (big ? kBigTileBytes : 8 * rw * kBinTile);
+    if (scatter) b += align16(8 * d1_max) + (big ? big_tile_bytes(true, rw) : 8 * rw * kBinTile);
     return b;
 }
 
@@ -504,7 +514,7 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
 // above) and s_gbase[j] is the run's frontier throughout.  A big tile is
 // four consecutive planning tiles of the chunk (fewer at its end).
 template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile>
-__global__ __launch_bounds__(ScatterShape<SHAPE>::block) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
+__global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -516,7 +526,7 @@ __global__ __launch_bounds__(ScatterShape<SHAPE>::block) __attribute__((amdgpu_w
                                                   const uint64_t *__restrict__ tile_read1,
                                                   uint32_t d1_max) {
     using R = typename RecOf<RW>::T;
-    using Sh = ScatterShape<SHAPE, RW>;
+    using Sh = ScatterShape<SHAPE, RW, true>;
     constexpr bool STAGED = SHAPE == kShapeStaged;
     constexpr uint32_t WPT = Sh::per, TILE = Sh::tile, RB = Sh::rb, TPS = TILE / kBinTile;
     static_assert(WPT * Sh::block == TILE && TILE % kBinTile == 0, "a tile is one window per thread slot");
@@ -816,7 +826,7 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 // when scattering).
 __host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1, bool big = false) {
     uint32_t b = align16(4 * (fan_max + 1));
-    if (scatter) b += align16(8 * fan_max) + (big ? kBigTileBytes : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
+    if (scatter) b += align16(8 * fan_max) + (big ? big_tile_bytes(false, rw) : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
     return b;
 }
 
@@ -865,14 +875,14 @@ __device__ __forceinline__ bool refine_has(uint32_t n, uint32_t it) {
 // continues, as in pass 1 (staged: whole lines only; big: tiles of 16384
 // records).
 template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile>
-__global__ __launch_bounds__(ScatterShape<SHAPE>::block) void k_refine(const BinTotals *__restrict__ tot,
+__global__ __launch_bounds__(scatter_block(SHAPE, false, RW)) void k_refine(const BinTotals *__restrict__ tot,
                                                      const RefChunk *__restrict__ chunk2,
                                                      const uint64_t *__restrict__ rec1w,
                                                      uint32_t *__restrict__ hist2,
                                                      const uint64_t *__restrict__ scan2,
                                                      uint64_t *__restrict__ rec2w, uint32_t fan_max) {
     using R = typename RecOf<RW>::T;
-    using Sh = ScatterShape<SHAPE, RW>;
+    using Sh = ScatterShape<SHAPE, RW, false>;
     constexpr bool STAGED = SHAPE == kShapeStaged;
     constexpr bool CHILD = RW == 1 && SHAPE == kShapeTile;  // segments kept in s_child
     constexpr uint32_t PT = Sh::per, TILE = Sh::tile, RB = Sh::rb;
@@ -1445,7 +1455,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb1), dim3(kFlatBlock), 0, s, len1, bb.scan1, bb.partials);
     if (marks) (void)hipEventRecord(marks[2], s);
 #define DBG_LAUNCH_BIN(SH)                                                                                      \
-    hipLaunchKernelGGL((k_bin<true, RW, SH>), dim3(g1s), dim3(ScatterShape<SH>::block), lb1, s, args, inst, packed, \
+    hipLaunchKernelGGL((k_bin<true, RW, SH>), dim3(g1s), dim3(scatter_block(SH, true, RW)), lb1, s, args, inst, packed, \
                        ws, bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max)
     bool launched = false;
     if (bb.shape1 == kShapeStaged) {
@@ -1463,7 +1473,8 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
 
     // pass 2
     hipLaunchKernelGGL(k_refine_plan, dim3(1), dim3(1024), 0, s, args, inst, bb.plan, bb.scan1, bb.totals,
-                       bb.buckets, bb.target2, bb.shape2 == kShapeBig ? ScatterShape<kShapeBig, RW>::tile / kRefTile : 1u);
+                       bb.buckets, bb.target2,
+                       bb.shape2 == kShapeBig ? ScatterShape<kShapeBig, RW, false>::tile / kRefTile : 1u);
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(bb.buckets_cap, 4096));
         hipLaunchKernelGGL(k_chunk_descs, dim3(g), dim3(256), 0, s, inst, bb.buckets, bb.totals, bb.chunk2,
@@ -1485,7 +1496,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     hipLaunchKernelGGL(k_flat_add, dim3((uint32_t)nb2), dim3(kFlatBlock), 0, s, len2, bb.scan2, bb.partials);
     if (marks) (void)hipEventRecord(marks[6], s);
 #define DBG_LAUNCH_REF(SH)                                                                                   \
-    hipLaunchKernelGGL((k_refine<true, RW, SH>), dim3(g2s), dim3(ScatterShape<SH>::block), lr1, s, bb.totals, \
+    hipLaunchKernelGGL((k_refine<true, RW, SH>), dim3(g2s), dim3(scatter_block(SH, false, RW)), lr1, s, bb.totals, \
                        bb.chunk2, bb.rec1, bb.hist2, bb.scan2, bb.rec2, bb.fan_max)
     launched = false;
     if (bb.shape2 == kShapeStaged) {
@@ -1531,7 +1542,7 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     (void)device;
     hipError_t e;
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1,
-                       bb.shape1 == kShapeBig ? kBigTileBytes / (8u * bb.rec_words) / kBinTile : 1u);
+                       bb.shape1 == kShapeBig ? big_tile_bytes(true, bb.rec_words) / (8u * bb.rec_words) / kBinTile : 1u);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
@@ -1606,7 +1617,7 @@ void grids_for(int device, BinBuffers &bb) {
         bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks1_cap, l1);
     if (bb.shape1 == kShapeBig)
         bb.grid_bin_scatter =
-            occupancy_grid(k_bin<true, RW, kShapeBig>, device, ScatterShape<kShapeBig>::block, bb.chunks1_cap, l1);
+            occupancy_grid(k_bin<true, RW, kShapeBig>, device, scatter_block(kShapeBig, true, RW), bb.chunks1_cap, l1);
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
     // Plain tiles write one short run per segment when a bucket has many
@@ -1620,7 +1631,7 @@ void grids_for(int device, BinBuffers &bb) {
         bb.grid_ref_scatter = occupancy_grid(k_refine<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks2_cap, l2);
     if (bb.shape2 == kShapeBig)
         bb.grid_ref_scatter =
-            occupancy_grid(k_refine<true, RW, kShapeBig>, device, ScatterShape<kShapeBig>::block, bb.chunks2_cap, l2);
+            occupancy_grid(k_refine<true, RW, kShapeBig>, device, scatter_block(kShapeBig, false, RW), bb.chunks2_cap, l2);
     bb.grid_reduce = RW == 2 ? occupancy_grid(k_reduce<4, 2, false>, device, kReduceBlock, bb.parts_cap, 0)
                    : bb.entry_words == 4 ? occupancy_grid(k_reduce<4, 1, false>, device, kReduceBlock, bb.parts_cap, 0)
                                          : occupancy_grid(k_reduce<3, 1, false>, device, kReduceBlock, bb.parts_cap, 0);
