@@ -219,6 +219,44 @@ __device__ __forceinline__ uint64_t funnel3(uint64_t a, uint64_t b, uint64_t c, 
     return o ? (a << o) | (b >> (64 - o)) : a;
 }
 
+// Rolling window state of one-word keys (k <= 31).  Consecutive windows of a
+// read share all but one base: the key of the next window is the key shifted
+// by one base, with the window's letter shifted in and its first base shifted
+// out.  The image multiplies the key by kKeyMul modulo 2^60, so with
+// x = key * kKeyMul mod 2^60 the next window's x is
+//   4 x + letter * kKeyMul - first * (4^(k-1) * kKeyMul)  (mod 2^60),
+// one shift-add of a table entry indexed by (first base, letter).  F holds
+// the 32 bases from the window's first on, L the 32 from its letter on, so a
+// thread rolls through up to 32 windows of one read without touching the
+// packed reads again.
+struct Roll {
+    uint64_t F, L, x;
+};
+
+// The state of the window whose first base is at position p of the packed
+// reads.  kshift = 64 - 2 (k - 1).
+__device__ __forceinline__ Roll roll_at(const uint64_t *__restrict__ packed, uint64_t p, uint32_t k,
+                                        uint32_t kshift) {
+    const uint64_t wb = p >> 5;
+    const uint64_t a = packed[wb], b = packed[wb + 1], c = packed[wb + 2];
+    const uint32_t o = (uint32_t)(p & 31) * 2;  // o + 2 (k - 1) <= 122: inside the triple
+    const uint64_t F = funnel3(a, b, c, o);
+    return Roll{F, funnel3(a, b, c, o + 2 * (k - 1)), ((F >> kshift) * kKeyMul) & kKey60};
+}
+
+// Table entry (first << 2 | letter): letter * kKeyMul - first * 4^(k-1) * kKeyMul, mod 2^60.
+__device__ __forceinline__ uint64_t roll_entry(uint32_t e, uint32_t k) {
+    const uint64_t out = (kKeyMul << (2 * (k - 1))) & kKey60;
+    return ((uint64_t)(e & 3u) * kKeyMul - (uint64_t)(e >> 2) * out) & kKey60;
+}
+
+__device__ __forceinline__ void roll_next(Roll &r, const uint64_t *s_roll) {
+    const uint32_t e = (uint32_t)(r.F >> 62) << 2 | (uint32_t)(r.L >> 62);
+    r.F <<= 2;
+    r.L <<= 2;
+    r.x = ((r.x << 2) + s_roll[e]) & kKey60;
+}
+
 // Scatter tiles count with tagged counters: s_cnt[j] starts at j << rb, so
 // the value a record's fetch-add returns is its tag, bucket << rb | rank, and
 // bucket j's count is s_cnt[j] - (j << rb) (rb = 12 for tiles of 4096
@@ -297,6 +335,15 @@ struct ScatterShape {
     static_assert((1u << rb) == tile, "a tag's rank holds a tile");
 };
 constexpr uint32_t kStageBlock = scatter_block(kShapeStaged, false, 1);
+
+// Windows per thread of a first-pass count of one-word keys: a count holds
+// no records, so its threads roll through more windows than a scatter's, and
+// the tile's fixed costs (staging its reads, locating each thread's first
+// window) spread over more of them.  The longer form needs chunks of four
+// planning tiles or more to fill its tiles; chunks are that long where the
+// first scatter runs big tiles.
+constexpr uint32_t kCountWindows = 16;
+constexpr uint32_t kCountWindowsLong = 32;
 
 template <typename R>
 struct Lines {
@@ -513,8 +560,8 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
 // by their number; staged, it stores whole lines only (line-staged scatters
 // above) and s_gbase[j] is the run's frontier throughout.  A big tile is
 // four consecutive planning tiles of the chunk (fewer at its end).
-template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile>
-__global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 1 ? 6 : 4))) void k_bin(const PassArgs *__restrict__ args,
+template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile, uint32_t CW = kCountWindows>
+__global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 2 ? 4 : SCATTER ? 6 : 8))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
                                                   const uint64_t *__restrict__ packed,
                                                   const uint64_t *__restrict__ ws,
@@ -528,11 +575,17 @@ __global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdg
     using R = typename RecOf<RW>::T;
     using Sh = ScatterShape<SHAPE, RW, true>;
     constexpr bool STAGED = SHAPE == kShapeStaged;
-    constexpr uint32_t WPT = Sh::per, TILE = Sh::tile, RB = Sh::rb, TPS = TILE / kBinTile;
+    // rolling window decode (one-word keys), except in plain scatter tiles,
+    // whose records and tags leave no registers for its state
+    constexpr bool ROLL = RW == 1 && !(SCATTER && SHAPE == kShapeTile);
+    // a count holds no records, so its threads roll through more windows
+    constexpr uint32_t WPT = SCATTER || !ROLL ? Sh::per : CW;
+    constexpr uint32_t TILE = WPT * Sh::block, RB = Sh::rb, TPS = TILE / kBinTile;
     static_assert(WPT * Sh::block == TILE && TILE % kBinTile == 0, "a tile is one window per thread slot");
     static_assert(SHAPE == kShapeTile || SCATTER, "counting uses plain tiles");
     __shared__ ReadStage S;
     __shared__ uint32_t s_nlines;
+    __shared__ uint64_t s_roll[16];  // one-word keys: the rolling table of the tile's k
     extern __shared__ __align__(16) unsigned char s_dyn[];
     const StageLayout lay = stage_layout<R>(d1_max, kBinTile);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn);
@@ -581,6 +634,7 @@ __global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdg
             const uint32_t n_in = (uint32_t)(min(w0 + TILE, w_end) - w0);
             if (SCATTER)
                 for (uint32_t j = tid; j <= d1; j += blockDim.x) s_cnt[j] = j << RB;
+            if (ROLL && tid < 16) s_roll[tid] = roll_entry(tid, in.k);
             stage_reads(S, ws, off, off0, tile_read1[plan[i].tile_base + tbeg + t], read_end);
 
             R rec[WPT];
@@ -591,53 +645,98 @@ __global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdg
             if (j0 < n_in) {
                 uint64_t w = w0 + j0;
                 ReadCursor rp = first_read(S, ws, off, off0, read_end, w);
-                uint64_t p = w + rp.delta;
-                uint64_t wbase = p >> 5;
-                uint64_t a = 0, b = 0, cc = 0;
-                if (RW == 1) {
-                    a = packed[wbase];
-                    b = packed[wbase + 1];
-                    cc = packed[wbase + 2];
-                }
+                bool rolled = false;
+                if constexpr (ROLL) {
+                    static_assert(WPT <= 32, "F and L hold the bases of 32 windows");
+                    const uint32_t k = in.k, jend = min(j0 + WPT, n_in);
+                    // read ends relative to w0, capped past the tile: 32-bit compares
+                    auto rel_end = [&](uint64_t wr1) { return (uint32_t)min<uint64_t>(wr1 - w0, n_in + 1u); };
+                    Roll st = roll_at(packed, w + rp.delta, k, kshift);
+                    Roll st2 = st;  // the next read's first window, if one starts among this thread's
+                    const uint32_t e1 = rel_end(rp.wr1);
+                    uint32_t e2 = e1;
+                    if (e1 < jend) {
+                        ReadCursor c = rp;
+                        next_read(c, S, ws, off, off0, read_end, rp.wr1);
+                        st2 = roll_at(packed, rp.wr1 + c.delta, k, kshift);
+                        e2 = rel_end(c.wr1);
+                    }
+                    if (e2 >= jend) {  // at most one read boundary: every window rolls
+                        rolled = true;
 #pragma unroll
-                for (uint32_t q = 0; q < WPT; ++q) {
-                    if (j0 + q >= n_in) break;
-                    if (w >= rp.wr1) {  // the next window starts another read
-                        next_read(rp, S, ws, off, off0, read_end, w);
-                        p = w + rp.delta;
-                        // the words must hold this and the remaining windows' first
-                        // bases at offsets below 64 (without a crossing a thread's
-                        // offsets stay below 32 + WPT)
-                        if (RW == 1 && p - 32 * wbase + (WPT - 1 - q) > 63) {
-                            wbase = p >> 5;
-                            a = packed[wbase];
-                            b = packed[wbase + 1];
-                            cc = packed[wbase + 2];
+                        for (uint32_t q = 0; q < WPT; ++q) {
+                            const uint32_t j = j0 + q;
+                            if (j >= n_in) break;
+                            if (j == e1) st = st2;
+                            const uint64_t sink = j + 1 == e1 || j + 1 == e2 ? 4u : 0u;
+                            const uint64_t img = st.x ^ (st.x >> 30);  // the key's image
+                            const uint64_t head = (img << 3) | sink | (uint32_t)(st.L >> 62);
+                            rec[q] = head;
+                            const uint32_t bk = bucket_of(image_top(img), d1);
+                            if (SCATTER) {
+                                tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
+                            } else {
+                                __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                            roll_next(st, s_roll);
                         }
                     }
-                    const uint64_t sink = w + 1 == rp.wr1 ? 4u : 0u;
-                    uint64_t head;
-                    if constexpr (RW == 1) {
-                        const uint64_t v = funnel3(a, b, cc, (uint32_t)(p - 32 * wbase) * 2);
-                        head = (key_image(v >> kshift) << 3) | sink | ((uint32_t)(v >> lshift) & 3u);
-                        rec[q] = head;
-                    } else {
-                        uint64_t x0, x1, kh, kl, ih, il;
-                        uint32_t letter;
-                        bases128_at(packed, p, x0, x1);
-                        wide_window(x0, x1, in.k - 1, kh, kl, letter);
-                        wide_image(kh, kl, ih, il);
-                        head = (ih << 3) | sink | letter;
-                        rec[q] = make_ulonglong2(head, il);
+                }
+                if (!rolled) {  // reads shorter than a thread's windows, long keys, plain scatter tiles
+                    uint64_t p = w + rp.delta;
+                    uint64_t wbase = p >> 5;
+                    uint64_t a = 0, b = 0, cc = 0;
+                    if (RW == 1) {
+                        a = packed[wbase];
+                        b = packed[wbase + 1];
+                        cc = packed[wbase + 2];
                     }
-                    const uint32_t bk = bucket_of(image_top(head >> 3), d1);
-                    if (SCATTER) {
-                        tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
-                    } else {
-                        __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // beside the rolling decode this loop may stay rolled (records
+                    // then go through indexed registers, in a path long reads never take)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wpass-failed"
+#pragma unroll
+                    for (uint32_t q = 0; q < WPT; ++q) {
+                        if (j0 + q >= n_in) break;
+                        if (w >= rp.wr1) {  // the next window starts another read
+                            next_read(rp, S, ws, off, off0, read_end, w);
+                            p = w + rp.delta;
+                            // the words must hold this and the remaining windows' first
+                            // bases at offsets below 64 (without a crossing a thread's
+                            // offsets stay below 32 + WPT)
+                            if (RW == 1 && p - 32 * wbase + (WPT - 1 - q) > 63) {
+                                wbase = p >> 5;
+                                a = packed[wbase];
+                                b = packed[wbase + 1];
+                                cc = packed[wbase + 2];
+                            }
+                        }
+                        const uint64_t sink = w + 1 == rp.wr1 ? 4u : 0u;
+                        uint64_t head;
+                        if constexpr (RW == 1) {
+                            const uint64_t v = funnel3(a, b, cc, (uint32_t)(p - 32 * wbase) * 2);
+                            head = (key_image(v >> kshift) << 3) | sink | ((uint32_t)(v >> lshift) & 3u);
+                            rec[q] = head;
+                        } else {
+                            uint64_t x0, x1, kh, kl, ih, il;
+                            uint32_t letter;
+                            bases128_at(packed, p, x0, x1);
+                            wide_window(x0, x1, in.k - 1, kh, kl, letter);
+                            wide_image(kh, kl, ih, il);
+                            head = (ih << 3) | sink | letter;
+                            rec[q] = make_ulonglong2(head, il);
+                        }
+                        const uint32_t bk = bucket_of(image_top(head >> 3), d1);
+                        if (SCATTER) {
+                            tag[q] = lds_add32(&s_cnt[bk], 1u);  // the tag itself: no use until placement
+                        } else {
+                            __hip_atomic_fetch_add(&s_cnt[bk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        ++w;
+                        ++p;
                     }
-                    ++w;
-                    ++p;
+#pragma clang diagnostic pop
                 }
             }
             __syncthreads();  // the next tile's staging waits on this barrier
@@ -1443,8 +1542,13 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     const uint32_t lb0 = bin_lds_bytes(bb.d1_max, false, RW);
     const uint32_t lb1 = scatter_lds_bytes<R>(bb.shape1, true, bb.d1_max);
     const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
-    hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
-                       bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    constexpr uint32_t CWL = RW == 1 ? kCountWindowsLong : kCountWindows;  // long counts: one-word keys
+    if (bb.shape1 == kShapeBig)
+        hipLaunchKernelGGL((k_bin<false, RW, kShapeTile, CWL>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed,
+                           ws, bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
+    else
+        hipLaunchKernelGGL((k_bin<false, RW>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed, ws, bb.plan,
+                           bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (marks) (void)hipEventRecord(marks[1], s);
     const uint64_t nb1 = std::max<uint64_t>((bb.hist1_cap + kFlatChunk - 1) / kFlatChunk, 1);
@@ -1586,13 +1690,17 @@ void grids_for(int device, BinBuffers &bb) {
     // big 9.5 and 8.1 ms for the first and second scatter; at 44.7 k
     // segments (212 runs) plain 0.52 and 0.61 ms, big 0.62 and 0.51 ms (the
     // first scatter also decodes windows, four planning tiles per thread
-    // group at once).  Automatic: the second scatter takes big tiles, the
-    // first beyond kScatterWide runs.  A big tile needs chunks of at least
-    // four planning tiles (the plan kernels' min_chunk).  The line numbers
-    // of a staged tile must fit s_pack's 11 bits.
+    // group at once).  With the rolling window decode and the first
+    // scatter's 8192-record tiles of one-word keys, big tiles also win at
+    // 35.7 k segments (189 runs): 0.43 against 0.50 ms, and the count
+    // before it 0.13 against 0.17 ms.  Automatic: the second scatter takes
+    // big tiles, and so does the first for one-word keys, or beyond
+    // kScatterWide runs.  A big tile needs chunks of at least as many
+    // planning tiles as it holds (the plan kernels' min_chunk).  The line
+    // numbers of a staged tile must fit s_pack's 11 bits.
     const auto pick = [&](uint32_t req, bool first, uint32_t n) -> uint32_t {
         uint32_t sh = req == 1 ? kShapeTile : req == 2 ? kShapeStaged : req == 3 ? kShapeBig
-                    : !first || n > kScatterWide ? kShapeBig : kShapeTile;
+                    : !first || RW == 1 || n > kScatterWide ? kShapeBig : kShapeTile;
         const uint32_t tile = first ? kBinTile : kRefTile;
         if (sh == kShapeStaged && !(tile / Lines<R>::L + n < 2048 &&
                                     (first ? stage_fits(k_bin<true, RW, kShapeStaged>, device,
@@ -1610,8 +1718,12 @@ void grids_for(int device, BinBuffers &bb) {
     bb.shape2 = pick(bb.shape_req2, false, bb.fan_max);
     const uint32_t l1 = scatter_lds_bytes<R>(bb.shape1, true, bb.d1_max);
     const uint32_t l2 = scatter_lds_bytes<R>(bb.shape2, false, bb.fan_max);
+    constexpr uint32_t CWL = RW == 1 ? kCountWindowsLong : kCountWindows;
     bb.grid_bin_count =
-        occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
+        bb.shape1 == kShapeBig
+            ? occupancy_grid(k_bin<false, RW, kShapeTile, CWL>, device, kBinBlock, bb.chunks1_cap,
+                             bin_lds_bytes(bb.d1_max, false, RW))
+            : occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
     bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW>, device, kBinBlock, bb.chunks1_cap, l1);
     if (bb.shape1 == kShapeStaged)
         bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeStaged>, device, kStageBlock, bb.chunks1_cap, l1);
