@@ -124,11 +124,12 @@ typedef struct {
      * few records when there are many runs); 2 = staged: each run's
      * records wait in LDS until they fill a 128-byte line, and only whole
      * lines are stored; 3 = big tiles of 128 KB of records (16384, or
-     * 8192 for k > 32; in the first scatter for k <= 31, 8192 records in
-     * 64 KB), runs two to four times longer; 0 = automatic (big tiles for
-     * the second scatter, and for the first when k <= 31 or beyond 384
-     * runs, else plain tiles).  A shape whose LDS does not fit one
-     * workgroup falls back to plain tiles.
+     * 8192 for k > 32; in the first scatter for k <= 31 up to 384 runs,
+     * 8192 records in 64 KB), runs two to four times longer; 4 = big
+     * tiles of 128 KB in every case; 0 = automatic (big tiles for the
+     * second scatter, and for the first when k <= 31 or beyond 384 runs,
+     * else plain tiles).  A shape whose LDS does not fit one workgroup
+     * falls back to a smaller one.
      * bin_scatter_div divides the resident grid of a second scatter of
      * plain tiles (0 = automatic: 2 when a level-1 bucket spans more than
      * 384 table segments, else 1). */

@@ -45,7 +45,7 @@ BINNED_PHASES = ("setup", "plan", "count1", "scan1", "scatter1", "plan2", "count
                  "starts", "reduce")
 TUNE_FORCE = 0x1
 # partition scatter shapes (dbg_config bin_shape1 / bin_shape2)
-SHAPE_AUTO, SHAPE_TILES, SHAPE_STAGED, SHAPE_BIG = 0, 1, 2, 3
+SHAPE_AUTO, SHAPE_TILES, SHAPE_STAGED, SHAPE_BIG, SHAPE_BIG_WIDE = 0, 1, 2, 3, 4
 
 
 class Config(ctypes.Structure):

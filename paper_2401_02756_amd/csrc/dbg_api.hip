@@ -32,8 +32,8 @@ int dbg_create(const dbg_config *cfg_in, dbg_graph **out) {
     if (block % 64 || block > 1024) return DBG_E_INVAL;
     const uint32_t wpt = cfg.windows_per_thread ? cfg.windows_per_thread : 4;
     if (wpt > 64) return DBG_E_INVAL;
-    if (cfg.bin_chunks > dbgk::kMaxChunkTarget || cfg.bin_scatter_div > 64 || cfg.bin_shape1 > 3 ||
-        cfg.bin_shape2 > 3)
+    if (cfg.bin_chunks > dbgk::kMaxChunkTarget || cfg.bin_scatter_div > 64 || cfg.bin_shape1 > 4 ||
+        cfg.bin_shape2 > 4)
         return DBG_E_INVAL;
 
     int device = cfg.device;

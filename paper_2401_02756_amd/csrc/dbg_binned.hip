@@ -316,20 +316,26 @@ constexpr uint32_t kLineBytes = 128;
 // one-word records: 64 KB there (8192 records, 512 threads, 16 windows
 // each, two workgroups per CU), whose window decode gains more from the
 // second workgroup's waves than from longer runs.
-enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2 };
+// kShapeBigWide is the 128 KB form of the first scatter's big tiles for
+// one-word records (16384 records, 1024 threads, one workgroup per CU): it
+// writes runs twice as long, which pays where the first pass has many
+// buckets.  The shape codes of dbg_config and dbg_stats are these plus one.
+enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2, kShapeBigWide = 3 };
 
-__host__ __device__ constexpr uint32_t big_tile_bytes(bool first, uint32_t rw) {
-    return first && rw == 1 ? 64u * 1024u : 128u * 1024u;
+__host__ __device__ constexpr bool is_big(uint32_t shape) { return shape == kShapeBig || shape == kShapeBigWide; }
+
+__host__ __device__ constexpr uint32_t big_tile_bytes(uint32_t shape, bool first, uint32_t rw) {
+    return first && rw == 1 && shape != kShapeBigWide ? 64u * 1024u : 128u * 1024u;
 }
 
 __host__ __device__ constexpr uint32_t scatter_block(uint32_t shape, bool first, uint32_t rw) {
-    return shape == kShapeStaged || (shape == kShapeBig && big_tile_bytes(first, rw) == 128u * 1024u) ? 1024u : 512u;
+    return shape == kShapeStaged || (is_big(shape) && big_tile_bytes(shape, first, rw) == 128u * 1024u) ? 1024u : 512u;
 }
 
 template <uint32_t SHAPE, uint32_t RW, bool FIRST>
 struct ScatterShape {
     static constexpr uint32_t block = scatter_block(SHAPE, FIRST, RW);
-    static constexpr uint32_t tile = SHAPE == kShapeBig ? big_tile_bytes(FIRST, RW) / (8u * RW) : 4096u;
+    static constexpr uint32_t tile = is_big(SHAPE) ? big_tile_bytes(SHAPE, FIRST, RW) / (8u * RW) : 4096u;
     static constexpr uint32_t per = tile / block;  // records per thread
     static constexpr uint32_t rb = tile == 16384u ? 14u : tile == 8192u ? 13u : 12u;  // rank bits of a tag
     static_assert((1u << rb) == tile, "a tag's rank holds a tile");
@@ -538,9 +544,10 @@ __global__ void k_tile_reads(const PassArgs *__restrict__ args, const Instance *
 // Dynamic LDS of the pass-1 kernels: s_cnt[d1_max + 1] (+ s_gbase[d1_max]
 // and s_rec[kBinTile] when scattering; the write-out recomputes each
 // record's bucket rather than keep it in LDS beside the record).
-__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1, bool big = false) {
+__host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter, uint32_t rw = 1,
+                                                 uint32_t shape = kShapeTile) {
     uint32_t b = align16(4 * (d1_max + 1));
-    if (scatter) b += align16(8 * d1_max) + (big ? big_tile_bytes(true, rw) : 8 * rw * kBinTile);
+    if (scatter) b += align16(8 * d1_max) + (is_big(shape) ? big_tile_bytes(shape, true, rw) : 8 * rw * kBinTile);
     return b;
 }
 
@@ -923,9 +930,10 @@ __global__ __launch_bounds__(1024) void k_refine_plan(const PassArgs *__restrict
 // Dynamic LDS of the pass-2 kernels: s_cnt[fan_max] (+ s_gbase[fan_max],
 // s_rec[tile] and, for one-word records in plain tiles, s_child[kRefTile]
 // when scattering).
-__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1, bool big = false) {
+__host__ __device__ inline uint32_t ref_lds_bytes(uint32_t fan_max, bool scatter, uint32_t rw = 1,
+                                                 uint32_t shape = kShapeTile) {
     uint32_t b = align16(4 * (fan_max + 1));
-    if (scatter) b += align16(8 * fan_max) + (big ? big_tile_bytes(false, rw) : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
+    if (scatter) b += align16(8 * fan_max) + (is_big(shape) ? big_tile_bytes(shape, false, rw) : 8 * rw * kRefTile + (rw == 1 ? 2 * kRefTile : 0));
     return b;
 }
 
@@ -1528,8 +1536,7 @@ template <typename R>
 uint32_t scatter_lds_bytes(uint32_t shape, bool first, uint32_t n) {
     constexpr uint32_t rw = sizeof(R) / 8;
     if (shape == kShapeStaged) return stage_layout<R>(n, first ? kBinTile : kRefTile).bytes;
-    const bool big = shape == kShapeBig;
-    return first ? bin_lds_bytes(n, true, rw, big) : ref_lds_bytes(n, true, rw, big);
+    return first ? bin_lds_bytes(n, true, rw, shape) : ref_lds_bytes(n, true, rw, shape);
 }
 
 // The binned pass for records of RW words (enqueue only).
@@ -1543,7 +1550,7 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     const uint32_t lb1 = scatter_lds_bytes<R>(bb.shape1, true, bb.d1_max);
     const uint32_t g1c = bb.grid_bin_count, g1s = bb.grid_bin_scatter;
     constexpr uint32_t CWL = RW == 1 ? kCountWindowsLong : kCountWindows;  // long counts: one-word keys
-    if (bb.shape1 == kShapeBig)
+    if (is_big(bb.shape1))
         hipLaunchKernelGGL((k_bin<false, RW, kShapeTile, CWL>), dim3(g1c), dim3(kBinBlock), lb0, s, args, inst, packed,
                            ws, bb.plan, bb.totals, bb.hist1, bb.scan1, bb.rec1, bb.tile_read1, bb.d1_max);
     else
@@ -1569,6 +1576,12 @@ hipError_t launch_passes(const PassArgs *args, const Instance *inst, const uint6
     if (bb.shape1 == kShapeBig) {
         DBG_LAUNCH_BIN(kShapeBig);
         launched = true;
+    }
+    if constexpr (RW == 1) {
+        if (bb.shape1 == kShapeBigWide) {
+            DBG_LAUNCH_BIN(kShapeBigWide);
+            launched = true;
+        }
     }
     if (!launched) DBG_LAUNCH_BIN(kShapeTile);
 #undef DBG_LAUNCH_BIN
@@ -1646,7 +1659,8 @@ hipError_t launch_binned(const PassArgs *args, const Instance *inst, const uint6
     (void)device;
     hipError_t e;
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(64), 0, s, args, inst, ws, st, bb.plan, bb.totals, bb.target1,
-                       bb.shape1 == kShapeBig ? big_tile_bytes(true, bb.rec_words) / (8u * bb.rec_words) / kBinTile : 1u);
+                       is_big(bb.shape1) ? big_tile_bytes(bb.shape1, true, bb.rec_words) / (8u * bb.rec_words) / kBinTile
+                                         : 1u);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n_cap + 255) / 256, 8192));
@@ -1693,14 +1707,21 @@ void grids_for(int device, BinBuffers &bb) {
     // group at once).  With the rolling window decode and the first
     // scatter's 8192-record tiles of one-word keys, big tiles also win at
     // 35.7 k segments (189 runs): 0.43 against 0.50 ms, and the count
-    // before it 0.13 against 0.17 ms.  Automatic: the second scatter takes
-    // big tiles, and so does the first for one-word keys, or beyond
-    // kScatterWide runs.  A big tile needs chunks of at least as many
-    // planning tiles as it holds (the plan kernels' min_chunk).  The line
-    // numbers of a staged tile must fit s_pack's 11 bits.
+    // before it 0.13 against 0.17 ms.  At 713 runs the first scatter's
+    // 16384-record tiles (kShapeBigWide) beat its 8192-record ones with the
+    // rolling decode, 8.28 against 8.76 ms; at 189 runs they lose, 0.49
+    // against 0.42 ms.  Automatic: the second scatter takes big tiles, and
+    // so does the first for one-word keys (the wide form beyond kScatterWide
+    // runs) or beyond kScatterWide runs.  Requested big tiles (3) take the
+    // same size rule; 4 asks for the wide form (for two-word records and
+    // the second scatter, plain big tiles, which are 128 KB already).  A big
+    // tile needs chunks of at least as many planning tiles as it holds (the
+    // plan kernels' min_chunk).  The line numbers of a staged tile must fit
+    // s_pack's 11 bits.
     const auto pick = [&](uint32_t req, bool first, uint32_t n) -> uint32_t {
-        uint32_t sh = req == 1 ? kShapeTile : req == 2 ? kShapeStaged : req == 3 ? kShapeBig
+        uint32_t sh = req == 1 ? kShapeTile : req == 2 ? kShapeStaged : req >= 3 ? kShapeBig
                     : !first || RW == 1 || n > kScatterWide ? kShapeBig : kShapeTile;
+        if (sh == kShapeBig && first && RW == 1 && (req == 4 || n > kScatterWide)) sh = kShapeBigWide;
         const uint32_t tile = first ? kBinTile : kRefTile;
         if (sh == kShapeStaged && !(tile / Lines<R>::L + n < 2048 &&
                                     (first ? stage_fits(k_bin<true, RW, kShapeStaged>, device,
@@ -1708,6 +1729,11 @@ void grids_for(int device, BinBuffers &bb) {
                                            : stage_fits(k_refine<true, RW, kShapeStaged>, device,
                                                         scatter_lds_bytes<R>(sh, first, n)))))
             sh = kShapeTile;
+        if constexpr (RW == 1) {
+            if (sh == kShapeBigWide &&
+                !stage_fits(k_bin<true, RW, kShapeBigWide>, device, scatter_lds_bytes<R>(sh, first, n)))
+                sh = kShapeBig;
+        }
         if (sh == kShapeBig &&
             !(first ? stage_fits(k_bin<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))
                     : stage_fits(k_refine<true, RW, kShapeBig>, device, scatter_lds_bytes<R>(sh, first, n))))
@@ -1720,7 +1746,7 @@ void grids_for(int device, BinBuffers &bb) {
     const uint32_t l2 = scatter_lds_bytes<R>(bb.shape2, false, bb.fan_max);
     constexpr uint32_t CWL = RW == 1 ? kCountWindowsLong : kCountWindows;
     bb.grid_bin_count =
-        bb.shape1 == kShapeBig
+        is_big(bb.shape1)
             ? occupancy_grid(k_bin<false, RW, kShapeTile, CWL>, device, kBinBlock, bb.chunks1_cap,
                              bin_lds_bytes(bb.d1_max, false, RW))
             : occupancy_grid(k_bin<false, RW>, device, kBinBlock, bb.chunks1_cap, bin_lds_bytes(bb.d1_max, false, RW));
@@ -1730,6 +1756,11 @@ void grids_for(int device, BinBuffers &bb) {
     if (bb.shape1 == kShapeBig)
         bb.grid_bin_scatter =
             occupancy_grid(k_bin<true, RW, kShapeBig>, device, scatter_block(kShapeBig, true, RW), bb.chunks1_cap, l1);
+    if constexpr (RW == 1) {
+        if (bb.shape1 == kShapeBigWide)
+            bb.grid_bin_scatter = occupancy_grid(k_bin<true, RW, kShapeBigWide>, device,
+                                                 scatter_block(kShapeBigWide, true, RW), bb.chunks1_cap, l1);
+    }
     bb.grid_ref_count =
         occupancy_grid(k_refine<false, RW>, device, kRefBlock, bb.chunks2_cap, ref_lds_bytes(bb.fan_max, false, RW));
     // Plain tiles write one short run per segment when a bucket has many

@@ -231,10 +231,10 @@ struct BinBuffers {     // device scratch of one binned pass
     // resident grid when it stores runs as they come (0: automatic, 2 when a
     // bucket has more than 384 segments), and the requested scatter shapes
     // (dbg_config bin_shape1/2: 0 automatic, 1 plain tiles, 2 staged lines,
-    // 3 big tiles)
+    // 3 big tiles, 4 big tiles of 128 KB)
     uint32_t chunks_per_group, scatter_div, shape_req1, shape_req2;
     // the scatter shapes in use (binned_grids decides: kShape* of
-    // dbg_binned.hip, 0 plain tiles, 1 staged, 2 big tiles)
+    // dbg_binned.hip, 0 plain tiles, 1 staged, 2 big tiles, 3 wide big tiles)
     uint32_t shape1, shape2;
 };
 

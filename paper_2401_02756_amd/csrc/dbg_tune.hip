@@ -32,8 +32,9 @@ constexpr double kLoadFactors[] = {0.5, 0.4, 0.6, 0.7};
 constexpr uint32_t kBinChunks[] = {0, 4, 8, 16, 64};  // 0: the default, 32
 constexpr uint32_t kBinDivs[] = {0, 1, 2, 4};         // 0: automatic
 // scatter shapes, first and second (dbg_config bin_shape1/2): automatic,
-// plain tiles, staged lines, big tiles, big tiles then staged lines
-constexpr uint32_t kBinShapes[][2] = {{0, 0}, {1, 1}, {2, 2}, {3, 3}, {3, 2}};
+// plain tiles, staged lines, big tiles, big tiles then staged lines, wide
+// big tiles then big tiles
+constexpr uint32_t kBinShapes[][2] = {{0, 0}, {1, 1}, {2, 2}, {3, 3}, {3, 2}, {4, 3}};
 constexpr uint32_t kBlocks[] = {256, 512, 1024};
 constexpr uint32_t kWpts[] = {2, 4, 8};
 

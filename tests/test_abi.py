@@ -164,15 +164,15 @@ def test_host_side_argument_errors_need_no_device():
     assert (cfg.bin_shape1, cfg.bin_shape2) == (dbg.SHAPE_BIG, dbg.SHAPE_STAGED)
     cfg.bin_chunks = 1 << 20  # more chunks per workgroup than a pass has
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
-    cfg.bin_chunks, cfg.bin_shape1, cfg.bin_shape2 = 0, 4, 0  # shapes are 0 (automatic) to 3 (big tiles)
+    cfg.bin_chunks, cfg.bin_shape1, cfg.bin_shape2 = 0, 5, 0  # shapes are 0 (automatic) to 4 (wide big tiles)
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
-    cfg.bin_shape1, cfg.bin_shape2 = 0, 4
+    cfg.bin_shape1, cfg.bin_shape2 = 0, 5
     assert L.dbg_create(ctypes.byref(cfg), ctypes.byref(h)) == dbg.E_INVAL
     # the search space: binned load factors x chunks x scatter shape pairs x divisors, direct load factors x
     # shapes x merging
     nb = len(dbg.autotune_space(True))
     nd = len(dbg.autotune_space(False))
-    assert nb == 4 * 5 * 5 * 4 and nd == 4 * 3 * 3 * 2
+    assert nb == 4 * 5 * 6 * 4 and nd == 4 * 3 * 3 * 2
     assert all(c.flags == dbg.F_BINNED and 0 < c.load_factor < dbg.BINNED_MAX_LOAD for c in dbg.autotune_space(True))
 
 

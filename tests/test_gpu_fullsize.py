@@ -169,8 +169,8 @@ def test_large_full_exact():
     del d_reads, d_off
     torch.cuda.empty_cache()
     assert st["inserts"] == ins and st["vertices"] == n
-    # ~713 buckets of ~713 segments: both scatters take big tiles
-    assert (st["bin_shape1"], st["bin_shape2"]) == (dbg.SHAPE_BIG, dbg.SHAPE_BIG), st
+    # ~713 buckets of ~713 segments: both scatters take big tiles, the first their 128 KB form
+    assert (st["bin_shape1"], st["bin_shape2"]) == (dbg.SHAPE_BIG_WIDE, dbg.SHAPE_BIG), st
     assert int(step_counts.sum(dtype=np.uint64)) == ins
     job = Job("large", rs, 16, lambda: [("the step's output", step_keys, step_counts),
                                         ("dbg_extract", table_keys, table_counts)])

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-T, S, B = dbg.SHAPE_TILES, dbg.SHAPE_STAGED, dbg.SHAPE_BIG
+T, S, B, BW = dbg.SHAPE_TILES, dbg.SHAPE_STAGED, dbg.SHAPE_BIG, dbg.SHAPE_BIG_WIDE
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -42,12 +42,15 @@ def _inputs():
 
 
 # requested shapes -> shapes used on these small tables (automatic: big tiles for both
-# scatters of one-word records; for two-word records plain tiles in the first below 385 runs)
+# scatters of one-word records, 8192 records in the first below 385 runs; for two-word records
+# plain tiles in the first below 385 runs).  Wide big tiles (16384 one-word records) exist in the
+# first scatter only: requested for the second, it takes big tiles (128 KB already).
 CASES = [((0, 0), (B, B)), ((T, T), (T, T)), ((S, S), (S, S)), ((B, B), (B, B)), ((B, S), (B, S)),
-         ((S, B), (S, B))]
+         ((S, B), (S, B)), ((BW, BW), (BW, B)), ((BW, S), (BW, S))]
 
 
-@pytest.mark.parametrize("req,used", CASES, ids=["auto", "tiles", "staged", "big", "big-staged", "staged-big"])
+@pytest.mark.parametrize("req,used", CASES, ids=["auto", "tiles", "staged", "big", "big-staged", "staged-big",
+                                                 "wide", "wide-staged"])
 def test_shapes_build_the_oracle_graph(req, used):
     for name, rs in _inputs():
         ref = oracle.build_graph(rs.reads, rs.offsets, rs.k)
@@ -69,7 +72,7 @@ def test_shapes_long_keys():
     reads = ["".join("ACGT"[x] for x in rng.integers(0, 4, int(rng.integers(40, 300)))) for _ in range(3000)]
     rs = readsim.reads_from_strings(reads, k)
     hi, lo, c = oracle.build_graph_wide(rs.reads, rs.offsets, k)
-    for req, used in (((T, T), (T, T)), ((S, S), (S, S)), ((B, B), (B, B)), ((0, 0), (T, B))):
+    for req, used in (((T, T), (T, T)), ((S, S), (S, S)), ((B, B), (B, B)), ((0, 0), (T, B)), ((BW, BW), (B, B))):
         say("long k, shapes %s: %d vertices" % (req, hi.shape[0]))
         with dbg.Graph(expected_vertices=hi.shape[0], flags=dbg.F_BINNED, bin_shape1=req[0],
                        bin_shape2=req[1]) as g:
@@ -80,7 +83,7 @@ def test_shapes_long_keys():
         assert np.array_equal(keys[:, 0], hi) and np.array_equal(keys[:, 1], lo) and np.array_equal(counts, c)
 
 
-@pytest.mark.parametrize("req", [(S, S), (B, S), (B, B)], ids=["staged", "big-staged", "big"])
+@pytest.mark.parametrize("req", [(S, S), (B, S), (B, B), (BW, B)], ids=["staged", "big-staged", "big", "wide"])
 def test_shapes_device_graph_and_batch(req):
     """Shaped scatters under graph capture (replayed) and in a batched pass."""
     sets = [readsim.simulate(int(gl), 120, 12.0, 0.01, 31, seed=500 + j) for j, gl in enumerate((3000, 20000, 9000))]

@@ -51,7 +51,7 @@ def check_choice(t):
     if t.flags & dbg.F_BINNED:
         assert t.block_size == 0 and t.windows_per_thread == 0 and not t.flags & dbg.F_MERGE
         assert t.bin_chunks in (0, 4, 8, 16, 64) and t.bin_scatter_div in (0, 1, 2, 4) and (t.bin_shape1, t.bin_shape2) in (
-            (0, 0), (1, 1), (2, 2), (3, 3), (3, 2))
+            (0, 0), (1, 1), (2, 2), (3, 3), (3, 2), (4, 3))
     else:
         assert t.block_size in (256, 512, 1024) and t.windows_per_thread in (2, 4, 8)
         assert t.bin_chunks == 0 and t.bin_scatter_div == 0 and t.bin_shape1 == 0 and t.bin_shape2 == 0
