@@ -70,13 +70,29 @@ def algorithmic_bytes(n_reads: int, total_bases: int, windows: int, inserts: int
     return (8 * windows + 8 * inserts + 8 * vertices_new + total_bases // 4 + 16 * n_reads)
 
 
+def code_digest(paths: list) -> str:
+    """SHA-256 of C/C++ sources with comments, blank lines and surrounding
+    whitespace removed: it changes when the code changes, not its comments."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for p in paths:
+        text = open(p, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.strip() for ln in text.splitlines() if ln.strip()]
+        h.update(("\n".join(lines) + "\n").encode())
+    return h.hexdigest()
+
+
 def committed_traffic(profile: str, workload: dict, kernel: str) -> int | None:
     """HBM bytes per launch of `kernel` recorded by the counter runs in
     `profile` (a line "traffic_bytes_per_launch[<kernel>]: N"), or None when
-    the profile does not exist, any of its kernel sources changed since the
-    counters were taken, or the run's workload parameters (`workload`, e.g.
-    load factor and mode) differ from the ones recorded there."""
-    import hashlib
+    the profile does not exist, the code of its kernel sources changed since
+    the counters were taken (code_digest), or the run's workload parameters
+    (`workload`, e.g. load factor and mode) differ from the ones recorded
+    there."""
 
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -86,10 +102,8 @@ def committed_traffic(profile: str, workload: dict, kernel: str) -> int | None:
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for src in fields.get("sources", "").split():
-        h.update(open(os.path.join(ROOT, src), "rb").read())
-    if not fields.get("sources") or h.hexdigest() != fields.get("source_sha256"):
+    srcs = fields.get("sources", "").split()
+    if not srcs or code_digest([os.path.join(ROOT, s) for s in srcs]) != fields.get("code_sha256"):
         return None
     for k, v in workload.items():
         if fields.get(k) != str(v):

@@ -314,12 +314,13 @@ constexpr uint32_t kLineBytes = 128;
 // tiles hold 128 KB of records (16384 one-word or 8192 two-word records;
 // 1024 threads, one workgroup per CU), except in the first scatter of
 // one-word records: 64 KB there (8192 records, 512 threads, 16 windows
-// each, two workgroups per CU), whose window decode gains more from the
-// second workgroup's waves than from longer runs.
-// kShapeBigWide is the 128 KB form of the first scatter's big tiles for
-// one-word records (16384 records, 1024 threads, one workgroup per CU): it
-// writes runs twice as long, which pays where the first pass has many
-// buckets.  The shape codes of dbg_config and dbg_stats are these plus one.
+// each, two workgroups per CU), where a second workgroup's waves help the
+// window decode more than longer runs help the stores, up to a few hundred
+// buckets.  kShapeBigWide is the 128 KB form of the first scatter's big
+// tiles for one-word records (16384 records, 1024 threads, one workgroup
+// per CU): it writes runs twice as long, which pays where the first pass
+// has many buckets.  The shape codes of dbg_config and dbg_stats are these
+// plus one.
 enum : uint32_t { kShapeTile = 0, kShapeStaged = 1, kShapeBig = 2, kShapeBigWide = 3 };
 
 __host__ __device__ constexpr bool is_big(uint32_t shape) { return shape == kShapeBig || shape == kShapeBigWide; }
@@ -552,21 +553,25 @@ __host__ __device__ inline uint32_t bin_lds_bytes(uint32_t d1_max, bool scatter,
 }
 
 // Pass 1, per chunk of tiles.  A thread takes WPT consecutive windows of a
-// tile (kBinPerThread; 4 in the staged scatter's 1024-thread workgroups): it finds their read once, loads three packed words, and
-// slides through them, so a window costs a few shifts instead of a search
-// and two loads.  The next read's bases follow the current read's in the
-// packed array, so a window that starts another read (k - 2 bases further
-// on) is found in the staged reads and mostly stays inside the three words.
-// Long keys (RW = 2) take each window's 128 bits from the packed array
-// directly.
+// tile (kBinPerThread in plain tiles, 4 in the staged scatter's 1024-thread
+// workgroups, 16 in big tiles, CW in a count): it finds their read once.
+// One-word keys then roll from window to window (Roll above), with the
+// thread's first read boundary prepared before the loop; a thread whose
+// windows cross two boundaries, and plain scatter tiles, load three packed
+// words and slide through them, a funnel shift per window.  The next
+// read's bases follow the current read's in the packed array, so a window
+// that starts another read (k - 2 bases further on) is found in the staged
+// reads and mostly stays inside the three words.  Long keys (RW = 2) take
+// each window's 128 bits from the packed array directly.
 //
 // Counting, a chunk's histogram accumulates in LDS over its tiles and is
 // written once.  Scattering, s_gbase[j] holds the global position where the
 // chunk's run of bucket j continues: each tile sorts its records by bucket
 // in LDS, writes bucket j's records at s_gbase[j] on, and advances s_gbase[j]
 // by their number; staged, it stores whole lines only (line-staged scatters
-// above) and s_gbase[j] is the run's frontier throughout.  A big tile is
-// four consecutive planning tiles of the chunk (fewer at its end).
+// above) and s_gbase[j] is the run's frontier throughout.  A big tile (and
+// a count tile of CW windows a thread) is two or four consecutive planning
+// tiles of the chunk (fewer at its end).
 template <bool SCATTER, uint32_t RW, uint32_t SHAPE = kShapeTile, uint32_t CW = kCountWindows>
 __global__ __launch_bounds__(scatter_block(SHAPE, true, RW)) __attribute__((amdgpu_waves_per_eu(SHAPE != kShapeTile ? 4 : RW == 2 ? 4 : SCATTER ? 6 : 8))) void k_bin(const PassArgs *__restrict__ args,
                                                   const Instance *__restrict__ inst,
@@ -1694,8 +1699,8 @@ template <uint32_t RW>
 void grids_for(int device, BinBuffers &bb) {
     using R = typename RecOf<RW>::T;
     // Scatter shapes (dbg_config bin_shape1/2: 0 automatic, 1 plain tiles,
-    // 2 staged, 3 big tiles; a shape whose LDS does not fit falls back to
-    // plain tiles).  Staging holds one LDS line per run, so with many runs
+    // 2 staged, 3 big tiles, 4 wide big tiles; a shape whose LDS does not
+    // fit falls back to a smaller one).  Staging holds one LDS line per run, so with many runs
     // a staged scatter runs one 1024-thread workgroup per CU, and it
     // executes about twice the instructions of a plain one per record.  Big
     // tiles make a tile's runs four times longer (about 23 records at 713
