@@ -73,8 +73,11 @@ extern "C" {
                               its size class and replay them afterwards */
 #define DBG_F_STATS 0x20u  /* count probes and compare-and-swap races of every build
                               of the graph (dbg_get_probe_stats); its builds run the
-                              counting kernels, which are slower; batched builds and
-                              dbg_build_device_static do not count */
+                              counting kernels, which are slower (in a binned
+                              segment they read each slot before any compare-and-
+                              swap, where the other kernels probe with the compare-
+                              and-swap itself; both find the same slots); batched
+                              builds and dbg_build_device_static do not count */
 #define DBG_F_TEST_HASH 0x40u /* tests only: every key's home slot is the low 3 bits
                               of its key (of its image in a binned segment), so all
                               keys of a table (of a segment) share one probe chain
